@@ -1,0 +1,441 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test computes its expectation independently of the oracle's code path
+(closed forms, lattice sums, a world-space ray/plane solve, interval-graph
+components, finite differences), so that a dropped term, a wrong sign or a
+transposed operand in the oracle fails one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import axis_camera, make_scene
+
+# gamma / 2 pi with gamma = 2 pi (Sec. 3.5.1); options reach both renderers as
+# float32, so gamma is float32(2 pi)
+KAPPA = float(np.float32(2 * math.pi)) / (2 * math.pi)
+
+
+def f32(x):
+    return np.asarray(x, np.float32).astype(np.float64)
+
+
+def lattice(n_side, spacing, s, z, color=None, seed=0, center=(0.0, 0.0)):
+    g = (np.arange(n_side) - (n_side - 1) / 2.0) * spacing
+    X, Y = np.meshgrid(g + center[0], g + center[1], indexing="ij")
+    n = X.size
+    pos = np.stack([X.ravel(), Y.ravel(), np.full(n, z)], 1)
+    rng = np.random.default_rng(seed)
+    alb = rng.uniform(0, 1, (n, 3)) if color is None else np.tile(color, (n, 1))
+    return pos, np.tile([0, 0, 1.0], (n, 1)), np.tile([1.0, 0, 0], (n, 1)), np.full((n, 2), s), alb
+
+
+def concat(*parts):
+    return [np.concatenate([p[i] for p in parts]) for i in range(5)]
+
+
+def lattice_weights(pos, s, z, cam, px, py, rcut):
+    """Lattice sum of the unnormalised Gaussian at the pixel's world-space hit of a
+    fronto-parallel plane z (sigma_f = 0, camera at the origin looking down +z)."""
+    z = float(f32(z))
+    X = (px + 0.5 - f32(cam.cx)) * z / f32(cam.fx)
+    Y = (py + 0.5 - f32(cam.cy)) * z / f32(cam.fy)
+    P = f32(pos)
+    q = ((X - P[:, 0]) ** 2 + (Y - P[:, 1]) ** 2) / f32(s) ** 2
+    return np.where(q < rcut * rcut, np.exp(-0.5 * q), 0.0)
+
+
+# ---------------------------------------------------------------- P1
+@pytest.mark.parametrize("sigma", [0.0, 0.1, 0.7])
+def test_isolated_surfel_is_its_gaussian(oracle_lib, sigma):
+    """Fronto-parallel isotropic surfel: w = n_f exp(-q/2) with n_f = 1/(1+phi),
+    q = d^2/(m^2 (1+phi)), m = f s / z, phi = sigma_f/m^2 (eq:mip_cov, eq:mip_eval);
+    sigma_f = 0 is the plain Gaussian of eq:kernel; alpha = 1 - exp(-w) (eq:alpha)."""
+    O = oracle_lib
+    cam = axis_camera(64, 64, 100.0)
+    c = np.array([0.013, -0.021, 2.0])
+    s = 0.05
+    alb = np.array([0.2, 0.5, 0.9])
+    sc = make_scene(c, [0, 0, -1], [1, 0, 0], [s, s], alb=alb)
+    pix = O.all_pixels(cam)
+    r = O.render(sc, cam, O.Options(sigma_f=sigma), pix)
+    cc = f32(c)
+    z = cc[2]
+    x0 = f32(cam.fx) * cc[0] / z + f32(cam.cx)
+    y0 = f32(cam.fy) * cc[1] / z + f32(cam.cy)
+    d2 = (pix[:, 0] + 0.5 - x0) ** 2 + (pix[:, 1] + 0.5 - y0) ** 2
+    m = f32(cam.fx) * f32(s) / z
+    phi = f32(sigma) / m ** 2
+    q = d2 / (m * m * (1 + phi))
+    w = np.where(q < 9.0, np.exp(-0.5 * q) / (1 + phi), 0.0)
+    a = 1 - np.exp(-KAPPA * w)
+    ok = np.abs(q - 9.0) > 1e-9
+    assert ok.sum() > 4000
+    np.testing.assert_allclose(r["alpha"][ok], a[ok], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(r["image"][ok], a[ok, None] * f32(alb)[None], rtol=0, atol=1e-13)
+    assert (r["n_layers"][ok] == (w[ok] > 0)).all()
+    assert r["alpha"].max() <= 1 - math.exp(-1.0) + 1e-15   # an isolated surfel stays translucent
+
+
+# ---------------------------------------------------------------- P2
+def _rot(rng):
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def _frame(n, t):
+    n = n / np.linalg.norm(n)
+    g = t - (t @ n) * n
+    u = g / np.linalg.norm(g)
+    return n, u, np.cross(n, u)
+
+
+def _ray_uv(cam, x, y, c, tu, tv):
+    """(u, v) of the point c + u tu + v tv that projects to pixel (x, y): a 3x3
+    linear solve in camera space (independent of the T-matrix route)."""
+    R, t = f32(cam.R), f32(cam.t)
+    d = np.array([(x - f32(cam.cx)) / f32(cam.fx), (y - f32(cam.cy)) / f32(cam.fy), 1.0])
+    A = np.stack([R @ tu, R @ tv, -d], 1)
+    sol = np.linalg.solve(A, -(R @ c + t))
+    return sol[0], sol[1], sol[2]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_tilted_surfel_matches_ray_plane_intersection(oracle_lib, seed):
+    """Sec. 3.1: (u, v) from k x l equals the world-space ray/plane intersection;
+    Sec. 3.3: with sigma_f > 0 the filter uses J = d(u,v)/d(x,y) at the centre,
+    here taken by central differences of that independent intersection."""
+    O = oracle_lib
+    rng = np.random.default_rng(seed)
+    R = _rot(rng)
+    t = rng.uniform(-0.5, 0.5, 3)
+    cam = axis_camera(48, 40, 90.0, R=R, t=t)
+    c_cam = np.array([rng.uniform(-0.1, 0.1), rng.uniform(-0.1, 0.1), rng.uniform(1.6, 2.4)])
+    Rf, tf = f32(cam.R), f32(cam.t)
+    c = np.linalg.solve(Rf, c_cam - tf)
+    n_cam = np.array([rng.uniform(-0.9, 0.9), rng.uniform(-0.9, 0.9), -1.0])
+    nrm = np.linalg.solve(Rf, n_cam)
+    tan = rng.normal(size=3)
+    scl = rng.uniform(0.03, 0.09, 2)
+    sc = make_scene(c, nrm, tan, scl)
+    n_, u_, v_ = _frame(f32(nrm), f32(tan))
+    tu, tv, cc = f32(scl)[0] * u_, f32(scl)[1] * v_, f32(c)
+    pix = O.all_pixels(cam)
+    for sigma in (0.0, 0.25):
+        r = O.render(sc, cam, O.Options(sigma_f=sigma), pix)
+        # projected centre and J by central differences of the independent map
+        pc = Rf @ cc + tf
+        x0, y0 = f32(cam.fx) * pc[0] / pc[2] + f32(cam.cx), f32(cam.fy) * pc[1] / pc[2] + f32(cam.cy)
+        h = 1e-4
+        J = np.zeros((2, 2))
+        for j, (dx, dy) in enumerate([(h, 0), (0, h)]):
+            up = _ray_uv(cam, x0 + dx, y0 + dy, cc, tu, tv)
+            um = _ray_uv(cam, x0 - dx, y0 - dy, cc, tu, tv)
+            J[0, j] = (up[0] - um[0]) / (2 * h)
+            J[1, j] = (up[1] - um[1]) / (2 * h)
+        Smip = np.eye(2) + sigma * J @ J.T
+        Si = np.linalg.inv(Smip)
+        nf = 1.0 / math.sqrt(np.linalg.det(Smip))
+        exp_a = np.zeros(len(pix))
+        ok = np.ones(len(pix), bool)
+        for k, (px, py) in enumerate(pix):
+            u, v, lam = _ray_uv(cam, px + 0.5, py + 0.5, cc, tu, tv)
+            uv = np.array([u, v])
+            q = uv @ Si @ uv
+            ok[k] = abs(q - 9.0) > 1e-6
+            if q < 9.0 and lam > 0:
+                exp_a[k] = 1 - math.exp(-KAPPA * nf * math.exp(-0.5 * q))
+        assert (exp_a > 0).sum() > 30
+        np.testing.assert_allclose(r["alpha"][ok], exp_a[ok], rtol=0, atol=2e-8 if sigma else 1e-12)
+
+
+# ---------------------------------------------------------------- P3 / P4
+def test_partition_of_unity_alpha_worked_value(oracle_lib):
+    """eq:alpha with gamma = 2 pi: a square lattice of spacing h = s sums to
+    W = 2 pi (1 + O(e^{-2 pi^2})) by Poisson summation, so alpha = 1 - e^{-2 pi};
+    the paper prints alpha ~ 0.998 at W ~ 2 pi (golden fixture)."""
+    O = oracle_lib
+    gold = {}
+    for line in open(__file__.replace("test_oracle_pins.py", "golden/coverage_alpha.txt")):
+        line = line.split("#")[0].strip()
+        if line:
+            k, v = line.split("=")
+            gold[k.strip()] = float(v)
+    cam = axis_camera(64, 64, 100.0)
+    s = 0.05
+    parts = lattice(41, s, s, 2.0, color=[0.3, 0.6, 0.9])
+    sc = make_scene(*parts)
+    pix = np.array([[32, 32], [33, 31], [30, 35]])
+    r8 = O.render(sc, cam, O.Options(sigma_f=0.0, r_cut=8.0), pix)
+    exact = 1 - math.exp(-KAPPA * 2 * math.pi)
+    np.testing.assert_allclose(r8["alpha"], exact, rtol=0, atol=1e-9)
+    assert abs(r8["alpha"][0] - gold["alpha_at_W_2pi"]) <= gold["printed_tolerance"]
+    assert (r8["n_layers"] == 1).all()
+    np.testing.assert_allclose(r8["image"], r8["alpha"][:, None] * f32([0.3, 0.6, 0.9])[None], atol=1e-14)
+    # at the paper's r_cut = 3, the truncated lattice sum (brute force) fixes W exactly
+    r3 = O.render(sc, cam, O.Options(sigma_f=0.0, r_cut=3.0), pix)
+    for k, (px, py) in enumerate(pix):
+        W = lattice_weights(parts[0], s, 2.0, cam, px, py, 3.0).sum()
+        assert abs(r3["alpha"][k] - (1 - math.exp(-KAPPA * W))) < 1e-13
+
+
+def test_dense_plane_full_coverage_and_shepard_mean(oracle_lib):
+    """eq:shepard: a dense plane (spacing s/3) reconstructs the weighted mean of
+    its colours exactly, and W ~ 18 pi (1 - e^{-4.5}) gives alpha = 1 to rounding."""
+    O = oracle_lib
+    cam = axis_camera(64, 64, 100.0)
+    s = 0.05
+    pix = np.array([[32, 32], [31, 29], [36, 33]])
+    const = make_scene(*lattice(61, s / 3, s, 2.0, color=[0.25, 0.5, 0.75]))
+    r = O.render(const, cam, O.Options(sigma_f=0.0), pix)
+    np.testing.assert_allclose(r["image"], np.tile(f32([0.25, 0.5, 0.75]), (3, 1)), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(r["alpha"], 1.0, atol=1e-15)
+    parts = lattice(61, s / 3, s, 2.0, seed=4)
+    rnd = make_scene(*parts)
+    r = O.render(rnd, cam, O.Options(sigma_f=0.0), pix)
+    for k, (px, py) in enumerate(pix):
+        w = lattice_weights(parts[0], s, 2.0, cam, px, py, 3.0)
+        assert w.sum() > 18 * math.pi * (1 - math.exp(-4.5)) * 0.99  # 9x the unit density, 3-sigma truncated
+        C = (w[:, None] * f32(parts[4])).sum(0) / w.sum()
+        np.testing.assert_allclose(r["image"][k], C, rtol=1e-13)
+
+
+# ---------------------------------------------------------------- P5 / P6
+def test_occlusion_by_front_layer(oracle_lib):
+    """eq:compositing with two layers: image = a1 C1 + (1 - a1) a2 C2 (+ T bg);
+    under a dense front plane the back plane's share is e^{-W1} < 1e-16."""
+    O = oracle_lib
+    cam = axis_camera(64, 64, 100.0, background=(0.1, 0.2, 0.3))
+    s = 0.05
+    pix = np.array([[32, 32], [34, 30]])
+    bg = f32([0.1, 0.2, 0.3])
+    for spacing in (2.0 * s, s / 3):
+        front = lattice(int(1.0 / spacing) | 1, spacing, s, 2.0, seed=1)
+        back = lattice(41, s, s, 2.6, seed=2)
+        sc = make_scene(*concat(front, back))
+        r = O.render(sc, cam, O.Options(sigma_f=0.0), pix)
+        for k, (px, py) in enumerate(pix):
+            w1 = lattice_weights(front[0], s, 2.0, cam, px, py, 3.0)
+            w2 = lattice_weights(back[0], s, 2.6, cam, px, py, 3.0)
+            a1, a2 = 1 - math.exp(-KAPPA * w1.sum()), 1 - math.exp(-KAPPA * w2.sum())
+            C1 = (w1[:, None] * f32(front[4])).sum(0) / w1.sum()
+            C2 = (w2[:, None] * f32(back[4])).sum(0) / w2.sum()
+            expect = a1 * C1 + (1 - a1) * a2 * C2 + (1 - a1) * (1 - a2) * bg
+            np.testing.assert_allclose(r["image"][k], expect, rtol=1e-12, atol=1e-15)
+            assert r["n_layers"][k] == 2
+            if spacing < s:
+                assert (1 - a1) < 1e-16
+
+
+def test_layer_cap_sixteen(oracle_lib):
+    """App. A.1: once the 16th layer is finalised later groups are discarded."""
+    O = oracle_lib
+    cam = axis_camera(64, 64, 100.0)
+    s = 0.05
+    planes = [lattice(7, 2 * s, s, 2.0 + 0.05 * k, seed=10 + k) for k in range(20)]
+    sc = make_scene(*concat(*planes))
+    pix = np.array([[32, 32]])
+    r = O.render(sc, cam, O.Options(sigma_f=0.0), pix)
+    assert r["n_layers"][0] == 16
+    T, C = 1.0, np.zeros(3)
+    for k in range(16):
+        z = 2.0 + 0.05 * k
+        w = lattice_weights(planes[k][0], s, z, cam, 32, 32, 3.0)
+        a = 1 - math.exp(-KAPPA * w.sum())
+        C += T * a * (w[:, None] * f32(planes[k][4])).sum(0) / w.sum()
+        T *= 1 - a
+    np.testing.assert_allclose(r["image"][0], C, rtol=1e-12)
+    np.testing.assert_allclose(r["alpha"][0], 1 - T, rtol=1e-12)
+
+
+# ---------------------------------------------------------------- P7 / P8
+def tilted_plane(n_side, spacing, s, z0, theta, seed=0, jitter=0.0):
+    g = (np.arange(n_side) - (n_side - 1) / 2.0) * spacing
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    X, Y = X.ravel(), Y.ravel()
+    n = X.size
+    rng = np.random.default_rng(seed)
+    pos = np.stack([X, Y * math.cos(theta), z0 + Y * math.sin(theta) + rng.uniform(-jitter, jitter, n)], 1)
+    nrm = np.tile([0.0, -math.sin(theta), math.cos(theta)], (n, 1))
+    return pos, nrm, np.tile([1.0, 0, 0], (n, 1)), np.full((n, 2), s), rng.uniform(0, 1, (n, 3))
+
+
+def test_surface_separation_and_thin_shell(oracle_lib):
+    """Sec. 3.2.1: tilted planes farther apart than their depth extents form two
+    layers; closer ones (the thin-shell limitation of Sec. 5) merge into one, as do
+    depth-jittered samples of one surface within eps_z."""
+    O = oracle_lib
+    cam = axis_camera(64, 64, 100.0)
+    s, th = 0.05, math.radians(30)
+    pix = np.array([[32, 32], [30, 33]])
+    far = make_scene(*concat(tilted_plane(25, s, s, 2.0, th, 1), tilted_plane(25, s, s, 2.6, th, 2)))
+    near = make_scene(*concat(tilted_plane(25, s, s, 2.0, th, 1), tilted_plane(25, s, s, 2.02, th, 2)))
+    jit = make_scene(*tilted_plane(25, s / 2, s, 2.0, th, 3, jitter=0.02))
+    assert (O.render(far, cam, O.Options(), pix)["n_layers"] == 2).all()
+    assert (O.render(near, cam, O.Options(), pix)["n_layers"] == 1).all()
+    assert (O.render(jit, cam, O.Options(), pix)["n_layers"] == 1).all()
+
+
+def _components(zs, ze):
+    """Connected components of the closed-interval overlap graph, ranked by their
+    smallest interval start (brute force union-find)."""
+    n = len(zs)
+    par = list(range(n))
+
+    def find(a):
+        while par[a] != a:
+            par[a] = par[par[a]]
+            a = par[a]
+        return a
+    for i in range(n):
+        for j in range(i + 1, n):
+            if max(zs[i], zs[j]) <= min(ze[i], ze[j]):
+                par[find(i)] = find(j)
+    roots = [find(i) for i in range(n)]
+    first = {}
+    for i in np.argsort(zs, kind="stable"):
+        first.setdefault(roots[i], zs[i])
+    order = sorted(first, key=lambda r: first[r])
+    rank = {r: k for k, r in enumerate(order)}
+    return np.array([rank[r] for r in roots])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_grouping_equals_interval_components(oracle_lib, seed):
+    """Sec. 3.2.1: Alg. 1 is single-pass interval merging over intervals sorted by
+    z_start, i.e. the layers are the connected components of the overlap graph."""
+    O = oracle_lib
+    rng = np.random.default_rng(seed)
+    n = 60
+    pos = np.stack([rng.uniform(-0.08, 0.08, n), rng.uniform(-0.08, 0.08, n), rng.uniform(1.8, 2.6, n)], 1)
+    nrm = np.stack([rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), -np.ones(n)], 1)
+    tan = rng.normal(size=(n, 3))
+    scl = rng.uniform(0.02, 0.08, (n, 2))
+    sc = make_scene(pos, nrm, tan, scl)
+    cam = axis_camera(64, 64, 100.0)
+    checked = 0
+    for px, py in rng.integers(26, 38, (12, 2)):
+        fr = O.pixel_fragments(sc, cam, O.Options(), int(px), int(py))
+        if len(fr["idx"]) < 2:
+            continue
+        # visiting order is (z_start, index) ascending
+        key = list(zip(fr["zs"], fr["idx"]))
+        assert key == sorted(key)
+        comp = _components(fr["zs"], fr["ze"])
+        if comp.max() >= 16:
+            continue
+        assert (fr["layer"] == comp).all()
+        checked += 1
+    assert checked >= 4
+
+
+# ---------------------------------------------------------------- P10 (shading)
+def test_constant_envmap_prefilter(oracle_lib):
+    """eq:ibl prefilter: normalised specular weights reproduce a constant
+    environment exactly; the cosine-weighted irradiance of a constant map tends to
+    the map's value (the hemisphere integral of the cosine is pi)."""
+    O = oracle_lib
+    errs = []
+    for He, We in ((16, 32), (32, 64)):
+        E = np.full((He, We, 3), 2.5)
+        m = O.envmap(E)
+        lay = O.map_layout(He, We)
+        for l in range(1, 6):
+            h, w, off = lay[l]
+            np.testing.assert_allclose(m[off:off + h * w * 3], 2.5, rtol=1e-12)
+        h, w, off = lay[6]
+        irr = m[off:off + h * w * 3]
+        errs.append(np.abs(irr / 2.5 - 1).max())
+        np.testing.assert_array_equal(m[:He * We * 3], E.ravel())
+    assert errs[0] < 0.05 and errs[1] < errs[0]
+
+
+def test_delta_envmap_irradiance(oracle_lib):
+    """Irradiance of a one-texel environment is max(0, d.d_t) dOmega_t / pi at every
+    output direction, with the texel's exact solid angle."""
+    O = oracle_lib
+    He, We = 8, 16
+    a, b = 3, 5
+    E = np.zeros((He, We, 3))
+    E[a, b] = [1.0, 2.0, 3.0]
+    m = O.envmap(E)
+    h, w, off = O.map_layout(He, We)[6]
+    irr = m[off:off + h * w * 3].reshape(h, w, 3)
+
+    def tdir(i, j, H, W):
+        th, ph = math.pi * (i + 0.5) / H, 2 * math.pi * (j + 0.5) / W
+        return np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+    dt = tdir(a, b, He, We)
+    dom = (2 * math.pi / We) * (math.cos(math.pi * a / He) - math.cos(math.pi * (a + 1) / He))
+    for i in range(0, h, 5):
+        for j in range(0, w, 7):
+            d = tdir(i, j, h, w)
+            np.testing.assert_allclose(irr[i, j], max(0.0, d @ dt) * dom / math.pi * np.array([1, 2, 3.0]),
+                                       rtol=1e-12, atol=1e-16)
+
+
+def test_brdf_lut_properties(oracle_lib):
+    """Split-sum table: at r = 0 the lobe is a mirror, so beta1 = 1 - (1-n.v)^5 and
+    beta2 = (1-n.v)^5 (Schlick); beta1 + beta2 <= 1 (energy) and beta2 >= 0."""
+    O = oracle_lib
+    L = O.brdf_lut(32, 33, 512)
+    nv = np.maximum(np.arange(32) / 31, 1e-3)
+    np.testing.assert_allclose(L[0, :, 0], 1 - (1 - nv) ** 5, atol=1e-12)
+    np.testing.assert_allclose(L[0, :, 1], (1 - nv) ** 5, atol=1e-12)
+    # the GGX-sampled quadrature of a directional albedo <= 1 (sampling error ~1e-4)
+    assert (L[..., 0] + L[..., 1] <= 1 + 1e-3).all()
+    assert (L[..., 1] >= 0).all() and (L[..., 0] >= 0).all()
+    tot = L[..., 0] + L[..., 1]
+    assert (np.diff(tot[:, 8:], axis=0) <= 1e-3).all()   # albedo does not grow with roughness
+
+
+def test_splitsum_colour_constant_environment(oracle_lib):
+    """eq:ibl with a constant environment L: L_s = L exactly, so for a surfel facing
+    the camera (n.w_o = 1) c = k_d rho L_d + L (F0 beta1 + beta2), F0 and k_d as in
+    Sec. 3.4.2; the pixel at the centre of a large surfel carries (1 - e^{-w}) c."""
+    O = oracle_lib
+    He, We = 16, 32
+    Lval = 1.7
+    E = np.full((He, We, 3), Lval)
+    maps = O.envmap(E)
+    lut = O.brdf_lut(16, 65, 256)
+    cam = axis_camera(64, 64, 100.0)
+    s = 0.5
+    rho = np.array([0.8, 0.3, 0.1])
+    for metal in (0.0, 1.0, 0.25):
+        sc = make_scene([0.0, 0.0, 2.0], [0, 0, -1], [1, 0, 0], [s, s], alb=rho, rough=[0.5], metal=[metal])
+        r = O.render(sc, cam, O.Options(sigma_f=0.0, shade="splitsum"), np.array([[32, 32]]),
+                     maps=maps, lut=lut, env_hw=(He, We))
+        h, w, off = O.map_layout(He, We)[6]
+        irr = maps[off:off + h * w * 3].reshape(h, w, 3)
+        Ld = 0.5 * (irr[h - 1, w - 1] + irr[h - 1, 0])   # direction -z: bottom row, phi = 0 seam
+        b1, b2 = lut[32, 15]
+        rf = f32(rho)
+        F0 = 0.04 * (1 - metal) + rf * metal
+        kd = (1 - F0) * (1 - metal)
+        col = kd * rf * Ld + Lval * (F0 * b1 + b2)
+        d2 = 2 * 0.5 ** 2
+        q = d2 / (100 * s / 2) ** 2
+        a = 1 - math.exp(-KAPPA * math.exp(-0.5 * q))
+        np.testing.assert_allclose(r["image"][0], a * col, rtol=1e-12)
+
+
+# ---------------------------------------------------------------- conservativeness
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_fp32_tile_rectangle_is_conservative(oracle_lib, tile):
+    """The FP32 bounding rectangle (exact bbox of the MIP acceptance ellipse,
+    widened by 0.01 px) contains every pixel the FP64 brute force finds covered."""
+    import scenegen as g
+    O = oracle_lib
+    for name, ns, rs in (("C1", 1.0, 1.0), ("C2", 0.02, 0.25)):
+        w = g.make_config(name, n_scale=ns, res_scale=rs)
+        sc, cam = w.scenes[0], w.cameras[0]
+        opt = O.Options(tile_w=tile[0], tile_h=tile[1], shade="albedo")
+        r = O.render(sc, cam, opt, O.all_pixels(cam))
+        assert r["viol"].sum() == 0
+        assert (r["n_layers"] > 0).sum() > 100
