@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Forward + backward throughput of the EWA surfel rasterizer on one MI355X.
+
+One step = one pass of the whole path over one batch: environment levels,
+preprocess + shade, binning (scan, emission, radix sort, ranges), raster
+forward, raster backward, preprocess/shade adjoint, environment adjoint, for
+every view of the workload.  Inputs are resident in HBM before timing.
+
+Default workload: 1M surfels on a union of 5 superquadrics, 8 views of
+800 x 800, split-sum shading with a 128 x 256 HDR environment, batched
+launches captured in a HIP graph.  Also reported: the same work as per-view
+launches, per-stage times, the dominant kernel against the HBM roofline, and
+the CPU oracle on a bounded sample.  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD_DESC = {
+    "C1": "4,096 surfels on the unit sphere, albedo shading, 1 view 128x128",
+    "C2": "200k surfels on a displaced torus, split-sum, envmap 64x128, 1 view 512x512",
+    "C3": "1M surfels on 5 superquadrics, split-sum, envmap 128x256, 8 views 800x800",
+    "C4": "3M density-clustered surfels on a displaced sphere, split-sum, envmap 128x256, 1 view 1920x1080",
+    "C5": "4 scenes (50k, 300k, 1M, 2M surfels), 16 views 256^2..1024^2, split-sum, envmaps 128x256",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(stage, n_pairs, n_rec_vis, n_pix, mean_layers, n_surf):
+    """Algorithmic HBM bytes of one launch of a raster kernel:
+    per pair a 4-byte sorted id and the 64-byte record; per pixel the image,
+    alpha and layer count (forward writes, backward reads dL/dimage, dL/dalpha),
+    16 bytes per composited layer; backward adds a read-modify-write of the 11
+    record gradients of every record that reaches a pixel."""
+    per_pair = 4 + 64
+    if stage == "raster_forward":
+        return n_pairs * per_pair + n_pix * (12 + 4 + 1 + 16 * mean_layers)
+    if stage == "raster_backward":
+        return n_pairs * per_pair + n_pix * (12 + 4 + 1 + 16 * mean_layers) + n_rec_vis * 11 * 4 * 2
+    return None
+
+
+def cpu_baseline(workload, opts_shade, budget_s=20.0):
+    """The oracle (FP64 brute force) on a bounded sample: view 0, a seeded set
+    of pixels, every surfel; forward + backward including the environment
+    prefilter and its adjoint.  Mpixel-views/s over the sampled pixels."""
+    import numpy as np
+    import oracle as O
+    sc, cam = workload.scenes[0], workload.cameras[0]
+    opt = O.Options(shade=opts_shade)
+    rng = np.random.default_rng(0)
+    t0 = time.perf_counter()
+    maps = lut = None
+    hw = (0, 0)
+    if opts_shade == "splitsum":
+        maps = O.envmap(np.asarray(sc.envmap, np.float64))
+        lut = O.brdf_lut(64, 64, 1024)
+        hw = sc.envmap.shape[:2]
+    t_env = time.perf_counter() - t0
+    # calibrate the pixel count on a small probe so the sample takes ~budget_s
+    probe = np.stack([rng.integers(cam.width // 4, 3 * cam.width // 4, 8),
+                      rng.integers(cam.height // 4, 3 * cam.height // 4, 8)], 1).astype(np.int32)
+    t1 = time.perf_counter()
+    O.render(sc, cam, opt, probe, maps=maps, lut=lut, env_hw=hw)
+    O.render_grad(sc, cam, opt, probe, np.ones((8, 3)), np.ones(8), maps=maps, lut=lut, env_hw=hw)
+    per_px = (time.perf_counter() - t1) / 8
+    k = int(max(16, min(4096, (budget_s - t_env) / max(per_px, 1e-6))))
+    pix = np.stack([rng.integers(0, cam.width, k), rng.integers(0, cam.height, k)], 1).astype(np.int32)
+    t2 = time.perf_counter()
+    if opts_shade == "splitsum":
+        maps = O.envmap(np.asarray(sc.envmap, np.float64))
+    O.render(sc, cam, opt, pix, maps=maps, lut=lut, env_hw=hw)
+    gr = O.render_grad(sc, cam, opt, pix, rng.normal(size=(k, 3)), rng.normal(size=k), maps=maps,
+                       lut=lut, env_hw=hw)
+    if opts_shade == "splitsum":
+        O.envmap_adjoint(gr["maps"], *hw)
+    dt = time.perf_counter() - t2
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": k / dt / 1e6, "unit": "Mpixel-views/s", "cores": cores, "kind": "oracle",
+            "sample": f"view 0 of the workload, {k} seeded pixels, all {sc.n} surfels, FP64 forward + "
+                      f"adjoint incl. environment prefilter and its adjoint; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="C3", choices=list(WORKLOAD_DESC))
+    ap.add_argument("--tile", default=None, help="WxH, e.g. 16x16 (default: autotune cache or 16x16)")
+    ap.add_argument("--lds-batch", type=int, default=None)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-only", action="store_true", help="eager steps only (for rocprofv3)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU design (split the "
+                                   "views, one all-reduce of the surfel gradients) is described in "
+                                   "DESIGN.md and not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2605_05876_amd as ss
+    import scenegen as g
+    from paper_2605_05876_amd import autotune
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    w = g.make_config(args.config)
+    log(f"[bench] workload {args.config}: {w.n_surfels} surfels, {len(w.cameras)} views, "
+        f"{w.pixel_views} pixel-views ({time.perf_counter() - t0:.1f} s to generate)")
+    tune = autotune.lookup(args.config)
+    tw, th = (16, 16)
+    lb = 128
+    if tune:
+        tw, th, lb = tune["tile_w"], tune["tile_h"], tune["lds_batch"]
+    if args.tile:
+        tw, th = (int(x) for x in args.tile.lower().split("x"))
+    if args.lds_batch:
+        lb = args.lds_batch
+    opts = ss.Options(shade=w.shade, tile_w=tw, tile_h=th, lds_batch=lb)
+    batch = ss.batch_from_scenes(w.scenes, w.cameras)
+    n_pix = batch.n_pixels
+    rng = np.random.default_rng(0)
+    G = torch.from_numpy(rng.normal(size=(n_pix, 3)).astype(np.float32)).cuda()
+    Ga = torch.from_numpy(rng.normal(size=n_pix).astype(np.float32)).cuda()
+
+    def make(launch):
+        r = ss.Renderer(ss.Options(**{**opts.__dict__, "launch": launch}))
+        ws = r.reserve(batch)
+        img = torch.empty((n_pix, 3), device="cuda")
+        alpha = torch.empty((n_pix,), device="cuda")
+        nl = torch.empty((n_pix,), device="cuda", dtype=torch.uint8)
+        grads = {k: torch.empty_like(batch.params[k]) for k in ss.PARAMS}
+        if batch.envmaps is not None:
+            grads["envmap"] = [torch.empty_like(e) for e in batch.envmaps]
+
+        def step():
+            r.forward(batch, out=(img, alpha, nl))
+            r.backward(batch, G, Ga, grads=grads)
+        return r, step, ws, (img, alpha, nl, grads)
+
+    def timed(step, n, graph):
+        if graph:
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                for _ in range(2):
+                    step()
+            torch.cuda.current_stream().wait_stream(s)
+            torch.cuda.synchronize()
+            cg = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(cg):
+                step()
+            run = cg.replay
+        else:
+            run = step
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t = time.perf_counter()
+        e0.record()
+        for _ in range(n):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) / n * 1e3
+        return max(wall, e0.elapsed_time(e1) / n)
+
+    r, step, ws, bufs = make("batched")
+    step()
+    torch.cuda.synchronize()
+    diag = r.poll()
+    if diag["status"] != 0:
+        raise RuntimeError(f"device status {diag}")
+    log(f"[bench] reserved {ws / 2**30:.2f} GiB; pairs {diag['n_pairs']}, records {diag['n_records']}")
+    use_graph = not args.no_graph and not args.profile_only
+    if args.profile_only:
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        log("[bench] profile-only run done")
+        return
+    ms = timed(step, args.steps, use_graph)
+    value = n_pix / (ms * 1e-3) / 1e6
+    log(f"[bench] batched{'+graph' if use_graph else ''}: {ms:.3f} ms/step, {value:.1f} Mpixel-views/s")
+
+    # per-stage times (eager, HIP events on the library's stream)
+    r.profile(True)
+    for _ in range(max(3, min(args.steps, 10))):
+        step()
+    prof = r.profile_read()
+    r.profile(False)
+    log(f"[bench] raw stage profile: {prof}")
+    stages = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
+    per_step = {k: v[0] / max(1, max(3, min(args.steps, 10))) for k, v in prof.items()}
+    log("[bench] stage ms/launch: " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
+    dom = max(("raster_forward", "raster_backward"), key=lambda k: per_step[k])
+    nl_mean = float(bufs[2].float().mean().item())
+    counts_vis = None
+    alg = algorithmic_bytes(dom, diag["n_pairs"], diag["n_records"], n_pix, nl_mean, w.n_surfels)
+    achieved = alg / (stages[dom] * 1e-3) / 1e9 if stages[dom] > 0 else 0.0
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "algorithmic_bytes_per_launch": int(alg), "launch_ms": round(stages[dom], 4),
+            "n_pairs": diag["n_pairs"], "mean_layers": round(nl_mean, 3)}
+
+    out = {"metric": "fwd+bwd Mpixel-views/s", "value": round(value, 2), "unit": "Mpixel-views/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"{args.config}: {WORKLOAD_DESC[args.config]}",
+                      "launch": "batched" + ("+hipgraph" if use_graph else ""),
+                      "tile": f"{tw}x{th}", "lds_batch": lb, "pixel_views": n_pix,
+                      "surfels": w.n_surfels},
+           "roofline": roof,
+           "stages_ms_per_step": {k: round(v, 4) for k, v in per_step.items()}}
+    del r, step, bufs
+    torch.cuda.empty_cache()
+
+    if not args.no_per_view:
+        rp, stepp, _, bp = make("per_view")
+        stepp()
+        torch.cuda.synchronize()
+        msp = timed(stepp, args.steps, use_graph)
+        out["per_view"] = {"value": round(n_pix / (msp * 1e-3) / 1e6, 2), "ms_per_step": round(msp, 4),
+                           "speedup_batched": round(msp / ms, 3)}
+        log(f"[bench] per-view{'+graph' if use_graph else ''}: {msp:.3f} ms/step")
+        del rp, stepp, bp
+        torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline ...")
+        out["cpu_baseline"] = cpu_baseline(w, w.shade)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * surfsplat: differentiable EWA surfel rasterizer of 3D Surface Splatting (3DSS)
+ * on AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * Forward (render): per (surfel, view) projection through the T-matrix with a
+ * centre-precomputed object-space MIP filter (Sec. 3.1, Sec. 3.3.2), per-surfel
+ * split-sum shading against an HDR environment map (eq:ibl, Sec. 3.4.2), tile
+ * binning and a radix sort keyed by the start of each surfel's depth interval
+ * (Sec. 3.2.1), and per pixel: interval-merging surface separation (Alg. 1),
+ * Shepard normalisation (eq:shepard), coverage opacity from the accumulated
+ * weight (eq:alpha) and front-to-back layer compositing with at most K_max
+ * layers (eq:compositing, App. A.1).
+ * Backward (render_backward): the adjoint of all of the above (App. A.1,
+ * "Backward Pass Implementation"), producing gradients with respect to surfel
+ * positions, normals, tangents, scales, albedo, roughness, metallic and the
+ * environment maps.
+ *
+ * Conventions (shared by every entry point):
+ *   - All buffers named "device" are device memory owned by the caller; they
+ *     must stay alive until the work queued on the given stream has finished.
+ *   - Surfel attributes are structure-of-arrays float32 [C][N]: row c of
+ *     attribute a is a + c*N.  N is the total surfel count over all scenes;
+ *     scene s owns surfels [surfel_offset[s], surfel_offset[s+1]).
+ *   - The surfel frame: n_hat = normal/|normal|, u_hat = Gram-Schmidt of
+ *     tangent against n_hat, v_hat = n_hat x u_hat, t_u = scale[0] u_hat,
+ *     t_v = scale[1] v_hat (world units; one standard deviation of the kernel).
+ *   - Cameras: pinhole, world->camera rotation R (row-major) and translation t,
+ *     OpenCV axes (x right, y down, z forward); pixel (i, j) has its centre at
+ *     (i + 1/2, j + 1/2) in pixel units.
+ *   - Images are float32 [sum_v H_v W_v][3] in view order, row-major per view;
+ *     alpha is float32 [sum_v H_v W_v] (alpha = 1 - residual transmittance).
+ *   - Environment maps are equirectangular float32 [H_e][W_e][3], z up; texel
+ *     (a, b) looks along (sin th cos ph, sin th sin ph, cos th) with
+ *     th = pi (a + 1/2)/H_e, ph = 2 pi (b + 1/2)/W_e.
+ *   - Calls never abort and never throw.  Argument errors are reported
+ *     synchronously; conditions found on the device (pair-capacity overflow)
+ *     are latched and reported by ss_poll.
+ *   - One context serves one stream at a time.
+ */
+#ifndef SURFSPLAT_H
+#define SURFSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* ss_stream;  /* a hipStream_t */
+
+typedef enum ss_status {
+  SS_OK = 0,
+  SS_ERR_INVALID_ARG = 1, /* a null pointer, a size out of range, bad options   */
+  SS_ERR_HIP = 2,         /* a HIP runtime call failed                           */
+  SS_ERR_CAPACITY = 3,    /* pair capacity too small; ss_reserve and call again  */
+  SS_ERR_STATE = 4,       /* call out of order (backward without forward, ...)   */
+  SS_ERR_UNSUPPORTED = 5, /* an option value this build does not implement       */
+  SS_ERR_NOMEM = 6        /* device allocation failed                            */
+} ss_status;
+
+typedef enum ss_shade_mode {
+  SS_SHADE_ALBEDO = 0,   /* colour = albedo                                      */
+  SS_SHADE_SPLITSUM = 1  /* split-sum microfacet IBL, eq:ibl                     */
+} ss_shade_mode;
+
+typedef enum ss_launch_mode {
+  SS_LAUNCH_BATCHED = 0,  /* every view of the batch in one launch per stage    */
+  SS_LAUNCH_PER_VIEW = 1  /* one launch sequence per view (comparison baseline) */
+} ss_launch_mode;
+
+typedef struct ss_options {
+  float r_cut;    /* kernel cutoff radius in standard deviations (App. A.1: 3)   */
+  int32_t k_max;  /* maximum composited layers per pixel, 1..16 (App. A.1: 16)   */
+  float gamma;    /* coverage gain of eq:alpha (Sec. 3.5.1: 2 pi)                */
+  float sigma_f;  /* screen-space prefilter variance, px^2 (eq:mip_cov)          */
+  int32_t shade;  /* ss_shade_mode                                                */
+  int32_t tile_w; /* tile width in pixels: 8, 16 or 32                           */
+  int32_t tile_h; /* tile height in pixels: 8 or 16                              */
+  int32_t lds_batch; /* surfels staged per LDS batch: 32, 64, 128 or 256         */
+  int32_t launch;    /* ss_launch_mode                                            */
+  int32_t persistent; /* 1: raster blocks pull (view, tile) items from a queue   */
+} ss_options;
+
+typedef struct ss_camera {
+  int32_t scene;           /* index of the scene this view renders               */
+  int32_t width, height;   /* pixels                                              */
+  float fx, fy, cx, cy;    /* focal lengths and principal point, pixels          */
+  float R[9];              /* world -> camera rotation, row-major                */
+  float t[3];              /* world -> camera translation                        */
+  float znear;             /* surfels not entirely beyond znear are culled      */
+  float background[3];     /* constant background colour                         */
+} ss_camera;
+
+typedef struct ss_batch {
+  int32_t n_scenes;
+  const int64_t* surfel_offset; /* host [n_scenes + 1], surfel_offset[0] = 0     */
+  const float* position;        /* device [3][N] */
+  const float* normal;          /* device [3][N] */
+  const float* tangent;         /* device [3][N] */
+  const float* scale;           /* device [2][N] */
+  const float* albedo;          /* device [3][N] */
+  const float* roughness;       /* device [N]    */
+  const float* metallic;        /* device [N]    */
+  const float* const* envmap;   /* host [n_scenes] of device [H_e][W_e][3]; unused (may be NULL) in albedo mode */
+  const int32_t* env_hw;        /* host [n_scenes][2] (H_e, W_e), each >= 4 x 8; unused in albedo mode */
+  int32_t n_views;
+  const ss_camera* cameras;     /* host [n_views] */
+} ss_batch;
+
+typedef struct ss_outputs {
+  float* image;       /* device [sum HW][3], written */
+  float* alpha;       /* device [sum HW], written    */
+  uint8_t* n_layers;  /* device [sum HW] or NULL: layers composited per pixel */
+} ss_outputs;
+
+typedef struct ss_grad_in {
+  const float* d_image; /* device [sum HW][3]: dL/dimage                       */
+  const float* d_alpha; /* device [sum HW] or NULL: dL/dalpha                  */
+} ss_grad_in;
+
+typedef struct ss_grads { /* every pointer may be NULL (skip); outputs are overwritten */
+  float* d_position;  /* device [3][N] */
+  float* d_normal;    /* device [3][N] */
+  float* d_tangent;   /* device [3][N] */
+  float* d_scale;     /* device [2][N] */
+  float* d_albedo;    /* device [3][N] */
+  float* d_roughness; /* device [N]    */
+  float* d_metallic;  /* device [N]    */
+  float* const* d_envmap; /* host [n_scenes] of device [H_e][W_e][3], or NULL */
+} ss_grads;
+
+typedef struct ss_diag {
+  int32_t status;        /* latched device status (ss_status)                   */
+  int64_t n_records;     /* (surfel, view) records of the last forward          */
+  int64_t n_pairs;       /* (tile, surfel) pairs of the last forward            */
+  int64_t pair_capacity; /* pairs the workspace holds                           */
+  int64_t workspace_bytes;
+} ss_diag;
+
+typedef struct ss_context ss_context;
+
+/* Fills *opt with the paper's settings: r_cut 3, K_max 16, gamma 2 pi,
+ * sigma_f 0.1 px^2, albedo shading, 16x16 tiles, LDS batch 128, batched,
+ * persistent raster. */
+ss_status ss_default_options(ss_options* opt);
+
+/* Creates a context on the current HIP device.  *out receives ownership. */
+ss_status ss_create(const ss_options* opt, ss_context** out);
+ss_status ss_destroy(ss_context* ctx);
+/* Replaces the options (tile size, batch, launch mode, ...); the next forward
+ * re-bins.  Invalidates the stored forward state. */
+ss_status ss_set_options(ss_context* ctx, const ss_options* opt);
+
+/* BRDF table of eq:ibl: (beta1, beta2) indexed by (n.w_o, roughness) on a
+ * vertex-centred [n_r][n_nv][2] grid (r = i/(n_r-1), n.v = max(j/(n_nv-1), 1e-3)),
+ * GGX (alpha = r^2) with separable Smith masking and Schlick Fresnel, integrated
+ * with `samples` Hammersley samples.  Writes the table to `lut` (device,
+ * [n_r][n_nv][2]) on `stream`.  n_nv, n_r in 2..1024, samples in 1..65536. */
+ss_status ss_brdf_lut(float* lut, int32_t n_nv, int32_t n_r, int32_t samples, ss_stream stream);
+/* Copies a table (device [n_r][n_nv][2]) into the context for split-sum shading. */
+ss_status ss_set_brdf_lut(ss_context* ctx, const float* lut, int32_t n_nv, int32_t n_r, ss_stream stream);
+
+/* Sizes the workspace for `batch` (runs the projection and the tile count once
+ * and synchronises `stream`).  After it, ss_render/ss_render_backward on the
+ * same batch shape allocate nothing and synchronise nothing (they may be
+ * captured in a HIP graph).  *workspace_bytes (may be NULL) receives the size. */
+ss_status ss_reserve(ss_context* ctx, const ss_batch* batch, ss_stream stream, size_t* workspace_bytes);
+
+/* Forward.  Calls ss_reserve itself when the batch shape (surfel counts,
+ * views, resolutions, environment sizes) differs from the reserved one.  When
+ * the surfels moved so that the pairs no longer fit, the device latches
+ * SS_ERR_CAPACITY (see ss_poll): the outputs of that call are invalid; call
+ * ss_reserve and render again. */
+ss_status ss_render(ss_context* ctx, const ss_batch* batch, const ss_outputs* out, ss_stream stream);
+
+/* Backward of the last ss_render on this context with the same batch.
+ * Returns SS_ERR_STATE without a matching forward. */
+ss_status ss_render_backward(ss_context* ctx, const ss_batch* batch, const ss_grad_in* gin,
+                             const ss_grads* grads, ss_stream stream);
+
+/* Synchronises the context's last stream and reports the latched status. */
+ss_status ss_poll(ss_context* ctx, ss_diag* out);
+
+/* Test access to the last forward's binning: record keys (depth-interval start
+ * bits, or 0xffffffff when culled), per-record pixel rectangles (int32
+ * [R][4]: i_lo, j_lo, i_hi, j_hi, or empty), the sorted pair list
+ * (keys = global tile << 32 | z_start bits, values = record index) and the
+ * per-tile [start, end) ranges.  Device destinations; any may be NULL.
+ * *n_pairs and *n_tiles receive the counts (synchronises the stream). */
+ss_status ss_debug_binning(ss_context* ctx, uint32_t* rec_zbits, int32_t* rec_rect,
+                           uint64_t* pair_keys, uint32_t* pair_vals, uint32_t* tile_ranges,
+                           int64_t* n_pairs, int64_t* n_tiles, ss_stream stream);
+
+/* Stage timing.  While enabled, every stage of ss_render / ss_render_backward
+ * is bracketed by HIP events on the caller's stream (not usable under graph
+ * capture).  ss_profile_read synchronises the last stream and writes, for each
+ * stage, the summed milliseconds and the number of timed launches since the
+ * previous read (ms and count: arrays of SS_NUM_STAGES, may be NULL).
+ * Stage order: envmap, preprocess, binning (scan, emission, sort, ranges),
+ * raster_forward, raster_backward, preprocess_backward, envmap_backward. */
+#define SS_NUM_STAGES 7
+ss_status ss_profile_enable(ss_context* ctx, int32_t enable);
+ss_status ss_profile_read(ss_context* ctx, double* ms, int64_t* count);
+
+const char* ss_status_str(ss_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SURFSPLAT_H */

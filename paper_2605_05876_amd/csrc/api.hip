@@ -1,0 +1,791 @@
+// C ABI of libsurfsplat: context, workspace, and the forward / backward
+// pipelines.  See include/surfsplat.h for the contract of every entry point.
+//
+// Pipeline of ss_render on one stream:
+//   envmap levels (per scene, split-sum) -> preprocess + shade (per record)
+//   -> per group: scan of tile counts -> pair emission -> radix sort ->
+//   tile ranges -> raster forward.
+// A "group" is a run of views that share one pair list: one group holding
+// every view (batched launches) or one group per view (per-view launches).
+// ss_render_backward: raster backward (per group) -> preprocess/shade adjoint
+// (per surfel) -> environment adjoint (per scene).
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+#include "surfsplat.h"
+
+using namespace ss;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+hipError_t ensure(DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.n >= bytes) return hipSuccess;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.n = 0;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e == hipSuccess) b.n = bytes;
+  return e;
+}
+void release(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.n = 0;
+}
+template <class T> T* P(DevBuf& b) { return reinterpret_cast<T*>(b.p); }
+
+struct Group {
+  int v0, v1;
+  int tile_base, n_tiles;
+  long long rec_begin, rec_end;
+  long long pair_base, pair_cap;
+  int key_bits;
+};
+
+struct SceneEnv {
+  int He = 0, We = 0;
+  DevBuf dirs, lv, Z /* output-texel table (R, 1/Z) of levels 1..6 */, dlv;
+  int lh[7], lw[7];
+  long long off[7];   // float offsets of levels 1..6 in lv
+  long long doff[7];  // float offsets of levels 0..6 in dlv
+  int loc_off[7];     // LDS layout of the privatised level gradients (-1: global atomics)
+  int loc_total = 0;
+};
+
+int bits_for(long long n) {
+  int b = 1;
+  while ((1LL << b) < n) ++b;
+  return b;
+}
+
+}  // namespace
+
+struct ss_context {
+  ss_options opt;
+  bool reserved = false;
+  std::vector<long long> sig;
+  std::vector<ViewDev> views_h;
+  bool views_uploaded = false;
+  int n_views = 0, n_scenes = 0;
+  long long N = 0, R = 0, n_pix = 0;
+  int n_tiles = 0, max_surf = 0;
+  std::vector<Group> groups;
+  std::vector<SceneEnv> env;
+  DevBuf views_d, recs, counts, offsets, scan_tmp, keys, vals, keys2, vals2, hist, ranges, nl, stats,
+      grad, misc, partial;
+  std::vector<long long> soff;
+  long long scan_tmp_n = 0, pair_total = 0;
+  DevBuf lut;
+  int lut_nv = 0, lut_r = 0;
+  bool fwd_valid = false;
+  std::vector<long long> fwd_sig;
+  hipStream_t last_stream = nullptr;  // may be the null stream
+  bool used = false;                  // a stream call has been made
+  // stage timing
+  bool prof = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_ev;
+  std::vector<hipEvent_t> ev_pool;
+};
+
+namespace {
+
+constexpr int kMiscStatus = 0, kMiscQueue = 1, kMiscPairs = 8;
+
+#define SS_HIP(x)                                                            \
+  do {                                                                       \
+    hipError_t e_ = (x);                                                     \
+    if (e_ != hipSuccess) return e_ == hipErrorOutOfMemory ? SS_ERR_NOMEM : SS_ERR_HIP; \
+  } while (0)
+#define SS_TRY(x)                       \
+  do {                                  \
+    ss_status s_ = (x);                 \
+    if (s_ != SS_OK) return s_;         \
+  } while (0)
+
+ss_status check_options(const ss_options* o) {
+  if (!o) return SS_ERR_INVALID_ARG;
+  if (!(o->r_cut > 0.f) || !(o->gamma > 0.f) || !(o->sigma_f >= 0.f)) return SS_ERR_INVALID_ARG;
+  if (o->k_max < 1 || o->k_max > kMaxLayers) return SS_ERR_INVALID_ARG;
+  if (o->shade != SS_SHADE_ALBEDO && o->shade != SS_SHADE_SPLITSUM) return SS_ERR_INVALID_ARG;
+  const int tk = o->tile_w * 100 + o->tile_h;
+  if (tk != 808 && tk != 1608 && tk != 1616 && tk != 3208 && tk != 3216) return SS_ERR_UNSUPPORTED;
+  if (o->lds_batch != 32 && o->lds_batch != 64 && o->lds_batch != 128 && o->lds_batch != 256)
+    return SS_ERR_UNSUPPORTED;
+  if (o->launch != SS_LAUNCH_BATCHED && o->launch != SS_LAUNCH_PER_VIEW) return SS_ERR_INVALID_ARG;
+  return SS_OK;
+}
+
+ss_status check_batch(const ss_context* c, const ss_batch* b) {
+  if (!b || b->n_scenes < 1 || !b->surfel_offset || b->n_views < 1 || b->n_views > kMaxViews ||
+      !b->cameras)
+    return SS_ERR_INVALID_ARG;
+  if (b->surfel_offset[0] != 0) return SS_ERR_INVALID_ARG;
+  for (int s = 0; s < b->n_scenes; ++s) {
+    long long n = b->surfel_offset[s + 1] - b->surfel_offset[s];
+    if (n < 0 || n > (1LL << 30)) return SS_ERR_INVALID_ARG;
+  }
+  const long long N = b->surfel_offset[b->n_scenes];
+  if (N > 0 && (!b->position || !b->normal || !b->tangent || !b->scale || !b->albedo ||
+                !b->roughness || !b->metallic))
+    return SS_ERR_INVALID_ARG;
+  long long R = 0;
+  for (int v = 0; v < b->n_views; ++v) {
+    const ss_camera& k = b->cameras[v];
+    if (k.scene < 0 || k.scene >= b->n_scenes) return SS_ERR_INVALID_ARG;
+    if (k.width < 1 || k.height < 1 || k.width > 16384 || k.height > 16384) return SS_ERR_INVALID_ARG;
+    if (!(k.fx > 0.f) || !(k.fy > 0.f) || !(k.znear > 0.f)) return SS_ERR_INVALID_ARG;
+    R += b->surfel_offset[k.scene + 1] - b->surfel_offset[k.scene];
+  }
+  if (R >= (1LL << 32) - 1) return SS_ERR_INVALID_ARG;
+  if (c->opt.shade == SS_SHADE_SPLITSUM) {
+    if (!b->envmap || !b->env_hw) return SS_ERR_INVALID_ARG;
+    for (int s = 0; s < b->n_scenes; ++s) {
+      if (!b->envmap[s]) return SS_ERR_INVALID_ARG;
+      if (b->env_hw[2 * s] < 4 || b->env_hw[2 * s + 1] < 8 || b->env_hw[2 * s] > 4096 ||
+          b->env_hw[2 * s + 1] > 8192)
+        return SS_ERR_INVALID_ARG;
+    }
+  }
+  return SS_OK;
+}
+
+std::vector<long long> signature(const ss_context* c, const ss_batch* b) {
+  std::vector<long long> s;
+  s.push_back(b->n_scenes);
+  for (int i = 0; i <= b->n_scenes; ++i) s.push_back(b->surfel_offset[i]);
+  s.push_back(b->n_views);
+  for (int v = 0; v < b->n_views; ++v) {
+    s.push_back(b->cameras[v].scene);
+    s.push_back(b->cameras[v].width);
+    s.push_back(b->cameras[v].height);
+  }
+  s.push_back(c->opt.shade);
+  s.push_back(c->opt.tile_w);
+  s.push_back(c->opt.tile_h);
+  s.push_back(c->opt.launch);
+  if (c->opt.shade == SS_SHADE_SPLITSUM)
+    for (int i = 0; i < 2 * b->n_scenes; ++i) s.push_back(b->env_hw[i]);
+  return s;
+}
+
+Params make_params(const ss_context* c) {
+  Params p;
+  p.r_cut = c->opt.r_cut;
+  p.r2 = c->opt.r_cut * c->opt.r_cut;
+  p.kappa = c->opt.gamma / (2.f * kPi);
+  p.sigma_f = c->opt.sigma_f;
+  p.k_max = c->opt.k_max;
+  p.shade = c->opt.shade;
+  p.tile_w = c->opt.tile_w;
+  p.tile_h = c->opt.tile_h;
+  p.lut = reinterpret_cast<const float*>(c->lut.p);
+  p.lut_nv = c->lut_nv;
+  p.lut_r = c->lut_r;
+  return p;
+}
+
+// Host view descriptors for `b` (layout, cameras and map pointers).
+void build_views(ss_context* c, const ss_batch* b, std::vector<ViewDev>& out) {
+  out.assign(b->n_views, ViewDev());
+  long long pix = 0, rec = 0;
+  int tile = 0;
+  for (int v = 0; v < b->n_views; ++v) {
+    const ss_camera& k = b->cameras[v];
+    ViewDev& d = out[v];
+    std::memset(&d, 0, sizeof(d));
+    d.fx = k.fx; d.fy = k.fy; d.cx = k.cx; d.cy = k.cy;
+    for (int i = 0; i < 9; ++i) d.R[i] = k.R[i];
+    for (int i = 0; i < 3; ++i) { d.t[i] = k.t[i]; d.bg[i] = k.background[i]; }
+    for (int j = 0; j < 3; ++j)
+      d.cam_o[j] = -(k.R[j] * k.t[0] + k.R[3 + j] * k.t[1] + k.R[6 + j] * k.t[2]);
+    d.znear = k.znear;
+    d.W = k.width; d.H = k.height;
+    d.tiles_x = (k.width + c->opt.tile_w - 1) / c->opt.tile_w;
+    d.tiles_y = (k.height + c->opt.tile_h - 1) / c->opt.tile_h;
+    d.tile_base = tile;
+    d.scene = k.scene;
+    d.surf_off = b->surfel_offset[k.scene];
+    d.n_surf = (int)(b->surfel_offset[k.scene + 1] - d.surf_off);
+    d.pix_off = pix;
+    d.rec_off = rec;
+    tile += d.tiles_x * d.tiles_y;
+    pix += (long long)k.width * k.height;
+    rec += d.n_surf;
+    if (c->opt.shade == SS_SHADE_SPLITSUM && k.scene < (int)c->env.size()) {
+      SceneEnv& e = c->env[k.scene];
+      d.lvl[0] = b->envmap[k.scene];
+      d.dlvl[0] = P<float>(e.dlv) + e.doff[0];
+      for (int l = 1; l < 7; ++l) {
+        d.lvl[l] = P<float>(e.lv) + e.off[l];
+        d.dlvl[l] = P<float>(e.dlv) + e.doff[l];
+      }
+      for (int l = 0; l < 7; ++l) { d.lh[l] = e.lh[l]; d.lw[l] = e.lw[l]; }
+    }
+  }
+}
+
+ss_status upload_views(ss_context* c, const ss_batch* b, hipStream_t st) {
+  std::vector<ViewDev> v;
+  build_views(c, b, v);
+  const size_t bytes = v.size() * sizeof(ViewDev);
+  if (c->views_uploaded && v.size() == c->views_h.size() &&
+      std::memcmp(v.data(), c->views_h.data(), bytes) == 0)
+    return SS_OK;
+  SS_HIP(hipStreamSynchronize(st));
+  SS_HIP(hipMemcpy(c->views_d.p, v.data(), bytes, hipMemcpyHostToDevice));
+  c->views_h = v;
+  c->views_uploaded = true;
+  return SS_OK;
+}
+
+ss_status prepare_env(ss_context* c, const ss_batch* b, hipStream_t st) {
+  if (c->opt.shade != SS_SHADE_SPLITSUM) {
+    c->env.clear();
+    return SS_OK;
+  }
+  c->env.resize(b->n_scenes);
+  for (int s = 0; s < b->n_scenes; ++s) {
+    SceneEnv& e = c->env[s];
+    const int He = b->env_hw[2 * s], We = b->env_hw[2 * s + 1];
+    e.lh[0] = He; e.lw[0] = We;
+    for (int l = 1; l <= 5; ++l) { e.lh[l] = He >> l > 4 ? He >> l : 4; e.lw[l] = We >> l > 8 ? We >> l : 8; }
+    e.lh[6] = 32; e.lw[6] = 64;
+    long long o = 0;
+    e.off[0] = 0;
+    for (int l = 1; l < 7; ++l) { e.off[l] = o; o += 3LL * e.lh[l] * e.lw[l]; }
+    const long long lv_n = o;
+    long long d = 0;
+    for (int l = 0; l < 7; ++l) { e.doff[l] = d; d += 3LL * e.lh[l] * e.lw[l]; }
+    // privatise the irradiance level and the smallest specular levels in LDS
+    for (int l = 0; l < 7; ++l) e.loc_off[l] = -1;
+    e.loc_total = 0;
+    for (int l : {6, 5, 4, 3, 2, 1}) {
+      const int n = 3 * e.lh[l] * e.lw[l];
+      if (e.loc_total + n > kLocalMapFloats) break;
+      e.loc_off[l] = e.loc_total;
+      e.loc_total += n;
+    }
+    SS_HIP(ensure(c->partial, (size_t)kBackwardBlocks * kLocalMapFloats * sizeof(float)));
+    SS_HIP(ensure(e.lv, lv_n * sizeof(float)));
+    SS_HIP(ensure(e.dlv, d * sizeof(float)));
+    SS_HIP(ensure(e.Z, (size_t)(lv_n / 3 + 1) * 4 * sizeof(float)));
+    if (e.He != He || e.We != We || !e.dirs.p) {
+      SS_HIP(ensure(e.dirs, (size_t)He * We * 4 * sizeof(float)));
+      SS_HIP(launch_envmap_dirs(P<float>(e.dirs), He, We, st));
+      SS_HIP(launch_envmap_out_dirs(He, We, P<float>(e.dirs), e.lh, e.lw, P<float>(e.Z), st));
+      e.He = He;
+      e.We = We;
+    }
+  }
+  return SS_OK;
+}
+
+ss_status run_envmap_prefilter(ss_context* c, const ss_batch* b, hipStream_t st) {
+  if (c->opt.shade != SS_SHADE_SPLITSUM) return SS_OK;
+  for (int s = 0; s < b->n_scenes; ++s) {
+    SceneEnv& e = c->env[s];
+    float* out[7];
+    out[0] = nullptr;
+    for (int l = 1; l < 7; ++l) out[l] = P<float>(e.lv) + e.off[l];
+    SS_HIP(launch_envmap_prefilter(b->envmap[s], e.He, e.We, P<float>(e.dirs), P<float>(e.Z), out,
+                                   e.lh, e.lw, st));
+  }
+  return SS_OK;
+}
+
+void param_ptrs(const ss_batch* b, const float* p[7]) {
+  p[0] = b->position; p[1] = b->normal; p[2] = b->tangent; p[3] = b->scale;
+  p[4] = b->albedo; p[5] = b->roughness; p[6] = b->metallic;
+}
+
+ss_status run_preprocess(ss_context* c, const ss_batch* b, int v0, int v1, hipStream_t st) {
+  const float* pp[7];
+  param_ptrs(b, pp);
+  int ms = 0;
+  for (int v = v0; v < v1; ++v) ms = c->views_h[v].n_surf > ms ? c->views_h[v].n_surf : ms;
+  SS_HIP(launch_preprocess(pp, c->N, P<ViewDev>(c->views_d), v0, v1, ms, make_params(c),
+                           P<float>(c->recs), P<uint32_t>(c->counts), st));
+  return SS_OK;
+}
+
+ss_status run_count_scan(ss_context* c, const Group& g, hipStream_t st) {
+  uint32_t* misc = P<uint32_t>(c->misc);
+  const long long n = g.rec_end - g.rec_begin;
+  const int gi = (int)(&g - c->groups.data());
+  if (n <= 0) {
+    SS_HIP(launch_fill_u32(misc + kMiscPairs + gi, 0u, 1, st));
+    return SS_OK;
+  }
+  SS_HIP(launch_scan_u32(P<uint32_t>(c->counts) + g.rec_begin, P<uint32_t>(c->offsets) + g.rec_begin, n,
+                         misc + kMiscPairs + gi, P<uint32_t>(c->scan_tmp), c->scan_tmp_n, st));
+  return SS_OK;
+}
+
+ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
+  c->reserved = false;
+  c->fwd_valid = false;
+  c->views_uploaded = false;
+  c->n_views = b->n_views;
+  c->n_scenes = b->n_scenes;
+  c->N = b->surfel_offset[b->n_scenes];
+  c->soff.assign(b->surfel_offset, b->surfel_offset + b->n_scenes + 1);
+  SS_TRY(prepare_env(c, b, st));
+  std::vector<ViewDev> vh;
+  build_views(c, b, vh);
+  c->R = 0;
+  c->n_pix = 0;
+  c->n_tiles = 0;
+  c->max_surf = 0;
+  for (const ViewDev& v : vh) {
+    c->R += v.n_surf;
+    c->n_pix += (long long)v.W * v.H;
+    c->n_tiles += v.tiles_x * v.tiles_y;
+    c->max_surf = v.n_surf > c->max_surf ? v.n_surf : c->max_surf;
+  }
+  c->groups.clear();
+  const int ng = c->opt.launch == SS_LAUNCH_PER_VIEW ? b->n_views : 1;
+  for (int gi = 0; gi < ng; ++gi) {
+    Group g;
+    g.v0 = ng == 1 ? 0 : gi;
+    g.v1 = ng == 1 ? b->n_views : gi + 1;
+    g.tile_base = vh[g.v0].tile_base;
+    g.n_tiles = 0;
+    for (int v = g.v0; v < g.v1; ++v) g.n_tiles += vh[v].tiles_x * vh[v].tiles_y;
+    g.rec_begin = vh[g.v0].rec_off;
+    g.rec_end = vh[g.v1 - 1].rec_off + vh[g.v1 - 1].n_surf;
+    int kb = 32 + bits_for((long long)g.tile_base + g.n_tiles);
+    int passes = (kb + 7) / 8;
+    if (passes & 1) ++passes;  // an even pass count leaves the result in the primary buffers
+    g.key_bits = 8 * passes;
+    g.pair_base = 0;
+    g.pair_cap = 0;
+    c->groups.push_back(g);
+  }
+  const long long R = c->R > 0 ? c->R : 1;
+  SS_HIP(ensure(c->views_d, sizeof(ViewDev) * kMaxViews));
+  SS_HIP(ensure(c->recs, (size_t)R * kRecFloats * sizeof(float)));
+  SS_HIP(ensure(c->counts, (size_t)R * sizeof(uint32_t)));
+  SS_HIP(ensure(c->offsets, (size_t)R * sizeof(uint32_t)));
+  SS_HIP(ensure(c->misc, (kMiscPairs + kMaxViews) * sizeof(uint32_t)));
+  c->scan_tmp_n = scan_tmp_size(R) + 16;
+  SS_HIP(ensure(c->scan_tmp, (size_t)c->scan_tmp_n * sizeof(uint32_t)));
+  SS_HIP(ensure(c->ranges, (size_t)2 * (c->n_tiles > 0 ? c->n_tiles : 1) * sizeof(uint32_t)));
+  SS_HIP(ensure(c->nl, (size_t)(c->n_pix > 0 ? c->n_pix : 1)));
+  SS_HIP(ensure(c->stats, (size_t)(c->n_pix > 0 ? c->n_pix : 1) * kMaxLayers * sizeof(float4)));
+  SS_HIP(ensure(c->grad, (size_t)R * kNGrad * sizeof(float)));
+  SS_TRY(upload_views(c, b, st));
+  // count the pairs once
+  SS_TRY(run_envmap_prefilter(c, b, st));
+  SS_TRY(run_preprocess(c, b, 0, b->n_views, st));
+  for (Group& g : c->groups) SS_TRY(run_count_scan(c, g, st));
+  std::vector<uint32_t> np(c->groups.size());
+  SS_HIP(hipStreamSynchronize(st));
+  SS_HIP(hipMemcpy(np.data(), P<uint32_t>(c->misc) + kMiscPairs, np.size() * sizeof(uint32_t),
+                   hipMemcpyDeviceToHost));
+  long long base = 0, maxcap = 0;
+  for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+    Group& g = c->groups[gi];
+    const long long p = np[gi];
+    g.pair_cap = p + p / 4 + 4096;
+    g.pair_base = base;
+    base += g.pair_cap;
+    maxcap = g.pair_cap > maxcap ? g.pair_cap : maxcap;
+  }
+  c->pair_total = base;
+  SS_HIP(ensure(c->keys, (size_t)base * sizeof(uint64_t)));
+  SS_HIP(ensure(c->keys2, (size_t)base * sizeof(uint64_t)));
+  SS_HIP(ensure(c->vals, (size_t)base * sizeof(uint32_t)));
+  SS_HIP(ensure(c->vals2, (size_t)base * sizeof(uint32_t)));
+  const long long nblocks = (maxcap + 2047) / 2048;
+  SS_HIP(ensure(c->hist, (size_t)256 * nblocks * sizeof(uint32_t)));
+  const long long need_scan = scan_tmp_size(256 * nblocks > R ? 256 * nblocks : R) + 16;
+  if (need_scan > c->scan_tmp_n) {
+    c->scan_tmp_n = need_scan;
+    SS_HIP(ensure(c->scan_tmp, (size_t)need_scan * sizeof(uint32_t)));
+  }
+  c->sig = signature(c, b);
+  c->reserved = true;
+  return SS_OK;
+}
+
+// Stage timing: events recorded around a stage when profiling is on; resolved
+// (and recycled) by ss_profile_read.
+hipEvent_t prof_event(ss_context* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+hipEvent_t prof_begin(ss_context* c, hipStream_t st) {
+  if (!c->prof) return nullptr;
+  hipEvent_t a = prof_event(c);
+  if (a) {
+    const hipError_t e = hipEventRecord(a, st);
+    if (e != hipSuccess && std::getenv("SURFSPLAT_DEBUG"))
+      std::fprintf(stderr, "prof_begin: hipEventRecord: %s\n", hipGetErrorString(e));
+  }
+  return a;
+}
+void prof_end(ss_context* c, hipEvent_t a, int stage, hipStream_t st) {
+  if (!c->prof || !a) return;
+  hipEvent_t b = prof_event(c);
+  if (!b) return;
+  (void)hipEventRecord(b, st);
+  c->prof_ev.push_back({stage, {a, b}});
+}
+enum { ST_ENV = 0, ST_PRE, ST_BIN, ST_RFWD, ST_RBWD, ST_PREBWD, ST_ENVBWD };
+
+size_t workspace_bytes(const ss_context* c) {
+  size_t s = c->views_d.n + c->recs.n + c->counts.n + c->offsets.n + c->scan_tmp.n + c->keys.n +
+             c->vals.n + c->keys2.n + c->vals2.n + c->hist.n + c->ranges.n + c->nl.n + c->stats.n +
+             c->grad.n + c->misc.n + c->lut.n + c->partial.n;
+  for (const SceneEnv& e : c->env) s += e.dirs.n + e.lv.n + e.Z.n + e.dlv.n;
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+ss_status ss_default_options(ss_options* o) {
+  if (!o) return SS_ERR_INVALID_ARG;
+  o->r_cut = 3.f;
+  o->k_max = 16;
+  o->gamma = 2.f * kPi;
+  o->sigma_f = 0.1f;
+  o->shade = SS_SHADE_ALBEDO;
+  o->tile_w = 16;
+  o->tile_h = 16;
+  o->lds_batch = 128;
+  o->launch = SS_LAUNCH_BATCHED;
+  o->persistent = 1;
+  return SS_OK;
+}
+
+ss_status ss_create(const ss_options* opt, ss_context** out) {
+  if (!out) return SS_ERR_INVALID_ARG;
+  *out = nullptr;
+  SS_TRY(check_options(opt));
+  ss_context* c = new (std::nothrow) ss_context();
+  if (!c) return SS_ERR_NOMEM;
+  c->opt = *opt;
+  *out = c;
+  return SS_OK;
+}
+
+ss_status ss_destroy(ss_context* c) {
+  if (!c) return SS_ERR_INVALID_ARG;
+  if (c->used) (void)hipStreamSynchronize(c->last_stream);
+  DevBuf* bufs[] = {&c->views_d, &c->recs, &c->counts, &c->offsets, &c->scan_tmp, &c->keys,
+                    &c->vals, &c->keys2, &c->vals2, &c->hist, &c->ranges, &c->nl, &c->stats,
+                    &c->grad, &c->misc, &c->lut, &c->partial};
+  for (DevBuf* b : bufs) release(*b);
+  for (SceneEnv& e : c->env) { release(e.dirs); release(e.lv); release(e.Z); release(e.dlv); }
+  for (auto& pe : c->prof_ev) { c->ev_pool.push_back(pe.second.first); c->ev_pool.push_back(pe.second.second); }
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+  return SS_OK;
+}
+
+ss_status ss_set_options(ss_context* c, const ss_options* opt) {
+  if (!c) return SS_ERR_INVALID_ARG;
+  SS_TRY(check_options(opt));
+  if (c->used) SS_HIP(hipStreamSynchronize(c->last_stream));
+  c->opt = *opt;
+  c->reserved = false;
+  c->fwd_valid = false;
+  c->views_uploaded = false;
+  return SS_OK;
+}
+
+ss_status ss_brdf_lut(float* lut, int32_t n_nv, int32_t n_r, int32_t samples, ss_stream stream) {
+  if (!lut || n_nv < 2 || n_r < 2 || n_nv > 1024 || n_r > 1024 || samples < 1 || samples > 65536)
+    return SS_ERR_INVALID_ARG;
+  SS_HIP(launch_brdf_lut(lut, n_nv, n_r, samples, (hipStream_t)stream));
+  return SS_OK;
+}
+
+ss_status ss_set_brdf_lut(ss_context* c, const float* lut, int32_t n_nv, int32_t n_r, ss_stream stream) {
+  if (!c || !lut || n_nv < 2 || n_r < 2 || n_nv > 1024 || n_r > 1024) return SS_ERR_INVALID_ARG;
+  const size_t bytes = (size_t)n_nv * n_r * 2 * sizeof(float);
+  if (c->lut.n < bytes && c->used) SS_HIP(hipStreamSynchronize(c->last_stream));
+  SS_HIP(ensure(c->lut, bytes));
+  SS_HIP(hipMemcpyAsync(c->lut.p, lut, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  c->lut_nv = n_nv;
+  c->lut_r = n_r;
+  return SS_OK;
+}
+
+ss_status ss_reserve(ss_context* c, const ss_batch* b, ss_stream stream, size_t* ws) {
+  if (!c) return SS_ERR_INVALID_ARG;
+  SS_TRY(check_batch(c, b));
+  if (c->opt.shade == SS_SHADE_SPLITSUM && !c->lut.p) return SS_ERR_STATE;
+  hipStream_t st = (hipStream_t)stream;
+  c->last_stream = st;
+  c->used = true;
+  SS_TRY(reserve_impl(c, b, st));
+  if (ws) *ws = workspace_bytes(c);
+  return SS_OK;
+}
+
+ss_status ss_render(ss_context* c, const ss_batch* b, const ss_outputs* out, ss_stream stream) {
+  if (!c || !out || !out->image || !out->alpha) return SS_ERR_INVALID_ARG;
+  SS_TRY(check_batch(c, b));
+  if (c->opt.shade == SS_SHADE_SPLITSUM && !c->lut.p) return SS_ERR_STATE;
+  hipStream_t st = (hipStream_t)stream;
+  c->last_stream = st;
+  c->used = true;
+  if (!c->reserved || signature(c, b) != c->sig) SS_TRY(reserve_impl(c, b, st));
+  c->fwd_valid = false;
+  SS_TRY(upload_views(c, b, st));
+  uint32_t* misc = P<uint32_t>(c->misc);
+  SS_HIP(launch_fill_u32(misc, 0u, kMiscPairs, st));
+  hipEvent_t t0 = prof_begin(c, st);
+  SS_TRY(run_envmap_prefilter(c, b, st));
+  prof_end(c, t0, ST_ENV, st);
+  const Params prm = make_params(c);
+  int* status = reinterpret_cast<int*>(misc + kMiscStatus);
+  for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+    const Group& g = c->groups[gi];
+    t0 = prof_begin(c, st);
+    SS_TRY(run_preprocess(c, b, g.v0, g.v1, st));
+    prof_end(c, t0, ST_PRE, st);
+    t0 = prof_begin(c, st);
+    SS_TRY(run_count_scan(c, g, st));
+    int ms = 0;
+    for (int v = g.v0; v < g.v1; ++v) ms = c->views_h[v].n_surf > ms ? c->views_h[v].n_surf : ms;
+    const uint32_t* np = misc + kMiscPairs + gi;
+    uint64_t* keys = P<uint64_t>(c->keys) + g.pair_base;
+    uint32_t* vals = P<uint32_t>(c->vals) + g.pair_base;
+    SS_HIP(launch_emit_pairs(P<float>(c->recs), P<uint32_t>(c->offsets),
+                             P<ViewDev>(c->views_d), g.v0, g.v1, ms, c->opt.tile_w, c->opt.tile_h,
+                             keys, vals, np, g.pair_cap, status, st));
+    (void)ms;
+    bool in_tmp = false;
+    SS_HIP(launch_radix_sort(keys, vals, P<uint64_t>(c->keys2) + g.pair_base,
+                             P<uint32_t>(c->vals2) + g.pair_base, np, g.pair_cap, g.key_bits,
+                             P<uint32_t>(c->hist), P<uint32_t>(c->scan_tmp), c->scan_tmp_n, st,
+                             &in_tmp));
+    if (in_tmp) return SS_ERR_HIP;  // even pass counts by construction
+    SS_HIP(launch_tile_ranges(keys, np, g.pair_cap, P<uint32_t>(c->ranges), g.tile_base, g.n_tiles, st));
+    prof_end(c, t0, ST_BIN, st);
+    SS_HIP(launch_fill_u32(misc + kMiscQueue, 0u, 1, st));
+    t0 = prof_begin(c, st);
+    SS_HIP(launch_raster_forward(P<ViewDev>(c->views_d), c->n_views, g.tile_base,
+                                 g.tile_base + g.n_tiles, P<uint32_t>(c->ranges), vals,
+                                 P<float>(c->recs), prm, c->opt.lds_batch, out->image, out->alpha,
+                                 out->n_layers, P<uint8_t>(c->nl), P<float4>(c->stats),
+                                 reinterpret_cast<int*>(misc + kMiscQueue), nullptr,
+                                 c->opt.persistent, st));
+    prof_end(c, t0, ST_RFWD, st);
+  }
+  c->fwd_valid = true;
+  c->fwd_sig = c->sig;
+  return SS_OK;
+}
+
+ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in* gin,
+                             const ss_grads* gr, ss_stream stream) {
+  if (!c || !gin || !gin->d_image || !gr) return SS_ERR_INVALID_ARG;
+  SS_TRY(check_batch(c, b));
+  if (!c->fwd_valid || signature(c, b) != c->fwd_sig) return SS_ERR_STATE;
+  hipStream_t st = (hipStream_t)stream;
+  c->last_stream = st;
+  c->used = true;
+  SS_TRY(upload_views(c, b, st));
+  const Params prm = make_params(c);
+  uint32_t* misc = P<uint32_t>(c->misc);
+  SS_HIP(launch_fill_f32(P<float>(c->grad), 0.f, (long long)c->R * kNGrad, st));
+  if (c->opt.shade == SS_SHADE_SPLITSUM)
+    for (SceneEnv& e : c->env) SS_HIP(launch_fill_f32(P<float>(e.dlv), 0.f, (long long)(e.dlv.n / 4), st));
+  for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+    const Group& g = c->groups[gi];
+    SS_HIP(launch_fill_u32(misc + kMiscQueue, 0u, 1, st));
+    hipEvent_t t0 = prof_begin(c, st);
+    SS_HIP(launch_raster_backward(P<ViewDev>(c->views_d), c->n_views, g.tile_base,
+                                  g.tile_base + g.n_tiles, P<uint32_t>(c->ranges),
+                                  P<uint32_t>(c->vals) + g.pair_base, P<float>(c->recs), prm,
+                                  c->opt.lds_batch, gin->d_image, gin->d_alpha, P<uint8_t>(c->nl),
+                                  P<float4>(c->stats), P<float>(c->grad), c->R,
+                                  reinterpret_cast<int*>(misc + kMiscQueue), nullptr,
+                                  c->opt.persistent, st));
+    prof_end(c, t0, ST_RBWD, st);
+  }
+  const float* pp[7];
+  param_ptrs(b, pp);
+  float* G[7] = {gr->d_position, gr->d_normal, gr->d_tangent, gr->d_scale,
+                 gr->d_albedo, gr->d_roughness, gr->d_metallic};
+  hipEvent_t t1 = prof_begin(c, st);
+  if (c->opt.shade == SS_SHADE_SPLITSUM) {
+    for (int s = 0; s < c->n_scenes; ++s) {
+      SceneEnv& e = c->env[s];
+      float* lg[7];
+      for (int l = 0; l < 7; ++l) lg[l] = P<float>(e.dlv) + e.doff[l];
+      SS_HIP(launch_preprocess_backward(pp, c->N, P<ViewDev>(c->views_d), c->n_views, c->soff[s],
+                                        c->soff[s + 1], e.loc_off, e.loc_total, P<float>(c->partial),
+                                        lg, prm, P<float>(c->grad), c->R, G, st));
+    }
+  } else {
+    const int no[7] = {-1, -1, -1, -1, -1, -1, -1};
+    float* lg[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    SS_HIP(launch_preprocess_backward(pp, c->N, P<ViewDev>(c->views_d), c->n_views, 0, c->N, no, 0,
+                                      nullptr, lg, prm, P<float>(c->grad), c->R, G, st));
+  }
+  prof_end(c, t1, ST_PREBWD, st);
+  t1 = prof_begin(c, st);
+  if (c->opt.shade == SS_SHADE_SPLITSUM && gr->d_envmap) {
+    for (int s = 0; s < c->n_scenes; ++s) {
+      if (!gr->d_envmap[s]) continue;
+      SceneEnv& e = c->env[s];
+      const float* dl[7];
+      for (int l = 0; l < 7; ++l) dl[l] = P<float>(e.dlv) + e.doff[l];
+      SS_HIP(launch_envmap_adjoint(dl, e.lh, e.lw, P<float>(e.Z), e.He, e.We, P<float>(e.dirs),
+                                   gr->d_envmap[s], st));
+    }
+  }
+  prof_end(c, t1, ST_ENVBWD, st);
+  return SS_OK;
+}
+
+ss_status ss_poll(ss_context* c, ss_diag* out) {
+  if (!c || !out) return SS_ERR_INVALID_ARG;
+  std::memset(out, 0, sizeof(*out));
+  if (c->used) SS_HIP(hipStreamSynchronize(c->last_stream));
+  if (c->misc.p) {
+    std::vector<uint32_t> m(kMiscPairs + c->groups.size());
+    SS_HIP(hipMemcpy(m.data(), c->misc.p, m.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    out->status = (int32_t)m[kMiscStatus];
+    long long np = 0;
+    for (size_t g = 0; g < c->groups.size(); ++g) np += m[kMiscPairs + g];
+    out->n_pairs = np;
+  }
+  out->n_records = c->R;
+  out->pair_capacity = c->pair_total;
+  out->workspace_bytes = (int64_t)workspace_bytes(c);
+  return out->status == 0 ? SS_OK : (ss_status)out->status;
+}
+
+ss_status ss_profile_enable(ss_context* c, int32_t enable) {
+  if (!c) return SS_ERR_INVALID_ARG;
+  c->prof = enable != 0;
+  return SS_OK;
+}
+
+ss_status ss_profile_read(ss_context* c, double* ms, int64_t* count) {
+  if (!c) return SS_ERR_INVALID_ARG;
+  if (ms) for (int i = 0; i < SS_NUM_STAGES; ++i) ms[i] = 0.0;
+  if (count) for (int i = 0; i < SS_NUM_STAGES; ++i) count[i] = 0;
+  if (c->used) SS_HIP(hipStreamSynchronize(c->last_stream));
+  int reported = 0;
+  for (auto& pe : c->prof_ev) {
+    float t = 0.f;
+    (void)hipEventSynchronize(pe.second.second);
+    const hipError_t e = hipEventElapsedTime(&t, pe.second.first, pe.second.second);
+    if (e == hipSuccess) {
+      if (ms) ms[pe.first] += t;
+      if (count) count[pe.first] += 1;
+    } else if (std::getenv("SURFSPLAT_DEBUG") && reported++ < 4) {
+      std::fprintf(stderr, "ss_profile_read: stage %d: %s\n", pe.first, hipGetErrorString(e));
+    }
+    c->ev_pool.push_back(pe.second.first);
+    c->ev_pool.push_back(pe.second.second);
+  }
+  c->prof_ev.clear();
+  return SS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- test access
+namespace {
+__global__ void extract_records_kernel(const float* recs, long long R, uint32_t* zb, int32_t* rect) {
+  long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const float4 q = reinterpret_cast<const float4*>(recs + r * kRecFloats)[3];
+  const int rx = __float_as_int(q.x), ry = __float_as_int(q.y);
+  if (zb) zb[r] = (uint32_t)__float_as_int(q.z);
+  if (rect) {
+    rect[4 * r + 0] = rx & 0xffff;
+    rect[4 * r + 1] = ry & 0xffff;
+    rect[4 * r + 2] = rx >> 16;
+    rect[4 * r + 3] = ry >> 16;
+  }
+}
+__global__ void copy_pairs_kernel(const uint64_t* k, const uint32_t* v, long long n, uint64_t tile_base,
+                                  uint64_t* ko, uint32_t* vo) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (ko) ko[i] = k[i];
+  if (vo) vo[i] = v[i];
+  (void)tile_base;
+}
+__global__ void copy_ranges_kernel(const uint32_t* r, int n, uint32_t add, uint32_t* o) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t s = r[2 * i], e = r[2 * i + 1];
+  o[2 * i] = (e > s) ? s + add : 0u;
+  o[2 * i + 1] = (e > s) ? e + add : 0u;
+}
+}  // namespace
+
+extern "C" ss_status ss_debug_binning(ss_context* c, uint32_t* rec_zbits, int32_t* rec_rect,
+                                      uint64_t* pair_keys, uint32_t* pair_vals, uint32_t* tile_ranges,
+                                      int64_t* n_pairs, int64_t* n_tiles, ss_stream stream) {
+  if (!c || !c->fwd_valid) return SS_ERR_STATE;
+  hipStream_t st = (hipStream_t)stream;
+  SS_HIP(hipStreamSynchronize(st));
+  std::vector<uint32_t> np(c->groups.size());
+  SS_HIP(hipMemcpy(np.data(), P<uint32_t>(c->misc) + kMiscPairs, np.size() * sizeof(uint32_t),
+                   hipMemcpyDeviceToHost));
+  if (rec_zbits || rec_rect) {
+    hipLaunchKernelGGL(extract_records_kernel, dim3((unsigned)((c->R + 255) / 256)), dim3(256), 0, st,
+                       P<float>(c->recs), c->R, rec_zbits, rec_rect);
+  }
+  long long done = 0;
+  for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+    const Group& g = c->groups[gi];
+    const long long n = np[gi];
+    if ((pair_keys || pair_vals) && n > 0)
+      hipLaunchKernelGGL(copy_pairs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                         P<uint64_t>(c->keys) + g.pair_base, P<uint32_t>(c->vals) + g.pair_base, n,
+                         (uint64_t)g.tile_base, pair_keys ? pair_keys + done : nullptr,
+                         pair_vals ? pair_vals + done : nullptr);
+    if (tile_ranges && g.n_tiles > 0)
+      hipLaunchKernelGGL(copy_ranges_kernel, dim3((g.n_tiles + 255) / 256), dim3(256), 0, st,
+                         P<uint32_t>(c->ranges) + 2LL * g.tile_base, g.n_tiles, (uint32_t)done,
+                         tile_ranges + 2LL * g.tile_base);
+    done += n;
+  }
+  SS_HIP(hipGetLastError());
+  SS_HIP(hipStreamSynchronize(st));
+  if (n_pairs) *n_pairs = done;
+  if (n_tiles) *n_tiles = c->n_tiles;
+  return SS_OK;
+}
+
+extern "C" const char* ss_status_str(ss_status s) {
+  switch (s) {
+    case SS_OK: return "ok";
+    case SS_ERR_INVALID_ARG: return "invalid argument";
+    case SS_ERR_HIP: return "HIP runtime error";
+    case SS_ERR_CAPACITY: return "pair capacity exceeded (call ss_reserve and render again)";
+    case SS_ERR_STATE: return "call out of order";
+    case SS_ERR_UNSUPPORTED: return "unsupported option";
+    case SS_ERR_NOMEM: return "device allocation failed";
+  }
+  return "unknown status";
+}

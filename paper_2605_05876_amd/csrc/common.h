@@ -1,0 +1,244 @@
+// Internal declarations shared by the HIP translation units of libsurfsplat.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ss {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr int kMaxViews = 64;
+constexpr int kMaxLayers = 16;
+
+// ---------------------------------------------------------------- records
+// Raster record of one (surfel, view), 16 floats = one 64-byte line.  The
+// per-pixel weight uses the projective form of the centre-precomputed MIP
+// kernel (eq:mip_weight): with d = (x - x0, y - y0) the pixel offset from the
+// projected centre, s = 1 + a3 dx + b3 dy and Q = (M M^T + sigma_f I)^{-1}
+// (M = d(x,y)/d(u,v) at the centre), rho^2_mip = d^T Q d / s^2.
+enum RecField {
+  R_X0 = 0 /* x0 - i_lo */, R_Y0 /* y0 - j_lo */, R_QXX, R_QXY2 /* 2 Q_xy */, R_QYY, R_A3, R_B3, R_NF,
+  R_ZE, R_CR, R_CG, R_CB, R_RX /* i_lo | i_hi << 16 */, R_RY /* j_lo | j_hi << 16 */,
+  R_ZS, R_ID /* record index, as bits */
+};
+constexpr int kRecFloats = 16;
+// Gradient slots per record, written by the raster backward (SoA [kNGrad][R]).
+enum GradField { G_X0 = 0, G_Y0, G_QXX, G_QXY2, G_QYY, G_A3, G_B3, G_NF, G_CR, G_CG, G_CB };
+constexpr int kNGrad = 11;
+
+// ---------------------------------------------------------------- views
+struct ViewDev {
+  float fx, fy, cx, cy;
+  float R[9], t[3];
+  float znear;
+  float bg[3];
+  float cam_o[3];          // camera centre in world space, -R^T t
+  int W, H, tiles_x, tiles_y;
+  int tile_base;           // global index of the view's first tile
+  int scene;
+  int n_surf;              // surfels of the scene
+  int pad0;
+  long long pix_off;       // first pixel of the view in the image arrays
+  long long rec_off;       // first record of the view
+  long long surf_off;      // first surfel of the scene
+  // environment levels: 0 = E, 1..5 specular, 6 = irradiance (split-sum only)
+  const float* lvl[7];
+  float* dlvl[7];          // their gradients (backward)
+  int lh[7], lw[7];
+};
+
+struct Params {
+  float r_cut, r2, kappa, sigma_f;
+  int k_max, shade, tile_w, tile_h;
+  const float* lut;
+  int lut_nv, lut_r;
+};
+
+// ---------------------------------------------------------------- FP32 binning
+// The binning decision of one (surfel, view): cull, depth-interval start and
+// the pixel rectangle that contains the acceptance ellipse {u^T Sigma_mip^{-1}
+// u < r_cut^2} (bounding planes tangent to it, App. A.1), widened by 0.01 px.
+// Evaluated with a fixed order: no contraction, IEEE division and square root,
+// sums left to right.  The same sequence is followed by the CPU reference, so
+// keys and rectangles agree bit for bit.
+struct Geo {
+  float nh[3], uh[3], vh[3];
+  float nn, gn, d;
+  float tu[3], tv[3];
+  float cp[3], up[3], vp[3];
+  float z, ez, zs, ze, mx, my, x0, y0;
+  float M11, M12, M21, M22, g1, g2, dm, detA;
+  int keep;
+  int il, ih, jl, jh;  // inclusive pixel rectangle
+};
+
+__device__ inline void bin_geometry(const float p[3], const float n[3], const float tg[3],
+                                    float su, float sv, const ViewDev& v, float rcut,
+                                    float sigma, Geo& o) {
+#pragma clang fp contract(off)
+  o.keep = 0;
+  o.il = 1; o.ih = 0; o.jl = 1; o.jh = 0;
+  const float* R = v.R;
+  float nn = sqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  float nhx = n[0] / nn, nhy = n[1] / nn, nhz = n[2] / nn;
+  float d = tg[0] * nhx + tg[1] * nhy + tg[2] * nhz;
+  float gx = tg[0] - d * nhx, gy = tg[1] - d * nhy, gz = tg[2] - d * nhz;
+  float gn = sqrtf(gx * gx + gy * gy + gz * gz);
+  float ux = gx / gn, uy = gy / gn, uz = gz / gn;
+  float vx = nhy * uz - nhz * uy, vy = nhz * ux - nhx * uz, vz = nhx * uy - nhy * ux;
+  float tux = su * ux, tuy = su * uy, tuz = su * uz;
+  float tvx = sv * vx, tvy = sv * vy, tvz = sv * vz;
+  float cpx = R[0] * p[0] + R[1] * p[1] + R[2] * p[2] + v.t[0];
+  float cpy = R[3] * p[0] + R[4] * p[1] + R[5] * p[2] + v.t[1];
+  float cpz = R[6] * p[0] + R[7] * p[1] + R[8] * p[2] + v.t[2];
+  float upx = R[0] * tux + R[1] * tuy + R[2] * tuz;
+  float upy = R[3] * tux + R[4] * tuy + R[5] * tuz;
+  float upz = R[6] * tux + R[7] * tuy + R[8] * tuz;
+  float vpx = R[0] * tvx + R[1] * tvy + R[2] * tvz;
+  float vpy = R[3] * tvx + R[4] * tvy + R[5] * tvz;
+  float vpz = R[6] * tvx + R[7] * tvy + R[8] * tvz;
+  o.nn = nn; o.gn = gn; o.d = d;
+  o.nh[0] = nhx; o.nh[1] = nhy; o.nh[2] = nhz;
+  o.uh[0] = ux; o.uh[1] = uy; o.uh[2] = uz;
+  o.vh[0] = vx; o.vh[1] = vy; o.vh[2] = vz;
+  o.tu[0] = tux; o.tu[1] = tuy; o.tu[2] = tuz;
+  o.tv[0] = tvx; o.tv[1] = tvy; o.tv[2] = tvz;
+  o.cp[0] = cpx; o.cp[1] = cpy; o.cp[2] = cpz;
+  o.up[0] = upx; o.up[1] = upy; o.up[2] = upz;
+  o.vp[0] = vpx; o.vp[1] = vpy; o.vp[2] = vpz;
+  float z = cpz;
+  float ez = rcut * sqrtf(upz * upz + vpz * vpz);
+  o.z = z; o.ez = ez;
+  o.zs = z - ez;
+  o.ze = z + ez;
+  if (!(z > v.znear)) return;
+  float mx = cpx / z, my = cpy / z;
+  float x0 = v.fx * mx + v.cx, y0 = v.fy * my + v.cy;
+  float M11 = (v.fx * (upx - mx * upz)) / z, M12 = (v.fx * (vpx - mx * vpz)) / z;
+  float M21 = (v.fy * (upy - my * upz)) / z, M22 = (v.fy * (vpy - my * vpz)) / z;
+  float g1 = upz / z, g2 = vpz / z;
+  float dm = M11 * M22 - M12 * M21;
+  float detA = dm * dm;
+  o.mx = mx; o.my = my; o.x0 = x0; o.y0 = y0;
+  o.M11 = M11; o.M12 = M12; o.M21 = M21; o.M22 = M22; o.g1 = g1; o.g2 = g2;
+  o.dm = dm; o.detA = detA;
+  if (!(detA > 0.f)) return;
+  float a = M11 * M11 + M21 * M21, bb = M11 * M12 + M21 * M22, c = M12 * M12 + M22 * M22;
+  float S11 = detA + sigma * c, S12 = -(sigma * bb), S22 = detA + sigma * a;
+  float Sg1 = S11 * g1 + S12 * g2, Sg2 = S12 * g1 + S22 * g2;
+  float gSg = g1 * Sg1 + g2 * Sg2;
+  float r2 = rcut * rcut;
+  float kz = 1.f - v.znear / z;
+  if (!(r2 * gSg < detA * (kz * kz))) return;
+  float den = detA - r2 * gSg;
+  float SM1x = S11 * M11 + S12 * M12, SM1y = S12 * M11 + S22 * M12;
+  float M1SM1 = M11 * SM1x + M12 * SM1y, M1Sg = M11 * Sg1 + M12 * Sg2;
+  float SM2x = S11 * M21 + S12 * M22, SM2y = S12 * M21 + S22 * M22;
+  float M2SM2 = M21 * SM2x + M22 * SM2y, M2Sg = M21 * Sg1 + M22 * Sg2;
+  float Xc = -(r2 * M1Sg) / den;
+  float hx = sqrtf(Xc * Xc + (r2 * M1SM1) / den);
+  float Yc = -(r2 * M2Sg) / den;
+  float hy = sqrtf(Yc * Yc + (r2 * M2SM2) / den);
+  float xlo = ((x0 + Xc) - hx) - 0.01f, xhi = ((x0 + Xc) + hx) + 0.01f;
+  float ylo = ((y0 + Yc) - hy) - 0.01f, yhi = ((y0 + Yc) + hy) + 0.01f;
+  if (!(xlo <= xhi) || !(ylo <= yhi)) return;
+  float il = ceilf(xlo - 0.5f), ih = floorf(xhi - 0.5f);
+  float jl = ceilf(ylo - 0.5f), jh = floorf(yhi - 0.5f);
+  const float wm1 = (float)(v.W - 1), hm1 = (float)(v.H - 1);
+  il = (il < 0.f) ? 0.f : il;
+  ih = (wm1 < ih) ? wm1 : ih;
+  jl = (jl < 0.f) ? 0.f : jl;
+  jh = (hm1 < jh) ? hm1 : jh;
+  if (!(il <= ih) || !(jl <= jh)) return;
+  o.keep = 1;
+  o.il = (int)il; o.ih = (int)ih; o.jl = (int)jl; o.jh = (int)jh;
+}
+
+// ---------------------------------------------------------------- per fragment
+// Evaluation of one record at one pixel, shared by the forward and backward
+// raster kernels so that both take identical cutoff decisions: explicit fmaf
+// and a fixed order, independent of the surrounding code.
+struct FragEval {
+  float dx, dy, s, N, q, w;
+  bool cov;
+};
+__device__ __forceinline__ void frag_eval(const float* rec, int px, int py, float r2, FragEval& f) {
+  // R_X0/R_Y0 hold the centre relative to the rectangle's integer corner
+  const int il = __float_as_int(rec[R_RX]) & 0xffff, jl = __float_as_int(rec[R_RY]) & 0xffff;
+  f.dx = ((float)(px - il) + 0.5f) - rec[R_X0];
+  f.dy = ((float)(py - jl) + 0.5f) - rec[R_Y0];
+  f.s = __builtin_fmaf(rec[R_A3], f.dx, __builtin_fmaf(rec[R_B3], f.dy, 1.0f));
+  float t = __builtin_fmaf(rec[R_QXX], f.dx, rec[R_QXY2] * f.dy);
+  f.N = __builtin_fmaf(t, f.dx, (rec[R_QYY] * f.dy) * f.dy);
+  float s2 = f.s * f.s;
+  f.cov = f.N < r2 * s2;
+  f.q = f.N * __builtin_amdgcn_rcpf(s2);
+  f.w = rec[R_NF] * __expf(-0.5f * f.q);
+}
+
+__device__ __forceinline__ int view_of_tile(const ViewDev* views, int nv, int tile) {
+  int lo = 0, hi = nv - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (views[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- launchers
+// (implemented in the .hip files; all enqueue on `st` and return hipError_t)
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t st);
+hipError_t launch_fill_f32(float* p, float v, long long n, hipStream_t st);
+
+hipError_t launch_envmap_dirs(float* dirs, int H, int W, hipStream_t st);
+hipError_t launch_envmap_out_dirs(int He, int We, const float* in_dirs, const int lh[7],
+                                  const int lw[7], float* out_dirs, hipStream_t st);
+hipError_t launch_envmap_prefilter(const float* E, int He, int We, const float* in_dirs,
+                                   const float* out_dirs, float* const lvl_out[7], const int lh[7],
+                                   const int lw[7], hipStream_t st);
+hipError_t launch_envmap_adjoint(const float* const dlvl[7], const int lh[7], const int lw[7],
+                                 const float* out_dirs, int He, int We, const float* in_dirs,
+                                 float* dE, hipStream_t st);
+hipError_t launch_brdf_lut(float* lut, int n_nv, int n_r, int samples, hipStream_t st);
+
+hipError_t launch_preprocess(const float* const P[7], long long N, const ViewDev* views, int v0,
+                             int v1, int max_surf, const Params& prm, float* recs,
+                             uint32_t* counts, hipStream_t st);
+constexpr int kBackwardBlocks = 512;       // blocks of the surfel adjoint (per scene)
+constexpr int kLocalMapFloats = 16384;     // LDS budget for privatised environment levels
+int backward_blocks(long long n_surf);
+hipError_t launch_preprocess_backward(const float* const P[7], long long N, const ViewDev* views,
+                                      int n_views, long long s_begin, long long s_end,
+                                      const int local_off[7], int local_total, float* partial,
+                                      float* const level_grad[7], const Params& prm,
+                                      const float* grad, long long R, float* const G[7],
+                                      hipStream_t st);
+
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint32_t* total,
+                           uint32_t* tmp, long long tmp_n, hipStream_t st);
+long long scan_tmp_size(long long n);
+hipError_t launch_emit_pairs(const float* recs, const uint32_t* offsets, const ViewDev* views,
+                             int v0, int v1, int max_surf, int tile_w, int tile_h,
+                             uint64_t* keys, uint32_t* vals, const uint32_t* n_pairs,
+                             long long cap, int* status, hipStream_t st);
+hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp,
+                             const uint32_t* n_pairs, long long cap, int key_bits, uint32_t* hist,
+                             uint32_t* scan_tmp, long long scan_tmp_n, hipStream_t st,
+                             bool* result_in_tmp);
+hipError_t launch_tile_ranges(const uint64_t* keys, const uint32_t* n_pairs, long long cap,
+                              uint32_t* ranges, int tile_begin, int n_tiles, hipStream_t st);
+
+hipError_t launch_raster_forward(const ViewDev* views, int n_views, int tile_begin, int tile_end,
+                                 const uint32_t* ranges, const uint32_t* sorted_vals,
+                                 const float* recs, const Params& prm, int lds_batch,
+                                 float* image, float* alpha, uint8_t* n_layers_out,
+                                 uint8_t* n_layers, float4* layer_stats, int* queue,
+                                 const int* order, int persistent, hipStream_t st);
+hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_begin, int tile_end,
+                                  const uint32_t* ranges, const uint32_t* sorted_vals,
+                                  const float* recs, const Params& prm, int lds_batch,
+                                  const float* d_image, const float* d_alpha,
+                                  const uint8_t* n_layers, const float4* layer_stats,
+                                  float* grad, long long R, int* queue, const int* order,
+                                  int persistent, hipStream_t st);
+
+}  // namespace ss

@@ -1,0 +1,348 @@
+"""GPU parity: the HIP renderer (through the C ABI) against the CPU oracle.
+
+Binning is compared bit for bit; images and gradients with the protocol of
+parity_util (FP32 against FP64, decision-margin pixels excluded).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import scenegen as g
+from parity_util import (GRAD_REL_L2, assert_image_parity, compare_images, decision_ok,
+                         oracle_forward, oracle_maps, oracle_options, pixel_index, rel_l2)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def O():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+@pytest.fixture(scope="module")
+def ss():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2605_05876_amd as m
+    m.load_library()
+    return m
+
+
+def all_pix(cam):
+    ys, xs = np.meshgrid(np.arange(cam.height), np.arange(cam.width), indexing="ij")
+    return np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32)
+
+
+def sample_pix(cam, k, seed, frac=0.6):
+    """k seeded pixels, uniform over the central `frac` of the view."""
+    rng = np.random.default_rng(seed)
+    w0, h0 = int(cam.width * (1 - frac) / 2), int(cam.height * (1 - frac) / 2)
+    xs = rng.integers(w0, cam.width - w0, k)
+    ys = rng.integers(h0, cam.height - h0, k)
+    p = np.unique(np.stack([xs, ys], 1), axis=0)
+    return p.astype(np.int32)
+
+
+def gpu_run(ss, scenes, cams, opts, G=None, Ga=None):
+    r = ss.Renderer(opts)
+    b = ss.batch_from_scenes(scenes, cams)
+    img, a, nl = r.forward(b, want_layers=True)
+    d = r.poll()
+    assert d["status"] == 0, d
+    grads = None
+    if G is not None:
+        gt = torch.from_numpy(np.ascontiguousarray(G, np.float32)).cuda()
+        ga = None if Ga is None else torch.from_numpy(np.ascontiguousarray(Ga, np.float32)).cuda()
+        grads = r.backward(b, gt, ga)
+        grads = {k: ([e.cpu().numpy() for e in v] if isinstance(v, list) else v.cpu().numpy())
+                 for k, v in grads.items()}
+    torch.cuda.synchronize()
+    return r, b, img.cpu().numpy(), a.cpu().numpy(), nl.cpu().numpy(), grads
+
+
+def small_c2():
+    sc = g.torus_scene(22, 20_000, scale_mu=math.log(0.02), scale_sigma=0.3)
+    sc.envmap = g.lognormal_envmap(22, 16, 32)
+    el = math.radians(30.0)
+    cam = g.look_at_camera((0.0, -3.0 * math.cos(el), 3.0 * math.sin(el)), 96, 96)
+    return [sc], [cam]
+
+
+def small_multiview():
+    sc = g.superquadric_scene(33, 30_000, scale_mu=math.log(0.012), scale_sigma=0.5)
+    sc.envmap = g.lognormal_envmap(33, 16, 32)
+    cams = [g.look_at_camera(3.0 * d, 72, 56) for d in g.fibonacci_directions(3)]
+    return [sc], cams
+
+
+# ---------------------------------------------------------------- binning
+@pytest.mark.parametrize("case,tile", [("C1", (16, 16)), ("C1", (8, 8)), ("C2s", (16, 16)),
+                                       ("MV", (16, 8)), ("MV", (32, 16))])
+def test_binning_bit_exact(O, ss, case, tile):
+    if case == "C1":
+        w = g.make_config("C1")
+        scenes, cams, shade = w.scenes, w.cameras, "albedo"
+    elif case == "C2s":
+        (scenes, cams), shade = small_c2(), "splitsum"
+    else:
+        (scenes, cams), shade = small_multiview(), "splitsum"
+    opts = ss.Options(shade=shade, tile_w=tile[0], tile_h=tile[1])
+    r, b, *_ = gpu_run(ss, scenes, cams, opts)
+    dbg = r.debug_binning(b)
+    zb = dbg["rec_zbits"].cpu().numpy().view(np.uint32)
+    rect = dbg["rec_rect"].cpu().numpy()
+    keys = dbg["keys"].cpu().numpy().view(np.uint64)
+    vals = dbg["vals"].cpu().numpy().view(np.uint32)
+    ranges = dbg["ranges"].cpu().numpy().view(np.uint32)
+    oo = oracle_options(O, opts)
+    ref_k, ref_v = [], []
+    rec_base, tile_base = 0, 0
+    for cam in cams:
+        sc = scenes[cam.scene]
+        keep, rz, rr = O.bin_f32(sc, cam, oo)
+        n = sc.n
+        k = keep.astype(bool)
+        gz, grect = zb[rec_base:rec_base + n], rect[rec_base:rec_base + n]
+        assert (gz[k] == rz[k]).all(), "z_start bits differ"
+        # culled on the GPU <=> culled in the reference (empty rectangle)
+        g_keep = (grect[:, 0] <= grect[:, 2]) & (grect[:, 1] <= grect[:, 3])
+        assert (g_keep == k).all(), (np.nonzero(g_keep != k)[0][:10])
+        tiles_x = -(-cam.width // tile[0])
+        tr = np.stack([grect[:, 0] // tile[0], grect[:, 1] // tile[1], grect[:, 2] // tile[0],
+                       grect[:, 3] // tile[1]], 1)
+        assert (tr[k] == rr[k]).all(), "tile rectangles differ"
+        kk, vv = O.sorted_pairs(keep, rz, rr, tiles_x, tile_base=tile_base, rec_base=rec_base)
+        ref_k.append(kk)
+        ref_v.append(vv)
+        rec_base += n
+        tile_base += tiles_x * (-(-cam.height // tile[1]))
+    ref_k = np.concatenate(ref_k)
+    ref_v = np.concatenate(ref_v)
+    assert keys.shape == ref_k.shape
+    assert (keys == ref_k).all()
+    assert (vals == ref_v).all()
+    # per-tile ranges
+    tiles = (ref_k >> np.uint64(32)).astype(np.int64)
+    cnt = np.bincount(tiles, minlength=tile_base)
+    ends = np.cumsum(cnt)
+    starts = ends - cnt
+    nz = cnt > 0
+    assert (ranges[nz, 0] == starts[nz]).all() and (ranges[nz, 1] == ends[nz]).all()
+    assert (ranges[~nz] == 0).all()
+
+
+# ---------------------------------------------------------------- forward
+def _forward_case(O, ss, scenes, cams, shade, pix_fn, **kw):
+    opts = ss.Options(shade=shade, **kw)
+    maps, lut = oracle_maps(O, scenes, shade)
+    pix = [pix_fn(c, v) for v, c in enumerate(cams)]
+    ref = oracle_forward(O, scenes, cams, opts, pix, maps, lut)
+    _, _, img, a, nl, _ = gpu_run(ss, scenes, cams, opts)
+    rep, masks = compare_images(cams, pix, ref, img, a)
+    for v, c in enumerate(cams):
+        idx = pixel_index(cams, v, pix[v])
+        assert (nl[idx][masks[v]] == ref[v]["n_layers"][masks[v]]).all()
+    return rep
+
+
+def test_forward_parity_albedo_full_image(O, ss):
+    w = g.make_config("C1")
+    rep = _forward_case(O, ss, w.scenes, w.cameras, "albedo", lambda c, v: all_pix(c))
+    assert_image_parity(rep)
+    assert rep["total"] == 128 * 128
+
+
+def test_forward_parity_splitsum_full_image(O, ss):
+    scenes, cams = small_c2()
+    rep = _forward_case(O, ss, scenes, cams, "splitsum", lambda c, v: all_pix(c))
+    assert_image_parity(rep)
+
+
+def test_forward_parity_multiview_ragged(O, ss):
+    scenes, cams = small_multiview()   # 72 x 56: ragged against 16 x 16 tiles
+    rep = _forward_case(O, ss, scenes, cams, "splitsum", lambda c, v: all_pix(c))
+    assert_image_parity(rep)
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.5])
+def test_forward_parity_sigma(O, ss, sigma):
+    w = g.make_config("C1")
+    rep = _forward_case(O, ss, w.scenes, w.cameras, "albedo", lambda c, v: all_pix(c), sigma_f=sigma)
+    assert_image_parity(rep)
+
+
+# ---------------------------------------------------------------- backward
+def _backward_case(O, ss, scenes, cams, shade, pix_fn, seed=0, with_alpha=True, **kw):
+    opts = ss.Options(shade=shade, **kw)
+    maps, lut = oracle_maps(O, scenes, shade)
+    oo = oracle_options(O, opts)
+    pix = [pix_fn(c, v) for v, c in enumerate(cams)]
+    ref = oracle_forward(O, scenes, cams, opts, pix, maps, lut, conditioning=False)
+    n_pix = sum(c.width * c.height for c in cams)
+    rng = np.random.default_rng(seed)
+    G = np.zeros((n_pix, 3))
+    Ga = np.zeros(n_pix) if with_alpha else None
+    per_view = []
+    for v, c in enumerate(cams):
+        r = ref[v]
+        ok = decision_ok(r)
+        gv = rng.normal(size=(len(pix[v]), 3)) * ok[:, None]
+        gav = rng.normal(size=len(pix[v])) * ok if with_alpha else None
+        idx = pixel_index(cams, v, pix[v])
+        G[idx] = gv
+        if with_alpha:
+            Ga[idx] = gav
+        per_view.append((gv, gav))
+    _, _, img, a, nl, gg = gpu_run(ss, scenes, cams, opts, G, Ga)
+    # oracle gradient: sum over views of per-view adjoints (scene-local arrays)
+    names = ["position", "normal", "tangent", "scale", "albedo", "roughness", "metallic"]
+    ref_g = [{k: np.zeros_like(getattr(s, k), dtype=np.float64) for k in names} for s in scenes]
+    ref_maps = [None if maps[i] is None else np.zeros_like(maps[i]) for i in range(len(scenes))]
+    for v, c in enumerate(cams):
+        sc = scenes[c.scene]
+        hw = tuple(np.asarray(sc.envmap).shape[:2]) if maps[c.scene] is not None else (0, 0)
+        gr = O.render_grad(sc, c, oo, pix[v], per_view[v][0], per_view[v][1], maps=maps[c.scene],
+                           lut=lut, env_hw=hw)
+        for k in names:
+            ref_g[c.scene][k] += gr[k]
+        if ref_maps[c.scene] is not None:
+            ref_maps[c.scene] += gr["maps"]
+    offs = np.cumsum([0] + [s.n for s in scenes])
+    errs = {}
+    pos_norm = np.linalg.norm(np.concatenate([rg["position"] for rg in ref_g], axis=-1))
+    for k in names:
+        got = gg[k]
+        want = np.concatenate([rg[k] for rg in ref_g], axis=-1)
+        if np.linalg.norm(want) == 0 and shade == "albedo" and k in ("roughness", "metallic"):
+            assert np.abs(got).max() == 0
+            continue
+        if np.linalg.norm(want) < 1e-9 * pos_norm:
+            # analytically zero (e.g. the tangent of isotropic surfels): FP32 noise only
+            errs[k] = float(np.linalg.norm(got) / pos_norm)
+            continue
+        errs[k] = rel_l2(got, want)
+    if shade == "splitsum":
+        for i, sc in enumerate(scenes):
+            He, We = np.asarray(sc.envmap).shape[:2]
+            dE = O.envmap_adjoint(ref_maps[i], He, We)
+            errs[f"envmap{i}"] = rel_l2(gg["envmap"][i], dE)
+    return errs
+
+
+def test_backward_parity_albedo_full_image(O, ss):
+    w = g.make_config("C1")
+    errs = _backward_case(O, ss, w.scenes, w.cameras, "albedo", lambda c, v: all_pix(c))
+    assert max(errs.values()) <= GRAD_REL_L2, errs
+
+
+def test_backward_parity_splitsum_full_image(O, ss):
+    scenes, cams = small_c2()
+    errs = _backward_case(O, ss, scenes, cams, "splitsum", lambda c, v: all_pix(c))
+    assert max(errs.values()) <= GRAD_REL_L2, errs
+
+
+def test_backward_parity_multiview(O, ss):
+    scenes, cams = small_multiview()
+    errs = _backward_case(O, ss, scenes, cams, "splitsum", lambda c, v: all_pix(c), seed=3)
+    assert max(errs.values()) <= GRAD_REL_L2, errs
+
+
+# ---------------------------------------------------------------- tables, invariances, edges
+def test_brdf_lut_matches_oracle(O, ss):
+    lut = ss.make_brdf_lut(64, 64, 1024).cpu().numpy()
+    ref = O.brdf_lut(64, 64, 1024)
+    # both integrate in FP64; the GPU table is rounded to FP32
+    assert np.abs(lut - ref).max() < 1e-6
+
+
+def test_forward_parity_sampled_pixels(O, ss):
+    """Split-sum forward at seeded sampled pixels (the protocol used at full size)."""
+    scenes, cams = small_c2()
+    rep = _forward_case(O, ss, scenes, cams, "splitsum", lambda c, v: sample_pix(c, 300, 5))
+    assert_image_parity(rep)
+
+
+@pytest.mark.parametrize("variant", [dict(lds_batch=32), dict(lds_batch=256), dict(tile_w=8, tile_h=8),
+                                     dict(tile_w=32, tile_h=16), dict(persistent=False),
+                                     dict(launch="per_view")])
+def test_forward_bit_identical_across_tunables(ss, variant):
+    scenes, cams = small_multiview()
+    base = gpu_run(ss, scenes, cams, ss.Options(shade="splitsum"))
+    other = gpu_run(ss, scenes, cams, ss.Options(shade="splitsum", **variant))
+    assert np.array_equal(base[2], other[2]) and np.array_equal(base[3], other[3])
+    assert np.array_equal(base[4], other[4])
+
+
+def test_per_view_backward_matches_batched(ss):
+    scenes, cams = small_multiview()
+    n_pix = sum(c.width * c.height for c in cams)
+    G = np.random.default_rng(1).normal(size=(n_pix, 3))
+    a = gpu_run(ss, scenes, cams, ss.Options(shade="splitsum"), G)[5]
+    b = gpu_run(ss, scenes, cams, ss.Options(shade="splitsum", launch="per_view"), G)[5]
+    for k in a:
+        if k == "envmap":
+            assert rel_l2(b[k][0], a[k][0]) < 1e-5
+        else:
+            assert rel_l2(b[k], a[k]) < 1e-5, k
+
+
+def test_all_culled_gives_background(ss):
+    from conftest import axis_camera, make_scene
+    cam = axis_camera(40, 24, 50.0, background=(0.2, 0.4, 0.6))
+    sc = make_scene([[0, 0, -2.0], [0.1, 0, -1.0]], [[0, 0, 1.0]] * 2, [[1, 0, 0]] * 2, [[0.05, 0.05]] * 2)
+    _, _, img, a, nl, _ = gpu_run(ss, [sc], [cam], ss.Options())
+    assert np.allclose(img, np.array([0.2, 0.4, 0.6], np.float32)) and (a == 0).all() and (nl == 0).all()
+
+
+def test_layer_cap_matches_oracle(O, ss):
+    from conftest import axis_camera, make_scene
+    cam = axis_camera(40, 40, 100.0)
+    pos, nrm, tan, scl, alb = [], [], [], [], []
+    rng = np.random.default_rng(0)
+    th = np.radians(8.0)
+    for k in range(20):
+        # lattice not commensurate with the pixel grid (no exact cutoff ties), planes
+        # tilted by 8 degrees so that every surfel has a depth extent
+        gx, gy = np.meshgrid(np.arange(-4, 5) * 0.0317 + 0.0043 * k, np.arange(-4, 5) * 0.0317 - 0.0029 * k)
+        n = gx.size
+        pos.append(np.stack([gx.ravel(), gy.ravel() * np.cos(th), 2.0 + 0.05 * k + gy.ravel() * np.sin(th)], 1))
+        nrm.append(np.tile([0, -np.sin(th), np.cos(th)], (n, 1)))
+        tan.append(np.tile([1.0, 0, 0], (n, 1)))
+        scl.append(np.full((n, 2), 0.02))
+        alb.append(rng.uniform(0, 1, (n, 3)))
+    sc = make_scene(*[np.concatenate(x) for x in (pos, nrm, tan, scl, alb)])
+    rep = _forward_case(O, ss, [sc], [cam], "albedo", lambda c, v: all_pix(c))
+    assert_image_parity(rep)
+    _, _, img, a, nl, _ = gpu_run(ss, [sc], [cam], ss.Options())
+    assert nl.max() == 16
+
+
+def test_stage_profile_counts(ss):
+    scenes, cams = small_multiview()
+    r = ss.Renderer(ss.Options(shade="splitsum"))
+    b = ss.batch_from_scenes(scenes, cams)
+    r.forward(b)
+    r.profile(True)
+    for _ in range(2):
+        r.forward(b)
+        r.backward(b, torch.ones((b.n_pixels, 3), device="cuda"))
+    prof = r.profile_read()
+    print(prof)
+    for k, (ms, n) in prof.items():
+        assert n == 2 and ms > 0, (k, ms, n)
+
+
+def test_capacity_and_state_errors(ss):
+    w = g.make_config("C1")
+    r = ss.Renderer(ss.Options())
+    b = ss.batch_from_scenes(w.scenes, w.cameras)
+    with pytest.raises(ss.SurfsplatError) as e:
+        r.backward(b, torch.zeros((b.n_pixels, 3), device="cuda"))
+    assert e.value.status == 4  # SS_ERR_STATE
+    r.forward(b)
+    assert r.poll()["status"] == 0
