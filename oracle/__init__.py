@@ -56,6 +56,8 @@ def lib():
                                      dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, dp]
         L.orc_render_grad.argtypes = [fpp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, fpp, dp]
+        L.orc_screen_grad.argtypes = [fpp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, dp, dp, ip]
         L.orc_pixel_fragments.restype = ctypes.c_int
         L.orc_pixel_fragments.argtypes = [fpp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp,
                                           ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -263,6 +265,29 @@ def render_grad(scene, cam, opt: Options, pix, dimage, dalpha=None, maps=None, l
     out = dict(zip(PARAM_NAMES, grads))
     out["maps"] = dmaps
     return out
+
+
+def screen_grad(scene, cam, opt: Options, pix, dimage, dalpha=None, maps=None, lut=None,
+                env_hw=(0, 0)):
+    """Densification statistic (Sec. 3.6.1, eq:ss_grad) at the listed pixels:
+    per surfel, `abs` = sum over pixels of |(dL_p/dT1z, dL_p/dT2z)| T4z, `vec` =
+    the plain sum of those vectors ([2, n]), `visible` = culled-in with a
+    non-empty tile rectangle in this view."""
+    P = _Params(scene)
+    n = P.n
+    pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 2)
+    k = pix.shape[0]
+    maps, lut, He, We = _maps_lut(maps, lut, *env_hw)
+    dimage = np.ascontiguousarray(dimage, np.float64).reshape(k, 3)
+    da = None if dalpha is None else np.ascontiguousarray(dalpha, np.float64).reshape(k)
+    a = np.zeros(n, np.float64)
+    vec = np.zeros((2, n), np.float64)
+    vis = np.zeros(n, np.int32)
+    c, o = pack_camera(cam), opt.pack()
+    lib().orc_screen_grad(P.pp, n, _dptr(c), _dptr(o), _dptr(maps), He, We, _dptr(lut),
+                          lut.shape[1], lut.shape[0], k, _iptr(pix), _dptr(dimage),
+                          _dptr(da) if da is not None else None, _dptr(a), _dptr(vec), _iptr(vis))
+    return dict(abs=a, vec=vec, visible=vis.astype(bool))
 
 
 def pixel_fragments(scene, cam, opt: Options, px: int, py: int, maps=None, lut=None,

@@ -350,6 +350,33 @@ static void lut_lookup(const Lut& L, S nv, S r, S out[2]) {
 }
 
 // ------------------------------------------------------------ per (surfel, view)
+// Centre-precomputed MIP filter (Sec. 3.3.2): Sigma_mip = I + sigma_f J J^T with
+// J = M^{-1} the inverse of the screen Jacobian at the surfel centre, and the
+// normalisation n_f = sqrt(|I| / |Sigma_mip|).  A function of the T rows only,
+// so that it can also be differentiated with respect to T.
+template <class S>
+static void mip_filter(Rec<S>& r, double sigma_f) {
+  using std::sqrt;
+  // M = d(x,y)/d(u,v) at u = v = 0 (quotient rule on x = T1.(u,v,1)/T4.(u,v,1))
+  S z2 = r.T4[2] * r.T4[2];
+  S M11 = (r.T1[0] * r.T4[2] - r.T1[2] * r.T4[0]) / z2;
+  S M12 = (r.T1[1] * r.T4[2] - r.T1[2] * r.T4[1]) / z2;
+  S M21 = (r.T2[0] * r.T4[2] - r.T2[2] * r.T4[0]) / z2;
+  S M22 = (r.T2[1] * r.T4[2] - r.T2[2] * r.T4[1]) / z2;
+  S detM = M11 * M22 - M12 * M21;
+  // J = M^{-1}
+  S J11 = M22 / detM, J12 = -M12 / detM, J21 = -M21 / detM, J22 = M11 / detM;
+  // Sigma_mip = I + sigma_f J J^T
+  S s11 = 1.0 + sigma_f * (J11 * J11 + J12 * J12);
+  S s12 = sigma_f * (J11 * J21 + J12 * J22);
+  S s22 = 1.0 + sigma_f * (J21 * J21 + J22 * J22);
+  S dets = s11 * s22 - s12 * s12;
+  r.sinv[0] = s22 / dets;
+  r.sinv[1] = -s12 / dets;
+  r.sinv[2] = s11 / dets;
+  r.nf = sqrt(1.0 / dets);
+}
+
 // Sec. 3.1: frame, camera-space vectors, T = P S with the pixel-space pinhole
 // projection, depth extent eps_z = r_cut sqrt(t'_uz^2 + t'_vz^2).
 // Sec. 3.3.2: J = d(u,v)/d(x,y) at the surfel centre, Sigma_mip = I + sigma_f J J^T
@@ -391,24 +418,7 @@ static void preprocess(const Surf<S>& s, const Cam& cam, const Opt& o, const M& 
   S ez = o.r_cut * sqrt(tup[2] * tup[2] + tvp[2] * tvp[2]);
   r.zs = cp[2] - ez;
   r.ze = cp[2] + ez;
-  // M = d(x,y)/d(u,v) at u = v = 0 (quotient rule on x = T1.(u,v,1)/T4.(u,v,1))
-  S z2 = r.T4[2] * r.T4[2];
-  S M11 = (r.T1[0] * r.T4[2] - r.T1[2] * r.T4[0]) / z2;
-  S M12 = (r.T1[1] * r.T4[2] - r.T1[2] * r.T4[1]) / z2;
-  S M21 = (r.T2[0] * r.T4[2] - r.T2[2] * r.T4[0]) / z2;
-  S M22 = (r.T2[1] * r.T4[2] - r.T2[2] * r.T4[1]) / z2;
-  S detM = M11 * M22 - M12 * M21;
-  // J = M^{-1}
-  S J11 = M22 / detM, J12 = -M12 / detM, J21 = -M21 / detM, J22 = M11 / detM;
-  // Sigma_mip = I + sigma_f J J^T
-  S s11 = 1.0 + o.sigma_f * (J11 * J11 + J12 * J12);
-  S s12 = o.sigma_f * (J11 * J21 + J12 * J22);
-  S s22 = 1.0 + o.sigma_f * (J21 * J21 + J22 * J22);
-  S dets = s11 * s22 - s12 * s12;
-  r.sinv[0] = s22 / dets;
-  r.sinv[1] = -s12 / dets;
-  r.sinv[2] = s11 / dets;
-  r.nf = sqrt(1.0 / dets);
+  mip_filter(r, o.sigma_f);
   // colour
   if (o.shade == 0) {
     for (int c = 0; c < 3; ++c) r.col[c] = s.alb[c];
@@ -888,6 +898,91 @@ int orc_render_grad(const float* const* P, int n, const double* cam, const doubl
             dmaps[kv.first] += g;
           }
         }
+    }
+    g_tape = nullptr;
+  }
+  return 0;
+}
+
+// Densification statistic (Sec. 3.6.1, eq:ss_grad).  For each listed pixel p
+// with loss L_p = dimg_p . image_p + dalpha_p alpha_p and each surfel i that
+// reaches p, the screen-space positional gradient is
+//   g = (dL_p/dT1z * T4z, dL_p/dT2z * T4z),
+// with the whole pixel evaluation, MIP filter included, differentiated as a
+// function of the T rows.  Outputs per surfel (overwritten): the sum over the
+// pixels of |g| (abs_sum [n]), of g itself (vec_sum [2][n], nullable) and
+// whether the surfel survives the cull with a non-empty tile rectangle in this
+// view (visible [n], nullable).  The paper's criterion averages abs_sum over
+// the views in which a surfel is visible.
+int orc_screen_grad(const float* const* P, int n, const double* cam, const double* opt,
+                    const double* maps, int He, int We, const double* lut, int n_nv, int n_r,
+                    int npix, const int* pix, const double* dimg, const double* dalpha,
+                    double* abs_sum, double* vec_sum, int* visible) {
+  Cam c = unpack_cam(cam);
+  Opt o = unpack_opt(opt);
+  std::vector<Rec<double>> recs(n);
+  std::vector<int> keep(n), cand;
+  MapDims md(std::max(He, 4), std::max(We, 8));
+  Lut L{lut, n_nv, n_r};
+  MapsD Md{maps};
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < n; ++i) {
+    keep[i] = bin_f32(P, n, i, c, o).keep;
+    if (!keep[i]) continue;
+    Surf<double> s = load_surf<double>(P, n, i, nullptr);
+    preprocess(s, c, o, Md, &md, &L, recs[i]);
+  }
+  for (int i = 0; i < n; ++i) {
+    if (keep[i]) cand.push_back(i);
+    abs_sum[i] = 0.0;
+    if (vec_sum) vec_sum[i] = vec_sum[(size_t)n + i] = 0.0;
+    if (visible) visible[i] = keep[i];
+  }
+#pragma omp parallel
+  {
+    Tape tape;
+    g_tape = &tape;
+    std::vector<int> cov;
+#pragma omp for schedule(dynamic, 4)
+    for (int k = 0; k < npix; ++k) {
+      double x = pix[2 * k] + 0.5, y = pix[2 * k + 1] + 0.5;
+      PixOut<double> od;
+      pixel_eval(x, y, recs.data(), cand, c, o, od, nullptr, &cov);
+      if (cov.empty()) continue;
+      tape.clear();
+      // leaves: the T rows and the colour; the MIP filter is rebuilt from T
+      std::vector<Rec<Var>> vr(cov.size());
+      for (size_t j = 0; j < cov.size(); ++j) {
+        const Rec<double>& r = recs[cov[j]];
+        Rec<Var>& v = vr[j];
+        for (int a = 0; a < 3; ++a) { v.T1[a] = Var::leaf(r.T1[a]); v.T2[a] = Var::leaf(r.T2[a]); v.T4[a] = Var::leaf(r.T4[a]); }
+        v.zs = Var(r.zs); v.ze = Var(r.ze);
+        mip_filter(v, o.sigma_f);
+        for (int a = 0; a < 3; ++a) v.col[a] = Var::leaf(r.col[a]);
+      }
+      std::vector<int> dense(cov.size());
+      for (size_t j = 0; j < cov.size(); ++j) dense[j] = (int)j;
+      PixOut<Var> ov;
+      pixel_eval(x, y, vr.data(), dense, c, o, ov, nullptr, nullptr);
+      std::vector<double> adj(tape.nodes.size(), 0.0);
+      for (int ch = 0; ch < 3; ++ch)
+        if (ov.img[ch].id >= 0) adj[ov.img[ch].id] += dimg[3 * k + ch];
+      if (dalpha && ov.alpha.id >= 0) adj[ov.alpha.id] += dalpha[k];
+      tape.sweep(adj);
+      for (size_t j = 0; j < cov.size(); ++j) {
+        const int i = cov[j];
+        const double t4z = recs[i].T4[2];
+        const double gx = adj[vr[j].T1[2].id] * t4z, gy = adj[vr[j].T2[2].id] * t4z;
+        const double a = std::sqrt(gx * gx + gy * gy);
+#pragma omp atomic
+        abs_sum[i] += a;
+        if (vec_sum) {
+#pragma omp atomic
+          vec_sum[i] += gx;
+#pragma omp atomic
+          vec_sum[(size_t)n + i] += gy;
+        }
+      }
     }
     g_tape = nullptr;
   }
