@@ -51,11 +51,11 @@ def lib():
         L.orc_brdf_lut.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.orc_bin_f32.argtypes = [fpp, ctypes.c_int, dp, dp, ip, ctypes.POINTER(ctypes.c_uint32), ip]
         L.orc_render.argtypes = [fpp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp,
-                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, dp, dp, ip]
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, dp, dp, ip, dp]
         L.orc_render_jvp.argtypes = [fpp, ctypes.c_int, fpp, dp, dp, dp, dp, ctypes.c_int, ctypes.c_int,
-                                     dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, dp]
+                                     dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, dp, dp]
         L.orc_render_grad.argtypes = [fpp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp,
-                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, fpp, dp]
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, fpp, dp, dp]
         L.orc_screen_grad.argtypes = [fpp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, dp, dp, ip]
         L.orc_pixel_fragments.restype = ctypes.c_int
@@ -197,7 +197,8 @@ def _maps_lut(maps, lut, He, We):
 
 
 def render(scene, cam, opt: Options, pix, maps=None, lut=None, env_hw=(0, 0)):
-    """Forward at the listed pixels pix [K][2] (integer x, y)."""
+    """Forward at the listed pixels pix [K][2] (integer x, y); `cons` is the
+    per-pixel depth-consolidation term of eq:cons_loss."""
     P = _Params(scene)
     pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 2)
     k = pix.shape[0]
@@ -208,16 +209,17 @@ def render(scene, cam, opt: Options, pix, maps=None, lut=None, env_hw=(0, 0)):
     cm = np.zeros(k, np.float64)
     gm = np.zeros(k, np.float64)
     viol = np.zeros(k, np.int32)
+    cons = np.zeros(k, np.float64)
     c, o = pack_camera(cam), opt.pack()
     lib().orc_render(P.pp, P.n, _dptr(c), _dptr(o), _dptr(maps), He, We, _dptr(lut),
                      lut.shape[1], lut.shape[0], k, _iptr(pix), _dptr(img), _dptr(alpha),
-                     _iptr(nl), _dptr(cm), _dptr(gm), _iptr(viol))
-    return dict(image=img, alpha=alpha, n_layers=nl, cut_margin=cm, gap_margin=gm, viol=viol)
+                     _iptr(nl), _dptr(cm), _dptr(gm), _iptr(viol), _dptr(cons))
+    return dict(image=img, alpha=alpha, n_layers=nl, cut_margin=cm, gap_margin=gm, viol=viol, cons=cons)
 
 
 def render_jvp(scene, cam, opt: Options, pix, direction: dict, maps=None, dmaps=None,
                lut=None, env_hw=(0, 0)):
-    """Exact directional derivative of image and alpha along `direction`
+    """Exact directional derivative of image, alpha and cons along `direction`
     (dict of parameter-name -> float64 array of the parameter's shape)."""
     P = _Params(scene)
     pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 2)
@@ -236,17 +238,21 @@ def render_jvp(scene, cam, opt: Options, pix, direction: dict, maps=None, dmaps=
     img = np.zeros((k, 3), np.float64)
     img_dot = np.zeros((k, 3), np.float64)
     a_dot = np.zeros(k, np.float64)
+    c_dot = np.zeros(k, np.float64)
     c, o = pack_camera(cam), opt.pack()
     lib().orc_render_jvp(P.pp, P.n, ctypes.cast(vp, ctypes.POINTER(ctypes.c_void_p)), _dptr(c), _dptr(o),
                          _dptr(maps), _dptr(dm) if dm is not None else None, He, We, _dptr(lut),
-                         lut.shape[1], lut.shape[0], k, _iptr(pix), _dptr(img), _dptr(img_dot), _dptr(a_dot))
-    return dict(image=img, image_dot=img_dot, alpha_dot=a_dot)
+                         lut.shape[1], lut.shape[0], k, _iptr(pix), _dptr(img), _dptr(img_dot), _dptr(a_dot),
+                         _dptr(c_dot))
+    return dict(image=img, image_dot=img_dot, alpha_dot=a_dot, cons_dot=c_dot)
 
 
 def render_grad(scene, cam, opt: Options, pix, dimage, dalpha=None, maps=None, lut=None,
-                env_hw=(0, 0)):
-    """Adjoint at the listed pixels: returns dict of parameter gradients (float64,
-    parameter shapes) and `maps` (gradient w.r.t. the flat map set)."""
+                env_hw=(0, 0), dcons=None):
+    """Adjoint at the listed pixels (loss weights dimage [K][3], dalpha [K] and
+    dcons [K] on the depth-consolidation term): returns dict of parameter
+    gradients (float64, parameter shapes) and `maps` (gradient w.r.t. the flat
+    map set)."""
     P = _Params(scene)
     n = P.n
     pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 2)
@@ -257,11 +263,13 @@ def render_grad(scene, cam, opt: Options, pix, dimage, dalpha=None, maps=None, l
     grads = [np.zeros((r, n) if r > 1 else (n,), np.float64) for r in PARAM_ROWS]
     gp = (ctypes.c_void_p * 7)(*[g.ctypes.data for g in grads])
     dmaps = np.zeros(maps.size, np.float64)
+    dc = None if dcons is None else np.ascontiguousarray(dcons, np.float64).reshape(k)
     c, o = pack_camera(cam), opt.pack()
     lib().orc_render_grad(P.pp, n, _dptr(c), _dptr(o), _dptr(maps), He, We, _dptr(lut),
                           lut.shape[1], lut.shape[0], k, _iptr(pix), _dptr(dimage),
                           _dptr(da) if da is not None else None,
-                          ctypes.cast(gp, ctypes.POINTER(ctypes.c_void_p)), _dptr(dmaps))
+                          ctypes.cast(gp, ctypes.POINTER(ctypes.c_void_p)), _dptr(dmaps),
+                          _dptr(dc) if dc is not None else None)
     out = dict(zip(PARAM_NAMES, grads))
     out["maps"] = dmaps
     return out

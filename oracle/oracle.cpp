@@ -541,12 +541,17 @@ static BinOut bin_f32(const float* const* P, int n, int i, const Cam& cd, const 
 // interval grouping (Alg. 1), Shepard normalisation (eq:shepard), coverage
 // opacity (eq:alpha), front-to-back compositing (eq:compositing), K_max cap
 // (App. A.1), background blend and soft silhouette 1 - T_{K+1} (Sec. 3.5.2).
-template <class S> struct Frag { double zs; int idx; S w; S ze; const Rec<S>* r; };
-template <class S> struct PixOut { S img[3]; S alpha; int nl; };
+template <class S> struct Frag { double zs; int idx; S w; S ze; const Rec<S>* r; S z; };
+// cons: the pixel's depth-consolidation term (eq:cons_loss), inter-layer plus
+// intra-layer part, over the composited layers.
+template <class S> struct PixOut { S img[3]; S alpha; S cons; int nl; };
 struct PixDiag { double cut_margin, gap_margin; int viol; };
 
+// zf (nullable): camera-space depth of the ray-surfel intersection,
+// T4 . (u, v, 1) = c'_z + u t'_uz + v t'_vz.
 template <class S>
-static S frag_weight(const Rec<S>& r, double x, double y, double rc2, bool& hit, double& q_val) {
+static S frag_weight(const Rec<S>& r, double x, double y, double rc2, bool& hit, double& q_val,
+                     S* zf = nullptr) {
   // clip-space planes h_x = (-1,0,0,x), h_y = (0,-1,0,y) mapped by T^T
   S k[3], l[3];
   for (int i = 0; i < 3; ++i) { k[i] = x * r.T4[i] - r.T1[i]; l[i] = y * r.T4[i] - r.T2[i]; }
@@ -557,7 +562,9 @@ static S frag_weight(const Rec<S>& r, double x, double y, double rc2, bool& hit,
   q_val = INFINITY;
   if (val(p3) == 0.0) return S(0.0);
   S u = p1 / p3, v = p2 / p3;
-  if (val(r.T4[0] * u + r.T4[1] * v + r.T4[2]) <= 0.0) return S(0.0);  // behind the eye
+  S h = r.T4[0] * u + r.T4[1] * v + r.T4[2];
+  if (val(h) <= 0.0) return S(0.0);  // behind the eye
+  if (zf) *zf = h;
   S q = r.sinv[0] * u * u + 2.0 * r.sinv[1] * u * v + r.sinv[2] * v * v;
   q_val = val(q);
   if (!(q_val < rc2)) return S(0.0);
@@ -578,10 +585,11 @@ static void pixel_eval(double x, double y, const Rec<S>* recs, const std::vector
   for (int i : cand) {
     bool hit;
     double q;
-    S w = frag_weight(recs[i], x, y, rc2, hit, q);
+    S z(0.0);
+    S w = frag_weight(recs[i], x, y, rc2, hit, q, &z);
     if (std::isfinite(q)) cm = std::min(cm, std::fabs(q - rc2) / rc2);
     if (!hit) continue;
-    fr.push_back({val(recs[i].zs), i, w, recs[i].ze, &recs[i]});
+    fr.push_back({val(recs[i].zs), i, w, recs[i].ze, &recs[i], z});
   }
   std::sort(fr.begin(), fr.end(), [](const Frag<S>& a, const Frag<S>& b) {
     return a.zs < b.zs || (a.zs == b.zs && a.idx < b.idx);
@@ -595,9 +603,22 @@ static void pixel_eval(double x, double y, const Rec<S>* recs, const std::vector
   S Cout[3] = {S(0.0), S(0.0), S(0.0)}, Tb = S(1.0);
   int K = 0;
   double gm = INFINITY;
+  // depth statistics of the layers (eq:cons_loss): compositing weight
+  // T_k alpha_k, Shepard-weighted mean depth and variance of the fragments
+  std::vector<const Frag<S>*> members;
+  std::vector<S> lw, lz, lv;
   auto flush = [&]() {
     S a = 1.0 - exp(-kappa * Wg);
     for (int c = 0; c < 3; ++c) Cout[c] += Tb * a * (Cg[c] / Wg);
+    S zm(0.0), var(0.0);
+    for (const Frag<S>* f : members) zm += f->w * f->z;
+    zm = zm / Wg;
+    for (const Frag<S>* f : members) var += f->w * (f->z - zm) * (f->z - zm);
+    var = var / Wg;
+    lw.push_back(Tb * a);
+    lz.push_back(zm);
+    lv.push_back(var);
+    members.clear();
     Tb = Tb * (1.0 - a);
     ++K;
   };
@@ -618,10 +639,20 @@ static void pixel_eval(double x, double y, const Rec<S>* recs, const std::vector
     if (layer_of) (*layer_of)[fi] = K;
     for (int c = 0; c < 3; ++c) Cg[c] += f.w * f.r->col[c];
     Wg += f.w;
+    members.push_back(&f);
   }
   if (!done && val(Wg) > 0.0) flush();
   for (int c = 0; c < 3; ++c) out.img[c] = Cout[c] + Tb * cam.bg[c];
   out.alpha = 1.0 - Tb;
+  S cons(0.0);
+  for (int i = 0; i < K; ++i) {
+    for (int j = i + 1; j < K; ++j) {
+      S d = lz[i] - lz[j];
+      cons += lw[i] * lw[j] * (val(d) >= 0.0 ? d : -d);
+    }
+    cons += lw[i] * lw[i] * lv[i];
+  }
+  out.cons = cons;
   out.nl = K;
   if (dg) { dg->cut_margin = cm; dg->gap_margin = gm; }
 }
@@ -688,11 +719,12 @@ int orc_bin_f32(const float* const* P, int n, const double* cam, const double* o
 // pix: npix (x, y) integer pixel indices; pixel centres at (x + 1/2, y + 1/2).
 // Outputs per listed pixel: image [3], alpha, layer count, decision margins
 // (cutoff |q - r^2|/r^2 and gap |z_start - z_max|/z_max, minimum over the
-// pixel) and the number of covering fragments outside the FP32 tile rectangle.
+// pixel), the number of covering fragments outside the FP32 tile rectangle and
+// (cons, nullable) the depth-consolidation term of eq:cons_loss.
 int orc_render(const float* const* P, int n, const double* cam, const double* opt,
                const double* maps, int He, int We, const double* lut, int n_nv, int n_r,
                int npix, const int* pix, double* img, double* alpha, int* nl,
-               double* cut_margin, double* gap_margin, int* viol) {
+               double* cut_margin, double* gap_margin, int* viol, double* cons) {
   Cam c = unpack_cam(cam);
   Opt o = unpack_opt(opt);
   std::vector<Rec<double>> recs(n);
@@ -729,17 +761,18 @@ int orc_render(const float* const* P, int n, const double* cam, const double* op
     cut_margin[k] = dg.cut_margin;
     gap_margin[k] = dg.gap_margin;
     viol[k] = v;
+    if (cons) cons[k] = out.cons;
   }
   return 0;
 }
 
-// Directional derivative (exact, dual numbers) of the listed pixels' image and
-// alpha along the parameter direction V (7 arrays, NULL = 0) and the map-set
-// direction dmaps (NULL = 0).
+// Directional derivative (exact, dual numbers) of the listed pixels' image,
+// alpha and (cons_dot, nullable) depth-consolidation term along the parameter
+// direction V (7 arrays, NULL = 0) and the map-set direction dmaps (NULL = 0).
 int orc_render_jvp(const float* const* P, int n, const double* const* V, const double* cam,
                    const double* opt, const double* maps, const double* dmaps, int He, int We,
                    const double* lut, int n_nv, int n_r, int npix, const int* pix,
-                   double* img, double* img_dot, double* alpha_dot) {
+                   double* img, double* img_dot, double* alpha_dot, double* cons_dot) {
   Cam c = unpack_cam(cam);
   Opt o = unpack_opt(opt);
   std::vector<Rec<Dual>> recs(n);
@@ -762,19 +795,20 @@ int orc_render_jvp(const float* const* P, int n, const double* const* V, const d
     pixel_eval(pix[2 * k] + 0.5, pix[2 * k + 1] + 0.5, recs.data(), cand, c, o, out, nullptr, nullptr);
     for (int ch = 0; ch < 3; ++ch) { img[3 * k + ch] = out.img[ch].v; img_dot[3 * k + ch] = out.img[ch].d; }
     alpha_dot[k] = out.alpha.d;
+    if (cons_dot) cons_dot[k] = out.cons.d;
   }
   return 0;
 }
 
-// Adjoint.  Given dL/dimage [npix][3] and dL/dalpha [npix] (nullable) at the
-// listed pixels, accumulate dL/dparams (7 arrays, [C][n] double, overwritten)
+// Adjoint.  Given dL/dimage [npix][3], dL/dalpha [npix] (nullable) and dL/dcons
+// [npix] (nullable; cons = eq:cons_loss per pixel) at the listed pixels, accumulate dL/dparams (7 arrays, [C][n] double, overwritten)
 // and dL/dmaps (flat map set, overwritten; the environment itself is then
 // reached through orc_envmap_adjoint).  Reverse mode on a tape, per pixel for
 // the rasterisation and per surfel for preprocessing and shading.
 int orc_render_grad(const float* const* P, int n, const double* cam, const double* opt,
                     const double* maps, int He, int We, const double* lut, int n_nv, int n_r,
                     int npix, const int* pix, const double* dimg, const double* dalpha,
-                    double* const* dP, double* dmaps) {
+                    double* const* dP, double* dmaps, const double* dcons) {
   Cam c = unpack_cam(cam);
   Opt o = unpack_opt(opt);
   std::vector<Rec<double>> recs(n);
@@ -833,6 +867,7 @@ int orc_render_grad(const float* const* P, int n, const double* cam, const doubl
       for (int ch = 0; ch < 3; ++ch)
         if (ov.img[ch].id >= 0) adj[ov.img[ch].id] += dimg[3 * k + ch];
       if (dalpha && ov.alpha.id >= 0) adj[ov.alpha.id] += dalpha[k];
+      if (dcons && ov.cons.id >= 0) adj[ov.cons.id] += dcons[k];
       tape.sweep(adj);
       for (size_t j = 0; j < cov.size(); ++j) {
         const Rec<Var>& v = vr[j];
