@@ -51,13 +51,13 @@ def lib():
         L.orc_brdf_lut.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.orc_bin_f32.argtypes = [fpp, ctypes.c_int, dp, dp, ip, ctypes.POINTER(ctypes.c_uint32), ip]
         L.orc_render.argtypes = [fpp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp,
-                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, dp, dp, ip, dp]
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, dp, dp, ip, dp, dp]
         L.orc_render_jvp.argtypes = [fpp, ctypes.c_int, fpp, dp, dp, dp, dp, ctypes.c_int, ctypes.c_int,
-                                     dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, dp, dp]
+                                     dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, dp, dp, dp]
         L.orc_render_grad.argtypes = [fpp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp,
-                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, fpp, dp, dp]
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, fpp, dp, dp, dp]
         L.orc_screen_grad.argtypes = [fpp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp,
-                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, dp, dp, ip]
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, dp, dp, ip, dp]
         L.orc_pixel_fragments.restype = ctypes.c_int
         L.orc_pixel_fragments.argtypes = [fpp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp,
                                           ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -72,14 +72,15 @@ class Options:
     gamma: float = 2.0 * math.pi   # eq:alpha, Sec. 3.5.1
     sigma_f: float = 0.1           # pixel prefilter variance (not given by the paper)
     k_max: int = 16                # App. A.1
-    shade: str = "albedo"          # "albedo" | "splitsum"
+    shade: str = "albedo"          # "albedo" | "splitsum" | "normal"
     tile_w: int = 16
     tile_h: int = 16
 
     def pack(self):
         f = lambda x: float(np.float32(x))
         return np.array([f(self.r_cut), f(self.gamma), f(self.sigma_f), self.k_max,
-                         1 if self.shade == "splitsum" else 0, self.tile_w, self.tile_h], np.float64)
+                         {"albedo": 0, "splitsum": 1, "normal": 2}[self.shade], self.tile_w, self.tile_h],
+                        np.float64)
 
 
 def _dptr(a):
@@ -210,11 +211,13 @@ def render(scene, cam, opt: Options, pix, maps=None, lut=None, env_hw=(0, 0)):
     gm = np.zeros(k, np.float64)
     viol = np.zeros(k, np.int32)
     cons = np.zeros(k, np.float64)
+    depth = np.zeros(k, np.float64)
     c, o = pack_camera(cam), opt.pack()
     lib().orc_render(P.pp, P.n, _dptr(c), _dptr(o), _dptr(maps), He, We, _dptr(lut),
                      lut.shape[1], lut.shape[0], k, _iptr(pix), _dptr(img), _dptr(alpha),
-                     _iptr(nl), _dptr(cm), _dptr(gm), _iptr(viol), _dptr(cons))
-    return dict(image=img, alpha=alpha, n_layers=nl, cut_margin=cm, gap_margin=gm, viol=viol, cons=cons)
+                     _iptr(nl), _dptr(cm), _dptr(gm), _iptr(viol), _dptr(cons), _dptr(depth))
+    return dict(image=img, alpha=alpha, n_layers=nl, cut_margin=cm, gap_margin=gm, viol=viol, cons=cons,
+                depth=depth)
 
 
 def render_jvp(scene, cam, opt: Options, pix, direction: dict, maps=None, dmaps=None,
@@ -239,18 +242,20 @@ def render_jvp(scene, cam, opt: Options, pix, direction: dict, maps=None, dmaps=
     img_dot = np.zeros((k, 3), np.float64)
     a_dot = np.zeros(k, np.float64)
     c_dot = np.zeros(k, np.float64)
+    z_dot = np.zeros(k, np.float64)
     c, o = pack_camera(cam), opt.pack()
     lib().orc_render_jvp(P.pp, P.n, ctypes.cast(vp, ctypes.POINTER(ctypes.c_void_p)), _dptr(c), _dptr(o),
                          _dptr(maps), _dptr(dm) if dm is not None else None, He, We, _dptr(lut),
                          lut.shape[1], lut.shape[0], k, _iptr(pix), _dptr(img), _dptr(img_dot), _dptr(a_dot),
-                         _dptr(c_dot))
-    return dict(image=img, image_dot=img_dot, alpha_dot=a_dot, cons_dot=c_dot)
+                         _dptr(c_dot), _dptr(z_dot))
+    return dict(image=img, image_dot=img_dot, alpha_dot=a_dot, cons_dot=c_dot, depth_dot=z_dot)
 
 
 def render_grad(scene, cam, opt: Options, pix, dimage, dalpha=None, maps=None, lut=None,
-                env_hw=(0, 0), dcons=None):
-    """Adjoint at the listed pixels (loss weights dimage [K][3], dalpha [K] and
-    dcons [K] on the depth-consolidation term): returns dict of parameter
+                env_hw=(0, 0), dcons=None, ddepth=None):
+    """Adjoint at the listed pixels (loss weights dimage [K][3], dalpha [K],
+    dcons [K] on the depth-consolidation term and ddepth [K] on the composited
+    depth): returns dict of parameter
     gradients (float64, parameter shapes) and `maps` (gradient w.r.t. the flat
     map set)."""
     P = _Params(scene)
@@ -264,19 +269,20 @@ def render_grad(scene, cam, opt: Options, pix, dimage, dalpha=None, maps=None, l
     gp = (ctypes.c_void_p * 7)(*[g.ctypes.data for g in grads])
     dmaps = np.zeros(maps.size, np.float64)
     dc = None if dcons is None else np.ascontiguousarray(dcons, np.float64).reshape(k)
+    dz = None if ddepth is None else np.ascontiguousarray(ddepth, np.float64).reshape(k)
     c, o = pack_camera(cam), opt.pack()
     lib().orc_render_grad(P.pp, n, _dptr(c), _dptr(o), _dptr(maps), He, We, _dptr(lut),
                           lut.shape[1], lut.shape[0], k, _iptr(pix), _dptr(dimage),
                           _dptr(da) if da is not None else None,
                           ctypes.cast(gp, ctypes.POINTER(ctypes.c_void_p)), _dptr(dmaps),
-                          _dptr(dc) if dc is not None else None)
+                          _dptr(dc) if dc is not None else None, _dptr(dz) if dz is not None else None)
     out = dict(zip(PARAM_NAMES, grads))
     out["maps"] = dmaps
     return out
 
 
 def screen_grad(scene, cam, opt: Options, pix, dimage, dalpha=None, maps=None, lut=None,
-                env_hw=(0, 0)):
+                env_hw=(0, 0), dcons=None):
     """Densification statistic (Sec. 3.6.1, eq:ss_grad) at the listed pixels:
     per surfel, `abs` = sum over pixels of |(dL_p/dT1z, dL_p/dT2z)| T4z, `vec` =
     the plain sum of those vectors ([2, n]), `visible` = culled-in with a
@@ -291,10 +297,12 @@ def screen_grad(scene, cam, opt: Options, pix, dimage, dalpha=None, maps=None, l
     a = np.zeros(n, np.float64)
     vec = np.zeros((2, n), np.float64)
     vis = np.zeros(n, np.int32)
+    dc = None if dcons is None else np.ascontiguousarray(dcons, np.float64).reshape(k)
     c, o = pack_camera(cam), opt.pack()
     lib().orc_screen_grad(P.pp, n, _dptr(c), _dptr(o), _dptr(maps), He, We, _dptr(lut),
                           lut.shape[1], lut.shape[0], k, _iptr(pix), _dptr(dimage),
-                          _dptr(da) if da is not None else None, _dptr(a), _dptr(vec), _iptr(vis))
+                          _dptr(da) if da is not None else None, _dptr(a), _dptr(vec), _iptr(vis),
+                          None if dc is None else _dptr(dc))
     return dict(abs=a, vec=vec, visible=vis.astype(bool))
 
 

@@ -424,6 +424,10 @@ static void preprocess(const Surf<S>& s, const Cam& cam, const Opt& o, const M& 
     for (int c = 0; c < 3; ++c) r.col[c] = s.alb[c];
     return;
   }
+  if (o.shade == 2) {  // normal image: the world-space unit normal is the attribute
+    for (int c = 0; c < 3; ++c) r.col[c] = nh[c];
+    return;
+  }
   // camera centre in world space: o = -R^T t
   double oc[3];
   for (int j = 0; j < 3; ++j)
@@ -544,7 +548,9 @@ static BinOut bin_f32(const float* const* P, int n, int i, const Cam& cd, const 
 template <class S> struct Frag { double zs; int idx; S w; S ze; const Rec<S>* r; S z; };
 // cons: the pixel's depth-consolidation term (eq:cons_loss), inter-layer plus
 // intra-layer part, over the composited layers.
-template <class S> struct PixOut { S img[3]; S alpha; S cons; int nl; };
+// depth: the composited layer depth sum_k T_k alpha_k z_k (alpha-weighted; the
+// background contributes nothing).
+template <class S> struct PixOut { S img[3]; S alpha; S cons; S depth; int nl; };
 struct PixDiag { double cut_margin, gap_margin; int viol; };
 
 // zf (nullable): camera-space depth of the ray-surfel intersection,
@@ -579,6 +585,7 @@ static void pixel_eval(double x, double y, const Rec<S>* recs, const std::vector
                        std::vector<int>* covering, std::vector<int>* layer_of = nullptr,
                        std::vector<double>* wout = nullptr) {
   using std::exp;
+  using std::sqrt;
   const double rc2 = o.r_cut * o.r_cut;
   std::vector<Frag<S>> fr;
   double cm = INFINITY;
@@ -609,7 +616,14 @@ static void pixel_eval(double x, double y, const Rec<S>* recs, const std::vector
   std::vector<S> lw, lz, lv;
   auto flush = [&]() {
     S a = 1.0 - exp(-kappa * Wg);
-    for (int c = 0; c < 3; ++c) Cout[c] += Tb * a * (Cg[c] / Wg);
+    if (o.shade == 2) {
+      // normal image (Sec. 4.2.3): the Shepard mean of the unit normals,
+      // renormalised to unit length, per layer
+      S nrm = sqrt(Cg[0] * Cg[0] + Cg[1] * Cg[1] + Cg[2] * Cg[2]);
+      for (int c = 0; c < 3; ++c) Cout[c] += Tb * a * (Cg[c] / nrm);
+    } else {
+      for (int c = 0; c < 3; ++c) Cout[c] += Tb * a * (Cg[c] / Wg);
+    }
     S zm(0.0), var(0.0);
     for (const Frag<S>* f : members) zm += f->w * f->z;
     zm = zm / Wg;
@@ -653,6 +667,9 @@ static void pixel_eval(double x, double y, const Rec<S>* recs, const std::vector
     cons += lw[i] * lw[i] * lv[i];
   }
   out.cons = cons;
+  S depth(0.0);
+  for (int i = 0; i < K; ++i) depth += lw[i] * lz[i];
+  out.depth = depth;
   out.nl = K;
   if (dg) { dg->cut_margin = cm; dg->gap_margin = gm; }
 }
@@ -720,11 +737,12 @@ int orc_bin_f32(const float* const* P, int n, const double* cam, const double* o
 // Outputs per listed pixel: image [3], alpha, layer count, decision margins
 // (cutoff |q - r^2|/r^2 and gap |z_start - z_max|/z_max, minimum over the
 // pixel), the number of covering fragments outside the FP32 tile rectangle and
-// (cons, nullable) the depth-consolidation term of eq:cons_loss.
+// (cons, nullable) the depth-consolidation term of eq:cons_loss and (depth,
+// nullable) the composited depth sum_k T_k alpha_k z_k.
 int orc_render(const float* const* P, int n, const double* cam, const double* opt,
                const double* maps, int He, int We, const double* lut, int n_nv, int n_r,
                int npix, const int* pix, double* img, double* alpha, int* nl,
-               double* cut_margin, double* gap_margin, int* viol, double* cons) {
+               double* cut_margin, double* gap_margin, int* viol, double* cons, double* depth) {
   Cam c = unpack_cam(cam);
   Opt o = unpack_opt(opt);
   std::vector<Rec<double>> recs(n);
@@ -762,17 +780,20 @@ int orc_render(const float* const* P, int n, const double* cam, const double* op
     gap_margin[k] = dg.gap_margin;
     viol[k] = v;
     if (cons) cons[k] = out.cons;
+    if (depth) depth[k] = out.depth;
   }
   return 0;
 }
 
 // Directional derivative (exact, dual numbers) of the listed pixels' image,
-// alpha and (cons_dot, nullable) depth-consolidation term along the parameter
+// alpha, (cons_dot, nullable) depth-consolidation term and (depth_dot, nullable)
+// composited depth along the parameter
 // direction V (7 arrays, NULL = 0) and the map-set direction dmaps (NULL = 0).
 int orc_render_jvp(const float* const* P, int n, const double* const* V, const double* cam,
                    const double* opt, const double* maps, const double* dmaps, int He, int We,
                    const double* lut, int n_nv, int n_r, int npix, const int* pix,
-                   double* img, double* img_dot, double* alpha_dot, double* cons_dot) {
+                   double* img, double* img_dot, double* alpha_dot, double* cons_dot,
+                   double* depth_dot) {
   Cam c = unpack_cam(cam);
   Opt o = unpack_opt(opt);
   std::vector<Rec<Dual>> recs(n);
@@ -796,19 +817,21 @@ int orc_render_jvp(const float* const* P, int n, const double* const* V, const d
     for (int ch = 0; ch < 3; ++ch) { img[3 * k + ch] = out.img[ch].v; img_dot[3 * k + ch] = out.img[ch].d; }
     alpha_dot[k] = out.alpha.d;
     if (cons_dot) cons_dot[k] = out.cons.d;
+    if (depth_dot) depth_dot[k] = out.depth.d;
   }
   return 0;
 }
 
-// Adjoint.  Given dL/dimage [npix][3], dL/dalpha [npix] (nullable) and dL/dcons
-// [npix] (nullable; cons = eq:cons_loss per pixel) at the listed pixels, accumulate dL/dparams (7 arrays, [C][n] double, overwritten)
+// Adjoint.  Given dL/dimage [npix][3], dL/dalpha [npix] (nullable), dL/dcons
+// [npix] (nullable; cons = eq:cons_loss per pixel) and dL/ddepth [npix]
+// (nullable) at the listed pixels, accumulate dL/dparams (7 arrays, [C][n] double, overwritten)
 // and dL/dmaps (flat map set, overwritten; the environment itself is then
 // reached through orc_envmap_adjoint).  Reverse mode on a tape, per pixel for
 // the rasterisation and per surfel for preprocessing and shading.
 int orc_render_grad(const float* const* P, int n, const double* cam, const double* opt,
                     const double* maps, int He, int We, const double* lut, int n_nv, int n_r,
                     int npix, const int* pix, const double* dimg, const double* dalpha,
-                    double* const* dP, double* dmaps, const double* dcons) {
+                    double* const* dP, double* dmaps, const double* dcons, const double* ddepth) {
   Cam c = unpack_cam(cam);
   Opt o = unpack_opt(opt);
   std::vector<Rec<double>> recs(n);
@@ -868,6 +891,7 @@ int orc_render_grad(const float* const* P, int n, const double* cam, const doubl
         if (ov.img[ch].id >= 0) adj[ov.img[ch].id] += dimg[3 * k + ch];
       if (dalpha && ov.alpha.id >= 0) adj[ov.alpha.id] += dalpha[k];
       if (dcons && ov.cons.id >= 0) adj[ov.cons.id] += dcons[k];
+      if (ddepth && ov.depth.id >= 0) adj[ov.depth.id] += ddepth[k];
       tape.sweep(adj);
       for (size_t j = 0; j < cov.size(); ++j) {
         const Rec<Var>& v = vr[j];
@@ -940,7 +964,8 @@ int orc_render_grad(const float* const* P, int n, const double* cam, const doubl
 }
 
 // Densification statistic (Sec. 3.6.1, eq:ss_grad).  For each listed pixel p
-// with loss L_p = dimg_p . image_p + dalpha_p alpha_p and each surfel i that
+// with loss L_p = dimg_p . image_p + dalpha_p alpha_p (+ dcons_p cons_p, the
+// depth-consolidation term, when dcons is given) and each surfel i that
 // reaches p, the screen-space positional gradient is
 //   g = (dL_p/dT1z * T4z, dL_p/dT2z * T4z),
 // with the whole pixel evaluation, MIP filter included, differentiated as a
@@ -952,7 +977,7 @@ int orc_render_grad(const float* const* P, int n, const double* cam, const doubl
 int orc_screen_grad(const float* const* P, int n, const double* cam, const double* opt,
                     const double* maps, int He, int We, const double* lut, int n_nv, int n_r,
                     int npix, const int* pix, const double* dimg, const double* dalpha,
-                    double* abs_sum, double* vec_sum, int* visible) {
+                    double* abs_sum, double* vec_sum, int* visible, const double* dcons) {
   Cam c = unpack_cam(cam);
   Opt o = unpack_opt(opt);
   std::vector<Rec<double>> recs(n);
@@ -1003,6 +1028,7 @@ int orc_screen_grad(const float* const* P, int n, const double* cam, const doubl
       for (int ch = 0; ch < 3; ++ch)
         if (ov.img[ch].id >= 0) adj[ov.img[ch].id] += dimg[3 * k + ch];
       if (dalpha && ov.alpha.id >= 0) adj[ov.alpha.id] += dalpha[k];
+      if (dcons && ov.cons.id >= 0) adj[ov.cons.id] += dcons[k];
       tape.sweep(adj);
       for (size_t j = 0; j < cov.size(); ++j) {
         const int i = cov[j];
