@@ -61,7 +61,10 @@ typedef enum ss_status {
 
 typedef enum ss_shade_mode {
   SS_SHADE_ALBEDO = 0,   /* colour = albedo                                      */
-  SS_SHADE_SPLITSUM = 1  /* split-sum microfacet IBL, eq:ibl                     */
+  SS_SHADE_SPLITSUM = 1, /* split-sum microfacet IBL, eq:ibl                     */
+  SS_SHADE_NORMAL = 2    /* normal image (Sec. 4.2.3): the attribute is the world-space
+                            unit normal, and each layer's Shepard mean is renormalised
+                            to unit length before compositing                     */
 } ss_shade_mode;
 
 typedef enum ss_launch_mode {
@@ -80,6 +83,9 @@ typedef struct ss_options {
   int32_t lds_batch; /* surfels staged per LDS batch: 32, 64, 128 or 256         */
   int32_t launch;    /* ss_launch_mode                                            */
   int32_t persistent; /* 1: raster blocks pull (view, tile) items from a queue   */
+  int32_t depth_stats; /* 1: reserve per-layer depth statistics (8 bytes x 16 layers
+                          per pixel) so that forwards may output the
+                          depth-consolidation term (ss_outputs.cons)            */
 } ss_options;
 
 typedef struct ss_camera {
@@ -112,11 +118,25 @@ typedef struct ss_outputs {
   float* image;       /* device [sum HW][3], written */
   float* alpha;       /* device [sum HW], written    */
   uint8_t* n_layers;  /* device [sum HW] or NULL: layers composited per pixel */
+  /* device [sum HW] or NULL: per-pixel depth-consolidation term of eq:cons_loss
+   * (Sec. 3.7.1), sum_{i<j} w_i w_j |z_i - z_j| + sum_i w_i^2 var_i over the
+   * composited layers, w_i = T_i alpha_i, z_i and var_i the Shepard-weighted
+   * mean and variance of the layer's fragment depths (camera-space z of the
+   * ray-surfel intersection).  The 1/|P| mean and the loss weight are the
+   * caller's.  Needs options.depth_stats = 1 (else SS_ERR_INVALID_ARG). */
+  float* cons;
+  /* device [sum HW] or NULL: composited depth sum_k T_k alpha_k z_k with z_k the
+   * layer's mean depth as above (divide by alpha for the expected depth of the
+   * covered part).  Needs options.depth_stats = 1. */
+  float* depth;
 } ss_outputs;
 
 typedef struct ss_grad_in {
   const float* d_image; /* device [sum HW][3]: dL/dimage                       */
   const float* d_alpha; /* device [sum HW] or NULL: dL/dalpha                  */
+  const float* d_cons;  /* device [sum HW] or NULL: dL/dcons; needs the last forward to
+                           have written cons or depth (else SS_ERR_STATE)       */
+  const float* d_depth; /* device [sum HW] or NULL: dL/ddepth; same condition  */
 } ss_grad_in;
 
 typedef struct ss_grads { /* every pointer may be NULL (skip); outputs are overwritten */
@@ -128,6 +148,18 @@ typedef struct ss_grads { /* every pointer may be NULL (skip); outputs are overw
   float* d_roughness; /* device [N]    */
   float* d_metallic;  /* device [N]    */
   float* const* d_envmap; /* host [n_scenes] of device [H_e][W_e][3], or NULL */
+  /* Densification statistic (Sec. 3.6.1, eq:ss_grad): for every pixel p of
+   * every view and every surfel whose fragment reaches p, the per-pixel
+   * screen-space positional gradient g = (dL_p/dT1z, dL_p/dT2z) T4z, with L_p
+   * the pixel's share of the loss (d_image . image + d_alpha alpha) and T1z,
+   * T2z, T4z the z entries of the surfel's T rows in that view (the MIP filter
+   * differentiated with them).  screen_grad[s] = sum over views and pixels of
+   * |g| (summation order not fixed).  visible_views[s] = number of views in
+   * which the surfel passes the cull with a non-empty tile rectangle; the
+   * paper's criterion is screen_grad / visible_views.  Both device [N], NULL to
+   * skip; computing screen_grad adds work to the raster backward. */
+  float* screen_grad;
+  int32_t* visible_views;
 } ss_grads;
 
 typedef struct ss_diag {

@@ -82,12 +82,13 @@ struct ss_context {
   std::vector<Group> groups;
   std::vector<SceneEnv> env;
   DevBuf views_d, recs, counts, offsets, scan_tmp, keys, vals, keys2, vals2, hist, ranges, nl, stats,
-      grad, misc, partial;
+      grad, misc, partial, sg, order, stats2;
   std::vector<long long> soff;
   long long scan_tmp_n = 0, pair_total = 0;
   DevBuf lut;
   int lut_nv = 0, lut_r = 0;
   bool fwd_valid = false;
+  bool fwd_cons = false;  // the last forward wrote the per-layer depth statistics
   std::vector<long long> fwd_sig;
   hipStream_t last_stream = nullptr;  // may be the null stream
   bool used = false;                  // a stream call has been made
@@ -116,12 +117,14 @@ ss_status check_options(const ss_options* o) {
   if (!o) return SS_ERR_INVALID_ARG;
   if (!(o->r_cut > 0.f) || !(o->gamma > 0.f) || !(o->sigma_f >= 0.f)) return SS_ERR_INVALID_ARG;
   if (o->k_max < 1 || o->k_max > kMaxLayers) return SS_ERR_INVALID_ARG;
-  if (o->shade != SS_SHADE_ALBEDO && o->shade != SS_SHADE_SPLITSUM) return SS_ERR_INVALID_ARG;
+  if (o->shade != SS_SHADE_ALBEDO && o->shade != SS_SHADE_SPLITSUM && o->shade != SS_SHADE_NORMAL)
+    return SS_ERR_INVALID_ARG;
   const int tk = o->tile_w * 100 + o->tile_h;
   if (tk != 808 && tk != 1608 && tk != 1616 && tk != 3208 && tk != 3216) return SS_ERR_UNSUPPORTED;
   if (o->lds_batch != 32 && o->lds_batch != 64 && o->lds_batch != 128 && o->lds_batch != 256)
     return SS_ERR_UNSUPPORTED;
   if (o->launch != SS_LAUNCH_BATCHED && o->launch != SS_LAUNCH_PER_VIEW) return SS_ERR_INVALID_ARG;
+  if (o->depth_stats != 0 && o->depth_stats != 1) return SS_ERR_INVALID_ARG;
   return SS_OK;
 }
 
@@ -191,6 +194,8 @@ Params make_params(const ss_context* c) {
   p.lut = reinterpret_cast<const float*>(c->lut.p);
   p.lut_nv = c->lut_nv;
   p.lut_r = c->lut_r;
+  p.ss_grad = 0;
+  p.cons = 0;
   return p;
 }
 
@@ -275,7 +280,7 @@ ss_status prepare_env(ss_context* c, const ss_batch* b, hipStream_t st) {
       e.loc_off[l] = e.loc_total;
       e.loc_total += n;
     }
-    SS_HIP(ensure(c->partial, (size_t)kBackwardBlocks * kLocalMapFloats * sizeof(float)));
+    SS_HIP(ensure(c->partial, (size_t)(kBackwardBlocks + kReduceSplit) * kLocalMapFloats * sizeof(float)));
     SS_HIP(ensure(e.lv, lv_n * sizeof(float)));
     SS_HIP(ensure(e.dlv, d * sizeof(float)));
     SS_HIP(ensure(e.Z, (size_t)(lv_n / 3 + 1) * 4 * sizeof(float)));
@@ -381,8 +386,12 @@ ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
   SS_HIP(ensure(c->scan_tmp, (size_t)c->scan_tmp_n * sizeof(uint32_t)));
   SS_HIP(ensure(c->ranges, (size_t)2 * (c->n_tiles > 0 ? c->n_tiles : 1) * sizeof(uint32_t)));
   SS_HIP(ensure(c->nl, (size_t)(c->n_pix > 0 ? c->n_pix : 1)));
+  SS_HIP(ensure(c->order, (size_t)(c->n_tiles > 0 ? c->n_tiles : 1) * sizeof(int)));
   SS_HIP(ensure(c->stats, (size_t)(c->n_pix > 0 ? c->n_pix : 1) * kMaxLayers * sizeof(float4)));
-  SS_HIP(ensure(c->grad, (size_t)R * kNGrad * sizeof(float)));
+  if (c->opt.depth_stats)
+    SS_HIP(ensure(c->stats2, (size_t)(c->n_pix > 0 ? c->n_pix : 1) * kMaxLayers * sizeof(float2)));
+  SS_HIP(ensure(c->grad, (size_t)R * kGradStride * sizeof(float)));
+  if (c->opt.shade == SS_SHADE_SPLITSUM) SS_HIP(ensure(c->sg, (size_t)R * 12 * sizeof(float)));
   SS_TRY(upload_views(c, b, st));
   // count the pairs once
   SS_TRY(run_envmap_prefilter(c, b, st));
@@ -452,7 +461,7 @@ enum { ST_ENV = 0, ST_PRE, ST_BIN, ST_RFWD, ST_RBWD, ST_PREBWD, ST_ENVBWD };
 size_t workspace_bytes(const ss_context* c) {
   size_t s = c->views_d.n + c->recs.n + c->counts.n + c->offsets.n + c->scan_tmp.n + c->keys.n +
              c->vals.n + c->keys2.n + c->vals2.n + c->hist.n + c->ranges.n + c->nl.n + c->stats.n +
-             c->grad.n + c->misc.n + c->lut.n + c->partial.n;
+             c->grad.n + c->misc.n + c->lut.n + c->partial.n + c->sg.n + c->order.n + c->stats2.n;
   for (const SceneEnv& e : c->env) s += e.dirs.n + e.lv.n + e.Z.n + e.dlv.n;
   return s;
 }
@@ -473,6 +482,7 @@ ss_status ss_default_options(ss_options* o) {
   o->lds_batch = 128;
   o->launch = SS_LAUNCH_BATCHED;
   o->persistent = 1;
+  o->depth_stats = 0;
   return SS_OK;
 }
 
@@ -492,7 +502,7 @@ ss_status ss_destroy(ss_context* c) {
   if (c->used) (void)hipStreamSynchronize(c->last_stream);
   DevBuf* bufs[] = {&c->views_d, &c->recs, &c->counts, &c->offsets, &c->scan_tmp, &c->keys,
                     &c->vals, &c->keys2, &c->vals2, &c->hist, &c->ranges, &c->nl, &c->stats,
-                    &c->grad, &c->misc, &c->lut, &c->partial};
+                    &c->grad, &c->misc, &c->lut, &c->partial, &c->sg, &c->order, &c->stats2};
   for (DevBuf* b : bufs) release(*b);
   for (SceneEnv& e : c->env) { release(e.dirs); release(e.lv); release(e.Z); release(e.dlv); }
   for (auto& pe : c->prof_ev) { c->ev_pool.push_back(pe.second.first); c->ev_pool.push_back(pe.second.second); }
@@ -544,6 +554,7 @@ ss_status ss_reserve(ss_context* c, const ss_batch* b, ss_stream stream, size_t*
 
 ss_status ss_render(ss_context* c, const ss_batch* b, const ss_outputs* out, ss_stream stream) {
   if (!c || !out || !out->image || !out->alpha) return SS_ERR_INVALID_ARG;
+  if ((out->cons || out->depth) && !c->opt.depth_stats) return SS_ERR_INVALID_ARG;
   SS_TRY(check_batch(c, b));
   if (c->opt.shade == SS_SHADE_SPLITSUM && !c->lut.p) return SS_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;
@@ -557,7 +568,8 @@ ss_status ss_render(ss_context* c, const ss_batch* b, const ss_outputs* out, ss_
   hipEvent_t t0 = prof_begin(c, st);
   SS_TRY(run_envmap_prefilter(c, b, st));
   prof_end(c, t0, ST_ENV, st);
-  const Params prm = make_params(c);
+  Params prm = make_params(c);
+  prm.cons = (out->cons || out->depth) ? 1 : 0;
   int* status = reinterpret_cast<int*>(misc + kMiscStatus);
   for (size_t gi = 0; gi < c->groups.size(); ++gi) {
     const Group& g = c->groups[gi];
@@ -582,6 +594,11 @@ ss_status ss_render(ss_context* c, const ss_batch* b, const ss_outputs* out, ss_
                              &in_tmp));
     if (in_tmp) return SS_ERR_HIP;  // even pass counts by construction
     SS_HIP(launch_tile_ranges(keys, np, g.pair_cap, P<uint32_t>(c->ranges), g.tile_base, g.n_tiles, st));
+    int* order = nullptr;
+    if (c->opt.persistent) {
+      order = P<int>(c->order) + g.tile_base;
+      SS_HIP(launch_tile_order(P<uint32_t>(c->ranges), g.tile_base, g.n_tiles, order, st));
+    }
     prof_end(c, t0, ST_BIN, st);
     SS_HIP(launch_fill_u32(misc + kMiscQueue, 0u, 1, st));
     t0 = prof_begin(c, st);
@@ -589,11 +606,13 @@ ss_status ss_render(ss_context* c, const ss_batch* b, const ss_outputs* out, ss_
                                  g.tile_base + g.n_tiles, P<uint32_t>(c->ranges), vals,
                                  P<float>(c->recs), prm, c->opt.lds_batch, out->image, out->alpha,
                                  out->n_layers, P<uint8_t>(c->nl), P<float4>(c->stats),
-                                 reinterpret_cast<int*>(misc + kMiscQueue), nullptr,
+                                 P<float2>(c->stats2), out->cons, out->depth,
+                                 reinterpret_cast<int*>(misc + kMiscQueue), order,
                                  c->opt.persistent, st));
     prof_end(c, t0, ST_RFWD, st);
   }
   c->fwd_valid = true;
+  c->fwd_cons = prm.cons != 0;
   c->fwd_sig = c->sig;
   return SS_OK;
 }
@@ -603,13 +622,16 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
   if (!c || !gin || !gin->d_image || !gr) return SS_ERR_INVALID_ARG;
   SS_TRY(check_batch(c, b));
   if (!c->fwd_valid || signature(c, b) != c->fwd_sig) return SS_ERR_STATE;
+  if ((gin->d_cons || gin->d_depth) && !c->fwd_cons) return SS_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;
   c->last_stream = st;
   c->used = true;
   SS_TRY(upload_views(c, b, st));
-  const Params prm = make_params(c);
+  Params prm = make_params(c);
+  prm.ss_grad = gr->screen_grad ? 1 : 0;
+  prm.cons = (gin->d_cons || gin->d_depth) ? 1 : 0;
   uint32_t* misc = P<uint32_t>(c->misc);
-  SS_HIP(launch_fill_f32(P<float>(c->grad), 0.f, (long long)c->R * kNGrad, st));
+  SS_HIP(launch_fill_f32(P<float>(c->grad), 0.f, (long long)c->R * kGradStride, st));
   if (c->opt.shade == SS_SHADE_SPLITSUM)
     for (SceneEnv& e : c->env) SS_HIP(launch_fill_f32(P<float>(e.dlv), 0.f, (long long)(e.dlv.n / 4), st));
   for (size_t gi = 0; gi < c->groups.size(); ++gi) {
@@ -620,8 +642,10 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
                                   g.tile_base + g.n_tiles, P<uint32_t>(c->ranges),
                                   P<uint32_t>(c->vals) + g.pair_base, P<float>(c->recs), prm,
                                   c->opt.lds_batch, gin->d_image, gin->d_alpha, P<uint8_t>(c->nl),
-                                  P<float4>(c->stats), P<float>(c->grad), c->R,
-                                  reinterpret_cast<int*>(misc + kMiscQueue), nullptr,
+                                  P<float4>(c->stats), P<float2>(c->stats2), gin->d_cons, gin->d_depth,
+                                  P<float>(c->grad), c->R,
+                                  reinterpret_cast<int*>(misc + kMiscQueue),
+                                  c->opt.persistent ? P<int>(c->order) + g.tile_base : nullptr,
                                   c->opt.persistent, st));
     prof_end(c, t0, ST_RBWD, st);
   }
@@ -635,16 +659,17 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
       SceneEnv& e = c->env[s];
       float* lg[7];
       for (int l = 0; l < 7; ++l) lg[l] = P<float>(e.dlv) + e.doff[l];
-      SS_HIP(launch_preprocess_backward(pp, c->N, P<ViewDev>(c->views_d), c->n_views, c->soff[s],
-                                        c->soff[s + 1], e.loc_off, e.loc_total, P<float>(c->partial),
-                                        lg, prm, P<float>(c->grad), c->R, G, st));
+      std::vector<int> sv;
+      for (int v = 0; v < c->n_views; ++v)
+        if (c->views_h[v].scene == s) sv.push_back(v);
+      SS_HIP(launch_shade_backward(pp, c->N, P<ViewDev>(c->views_d), sv.data(), (int)sv.size(), c->soff[s],
+                                   (int)(c->soff[s + 1] - c->soff[s]), e.loc_off, e.loc_total,
+                                   P<float>(c->partial), lg, prm, P<float>(c->grad), P<float>(c->sg), st));
     }
-  } else {
-    const int no[7] = {-1, -1, -1, -1, -1, -1, -1};
-    float* lg[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    SS_HIP(launch_preprocess_backward(pp, c->N, P<ViewDev>(c->views_d), c->n_views, 0, c->N, no, 0,
-                                      nullptr, lg, prm, P<float>(c->grad), c->R, G, st));
   }
+  SS_HIP(launch_geometry_backward(pp, c->N, P<ViewDev>(c->views_d), c->n_views, prm, P<float>(c->grad),
+                                  P<float>(c->sg), G, P<float>(c->recs), gr->screen_grad,
+                                  gr->visible_views, st));
   prof_end(c, t1, ST_PREBWD, st);
   t1 = prof_begin(c, st);
   if (c->opt.shade == SS_SHADE_SPLITSUM && gr->d_envmap) {

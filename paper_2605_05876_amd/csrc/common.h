@@ -21,9 +21,15 @@ enum RecField {
   R_ZS, R_ID /* record index, as bits */
 };
 constexpr int kRecFloats = 16;
-// Gradient slots per record, written by the raster backward (SoA [kNGrad][R]).
-enum GradField { G_X0 = 0, G_Y0, G_QXX, G_QXY2, G_QYY, G_A3, G_B3, G_NF, G_CR, G_CG, G_CB };
+// Gradient slots per record, written by the raster backward.  Layout
+// [R][kGradStride]: the 11 values of one record share one 64-byte line, so the
+// atomics a wave issues for one record touch a single line.  Slot G_SS holds
+// the densification statistic (sum over pixels of |(dL_p/dT1z, dL_p/dT2z)| T4z,
+// Sec. 3.6.1) when it is requested; slot G_TZ the gradient with respect to
+// T4z = c'_z through the fragment depths of the depth-consolidation term.
+enum GradField { G_X0 = 0, G_Y0, G_QXX, G_QXY2, G_QYY, G_A3, G_B3, G_NF, G_CR, G_CG, G_CB, G_SS, G_TZ };
 constexpr int kNGrad = 11;
+constexpr int kGradStride = 16;
 
 // ---------------------------------------------------------------- views
 struct ViewDev {
@@ -51,6 +57,8 @@ struct Params {
   int k_max, shade, tile_w, tile_h;
   const float* lut;
   int lut_nv, lut_r;
+  int ss_grad;  // backward: accumulate the screen-space gradient statistic in slot G_SS
+  int cons;     // forward: depth statistics (eq:cons_loss, depth image); backward: their adjoint
 };
 
 // ---------------------------------------------------------------- FP32 binning
@@ -204,14 +212,19 @@ hipError_t launch_preprocess(const float* const P[7], long long N, const ViewDev
                              int v1, int max_surf, const Params& prm, float* recs,
                              uint32_t* counts, hipStream_t st);
 constexpr int kBackwardBlocks = 512;       // blocks of the surfel adjoint (per scene)
+constexpr int kBackwardThreads = 512;      // threads per block of the surfel adjoint
 constexpr int kLocalMapFloats = 16384;     // LDS budget for privatised environment levels
-int backward_blocks(long long n_surf);
-hipError_t launch_preprocess_backward(const float* const P[7], long long N, const ViewDev* views,
-                                      int n_views, long long s_begin, long long s_end,
-                                      const int local_off[7], int local_total, float* partial,
-                                      float* const level_grad[7], const Params& prm,
-                                      const float* grad, long long R, float* const G[7],
-                                      hipStream_t st);
+constexpr int kReduceSplit = 32;           // first-stage chunks of the partial reduction
+int backward_blocks(long long n_items);
+hipError_t launch_shade_backward(const float* const P[7], long long N, const ViewDev* views,
+                                 const int* scene_views, int n_scene_views, long long surf_off,
+                                 int n_surf, const int local_off[7], int local_total, float* partial,
+                                 float* const level_grad[7], const Params& prm, const float* grad,
+                                 float* sg, hipStream_t st);
+hipError_t launch_geometry_backward(const float* const P[7], long long N, const ViewDev* views,
+                                    int n_views, const Params& prm, const float* grad,
+                                    const float* sg, float* const G[7], const float* recs,
+                                    float* ss_out, int* vis_out, hipStream_t st);
 
 hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint32_t* total,
                            uint32_t* tmp, long long tmp_n, hipStream_t st);
@@ -227,18 +240,21 @@ hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp,
 hipError_t launch_tile_ranges(const uint64_t* keys, const uint32_t* n_pairs, long long cap,
                               uint32_t* ranges, int tile_begin, int n_tiles, hipStream_t st);
 
+hipError_t launch_tile_order(const uint32_t* ranges, int tile_begin, int n_tiles, int* order, hipStream_t st);
 hipError_t launch_raster_forward(const ViewDev* views, int n_views, int tile_begin, int tile_end,
                                  const uint32_t* ranges, const uint32_t* sorted_vals,
                                  const float* recs, const Params& prm, int lds_batch,
                                  float* image, float* alpha, uint8_t* n_layers_out,
-                                 uint8_t* n_layers, float4* layer_stats, int* queue,
-                                 const int* order, int persistent, hipStream_t st);
+                                 uint8_t* n_layers, float4* layer_stats, float2* layer_stats2,
+                                 float* cons, float* depth, int* queue, const int* order,
+                                 int persistent, hipStream_t st);
 hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_begin, int tile_end,
                                   const uint32_t* ranges, const uint32_t* sorted_vals,
                                   const float* recs, const Params& prm, int lds_batch,
                                   const float* d_image, const float* d_alpha,
                                   const uint8_t* n_layers, const float4* layer_stats,
-                                  float* grad, long long R, int* queue, const int* order,
-                                  int persistent, hipStream_t st);
+                                  const float2* layer_stats2, const float* d_cons,
+                                  const float* d_depth, float* grad, long long R, int* queue,
+                                  const int* order, int persistent, hipStream_t st);
 
 }  // namespace ss

@@ -49,37 +49,6 @@ __device__ inline void latlong_fetch(const float* m, int W, const LatLong& L, fl
     out[c] = (1.f - L.fa) * ((1.f - L.fb) * t00[c] + L.fb * t01[c]) +
              L.fa * ((1.f - L.fb) * t10[c] + L.fb * t11[c]);
 }
-// Adjoint of the bilinear lat-long lookup: scatters texel gradients into dm
-// and accumulates the gradient with respect to the (not necessarily unit)
-// direction d into gd.
-__device__ inline void latlong_backward(const float* m, float* dm, int H, int W, const float d[3],
-                                        const LatLong& L, const float g[3], float gd[3]) {
-  const int o00 = 3 * (L.r0 * W + L.c0), o01 = 3 * (L.r0 * W + L.c1);
-  const int o10 = 3 * (L.r1 * W + L.c0), o11 = 3 * (L.r1 * W + L.c1);
-  float ga = 0.f, gb = 0.f;
-  for (int c = 0; c < 3; ++c) {
-    float v00 = m[o00 + c], v01 = m[o01 + c], v10 = m[o10 + c], v11 = m[o11 + c];
-    ga += g[c] * ((1.f - L.fb) * (v10 - v00) + L.fb * (v11 - v01));
-    gb += g[c] * ((1.f - L.fa) * (v01 - v00) + L.fa * (v11 - v10));
-    if (dm != nullptr && g[c] != 0.f) {
-      atomicAdd(dm + o00 + c, g[c] * (1.f - L.fa) * (1.f - L.fb));
-      atomicAdd(dm + o01 + c, g[c] * (1.f - L.fa) * L.fb);
-      atomicAdd(dm + o10 + c, g[c] * L.fa * (1.f - L.fb));
-      atomicAdd(dm + o11 + c, g[c] * L.fa * L.fb);
-    }
-  }
-  float gth = ga * ((float)H / kPi);
-  float gph = gb * ((float)W / (2.f * kPi));
-  if (L.rho > 1e-20f && L.den > 0.f) {
-    // th = atan2(rho, z), ph = atan2(y, x), rho = sqrt(x^2 + y^2)
-    float dth_drho = d[2] / L.den, dth_dz = -L.rho / L.den;
-    float r2 = L.rho * L.rho;
-    gd[0] += gth * dth_drho * d[0] / L.rho - gph * d[1] / r2;
-    gd[1] += gth * dth_drho * d[1] / L.rho + gph * d[0] / r2;
-    gd[2] += gth * dth_dz;
-  }
-}
-
 struct LutTap { int i0, j0; float fx, fy; };
 __device__ inline void lut_fetch(const Params& P, float nv, float r, LutTap& T, float beta[2]) {
   float x = nv * (float)(P.lut_nv - 1), y = r * (float)(P.lut_r - 1);
@@ -133,57 +102,106 @@ __device__ inline void shade_forward(const ViewDev& v, const Params& P, const fl
   }
 }
 
+// One bilinear lat-long lookup with its adjoint: returns the value, scatters
+// g (the gradient of the looked-up value, known up front) into the texels of
+// dm (may be null) and adds the gradient with respect to the direction d to gd.
+__device__ inline void latlong_lookup_adjoint(const float* m, float* dm, int H, int W, const float d[3],
+                                              const float g[3], float val[3], float gd[3]) {
+  LatLong L;
+  latlong_coords(d, H, W, L);
+  const int o00 = 3 * (L.r0 * W + L.c0), o01 = 3 * (L.r0 * W + L.c1);
+  const int o10 = 3 * (L.r1 * W + L.c0), o11 = 3 * (L.r1 * W + L.c1);
+  const float w00 = (1.f - L.fa) * (1.f - L.fb), w01 = (1.f - L.fa) * L.fb;
+  const float w10 = L.fa * (1.f - L.fb), w11 = L.fa * L.fb;
+  float ga = 0.f, gb = 0.f;
+  for (int c = 0; c < 3; ++c) {
+    const float v00 = m[o00 + c], v01 = m[o01 + c], v10 = m[o10 + c], v11 = m[o11 + c];
+    val[c] = w00 * v00 + w01 * v01 + w10 * v10 + w11 * v11;
+    ga += g[c] * ((1.f - L.fb) * (v10 - v00) + L.fb * (v11 - v01));
+    gb += g[c] * ((1.f - L.fa) * (v01 - v00) + L.fa * (v11 - v10));
+    if (dm != nullptr && g[c] != 0.f) {
+      atomicAdd(dm + o00 + c, g[c] * w00);
+      atomicAdd(dm + o01 + c, g[c] * w01);
+      atomicAdd(dm + o10 + c, g[c] * w10);
+      atomicAdd(dm + o11 + c, g[c] * w11);
+    }
+  }
+  const float gth = ga * ((float)H / kPi);
+  const float gph = gb * ((float)W / (2.f * kPi));
+  if (L.rho > 1e-20f && L.den > 0.f) {
+    // th = atan2(rho, z), ph = atan2(y, x), rho = sqrt(x^2 + y^2)
+    const float dth_drho = d[2] / L.den, dth_dz = -L.rho / L.den;
+    const float r2 = L.rho * L.rho;
+    gd[0] += gth * dth_drho * d[0] / L.rho - gph * d[1] / r2;
+    gd[1] += gth * dth_drho * d[1] / L.rho + gph * d[0] / r2;
+    gd[2] += gth * dth_dz;
+  }
+}
+
 // Adjoint of shade_forward: given g = dL/dcol, accumulates into g_p, g_nh,
-// g_rho, g_rough, g_metal and scatters texel gradients into v.dlvl.
+// g_rho, g_rough, g_metal and scatters texel gradients into dst[l].  Each
+// lookup's adjoint needs only quantities known before the lookup, so the three
+// lookups are processed one after the other (few live registers).
+__device__ inline float* level_grad_ptr(const ViewDev& v, const float* sm, const int loc_off[7], int l) {
+  return loc_off[l] >= 0 ? const_cast<float*>(sm) + loc_off[l] : v.dlvl[l];
+}
+
 __device__ inline void shade_backward(const ViewDev& v, const Params& P, const float p[3],
                                       const float nh[3], const float rho[3], float rough,
-                                      float metal, const float g[3], float* const dst[7],
-                                      float g_p[3], float g_nh[3], float g_rho[3], float& g_rough,
-                                      float& g_metal) {
+                                      float metal, const float g[3], const float* sm,
+                                      const int loc_off[7], float g_p[3], float g_nh[3],
+                                      float g_rho[3], float& g_rough, float& g_metal) {
   float wv[3] = {v.cam_o[0] - p[0], v.cam_o[1] - p[1], v.cam_o[2] - p[2]};
-  float wl = sqrtf(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
-  float wo[3] = {wv[0] / wl, wv[1] / wl, wv[2] / wl};
-  LatLong Li;
-  latlong_coords(nh, v.lh[6], v.lw[6], Li);
-  float Ld[3];
-  latlong_fetch(v.lvl[6], v.lw[6], Li, Ld);
-  float nv = nh[0] * wo[0] + nh[1] * wo[1] + nh[2] * wo[2];
-  float rd[3] = {2.f * nv * nh[0] - wo[0], 2.f * nv * nh[1] - wo[1], 2.f * nv * nh[2] - wo[2]};
-  float rc = clamp01(rough);
-  float lam = 5.f * rc;
-  int l0 = min((int)floorf(lam), 4);
-  float tl = lam - (float)l0;
-  LatLong La, Lb;
-  latlong_coords(rd, v.lh[l0], v.lw[l0], La);
-  latlong_coords(rd, v.lh[l0 + 1], v.lw[l0 + 1], Lb);
-  float A[3], B[3];
-  latlong_fetch(v.lvl[l0], v.lw[l0], La, A);
-  latlong_fetch(v.lvl[l0 + 1], v.lw[l0 + 1], Lb, B);
-  float nvc = clamp01(nv);
+  const float wl = sqrtf(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
+  const float wo[3] = {wv[0] / wl, wv[1] / wl, wv[2] / wl};
+  const float nv = nh[0] * wo[0] + nh[1] * wo[1] + nh[2] * wo[2];
+  const float rd[3] = {2.f * nv * nh[0] - wo[0], 2.f * nv * nh[1] - wo[1], 2.f * nv * nh[2] - wo[2]};
+  const float rc = clamp01(rough);
+  const float lam = 5.f * rc;
+  const int l0 = min((int)floorf(lam), 4);
+  const float tl = lam - (float)l0;
+  const float nvc = clamp01(nv);
   LutTap T;
   float beta[2];
   lut_fetch(P, nvc, rc, T, beta);
-
-  float gLd[3], gA[3], gB[3];
-  float gb1 = 0.f, gb2 = 0.f, gtl = 0.f;
+  float F0[3], kd[3], gLs[3], gF0[3];
   for (int c = 0; c < 3; ++c) {
-    float F0 = 0.04f * (1.f - metal) + rho[c] * metal;
-    float kd = (1.f - F0) * (1.f - metal);
-    float Ls = (1.f - tl) * A[c] + tl * B[c];
-    float gkd = g[c] * rho[c] * Ld[c];
-    g_rho[c] += g[c] * kd * Ld[c];
-    gLd[c] = g[c] * kd * rho[c];
-    float gLs = g[c] * (F0 * beta[0] + beta[1]);
-    float gF0 = g[c] * Ls * beta[0];
-    gb1 += g[c] * Ls * F0;
-    gb2 += g[c] * Ls;
-    gF0 += -gkd * (1.f - metal);
-    g_metal += -gkd * (1.f - F0);
-    g_metal += gF0 * (rho[c] - 0.04f);
-    g_rho[c] += gF0 * metal;
-    gA[c] = (1.f - tl) * gLs;
-    gB[c] = tl * gLs;
-    gtl += gLs * (B[c] - A[c]);
+    F0[c] = 0.04f * (1.f - metal) + rho[c] * metal;
+    kd[c] = (1.f - F0[c]) * (1.f - metal);
+    gLs[c] = g[c] * (F0[c] * beta[0] + beta[1]);
+    gF0[c] = 0.f;
+  }
+  float gb1 = 0.f, gb2 = 0.f, gtl = 0.f, grd[3] = {0.f, 0.f, 0.f};
+  // diffuse: L_d(n)
+  {
+    float gLd[3], Ld[3];
+    for (int c = 0; c < 3; ++c) gLd[c] = g[c] * kd[c] * rho[c];
+    latlong_lookup_adjoint(v.lvl[6], level_grad_ptr(v, sm, loc_off, 6), v.lh[6], v.lw[6], nh, gLd, Ld, g_nh);
+    for (int c = 0; c < 3; ++c) {
+      const float gkd = g[c] * rho[c] * Ld[c];
+      g_rho[c] += g[c] * kd[c] * Ld[c];
+      gF0[c] -= gkd * (1.f - metal);
+      g_metal -= gkd * (1.f - F0[c]);
+    }
+  }
+  // specular: the two levels around lambda, weights (1 - t) and t
+  for (int side = 0; side < 2; ++side) {
+    const int l = l0 + side;
+    const float wt = side ? tl : 1.f - tl;
+    float gX[3], X[3];
+    for (int c = 0; c < 3; ++c) gX[c] = wt * gLs[c];
+    latlong_lookup_adjoint(v.lvl[l], level_grad_ptr(v, sm, loc_off, l), v.lh[l], v.lw[l], rd, gX, X, grd);
+    for (int c = 0; c < 3; ++c) {
+      const float Ls = wt * X[c];
+      gF0[c] += g[c] * Ls * beta[0];
+      gb1 += g[c] * Ls * F0[c];
+      gb2 += g[c] * Ls;
+      gtl += (side ? 1.f : -1.f) * gLs[c] * X[c];
+    }
+  }
+  for (int c = 0; c < 3; ++c) {
+    g_metal += gF0[c] * (rho[c] - 0.04f);
+    g_rho[c] += gF0[c] * metal;
   }
   float g_rc = 5.f * gtl;
   // BRDF table slopes
@@ -191,31 +209,27 @@ __device__ inline void shade_backward(const ViewDev& v, const Params& P, const f
   {
     const float* L = P.lut;
     for (int c = 0; c < 2; ++c) {
-      float t00 = L[(T.i0 * P.lut_nv + T.j0) * 2 + c];
-      float t01 = L[(T.i0 * P.lut_nv + T.j0 + 1) * 2 + c];
-      float t10 = L[((T.i0 + 1) * P.lut_nv + T.j0) * 2 + c];
-      float t11 = L[((T.i0 + 1) * P.lut_nv + T.j0 + 1) * 2 + c];
-      float dx = (1.f - T.fy) * (t01 - t00) + T.fy * (t11 - t10);
-      float dy = (1.f - T.fx) * (t10 - t00) + T.fx * (t11 - t01);
-      float gc = (c == 0) ? gb1 : gb2;
+      const float t00 = L[(T.i0 * P.lut_nv + T.j0) * 2 + c];
+      const float t01 = L[(T.i0 * P.lut_nv + T.j0 + 1) * 2 + c];
+      const float t10 = L[((T.i0 + 1) * P.lut_nv + T.j0) * 2 + c];
+      const float t11 = L[((T.i0 + 1) * P.lut_nv + T.j0 + 1) * 2 + c];
+      const float dx = (1.f - T.fy) * (t01 - t00) + T.fy * (t11 - t10);
+      const float dy = (1.f - T.fx) * (t10 - t00) + T.fx * (t11 - t01);
+      const float gc = (c == 0) ? gb1 : gb2;
       gnvc += gc * dx * (float)(P.lut_nv - 1);
       g_rc += gc * dy * (float)(P.lut_r - 1);
     }
   }
-  float grd[3] = {0.f, 0.f, 0.f};
-  latlong_backward(v.lvl[l0], dst[l0], v.lh[l0], v.lw[l0], rd, La, gA, grd);
-  latlong_backward(v.lvl[l0 + 1], dst[l0 + 1], v.lh[l0 + 1], v.lw[l0 + 1], rd, Lb, gB, grd);
-  latlong_backward(v.lvl[6], dst[6], v.lh[6], v.lw[6], nh, Li, gLd, g_nh);
   float gnv = (nv >= 0.f && nv <= 1.f) ? gnvc : 0.f;
-  float gwo[3];
-  float nhg = nh[0] * grd[0] + nh[1] * grd[1] + nh[2] * grd[2];
+  const float nhg = nh[0] * grd[0] + nh[1] * grd[1] + nh[2] * grd[2];
   gnv += 2.f * nhg;
+  float gwo[3];
   for (int i = 0; i < 3; ++i) {
     g_nh[i] += 2.f * nv * grd[i] + gnv * wo[i];
     gwo[i] = -grd[i] + gnv * nh[i];
   }
   if (rough >= 0.f && rough <= 1.f) g_rough += g_rc;
-  float wg = wo[0] * gwo[0] + wo[1] * gwo[1] + wo[2] * gwo[2];
+  const float wg = wo[0] * gwo[0] + wo[1] * gwo[1] + wo[2] * gwo[2];
   for (int i = 0; i < 3; ++i) g_p[i] -= (gwo[i] - wo[i] * wg) / wl;
 }
 
@@ -332,6 +346,8 @@ __global__ void __launch_bounds__(256) preprocess_kernel(PPtrs PP, long long N, 
   float col[3];
   if (prm.shade == 0) {
     for (int c = 0; c < 3; ++c) col[c] = PP.p[4][c * N + s];
+  } else if (prm.shade == 2) {
+    for (int c = 0; c < 3; ++c) col[c] = o.nh[c];
   } else {
     float rho[3] = {PP.p[4][s], PP.p[4][N + s], PP.p[4][2 * N + s]};
     shade_forward(v, prm, p, o.nh, rho, PP.p[5][s], PP.p[6][s], col);
@@ -360,45 +376,108 @@ hipError_t launch_preprocess(const float* const P[7], long long N, const ViewDev
 // ---------------------------------------------------------------- backward
 struct GPtrs { float* p[7]; };
 
-// Threads stride over the surfels of one scene: for every view of the scene,
-// read the 11 record gradients and apply the adjoint of bin_geometry /
-// raster_geometry / shade_forward.  Parameter gradients are summed over views
-// in registers and written once (deterministic).  Texel gradients of the small
-// environment levels accumulate in a block-private LDS copy, written out as a
-// per-block partial and summed in a fixed order by envmap_partial_reduce; the
-// large levels take global atomics.
+// Surfel adjoint in two kernels.
+//   shade_backward_kernel (split-sum only): one thread per record, striding over
+//   the records of one scene.  The adjoint of the split-sum colour gives
+//   dL/d(position, n_hat, albedo, roughness, metallic) of that record (written
+//   to sg[r][12]) and the texel gradients of the environment levels: the small
+//   levels accumulate in a block-private LDS copy (written out as a per-block
+//   partial and summed in a fixed order by envmap_partial_reduce*), the large
+//   ones take global atomics.
+//   geometry_backward_kernel: one thread per surfel; for every view of its
+//   scene it reads the 11 record gradients (and sg), applies the adjoint of
+//   bin_geometry / raster_geometry and sums over views in registers, so the
+//   parameter gradients are written once and deterministically.  On request
+//   it also sums the screen-space statistic (slot G_SS) over the views and
+//   counts the views whose record survived the cull (non-empty rectangle).
 struct LocalMaps {
   int off[7];  // float offset of level l in the LDS copy, -1 if not privatised
   int total;   // floats
 };
+struct SceneViews {
+  int idx[kMaxViews];
+  int n;
+  int n_surf;
+  long long surf_off;
+};
 
-__global__ void __launch_bounds__(256) preprocess_backward_kernel(
-    PPtrs PP, long long N, const ViewDev* __restrict__ views, int n_views, Params prm,
-    const float* __restrict__ grad, long long R, GPtrs G, long long s_begin, long long s_end,
-    LocalMaps lm, float* __restrict__ partial) {
+__device__ inline bool record_has_grad(const float* grad, long long r, float gr[12]) {
+  const float4* g4 = reinterpret_cast<const float4*>(grad + r * kGradStride);
+  const float4 a = g4[0], b = g4[1], c = g4[2];
+  gr[0] = a.x; gr[1] = a.y; gr[2] = a.z; gr[3] = a.w;
+  gr[4] = b.x; gr[5] = b.y; gr[6] = b.z; gr[7] = b.w;
+  gr[8] = c.x; gr[9] = c.y; gr[10] = c.z; gr[11] = 0.f;
+  bool any = false;
+  for (int k = 0; k < kNGrad; ++k) any |= gr[k] != 0.f;
+  return any;
+}
+
+__global__ void __launch_bounds__(kBackwardThreads, 4) shade_backward_kernel(
+    PPtrs PP, long long N, const ViewDev* __restrict__ views, SceneViews sv, Params prm,
+    const float* __restrict__ grad, float* __restrict__ sg, LocalMaps lm, float* __restrict__ partial) {
   extern __shared__ float sm[];
   for (int i = threadIdx.x; i < lm.total; i += blockDim.x) sm[i] = 0.f;
-  if (lm.total > 0) __syncthreads();
-  for (long long s = s_begin + (long long)blockIdx.x * blockDim.x + threadIdx.x; s < s_end;
-       s += (long long)gridDim.x * blockDim.x) {
+  __syncthreads();
+  const long long n_rec = (long long)sv.n * sv.n_surf;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_rec;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(i / sv.n_surf);
+    const long long local = i - (long long)k * sv.n_surf;
+    const ViewDev& v = views[sv.idx[k]];
+    const long long r = v.rec_off + local, s = sv.surf_off + local;
+    float gr[12];
+    if (!record_has_grad(grad, r, gr)) continue;
+    // a record with a gradient was rasterised, hence kept by the cull; the
+    // shading needs only the position and the unit normal
+    const float p[3] = {PP.p[0][s], PP.p[0][N + s], PP.p[0][2 * N + s]};
+    const float n[3] = {PP.p[1][s], PP.p[1][N + s], PP.p[1][2 * N + s]};
+    const float nn = sqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    const float nh[3] = {n[0] / nn, n[1] / nn, n[2] / nn};
+    const float rho[3] = {PP.p[4][s], PP.p[4][N + s], PP.p[4][2 * N + s]};
+    float gp[3] = {0.f, 0.f, 0.f}, gnh[3] = {0.f, 0.f, 0.f}, grho[3] = {0.f, 0.f, 0.f};
+    float grough = 0.f, gmetal = 0.f;
+    const float gcol[3] = {gr[G_CR], gr[G_CG], gr[G_CB]};
+    shade_backward(v, prm, p, nh, rho, PP.p[5][s], PP.p[6][s], gcol, sm, lm.off, gp, gnh, grho, grough,
+                   gmetal);
+    float4* out = reinterpret_cast<float4*>(sg + r * 12);
+    out[0] = make_float4(gp[0], gp[1], gp[2], gnh[0]);
+    out[1] = make_float4(gnh[1], gnh[2], grho[0], grho[1]);
+    out[2] = make_float4(grho[2], grough, gmetal, 0.f);
+  }
+  if (lm.total > 0) {
+    __syncthreads();
+    float* dstp = partial + (long long)blockIdx.x * lm.total;
+    for (int i = threadIdx.x; i < lm.total; i += blockDim.x) dstp[i] = sm[i];
+  }
+}
+
+__global__ void __launch_bounds__(256) geometry_backward_kernel(
+    PPtrs PP, long long N, const ViewDev* __restrict__ views, int n_views, Params prm,
+    const float* __restrict__ grad, const float* __restrict__ sg, GPtrs G,
+    const float* __restrict__ recs, float* __restrict__ ss_out, int* __restrict__ vis_out) {
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
   float p[3], n[3], t[3], su, sv;
   load_surfel(PP.p, N, s, p, n, t, su, sv);
-  float rho[3] = {PP.p[4][s], PP.p[4][N + s], PP.p[4][2 * N + s]};
-  const float rough = PP.p[5][s], metal = PP.p[6][s];
   float gp[3] = {0, 0, 0}, gn[3] = {0, 0, 0}, gt[3] = {0, 0, 0}, gsu = 0.f, gsv = 0.f;
   float grho[3] = {0, 0, 0}, grough = 0.f, gmetal = 0.f;
+  float ss_sum = 0.f;
+  int n_vis = 0;
   const float sig = prm.sigma_f;
   for (int vi = 0; vi < n_views; ++vi) {
     const ViewDev& v = views[vi];
     if (s < v.surf_off || s >= v.surf_off + v.n_surf) continue;
     const long long r = v.rec_off + (s - v.surf_off);
-    float gr[kNGrad];
-    bool any = false;
-    for (int k = 0; k < kNGrad; ++k) {
-      gr[k] = grad[k * R + r];
-      any |= gr[k] != 0.f;
+    if (ss_out) ss_sum += grad[r * kGradStride + G_SS];
+    if (vis_out) {
+      // culled records carry the empty rectangle i_lo = 1 > i_hi = 0
+      const uint32_t rx = __float_as_uint(recs[r * kRecFloats + R_RX]);
+      n_vis += (rx & 0xffffu) <= (rx >> 16) ? 1 : 0;
     }
-    if (!any) continue;
+    float gr[12];
+    // depth-consolidation term: gradient with respect to T4z = c'_z
+    const float gtz = prm.cons ? grad[r * kGradStride + G_TZ] : 0.f;
+    if (!record_has_grad(grad, r, gr) && gtz == 0.f) continue;
     Geo o;
     bin_geometry(p, n, t, su, sv, v, prm.r_cut, sig, o);
     if (!o.keep) continue;
@@ -406,13 +485,17 @@ __global__ void __launch_bounds__(256) preprocess_backward_kernel(
     raster_geometry(o, sig, g);
     float gnh[3] = {0, 0, 0};
     // colour
-    float gcol[3] = {gr[G_CR], gr[G_CG], gr[G_CB]};
     if (prm.shade == 0) {
-      for (int c = 0; c < 3; ++c) grho[c] += gcol[c];
+      grho[0] += gr[G_CR]; grho[1] += gr[G_CG]; grho[2] += gr[G_CB];
+    } else if (prm.shade == 2) {
+      gnh[0] += gr[G_CR]; gnh[1] += gr[G_CG]; gnh[2] += gr[G_CB];
     } else {
-      float* dst[7];
-      for (int l = 0; l < 7; ++l) dst[l] = lm.off[l] >= 0 ? sm + lm.off[l] : v.dlvl[l];
-      shade_backward(v, prm, p, o.nh, rho, rough, metal, gcol, dst, gp, gnh, grho, grough, gmetal);
+      const float4* in = reinterpret_cast<const float4*>(sg + r * 12);
+      const float4 a = in[0], b = in[1], c = in[2];
+      gp[0] += a.x; gp[1] += a.y; gp[2] += a.z;
+      gnh[0] += a.w; gnh[1] += b.x; gnh[2] += b.y;
+      grho[0] += b.z; grho[1] += b.w; grho[2] += c.x;
+      grough += c.y; gmetal += c.z;
     }
     // MIP kernel parameters -> M, g
     const float detB = g.detB, dm = o.dm;
@@ -447,7 +530,7 @@ __global__ void __launch_bounds__(256) preprocess_backward_kernel(
     // M, g, x0, y0 -> camera-space c', t'_u, t'_v
     const float z = o.z, iz = 1.f / z, fx = v.fx, fy = v.fy;
     float gcp[3] = {0, 0, 0}, gup[3] = {0, 0, 0}, gvp[3] = {0, 0, 0};
-    float gmx = fx * gr[G_X0], gmy = fy * gr[G_Y0], gz = 0.f;
+    float gmx = fx * gr[G_X0], gmy = fy * gr[G_Y0], gz = gtz;
     gup[0] += fx * gM11 * iz; gup[2] -= fx * o.mx * gM11 * iz; gmx -= fx * o.up[2] * gM11 * iz; gz -= o.M11 * gM11 * iz;
     gvp[0] += fx * gM12 * iz; gvp[2] -= fx * o.mx * gM12 * iz; gmx -= fx * o.vp[2] * gM12 * iz; gz -= o.M12 * gM12 * iz;
     gup[1] += fy * gM21 * iz; gup[2] -= fy * o.my * gM21 * iz; gmy -= fy * o.up[2] * gM21 * iz; gz -= o.M21 * gM21 * iz;
@@ -490,6 +573,8 @@ __global__ void __launch_bounds__(256) preprocess_backward_kernel(
     float ng = o.nh[0] * gnh[0] + o.nh[1] * gnh[1] + o.nh[2] * gnh[2];
     for (int j = 0; j < 3; ++j) gn[j] += (gnh[j] - o.nh[j] * ng) / o.nn;
   }
+  if (ss_out) ss_out[s] = ss_sum;
+  if (vis_out) vis_out[s] = n_vis;
   for (int k = 0; k < 3; ++k) {
     if (G.p[0]) G.p[0][k * N + s] = gp[k];
     if (G.p[1]) G.p[1][k * N + s] = gn[k];
@@ -499,57 +584,81 @@ __global__ void __launch_bounds__(256) preprocess_backward_kernel(
   if (G.p[3]) { G.p[3][s] = gsu; G.p[3][N + s] = gsv; }
   if (G.p[5]) G.p[5][s] = grough;
   if (G.p[6]) G.p[6][s] = gmetal;
-  }
-  if (lm.total > 0) {
-    __syncthreads();
-    float* dstp = partial + (long long)blockIdx.x * lm.total;
-    for (int i = threadIdx.x; i < lm.total; i += blockDim.x) dstp[i] = sm[i];
-  }
 }
 
 struct LevelPtrs { float* p[7]; };
 
-// Sums the per-block partials of the privatised levels (fixed order) into the
-// level gradients.
-__global__ void envmap_partial_reduce(const float* __restrict__ partial, int n_blocks, LocalMaps lm,
-                                      LevelPtrs dst) {
+// Sums the per-block partials of the privatised levels in a fixed order, in two
+// stages: kReduceSplit chunks of blocks, then the chunks, into the level
+// gradients.
+__global__ void envmap_partial_reduce1(const float* __restrict__ partial, int n_blocks, int total,
+                                       float* __restrict__ stage) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int per = (n_blocks + kReduceSplit - 1) / kReduceSplit;
+  const int b0 = blockIdx.y * per, b1 = min(b0 + per, n_blocks);
+  float acc = 0.f;
+  for (int b = b0; b < b1; ++b) acc += partial[(long long)b * total + i];
+  stage[(long long)blockIdx.y * total + i] = acc;
+}
+__global__ void envmap_partial_reduce2(const float* __restrict__ stage, LocalMaps lm, LevelPtrs dst) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= lm.total) return;
   float acc = 0.f;
-  for (int b = 0; b < n_blocks; ++b) acc += partial[(long long)b * lm.total + i];
+  for (int c = 0; c < kReduceSplit; ++c) acc += stage[(long long)c * lm.total + i];
   int l = -1, best = -1;
   for (int k = 0; k < 7; ++k)
     if (lm.off[k] >= 0 && lm.off[k] <= i && lm.off[k] > best) { best = lm.off[k]; l = k; }
   dst.p[l][i - best] = acc;
 }
 
-int backward_blocks(long long n_surf) {
-  long long b = (n_surf + 255) / 256;
+int backward_blocks(long long n_items) {
+  long long b = (n_items + kBackwardThreads - 1) / kBackwardThreads;
   return (int)(b < kBackwardBlocks ? (b > 0 ? b : 1) : kBackwardBlocks);
 }
 
-hipError_t launch_preprocess_backward(const float* const P[7], long long N, const ViewDev* views,
-                                      int n_views, long long s_begin, long long s_end,
-                                      const int local_off[7], int local_total, float* partial,
-                                      float* const level_grad[7], const Params& prm,
-                                      const float* grad, long long R, float* const G[7],
-                                      hipStream_t st) {
-  if (s_end <= s_begin) return hipSuccess;
+hipError_t launch_shade_backward(const float* const P[7], long long N, const ViewDev* views,
+                                 const int* scene_views, int n_scene_views, long long surf_off,
+                                 int n_surf, const int local_off[7], int local_total, float* partial,
+                                 float* const level_grad[7], const Params& prm, const float* grad,
+                                 float* sg, hipStream_t st) {
+  if (n_surf <= 0 || n_scene_views <= 0) return hipSuccess;
   PPtrs PP;
-  GPtrs GG;
-  for (int k = 0; k < 7; ++k) { PP.p[k] = P[k]; GG.p[k] = G[k]; }
+  for (int k = 0; k < 7; ++k) PP.p[k] = P[k];
+  SceneViews sv;
+  for (int k = 0; k < n_scene_views; ++k) sv.idx[k] = scene_views[k];
+  sv.n = n_scene_views;
+  sv.n_surf = n_surf;
+  sv.surf_off = surf_off;
   LocalMaps lm;
   lm.total = local_total;
   for (int l = 0; l < 7; ++l) lm.off[l] = local_total > 0 ? local_off[l] : -1;
-  const int nb = backward_blocks(s_end - s_begin);
-  hipLaunchKernelGGL(preprocess_backward_kernel, dim3(nb), dim3(256), (size_t)local_total * sizeof(float),
-                     st, PP, N, views, n_views, prm, grad, R, GG, s_begin, s_end, lm, partial);
+  const int nb = backward_blocks((long long)n_surf * n_scene_views);
+  hipLaunchKernelGGL(shade_backward_kernel, dim3(nb), dim3(kBackwardThreads),
+                     (size_t)local_total * sizeof(float), st, PP, N, views, sv, prm, grad, sg, lm,
+                     partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || local_total == 0) return e;
   LevelPtrs lp;
   for (int l = 0; l < 7; ++l) lp.p[l] = level_grad[l];
-  hipLaunchKernelGGL(envmap_partial_reduce, dim3((local_total + 255) / 256), dim3(256), 0, st, partial,
-                     nb, lm, lp);
+  float* stage = partial + (long long)kBackwardBlocks * kLocalMapFloats;
+  hipLaunchKernelGGL(envmap_partial_reduce1, dim3((local_total + 255) / 256, kReduceSplit), dim3(256), 0,
+                     st, partial, nb, local_total, stage);
+  hipLaunchKernelGGL(envmap_partial_reduce2, dim3((local_total + 255) / 256), dim3(256), 0, st, stage,
+                     lm, lp);
+  return hipGetLastError();
+}
+
+hipError_t launch_geometry_backward(const float* const P[7], long long N, const ViewDev* views,
+                                    int n_views, const Params& prm, const float* grad,
+                                    const float* sg, float* const G[7], const float* recs,
+                                    float* ss_out, int* vis_out, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  PPtrs PP;
+  GPtrs GG;
+  for (int k = 0; k < 7; ++k) { PP.p[k] = P[k]; GG.p[k] = G[k]; }
+  hipLaunchKernelGGL(geometry_backward_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, PP, N,
+                     views, n_views, prm, grad, sg, GG, recs, ss_out, vis_out);
   return hipGetLastError();
 }
 

@@ -50,14 +50,48 @@ __device__ __forceinline__ void load_batch(float4* lds, const uint32_t* __restri
   }
 }
 
+// Can the acceptance ellipse of a record reach a pixel centre of the 8 x 8
+// sub-tile at (sx0, sy0)?  Conservative: with d the pixel offset from the
+// centre, rho^2 = d^T Q d / s^2 >= min_box(d^T Q d) / max_box(s)^2, where the
+// minimum of the convex quadratic over the box is 0 when the centre is inside
+// and otherwise lies on one of its edges (1-D minimum, clamped), and s is
+// linear so its maximum is at a corner.  A 1e-3 margin keeps the test far from
+// the per-pixel FP32 cutoff decision.
+__device__ __forceinline__ bool ellipse_meets(const float4 q0, const float4 q1, const float4 q3,
+                                              int sx0, int sy0, float r2) {
+  const int il = __float_as_int(q3.x) & 0xffff, jl = __float_as_int(q3.y) & 0xffff;
+  const float x0 = (float)(sx0 - il) + 0.5f - q0.x, x1 = x0 + 7.f;
+  const float y0 = (float)(sy0 - jl) + 0.5f - q0.y, y1 = y0 + 7.f;
+  const float qxx = q0.z, qxy = 0.5f * q0.w, qyy = q1.x, a3 = q1.y, b3 = q1.z;
+  const float s00 = 1.f + a3 * x0 + b3 * y0, s01 = 1.f + a3 * x0 + b3 * y1;
+  const float s10 = 1.f + a3 * x1 + b3 * y0, s11 = 1.f + a3 * x1 + b3 * y1;
+  const float smin = fminf(fminf(s00, s01), fminf(s10, s11));
+  const float smax = fmaxf(fmaxf(s00, s01), fmaxf(s10, s11));
+  if (!(smin > 0.f)) return true;
+  if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return true;
+  float nmin = 3.4e38f;
+  {
+    const float ya = fminf(fmaxf(-qxy * x0 / qyy, y0), y1), yb = fminf(fmaxf(-qxy * x1 / qyy, y0), y1);
+    nmin = fminf(nmin, qxx * x0 * x0 + 2.f * qxy * x0 * ya + qyy * ya * ya);
+    nmin = fminf(nmin, qxx * x1 * x1 + 2.f * qxy * x1 * yb + qyy * yb * yb);
+    const float xa = fminf(fmaxf(-qxy * y0 / qxx, x0), x1), xb = fminf(fmaxf(-qxy * y1 / qxx, x0), x1);
+    nmin = fminf(nmin, qxx * xa * xa + 2.f * qxy * xa * y0 + qyy * y0 * y0);
+    nmin = fminf(nmin, qxx * xb * xb + 2.f * qxy * xb * y1 + qyy * y1 * y1);
+  }
+  return !(nmin >= r2 * smax * smax * 1.001f);
+}
+
 // Wave-level compaction of a chunk of up to 64 staged records: lane j tests
-// record c0 + j against the wave's sub-tile; the ballot is the (wave-uniform)
-// set of records this wave visits, in list order.
+// record c0 + j against the wave's sub-tile (rectangle, then ellipse); the
+// ballot is the (wave-uniform) set of records this wave visits, in list order.
 __device__ __forceinline__ uint64_t chunk_mask(const float4* lds, int c0, int cnt, int lane, int sx0,
-                                               int sy0) {
+                                               int sy0, float r2) {
   const int j = c0 + lane;
   bool ov = false;
-  if (j < cnt) ov = rect_meets(lds[4 * j + 3], sx0, sy0);
+  if (j < cnt) {
+    const float4 q3 = lds[4 * j + 3];
+    ov = rect_meets(q3, sx0, sy0) && ellipse_meets(lds[4 * j], lds[4 * j + 1], q3, sx0, sy0, r2);
+  }
   return __ballot(ov);
 }
 
@@ -70,14 +104,55 @@ __device__ __forceinline__ int next_item(int* queue, int persistent, int& s_item
   return it;
 }
 
+// Camera-space depth of the ray-surfel intersection: T4 . (u, v, 1) = T4z / s
+// (the perspective denominator s is exactly T4z times an affine function of
+// the pixel); T4z = c'_z is the midpoint of the record's depth interval.
+__device__ __forceinline__ float frag_depth(const float* rec, const FragEval& f) {
+  return 0.5f * (rec[R_ZS] + rec[R_ZE]) / f.s;
+}
+
+// Depth statistics of one pixel from its layers (w_k = T_k alpha_k, mean depth
+// z_k, depth variance v_k): the depth-consolidation term of eq:cons_loss and
+// the composited depth sum_k w_k z_k.
+__device__ inline void depth_stats_of_pixel(const float4* __restrict__ st, const float2* __restrict__ st2,
+                                            int K, float kappa, float& cons, float& depth) {
+  float Ti = 1.f;
+  cons = 0.f;
+  depth = 0.f;
+  for (int i = 0; i < K; ++i) {
+    const float Wi = st[i].x, wi = Ti * -expm1f(-kappa * Wi);
+    const float2 zi = st2[i];
+    float inter = 0.f, Tj = Ti * __expf(-kappa * Wi);
+    for (int j = i + 1; j < K; ++j) {
+      const float Wj = st[j].x;
+      inter += Tj * -expm1f(-kappa * Wj) * fabsf(zi.x - st2[j].x);
+      Tj *= __expf(-kappa * Wj);
+    }
+    cons += wi * (inter + wi * zi.y);
+    depth += wi * zi.x;
+    Ti *= __expf(-kappa * Wi);
+  }
+}
+
+// Shepard normalisation of a layer's colour sum: 1/W_k, or 1/|C_k| for the
+// normal image (the mean unit normal renormalised to unit length).
+__device__ __forceinline__ float layer_norm(int shade, float W, float C0, float C1, float C2) {
+  return shade == 2 ? rsqrtf(C0 * C0 + C1 * C1 + C2 * C2) : 1.f / W;
+}
+
 // ---------------------------------------------------------------- forward
-template <int TW, int TH>
+// CONS: also the per-layer depth statistics (mean, variance; stats2) and the
+// per-pixel depth-consolidation term and composited depth (each output
+// nullable).  Depths are accumulated relative to the layer's first fragment,
+// so the variance does not cancel against z^2.
+template <int TW, int TH, bool CONS>
 __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     const ViewDev* __restrict__ views, int n_views, int tile_begin, int n_items,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float* __restrict__ recs, Params prm, int B, float* __restrict__ image,
     float* __restrict__ alpha, uint8_t* __restrict__ nl_out, uint8_t* __restrict__ nl_int,
-    float4* __restrict__ stats, int* queue, const int* __restrict__ order, int persistent) {
+    float4* __restrict__ stats, float2* __restrict__ stats2, float* __restrict__ cons_out,
+    float* __restrict__ depth_out, int* queue, const int* __restrict__ order, int persistent) {
   extern __shared__ float4 lds[];
   __shared__ int s_item;
   constexpr int NT = TW * TH;
@@ -100,6 +175,7 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
 
     float C0 = 0.f, C1 = 0.f, C2 = 0.f, Wg = 0.f, zmax = 0.f;
     float O0 = 0.f, O1 = 0.f, O2 = 0.f, T = 1.f;
+    float zr = 0.f, S1 = 0.f, S2 = 0.f;  // CONS: reference depth, sum w dz, sum w dz^2
     int K = 0;
     bool done = !inside;
     for (uint32_t b0 = start; b0 < end; b0 += (uint32_t)B) {
@@ -109,7 +185,7 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
       __syncthreads();
       for (int c0 = 0; c0 < cnt; c0 += 64) {
         if (__ballot(!done) == 0ull) break;
-        uint64_t m = chunk_mask(lds, c0, cnt, lane, sx0, sy0);
+        uint64_t m = chunk_mask(lds, c0, cnt, lane, sx0, sy0, r2);
         while (m) {
           const int j = c0 + __builtin_ctzll(m);
           m &= m - 1;
@@ -120,15 +196,27 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
           if (Wg > 0.f && rec[R_ZS] > zmax) {
             // gap: finalise the layer (Shepard-normalised colour, coverage opacity)
             const float a = -expm1f(-kappa * Wg), e = __expf(-kappa * Wg);
-            const float s = T * a / Wg;
+            const float s = T * a * layer_norm(prm.shade, Wg, C0, C1, C2);
             O0 += s * C0; O1 += s * C1; O2 += s * C2;
             stats[pix * kMaxLayers + K] = make_float4(Wg, C0, C1, C2);
+            if constexpr (CONS) {
+              const float m = S1 / Wg;
+              stats2[pix * kMaxLayers + K] = make_float2(zr + m, S2 / Wg - m * m);
+              S1 = S2 = 0.f;
+            }
             T *= e;
             ++K;
             C0 = C1 = C2 = 0.f;
             Wg = 0.f;
             zmax = 0.f;
             if (K >= kmax) { done = true; continue; }
+          }
+          if constexpr (CONS) {
+            const float z = frag_depth(rec, f);
+            if (Wg == 0.f) zr = z;
+            const float dz = z - zr;
+            S1 += f.w * dz;
+            S2 += f.w * dz * dz;
           }
           zmax = fmaxf(zmax, rec[R_ZE]);
           C0 += f.w * rec[R_CR];
@@ -142,11 +230,21 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     if (inside) {
       if (!done && Wg > 0.f) {
         const float a = -expm1f(-kappa * Wg), e = __expf(-kappa * Wg);
-        const float s = T * a / Wg;
+        const float s = T * a * layer_norm(prm.shade, Wg, C0, C1, C2);
         O0 += s * C0; O1 += s * C1; O2 += s * C2;
         stats[pix * kMaxLayers + K] = make_float4(Wg, C0, C1, C2);
+        if constexpr (CONS) {
+          const float m = S1 / Wg;
+          stats2[pix * kMaxLayers + K] = make_float2(zr + m, S2 / Wg - m * m);
+        }
         T *= e;
         ++K;
+      }
+      if constexpr (CONS) {
+        float cs, dp;
+        depth_stats_of_pixel(stats + pix * kMaxLayers, stats2 + pix * kMaxLayers, K, kappa, cs, dp);
+        if (cons_out) cons_out[pix] = cs;
+        if (depth_out) depth_out[pix] = dp;
       }
       image[3 * pix + 0] = O0 + T * v.bg[0];
       image[3 * pix + 1] = O1 + T * v.bg[1];
@@ -194,18 +292,47 @@ __device__ __forceinline__ float wave_reduce12(const float g[12], int lane, int*
   return k == 0 ? t3[0] : (k == 1 ? t3[1] : t3[2]);
 }
 
+// Same for 16 values: permlane32_swap pairs (g_i, g_{i+8}), permlane16_swap
+// pairs (s_i, s_{i+4}), row sum; lane 16r + k (k < 4) returns value 4r + k.
+__device__ __forceinline__ float wave_reduce16(const float g[16], int lane, int* vidx) {
+  float s[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(g[i]), __float_as_uint(g[i + 8]),
+                                                    false, false);
+    s[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  float t4[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(s[i]), __float_as_uint(s[i + 4]),
+                                                    false, false);
+    t4[i] = row_sum16(__uint_as_float(r[0]) + __uint_as_float(r[1]));
+  }
+  const int row = lane >> 4, k = lane & 15;
+  *vidx = k < 4 ? 4 * row + k : -1;
+  return k == 0 ? t4[0] : (k == 1 ? t4[1] : (k == 2 ? t4[2] : t4[3]));
+}
+
+// Per-layer coefficients of the backward.  The layer's composited value is
+// C_hat = C / W (or C / |C| for the normal image); per fragment
+//   dL/dw_f = dW + coef (G' . c_f - GC),  dL/dc_f = w_f coef G',
+// with coef = T_k alpha_k / W_k, G' = G and GC = G . C_hat, or, for the
+// normal image (C_hat independent of W), G' = (I - C_hat C_hat^T) G W / |C|
+// and GC = 0.
 struct LayerCoef {
-  float W, e, a, Ch0, Ch1, Ch2, dW, coef, GC;
+  float W, e, a, Ch0, Ch1, Ch2, dW, coef, GC, G0, G1, G2;
 };
 
 __device__ __forceinline__ void layer_coef(const float4 st, float Tk, float kappa, const float G[3],
                                            float ga, float Tfin, const float Cf[3], const float pre[3],
-                                           LayerCoef& L) {
+                                           int shade, LayerCoef& L) {
   L.W = st.x;
   L.a = -expm1f(-kappa * st.x);
   L.e = __expf(-kappa * st.x);
   const float iW = 1.f / st.x;
-  L.Ch0 = st.y * iW; L.Ch1 = st.z * iW; L.Ch2 = st.w * iW;
+  const float nrm = layer_norm(shade, st.x, st.y, st.z, st.w);
+  L.Ch0 = st.y * nrm; L.Ch1 = st.z * nrm; L.Ch2 = st.w * nrm;
   const float ta = Tk * L.a;
   // suffix S_k = sum_{j>k} T_j a_j C_j + T_{K+1} bg = C_final - prefix - T_k a_k C_k
   const float S0 = Cf[0] - pre[0] - ta * L.Ch0;
@@ -215,17 +342,73 @@ __device__ __forceinline__ void layer_coef(const float4 st, float Tk, float kapp
   L.dW = kappa * (G[0] * (Tk1 * L.Ch0 - S0) + G[1] * (Tk1 * L.Ch1 - S1) + G[2] * (Tk1 * L.Ch2 - S2) +
                   ga * Tfin);
   L.coef = ta * iW;
-  L.GC = G[0] * L.Ch0 + G[1] * L.Ch1 + G[2] * L.Ch2;
+  if (shade == 2) {
+    const float gn = G[0] * L.Ch0 + G[1] * L.Ch1 + G[2] * L.Ch2, sc = st.x * nrm;
+    L.G0 = (G[0] - gn * L.Ch0) * sc;
+    L.G1 = (G[1] - gn * L.Ch1) * sc;
+    L.G2 = (G[2] - gn * L.Ch2) * sc;
+    L.GC = 0.f;
+  } else {
+    L.G0 = G[0]; L.G1 = G[1]; L.G2 = G[2];
+    L.GC = G[0] * L.Ch0 + G[1] * L.Ch1 + G[2] * L.Ch2;
+  }
 }
 
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW* TH) raster_backward_kernel(
+// Adjoint of the depth statistics for layer k of a pixel: loss weight dc on
+// the depth-consolidation term and dd on the composited depth, with U the
+// running sum over the layers not yet visited of w_i dL/dw_i (2 dc cons + dd
+// depth before the first layer).  With
+//   dL/dw_k = dc (sum_{j!=k} w_j |z_k - z_j| + 2 w_k v_k) + dd z_k,
+//   dL/dz_k = dc w_k sum_{j!=k} w_j sign(z_k - z_j) + dd w_k,  dL/dv_k = dc w_k^2,
+// the per-fragment terms are
+//   dL/dw_f += A + B (z_f - z_k) + C ((z_f - z_k)^2 - v_k),
+//   dL/dz_f  = w_f (B + 2 C (z_f - z_k)),
+// A = kappa (T_{k+1} dL/dw_k - sum_{i>k} w_i dL/dw_i) (w_i = T_i alpha_i
+// depends on W_k through T_i for i > k), B = dL/dz_k / W_k, C = dL/dv_k / W_k.
+struct ConsCoef {
+  float A, B, C, z, v;
+};
+__device__ inline void cons_coef(const float4* __restrict__ st, const float2* __restrict__ st2, int K, int k,
+                                 float kappa, float dc, float dd, float& U, ConsCoef& c) {
+  const float2 zk = st2[k];
+  float T = 1.f, wk = 0.f, Tk1 = 0.f, sabs = 0.f, ssgn = 0.f;
+  for (int j = 0; j < K; ++j) {
+    const float Wj = st[j].x, e = __expf(-kappa * Wj), wj = T * -expm1f(-kappa * Wj);
+    if (j == k) {
+      wk = wj;
+      Tk1 = T * e;
+    } else {
+      const float d = zk.x - st2[j].x;
+      sabs += wj * fabsf(d);
+      ssgn += d > 0.f ? wj : (d < 0.f ? -wj : 0.f);
+    }
+    T *= e;
+  }
+  const float dldw = dc * (sabs + 2.f * wk * zk.y) + dd * zk.x;
+  U -= dldw * wk;
+  c.A = kappa * (dldw * Tk1 - U);
+  const float iW = 1.f / st[k].x;
+  c.B = wk * (dc * ssgn + dd) * iW;
+  c.C = dc * wk * wk * iW;
+  c.z = zk.x;
+  c.v = zk.y;
+}
+
+// SS: also accumulate the densification statistic in slot G_SS.
+// CONS: add the adjoint of the depth statistics (loss weights d_cons on the
+// consolidation term, d_depth on the composited depth; either may be null).
+template <int TW, int TH, bool SS, bool CONS>
+__global__ void __launch_bounds__(TW* TH, (SS || CONS) ? 4 : 8) raster_backward_kernel(
     const ViewDev* __restrict__ views, int n_views, int tile_begin, int n_items,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float* __restrict__ recs, Params prm, int B, const float* __restrict__ d_image,
     const float* __restrict__ d_alpha, const uint8_t* __restrict__ nl_int,
-    const float4* __restrict__ stats, float* __restrict__ grad, long long R, int* queue,
+    const float4* __restrict__ stats, const float2* __restrict__ stats2, const float* __restrict__ d_cons,
+    const float* __restrict__ d_depth, float* __restrict__ grad, long long R, int* queue,
     const int* __restrict__ order, int persistent) {
+  // values reduced per fragment: the 11 record slots, then G_SS, then G_TZ
+  constexpr int NV = kNGrad + (SS ? 1 : 0) + (CONS ? 1 : 0);
+  constexpr int RW = NV <= 12 ? 12 : 16;
   extern __shared__ float4 lds[];
   __shared__ int s_item;
   constexpr int NT = TW * TH;
@@ -252,6 +435,10 @@ __global__ void __launch_bounds__(TW* TH) raster_backward_kernel(
     float Tfin = 1.f, Tk = 1.f;
     LayerCoef L;
     L.W = 1.f; L.e = 1.f; L.a = 0.f; L.Ch0 = L.Ch1 = L.Ch2 = 0.f; L.dW = 0.f; L.coef = 0.f; L.GC = 0.f;
+    L.G0 = L.G1 = L.G2 = 0.f;
+    ConsCoef CC;
+    CC.A = CC.B = CC.C = CC.z = CC.v = 0.f;
+    float dc = 0.f, dd = 0.f, U = 0.f;
     bool done = true;
     if (inside) {
       G[0] = d_image[3 * pix]; G[1] = d_image[3 * pix + 1]; G[2] = d_image[3 * pix + 2];
@@ -261,14 +448,22 @@ __global__ void __launch_bounds__(TW* TH) raster_backward_kernel(
       for (int k = 0; k < nl; ++k) {
         const float4 st = stats[pix * kMaxLayers + k];
         const float a = -expm1f(-kappa * st.x), e = __expf(-kappa * st.x);
-        const float s = T * a / st.x;
+        const float s = T * a * layer_norm(prm.shade, st.x, st.y, st.z, st.w);
         Cf[0] += s * st.y; Cf[1] += s * st.z; Cf[2] += s * st.w;
         T *= e;
       }
       Tfin = T;
       Cf[0] += T * v.bg[0]; Cf[1] += T * v.bg[1]; Cf[2] += T * v.bg[2];
       if (nl > 0) {
-        layer_coef(stats[pix * kMaxLayers], 1.f, kappa, G, ga, Tfin, Cf, pre, L);
+        layer_coef(stats[pix * kMaxLayers], 1.f, kappa, G, ga, Tfin, Cf, pre, prm.shade, L);
+        if constexpr (CONS) {
+          dc = d_cons ? d_cons[pix] : 0.f;
+          dd = d_depth ? d_depth[pix] : 0.f;
+          float cs, dp;
+          depth_stats_of_pixel(stats + pix * kMaxLayers, stats2 + pix * kMaxLayers, nl, kappa, cs, dp);
+          U = 2.f * dc * cs + dd * dp;
+          cons_coef(stats + pix * kMaxLayers, stats2 + pix * kMaxLayers, nl, 0, kappa, dc, dd, U, CC);
+        }
         done = false;
       }
     }
@@ -281,7 +476,7 @@ __global__ void __launch_bounds__(TW* TH) raster_backward_kernel(
       __syncthreads();
       for (int c0 = 0; c0 < cnt; c0 += 64) {
         if (__ballot(!done) == 0ull) break;
-        uint64_t m = chunk_mask(lds, c0, cnt, lane, sx0, sy0);
+        uint64_t m = chunk_mask(lds, c0, cnt, lane, sx0, sy0, r2);
         while (m) {
           const int j = c0 + __builtin_ctzll(m);
           m &= m - 1;
@@ -289,7 +484,7 @@ __global__ void __launch_bounds__(TW* TH) raster_backward_kernel(
           FragEval f;
           frag_eval(rec, px, py, r2, f);
           bool contrib = false;
-          float gw = 0.f, gcs = 0.f;
+          float gw = 0.f, gcs = 0.f, gz = 0.f, zf = 0.f;
           if (f.cov && !done) {
             bool live = true;
             if (Wg > 0.f && rec[R_ZS] > zmax) {
@@ -301,7 +496,9 @@ __global__ void __launch_bounds__(TW* TH) raster_backward_kernel(
                 done = true;
                 live = false;
               } else {
-                layer_coef(stats[pix * kMaxLayers + k], Tk, kappa, G, ga, Tfin, Cf, pre, L);
+                layer_coef(stats[pix * kMaxLayers + k], Tk, kappa, G, ga, Tfin, Cf, pre, prm.shade, L);
+                if constexpr (CONS)
+                  cons_coef(stats + pix * kMaxLayers, stats2 + pix * kMaxLayers, nl, k, kappa, dc, dd, U, CC);
                 Wg = 0.f;
                 zmax = 0.f;
               }
@@ -309,9 +506,15 @@ __global__ void __launch_bounds__(TW* TH) raster_backward_kernel(
             if (live) {
               zmax = fmaxf(zmax, rec[R_ZE]);
               Wg += f.w;
-              const float Gc = G[0] * rec[R_CR] + G[1] * rec[R_CG] + G[2] * rec[R_CB];
+              const float Gc = L.G0 * rec[R_CR] + L.G1 * rec[R_CG] + L.G2 * rec[R_CB];
               gw = L.dW + L.coef * (Gc - L.GC);
               gcs = f.w * L.coef;
+              if constexpr (CONS) {
+                zf = frag_depth(rec, f);
+                const float dz = zf - CC.z;
+                gw += CC.A + CC.B * dz + CC.C * (dz * dz - CC.v);
+                gz = f.w * (CC.B + 2.f * CC.C * dz);
+              }
               contrib = true;
             }
           }
@@ -321,7 +524,7 @@ __global__ void __launch_bounds__(TW* TH) raster_backward_kernel(
           const float gq = -0.5f * f.w * gw;
           const float dx = f.dx, dy = f.dy, q = f.q;
           const float qxx = rec[R_QXX], qxy2 = rec[R_QXY2], qyy = rec[R_QYY];
-          float g[12];
+          float g[RW];
           g[G_X0] = -gq * ((2.f * qxx * dx + qxy2 * dy) * is2 - 2.f * q * rec[R_A3] * is);
           g[G_Y0] = -gq * ((qxy2 * dx + 2.f * qyy * dy) * is2 - 2.f * q * rec[R_B3] * is);
           g[G_QXX] = gq * dx * dx * is2;
@@ -330,17 +533,53 @@ __global__ void __launch_bounds__(TW* TH) raster_backward_kernel(
           g[G_A3] = -2.f * gq * q * dx * is;
           g[G_B3] = -2.f * gq * q * dy * is;
           g[G_NF] = gw * f.w * __builtin_amdgcn_rcpf(rec[R_NF]);
-          g[G_CR] = gcs * G[0];
-          g[G_CG] = gcs * G[1];
-          g[G_CB] = gcs * G[2];
-          g[11] = 0.f;
+          g[G_CR] = gcs * L.G0;
+          g[G_CG] = gcs * L.G1;
+          g[G_CB] = gcs * L.G2;
 #pragma unroll
-          for (int q2 = 0; q2 < 11; ++q2) g[q2] = contrib ? g[q2] : 0.f;
+          for (int q2 = kNGrad; q2 < RW; ++q2) g[q2] = 0.f;
+          if constexpr (CONS) {
+            // z_f = T4z / s: dz/dT4z = 1/s, dz/ds = -z_f/s, ds/d(a3, b3) = (dx, dy),
+            // ds/d(x0, y0) = -(a3, b3)
+            const float gs = -gz * zf * is;
+            g[G_X0] -= gs * rec[R_A3];
+            g[G_Y0] -= gs * rec[R_B3];
+            g[G_A3] += gs * dx;
+            g[G_B3] += gs * dy;
+            g[NV - 1] = gz * is;
+          }
+          if constexpr (SS) {
+            // (dL_p/dT1z, dL_p/dT2z) T4z from the record gradients: a change of
+            // T1z (T2z) is the screen map x += delta s / T4z (y += ...), which moves
+            // the centre by delta/T4z and M by E M with E = e1 (a3, b3) / T4z
+            // (e2 ...); the record fields follow in closed form, with
+            // P = I - sigma_f Q and (p1, p2) = (a3, b3) P.
+            const float a3 = rec[R_A3], b3 = rec[R_B3], qxy = 0.5f * qxy2, sg = prm.sigma_f;
+            const float p1 = a3 * (1.f - sg * qxx) - b3 * sg * qxy;
+            const float p2 = b3 * (1.f - sg * qyy) - a3 * sg * qxy;
+            const float gab = a3 * g[G_A3] + b3 * g[G_B3];
+            const float gnf = sg * gw * f.w;  // n_f dL/dn_f sigma_f
+            const float gx = g[G_X0] - 2.f * (qxx * p1 * g[G_QXX] + (qxx * p2 + qxy * p1) * g[G_QXY2] +
+                                              qxy * p2 * g[G_QYY]) -
+                             a3 * gab + gnf * (a3 * qxx + b3 * qxy);
+            const float gy = g[G_Y0] - 2.f * (qxy * p1 * g[G_QXX] + (qxy * p2 + qyy * p1) * g[G_QXY2] +
+                                              qyy * p2 * g[G_QYY]) -
+                             b3 * gab + gnf * (a3 * qxy + b3 * qyy);
+            g[kNGrad] = sqrtf(gx * gx + gy * gy);
+          }
+#pragma unroll
+          for (int q2 = 0; q2 < RW; ++q2) g[q2] = contrib ? g[q2] : 0.f;
           int vidx;
-          const float tot = wave_reduce12(g, lane, &vidx);
-          if (vidx >= 0 && vidx < kNGrad && tot != 0.f) {
+          float tot;
+          if constexpr (RW == 12)
+            tot = wave_reduce12(g, lane, &vidx);
+          else
+            tot = wave_reduce16(g, lane, &vidx);
+          if (vidx >= 0 && vidx < NV && tot != 0.f) {
+            // reduced index -> gradient slot (the extras are packed after the 11)
+            const int slot = vidx < kNGrad ? vidx : (vidx == NV - 1 && CONS ? (int)G_TZ : (int)G_SS);
             const uint32_t id = __float_as_uint(rec[R_ID]);
-            atomicAdd(grad + (long long)vidx * R + id, tot);
+            atomicAdd(grad + (long long)id * kGradStride + slot, tot);
           }
         }
       }
@@ -349,24 +588,82 @@ __global__ void __launch_bounds__(TW* TH) raster_backward_kernel(
   }
 }
 
+// ---------------------------------------------------------------- schedule
+// Longest-processing-time-first order of a group's tiles for the persistent
+// raster: counting sort by floor(log2(list length + 1)), descending.  The order
+// inside a bucket does not matter (it changes only which block renders a tile).
+__global__ void __launch_bounds__(1024) tile_order_kernel(const uint32_t* __restrict__ ranges, int tile_begin,
+                                                          int n_tiles, int* __restrict__ order) {
+  __shared__ int cnt[33], base[33];
+  if (threadIdx.x < 33) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) {
+    const uint32_t len = ranges[2 * (tile_begin + i) + 1] - ranges[2 * (tile_begin + i)];
+    atomicAdd(&cnt[32 - __clz(len + 1u)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int b = 32; b >= 0; --b) { base[b] = acc; acc += cnt[b]; }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) {
+    const uint32_t len = ranges[2 * (tile_begin + i) + 1] - ranges[2 * (tile_begin + i)];
+    const int pos = atomicAdd(&base[32 - __clz(len + 1u)], 1);
+    order[pos] = tile_begin + i;
+  }
+}
+
+hipError_t launch_tile_order(const uint32_t* ranges, int tile_begin, int n_tiles, int* order, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, st, ranges, tile_begin, n_tiles, order);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- launchers
 template <int TW, int TH>
 static hipError_t fwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* views, int nv, int tb,
                         int ni, const uint32_t* ranges, const uint32_t* vals, const float* recs,
                         const Params& prm, int B, float* image, float* alpha, uint8_t* nlo,
-                        uint8_t* nli, float4* stats, int* queue, const int* order, int pers) {
-  hipLaunchKernelGGL((raster_forward_kernel<TW, TH>), grid, dim3(TW * TH), lds, st, views, nv, tb, ni,
-                     ranges, vals, recs, prm, B, image, alpha, nlo, nli, stats, queue, order, pers);
+                        uint8_t* nli, float4* stats, float2* stats2, float* cons, float* depth,
+                        int* queue, const int* order, int pers) {
+  if (prm.cons)
+    hipLaunchKernelGGL((raster_forward_kernel<TW, TH, true>), grid, dim3(TW * TH), lds, st, views, nv, tb, ni,
+                       ranges, vals, recs, prm, B, image, alpha, nlo, nli, stats, stats2, cons, depth, queue,
+                       order, pers);
+  else
+    hipLaunchKernelGGL((raster_forward_kernel<TW, TH, false>), grid, dim3(TW * TH), lds, st, views, nv, tb,
+                       ni, ranges, vals, recs, prm, B, image, alpha, nlo, nli, stats, stats2, cons, depth,
+                       queue, order, pers);
   return hipGetLastError();
 }
+
+template <int TW, int TH, bool SS, bool CONS>
+static void bwd_launch(dim3 grid, size_t lds, hipStream_t st, const ViewDev* views, int nv, int tb, int ni,
+                       const uint32_t* ranges, const uint32_t* vals, const float* recs, const Params& prm,
+                       int B, const float* di, const float* da, const uint8_t* nli, const float4* stats,
+                       const float2* stats2, const float* dcons, const float* ddepth, float* grad, long long R,
+                       int* queue, const int* order, int pers) {
+  hipLaunchKernelGGL((raster_backward_kernel<TW, TH, SS, CONS>), grid, dim3(TW * TH), lds, st, views, nv, tb,
+                     ni, ranges, vals, recs, prm, B, di, da, nli, stats, stats2, dcons, ddepth, grad, R, queue,
+                     order, pers);
+}
+
 template <int TW, int TH>
 static hipError_t bwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* views, int nv, int tb,
                         int ni, const uint32_t* ranges, const uint32_t* vals, const float* recs,
                         const Params& prm, int B, const float* di, const float* da,
-                        const uint8_t* nli, const float4* stats, float* grad, long long R, int* queue,
-                        const int* order, int pers) {
-  hipLaunchKernelGGL((raster_backward_kernel<TW, TH>), grid, dim3(TW * TH), lds, st, views, nv, tb, ni,
-                     ranges, vals, recs, prm, B, di, da, nli, stats, grad, R, queue, order, pers);
+                        const uint8_t* nli, const float4* stats, const float2* stats2, const float* dcons,
+                        const float* ddepth, float* grad, long long R, int* queue, const int* order,
+                        int pers) {
+#define SS_BWD_V(SSV, CV) bwd_launch<TW, TH, SSV, CV>(grid, lds, st, views, nv, tb, ni, ranges, vals, recs, \
+                                                       prm, B, di, da, nli, stats, stats2, dcons, ddepth,    \
+                                                       grad, R, queue, order, pers)
+  if (prm.ss_grad && prm.cons) SS_BWD_V(true, true);
+  else if (prm.ss_grad) SS_BWD_V(true, false);
+  else if (prm.cons) SS_BWD_V(false, true);
+  else SS_BWD_V(false, false);
+#undef SS_BWD_V
   return hipGetLastError();
 }
 
@@ -381,16 +678,19 @@ hipError_t launch_raster_forward(const ViewDev* views, int n_views, int tile_beg
                                  const uint32_t* ranges, const uint32_t* sorted_vals,
                                  const float* recs, const Params& prm, int lds_batch,
                                  float* image, float* alpha, uint8_t* n_layers_out,
-                                 uint8_t* n_layers, float4* layer_stats, int* queue,
-                                 const int* order, int persistent, hipStream_t st) {
+                                 uint8_t* n_layers, float4* layer_stats, float2* layer_stats2,
+                                 float* cons, float* depth, int* queue, const int* order,
+                                 int persistent, hipStream_t st) {
   const int n_items = tile_end - tile_begin;
   if (n_items <= 0) return hipSuccess;
+  if (prm.cons && (!layer_stats2 || (!cons && !depth))) return hipErrorInvalidValue;
   const int threads = prm.tile_w * prm.tile_h;
   dim3 grid(persistent ? persistent_grid(n_items, threads) : (unsigned)n_items);
   const size_t lds = (size_t)lds_batch * kRecFloats * sizeof(float);
 #define SS_FWD(TW, TH) fwd_t<TW, TH>(grid, lds, st, views, n_views, tile_begin, n_items, ranges, \
                                      sorted_vals, recs, prm, lds_batch, image, alpha,            \
-                                     n_layers_out, n_layers, layer_stats, queue, order, persistent)
+                                     n_layers_out, n_layers, layer_stats, layer_stats2, cons,    \
+                                     depth, queue, order, persistent)
   switch (prm.tile_w * 100 + prm.tile_h) {
     case 808: return SS_FWD(8, 8);
     case 1608: return SS_FWD(16, 8);
@@ -407,16 +707,19 @@ hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_be
                                   const float* recs, const Params& prm, int lds_batch,
                                   const float* d_image, const float* d_alpha,
                                   const uint8_t* n_layers, const float4* layer_stats,
-                                  float* grad, long long R, int* queue, const int* order,
-                                  int persistent, hipStream_t st) {
+                                  const float2* layer_stats2, const float* d_cons,
+                                  const float* d_depth, float* grad, long long R, int* queue,
+                                  const int* order, int persistent, hipStream_t st) {
   const int n_items = tile_end - tile_begin;
   if (n_items <= 0) return hipSuccess;
+  if (prm.cons && (!layer_stats2 || (!d_cons && !d_depth))) return hipErrorInvalidValue;
   const int threads = prm.tile_w * prm.tile_h;
   dim3 grid(persistent ? persistent_grid(n_items, threads) : (unsigned)n_items);
   const size_t lds = (size_t)lds_batch * kRecFloats * sizeof(float);
 #define SS_BWD(TW, TH) bwd_t<TW, TH>(grid, lds, st, views, n_views, tile_begin, n_items, ranges, \
                                      sorted_vals, recs, prm, lds_batch, d_image, d_alpha,        \
-                                     n_layers, layer_stats, grad, R, queue, order, persistent)
+                                     n_layers, layer_stats, layer_stats2, d_cons, d_depth, grad, \
+                                     R, queue, order, persistent)
   switch (prm.tile_w * 100 + prm.tile_h) {
     case 808: return SS_BWD(8, 8);
     case 1608: return SS_BWD(16, 8);

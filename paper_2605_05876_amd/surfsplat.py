@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsurfsplat.so")
 
 SS_OK, SS_ERR_INVALID_ARG, SS_ERR_HIP, SS_ERR_CAPACITY, SS_ERR_STATE, SS_ERR_UNSUPPORTED, SS_ERR_NOMEM = range(7)
-SHADE = {"albedo": 0, "splitsum": 1}
+SHADE = {"albedo": 0, "splitsum": 1, "normal": 2}
 LAUNCH = {"batched": 0, "per_view": 1}
 
 EXPORTED = ["ss_default_options", "ss_create", "ss_destroy", "ss_set_options", "ss_brdf_lut",
@@ -38,7 +38,7 @@ class ss_options(ctypes.Structure):
     _fields_ = [("r_cut", ctypes.c_float), ("k_max", ctypes.c_int32), ("gamma", ctypes.c_float),
                 ("sigma_f", ctypes.c_float), ("shade", ctypes.c_int32), ("tile_w", ctypes.c_int32),
                 ("tile_h", ctypes.c_int32), ("lds_batch", ctypes.c_int32), ("launch", ctypes.c_int32),
-                ("persistent", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("depth_stats", ctypes.c_int32)]
 
 
 class ss_camera(ctypes.Structure):
@@ -61,18 +61,21 @@ class ss_batch(ctypes.Structure):
 
 
 class ss_outputs(ctypes.Structure):
-    _fields_ = [("image", ctypes.c_void_p), ("alpha", ctypes.c_void_p), ("n_layers", ctypes.c_void_p)]
+    _fields_ = [("image", ctypes.c_void_p), ("alpha", ctypes.c_void_p), ("n_layers", ctypes.c_void_p),
+                ("cons", ctypes.c_void_p), ("depth", ctypes.c_void_p)]
 
 
 class ss_grad_in(ctypes.Structure):
-    _fields_ = [("d_image", ctypes.c_void_p), ("d_alpha", ctypes.c_void_p)]
+    _fields_ = [("d_image", ctypes.c_void_p), ("d_alpha", ctypes.c_void_p), ("d_cons", ctypes.c_void_p),
+                ("d_depth", ctypes.c_void_p)]
 
 
 class ss_grads(ctypes.Structure):
     _fields_ = [("d_position", ctypes.c_void_p), ("d_normal", ctypes.c_void_p),
                 ("d_tangent", ctypes.c_void_p), ("d_scale", ctypes.c_void_p),
                 ("d_albedo", ctypes.c_void_p), ("d_roughness", ctypes.c_void_p),
-                ("d_metallic", ctypes.c_void_p), ("d_envmap", ctypes.POINTER(ctypes.c_void_p))]
+                ("d_metallic", ctypes.c_void_p), ("d_envmap", ctypes.POINTER(ctypes.c_void_p)),
+                ("screen_grad", ctypes.c_void_p), ("visible_views", ctypes.c_void_p)]
 
 
 class ss_diag(ctypes.Structure):
@@ -141,11 +144,12 @@ class Options:
     lds_batch: int = 128
     launch: str = "batched"
     persistent: bool = True
+    depth_stats: bool = False   # allow forwards to output the eq:cons_loss term
 
     def to_c(self) -> ss_options:
         return ss_options(self.r_cut, self.k_max, self.gamma, self.sigma_f, SHADE[self.shade],
                           self.tile_w, self.tile_h, self.lds_batch, LAUNCH[self.launch],
-                          1 if self.persistent else 0)
+                          1 if self.persistent else 0, 1 if self.depth_stats else 0)
 
 
 def camera_to_c(cam) -> ss_camera:
@@ -259,31 +263,58 @@ class Renderer:
         _check(self.L.ss_reserve(self.ctx, ctypes.byref(batch.c), _stream_ptr(), ctypes.byref(ws)), "ss_reserve")
         return int(ws.value)
 
-    def forward(self, batch: Batch, want_layers: bool = False, out=None):
+    def forward(self, batch: Batch, want_layers: bool = False, out=None, want_cons: bool = False,
+                want_depth: bool = False):
+        """Image [sum HW][3], alpha [sum HW] and layer counts (uint8, if
+        want_layers).  With want_cons / want_depth (options.depth_stats needed) a
+        fourth result, a dict with the per-pixel depth-consolidation term of
+        eq:cons_loss ("cons") and the composited depth ("depth")."""
         dev = batch.params["position"].device
+        aux = {}
         if out is None:
             image = torch.empty((batch.n_pixels, 3), device=dev, dtype=torch.float32)
             alpha = torch.empty((batch.n_pixels,), device=dev, dtype=torch.float32)
             nl = torch.empty((batch.n_pixels,), device=dev, dtype=torch.uint8) if want_layers else None
+            for k, want in (("cons", want_cons), ("depth", want_depth)):
+                if want:
+                    aux[k] = torch.empty((batch.n_pixels,), device=dev, dtype=torch.float32)
+        elif len(out) == 4:
+            image, alpha, nl, aux = out
         else:
             image, alpha, nl = out
-        o = ss_outputs(image.data_ptr(), alpha.data_ptr(), None if nl is None else nl.data_ptr())
+        o = ss_outputs(image.data_ptr(), alpha.data_ptr(), None if nl is None else nl.data_ptr(),
+                       _ptr(aux.get("cons")), _ptr(aux.get("depth")))
         _check(self.L.ss_render(self.ctx, ctypes.byref(batch.c), ctypes.byref(o), _stream_ptr()), "ss_render")
-        return image, alpha, nl
+        return (image, alpha, nl, aux) if aux else (image, alpha, nl)
 
     def backward(self, batch: Batch, d_image: torch.Tensor, d_alpha: Optional[torch.Tensor] = None,
-                 grads: Optional[dict] = None, want_envmap: bool = True):
+                 grads: Optional[dict] = None, want_envmap: bool = True, want_screen_grad: bool = False,
+                 d_cons: Optional[torch.Tensor] = None, d_depth: Optional[torch.Tensor] = None):
+        """Parameter gradients of the last forward.  With want_screen_grad (or
+        "screen_grad" / "visible_views" tensors in `grads`) also the
+        densification statistic of Sec. 3.6.1: float32 [N] sum over views and
+        pixels of |(dL_p/dT1z, dL_p/dT2z)| T4z and int32 [N] visible-view count."""
         dev = batch.params["position"].device
         if grads is None:
             grads = {k: torch.empty_like(batch.params[k]) for k in PARAMS}
             if batch.envmaps is not None and want_envmap:
                 grads["envmap"] = [torch.empty_like(e) for e in batch.envmaps]
+            if want_screen_grad:
+                n = batch.params["position"].shape[1]
+                grads["screen_grad"] = torch.empty(n, device=dev, dtype=torch.float32)
+                grads["visible_views"] = torch.empty(n, device=dev, dtype=torch.int32)
         d_image = d_image.contiguous()
         d_alpha = None if d_alpha is None else d_alpha.contiguous()
-        gi = ss_grad_in(d_image.data_ptr(), None if d_alpha is None else d_alpha.data_ptr())
+        d_cons = None if d_cons is None else d_cons.contiguous()
+        d_depth = None if d_depth is None else d_depth.contiguous()
+        gi = ss_grad_in(d_image.data_ptr(), None if d_alpha is None else d_alpha.data_ptr(),
+                        None if d_cons is None else d_cons.data_ptr(),
+                        None if d_depth is None else d_depth.data_ptr())
         g = ss_grads()
         for k in PARAMS:
             setattr(g, "d_" + k, None if grads.get(k) is None else grads[k].data_ptr())
+        for k in ("screen_grad", "visible_views"):
+            setattr(g, k, None if grads.get(k) is None else grads[k].data_ptr())
         env_keep = None
         if grads.get("envmap") is not None:
             env_keep = (ctypes.c_void_p * len(grads["envmap"]))(*[e.data_ptr() for e in grads["envmap"]])

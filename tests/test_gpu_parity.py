@@ -252,6 +252,170 @@ def test_backward_parity_multiview(O, ss):
     assert max(errs.values()) <= GRAD_REL_L2, errs
 
 
+# ---------------------------------------------------------------- densification statistic
+def _two_scene_views():
+    a = g.sphere_scene(41, 3000, scale=0.03, svbrdf=True)
+    b = g.torus_scene(42, 8000, scale_mu=math.log(0.02), scale_sigma=0.3)
+    a.envmap = g.lognormal_envmap(43, 16, 32)
+    b.envmap = g.lognormal_envmap(44, 16, 32)
+    cams = [g.look_at_camera(3.0 * d, 64, 48) for d in g.fibonacci_directions(2)]
+    cams += [g.look_at_camera(3.0 * d, 56, 72, scene=1) for d in g.fibonacci_directions(3)[1:]]
+    return [a, b], cams
+
+
+@pytest.mark.parametrize("case", ["C1_sigma0.5", "multiview", "two_scenes"])
+def test_screen_grad_parity(O, ss, case):
+    """Sec. 3.6.1 statistic (sum over views and pixels of |(dL_p/dT1z, dL_p/dT2z)| T4z)
+    and the visible-view count against the oracle; the other gradients are unchanged
+    by requesting it."""
+    if case == "C1_sigma0.5":
+        w = g.make_config("C1")
+        scenes, cams, shade, kw = w.scenes, w.cameras, "albedo", dict(sigma_f=0.5)
+    elif case == "multiview":
+        scenes, cams = small_multiview()
+        shade, kw = "splitsum", {}
+    else:
+        scenes, cams = _two_scene_views()
+        shade, kw = "splitsum", {}
+    opts = ss.Options(shade=shade, **kw)
+    maps, lut = oracle_maps(O, scenes, shade)
+    oo = oracle_options(O, opts)
+    pix = [all_pix(c) for c in cams]
+    ref = oracle_forward(O, scenes, cams, opts, pix, maps, lut, conditioning=False)
+    n_pix = sum(c.width * c.height for c in cams)
+    rng = np.random.default_rng(17)
+    G = np.zeros((n_pix, 3))
+    Ga = np.zeros(n_pix)
+    want_abs = [np.zeros(s.n) for s in scenes]
+    want_vis = [np.zeros(s.n, np.int64) for s in scenes]
+    for v, c in enumerate(cams):
+        ok = decision_ok(ref[v])
+        gv = rng.normal(size=(len(pix[v]), 3)) * ok[:, None]
+        gav = rng.normal(size=len(pix[v])) * ok
+        idx = pixel_index(cams, v, pix[v])
+        G[idx] = gv
+        Ga[idx] = gav
+        sc = scenes[c.scene]
+        hw = tuple(np.asarray(sc.envmap).shape[:2]) if maps[c.scene] is not None else (0, 0)
+        r = O.screen_grad(sc, c, oo, pix[v], gv, gav, maps=maps[c.scene], lut=lut, env_hw=hw)
+        want_abs[c.scene] += r["abs"]
+        want_vis[c.scene] += r["visible"]
+    r = ss.Renderer(opts)
+    b = ss.batch_from_scenes(scenes, cams)
+    r.forward(b)
+    assert r.poll()["status"] == 0
+    gt = torch.from_numpy(np.ascontiguousarray(G, np.float32)).cuda()
+    ga = torch.from_numpy(np.ascontiguousarray(Ga, np.float32)).cuda()
+    with_ss = r.backward(b, gt, ga, want_screen_grad=True)
+    plain = r.backward(b, gt, ga)
+    torch.cuda.synchronize()
+    got_abs = with_ss["screen_grad"].cpu().numpy()
+    got_vis = with_ss["visible_views"].cpu().numpy()
+    np.testing.assert_array_equal(got_vis, np.concatenate(want_vis))
+    wa = np.concatenate(want_abs)
+    assert wa.max() > 0 and (got_abs >= 0).all()
+    assert rel_l2(got_abs, wa) <= GRAD_REL_L2, rel_l2(got_abs, wa)
+    for k in ("position", "normal", "scale", "albedo"):
+        assert rel_l2(with_ss[k].cpu().numpy(), plain[k].cpu().numpy()) <= 1e-5, k
+
+
+# ---------------------------------------------------------------- depth consolidation
+@pytest.mark.parametrize("case", ["C1", "multiview"])
+def test_cons_parity(O, ss, case):
+    """eq:cons_loss per pixel against the oracle (relative L2 <= 1e-3: the FP32 depth of
+    a fragment carries ~2 ulp(z) from T4z = (z_start + z_end)/2, against layer depth
+    spreads of ~1e-2), the composited depth (image protocol), the image unchanged by
+    the extra statistics, and the gradients of a loss on image, cons and depth
+    together (relative L2 <= 1e-3 per group)."""
+    if case == "C1":
+        w = g.make_config("C1")
+        scenes, cams, shade = w.scenes, w.cameras, "albedo"
+    else:
+        scenes, cams = small_multiview()
+        shade = "splitsum"
+    opts = ss.Options(shade=shade, depth_stats=True)
+    maps, lut = oracle_maps(O, scenes, shade)
+    oo = oracle_options(O, opts)
+    pix = [all_pix(c) for c in cams]
+    ref = oracle_forward(O, scenes, cams, opts, pix, maps, lut, conditioning=False)
+    r = ss.Renderer(opts)
+    b = ss.batch_from_scenes(scenes, cams)
+    img0, a0, _ = r.forward(b)
+    img0, a0 = img0.cpu().numpy(), a0.cpu().numpy()
+    img, a, nl, aux = r.forward(b, want_layers=True, want_cons=True, want_depth=True)
+    assert r.poll()["status"] == 0
+    img, a = img.cpu().numpy(), a.cpu().numpy()
+    cons, depth = aux["cons"].cpu().numpy(), aux["depth"].cpu().numpy()
+    np.testing.assert_array_equal(img, img0)
+    np.testing.assert_array_equal(a, a0)
+    want, got, want_z, got_z = [], [], [], []
+    n_pix = sum(c.width * c.height for c in cams)
+    rng = np.random.default_rng(23)
+    G = np.zeros((n_pix, 3))
+    Dc = np.zeros(n_pix)
+    Dz = np.zeros(n_pix)
+    per_view = []
+    for v, c in enumerate(cams):
+        ok = decision_ok(ref[v])
+        idx = pixel_index(cams, v, pix[v])
+        want.append(ref[v]["cons"][ok])
+        got.append(cons[idx][ok])
+        want_z.append(ref[v]["depth"][ok])
+        got_z.append(depth[idx][ok])
+        gv = rng.normal(size=(len(pix[v]), 3)) * ok[:, None]
+        dcv = rng.normal(size=len(pix[v])) * ok * 10.0
+        dzv = rng.normal(size=len(pix[v])) * ok
+        G[idx] = gv
+        Dc[idx] = dcv
+        Dz[idx] = dzv
+        per_view.append((gv, dcv, dzv))
+    want, got = np.concatenate(want), np.concatenate(got)
+    assert want.max() > 0
+    assert rel_l2(got, want) <= 1e-3, rel_l2(got, want)
+    # composited depth: the image protocol (relative L2 1e-4, per pixel 1e-4 of max(|ref|, 1e-2 max))
+    want_z, got_z = np.concatenate(want_z), np.concatenate(got_z)
+    assert rel_l2(got_z, want_z) <= 1e-4, rel_l2(got_z, want_z)
+    bound = 1e-4 * np.maximum(np.abs(want_z), 1e-2 * np.abs(want_z).max())
+    assert (np.abs(got_z - want_z) <= bound).mean() >= 0.99
+    gt = torch.from_numpy(np.ascontiguousarray(G, np.float32)).cuda()
+    dct = torch.from_numpy(np.ascontiguousarray(Dc, np.float32)).cuda()
+    dzt = torch.from_numpy(np.ascontiguousarray(Dz, np.float32)).cuda()
+    gg = r.backward(b, gt, None, d_cons=dct, d_depth=dzt)
+    gg = {k: v.cpu().numpy() for k, v in gg.items() if not isinstance(v, list)}
+    names = ["position", "normal", "tangent", "scale", "albedo"]
+    ref_g = [{k: np.zeros_like(getattr(sc, k), dtype=np.float64) for k in names} for sc in scenes]
+    for v, c in enumerate(cams):
+        sc = scenes[c.scene]
+        hw = tuple(np.asarray(sc.envmap).shape[:2]) if maps[c.scene] is not None else (0, 0)
+        gr = O.render_grad(sc, c, oo, pix[v], per_view[v][0], None, maps=maps[c.scene], lut=lut, env_hw=hw,
+                           dcons=per_view[v][1], ddepth=per_view[v][2])
+        for k in names:
+            ref_g[c.scene][k] += gr[k]
+    pos_norm = np.linalg.norm(np.concatenate([rg["position"] for rg in ref_g], axis=-1))
+    for k in names:
+        want_k = np.concatenate([rg[k] for rg in ref_g], axis=-1)
+        if np.linalg.norm(want_k) < 1e-9 * pos_norm:
+            assert np.linalg.norm(gg[k]) <= 1e-6 * pos_norm, k
+            continue
+        assert rel_l2(gg[k], want_k) <= GRAD_REL_L2, (k, rel_l2(gg[k], want_k))
+    # without a cons forward the cons adjoint is refused
+    r.forward(b)
+    with pytest.raises(RuntimeError):
+        r.backward(b, gt, None, d_cons=dct)
+
+
+def test_normal_image_parity(O, ss):
+    """Normal image (Sec. 4.2.3): per layer the Shepard mean of the unit normals,
+    renormalised, composited like colour; forward with the image protocol and the
+    geometric gradients (relative L2 <= 1e-3 per group)."""
+    scenes, cams = small_multiview()
+    rep = _forward_case(O, ss, scenes, cams, "normal", lambda c, v: all_pix(c))
+    assert_image_parity(rep)
+    errs = _backward_case(O, ss, scenes, cams, "normal", lambda c, v: all_pix(c), seed=5)
+    errs = {k: e for k, e in errs.items() if k not in ("albedo", "roughness", "metallic")}
+    assert max(errs.values()) <= GRAD_REL_L2, errs
+
+
 # ---------------------------------------------------------------- tables, invariances, edges
 def test_brdf_lut_matches_oracle(O, ss):
     lut = ss.make_brdf_lut(64, 64, 1024).cpu().numpy()
