@@ -49,7 +49,7 @@ def lib():
         L.orc_envmap.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp]
         L.orc_envmap_adjoint.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp]
         L.orc_brdf_lut.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
-        L.orc_bin_f32.argtypes = [fpp, ctypes.c_int, dp, dp, ip, ctypes.POINTER(ctypes.c_uint32), ip]
+        L.orc_bin_f32.argtypes = [fpp, ctypes.c_int, dp, dp, ip, ctypes.POINTER(ctypes.c_uint32), ip, ip]
         L.orc_render.argtypes = [fpp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp,
                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, dp, dp, ip, dp, dp]
         L.orc_render_jvp.argtypes = [fpp, ctypes.c_int, fpp, dp, dp, dp, dp, ctypes.c_int, ctypes.c_int,
@@ -75,12 +75,13 @@ class Options:
     shade: str = "albedo"          # "albedo" | "splitsum" | "normal"
     tile_w: int = 16
     tile_h: int = 16
+    mip: str = "centre"            # "centre" (Sec. 3.3.2) | "pixel" (per-pixel Jacobian, Sec. 3.3.1)
 
     def pack(self):
         f = lambda x: float(np.float32(x))
         return np.array([f(self.r_cut), f(self.gamma), f(self.sigma_f), self.k_max,
-                         {"albedo": 0, "splitsum": 1, "normal": 2}[self.shade], self.tile_w, self.tile_h],
-                        np.float64)
+                         {"albedo": 0, "splitsum": 1, "normal": 2}[self.shade], self.tile_w, self.tile_h,
+                         {"centre": 0, "pixel": 1}[self.mip]], np.float64)
 
 
 def _dptr(a):
@@ -161,8 +162,22 @@ def bin_f32(scene, cam, opt: Options):
     c = pack_camera(cam)
     o = opt.pack()
     lib().orc_bin_f32(P.pp, n, _dptr(c), _dptr(o), _iptr(keep),
-                      zbits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), _iptr(rect))
+                      zbits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), _iptr(rect), None)
     return keep, zbits, rect
+
+
+def pixel_rects(scene, cam, opt: Options):
+    """Inclusive pixel rectangles (il, ih, jl, jh) of the FP32 binning, [n][4]."""
+    P = _Params(scene)
+    n = P.n
+    keep = np.zeros(n, np.int32)
+    zbits = np.zeros(n, np.uint32)
+    rect = np.zeros((n, 4), np.int32)
+    prect = np.zeros((n, 4), np.int32)
+    c, o = pack_camera(cam), opt.pack()
+    lib().orc_bin_f32(P.pp, n, _dptr(c), _dptr(o), _iptr(keep),
+                      zbits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), _iptr(rect), _iptr(prect))
+    return prect
 
 
 def sorted_pairs(keep, zbits, rect, tiles_x, tile_base=0, rec_base=0):

@@ -48,6 +48,7 @@ struct Cam {
 struct Opt {
   double r_cut, gamma, sigma_f;
   int k_max, shade, tile_w, tile_h;
+  int mip;  // 0: centre-precomputed MIP filter (Sec. 3.3.2); 1: per-pixel Jacobian (Sec. 3.3.1)
 };
 static Cam unpack_cam(const double* c) {
   Cam k;
@@ -63,6 +64,7 @@ static Opt unpack_opt(const double* o) {
   Opt p;
   p.r_cut = o[0]; p.gamma = o[1]; p.sigma_f = o[2];
   p.k_max = (int)o[3]; p.shade = (int)o[4]; p.tile_w = (int)o[5]; p.tile_h = (int)o[6];
+  p.mip = (int)o[7];
   return p;
 }
 
@@ -79,6 +81,7 @@ template <class S> struct Rec {
   S sinv[3];  // Sigma_mip^{-1}: uu, uv, vv
   S nf;
   S col[3];
+  int rect[4] = {0, -1, 0, -1};  // FP32 binning pixel rectangle il, ih, jl, jh
 };
 
 // ------------------------------------------------------------ environment maps
@@ -468,9 +471,14 @@ struct BinOut {
   int keep;
   float zs;
   int tx0, ty0, tx1, ty1;  // inclusive tile rectangle (empty: keep = 0)
+  int il, ih, jl, jh;      // inclusive pixel rectangle
 };
+template <class S> static void set_rect(Rec<S>& r, const BinOut& b) {
+  r.rect[0] = b.il; r.rect[1] = b.ih; r.rect[2] = b.jl; r.rect[3] = b.jh;
+}
+
 static BinOut bin_f32(const float* const* P, int n, int i, const Cam& cd, const Opt& od) {
-  BinOut b{0, 0.f, 0, 0, -1, -1};
+  BinOut b{0, 0.f, 0, 0, -1, -1, 0, -1, 0, -1};
   const float nx = P[1][i], ny = P[1][n + i], nz = P[1][2 * n + i];
   const float tx = P[2][i], ty = P[2][n + i], tz = P[2][2 * n + i];
   const float su = P[3][i], sv = P[3][n + i];
@@ -535,6 +543,7 @@ static BinOut bin_f32(const float* const* P, int n, int i, const Cam& cd, const 
   jl = std::max(jl, 0.f); jh = std::min(jh, (float)(cd.H - 1));
   if (!(il <= ih) || !(jl <= jh)) return b;
   b.keep = 1;
+  b.il = (int)il; b.ih = (int)ih; b.jl = (int)jl; b.jh = (int)jh;
   b.tx0 = (int)il / od.tile_w; b.tx1 = (int)ih / od.tile_w;
   b.ty0 = (int)jl / od.tile_h; b.ty1 = (int)jh / od.tile_h;
   return b;
@@ -579,6 +588,50 @@ static S frag_weight(const Rec<S>& r, double x, double y, double rc2, bool& hit,
   return r.nf * exp(-0.5 * q);
 }
 
+// Per-pixel MIP variant (Sec. 3.3.1, the formulation the centre precomputation
+// approximates): the Jacobian J = d(u,v)/d(x,y) of the ray-surfel
+// intersection is taken at this pixel's intersection (quotient rule on
+// u = p1/p3, v = p2/p3 with dp/dx = T4 x l, dp/dy = k x T4), then
+// Sigma_mip = I + sigma_f J J^T, q = u^T Sigma_mip^{-1} u, n_f = |Sigma_mip|^{-1/2}.
+// Reading: the support stays the FP32 binning rectangle of the centre filter
+// (the variant runs inside the same binning) intersected with q < r_cut^2.
+template <class S>
+static S frag_weight_pp(const Rec<S>& r, double x, double y, double rc2, double sigma_f, bool& hit,
+                        double& q_val, S* zf = nullptr) {
+  using std::sqrt;
+  using std::exp;
+  hit = false;
+  q_val = INFINITY;
+  const int px = (int)std::floor(x), py = (int)std::floor(y);
+  if (px < r.rect[0] || px > r.rect[1] || py < r.rect[2] || py > r.rect[3]) return S(0.0);
+  S k[3], l[3];
+  for (int i = 0; i < 3; ++i) { k[i] = x * r.T4[i] - r.T1[i]; l[i] = y * r.T4[i] - r.T2[i]; }
+  S p1 = k[1] * l[2] - k[2] * l[1];
+  S p2 = k[2] * l[0] - k[0] * l[2];
+  S p3 = k[0] * l[1] - k[1] * l[0];
+  if (val(p3) == 0.0) return S(0.0);
+  S u = p1 / p3, v = p2 / p3;
+  S h = r.T4[0] * u + r.T4[1] * v + r.T4[2];
+  if (val(h) <= 0.0) return S(0.0);
+  if (zf) *zf = h;
+  // dp/dx = T4 x l, dp/dy = k x T4
+  S px1 = r.T4[1] * l[2] - r.T4[2] * l[1], px2 = r.T4[2] * l[0] - r.T4[0] * l[2],
+    px3 = r.T4[0] * l[1] - r.T4[1] * l[0];
+  S py1 = k[1] * r.T4[2] - k[2] * r.T4[1], py2 = k[2] * r.T4[0] - k[0] * r.T4[2],
+    py3 = k[0] * r.T4[1] - k[1] * r.T4[0];
+  S Jux = (px1 - u * px3) / p3, Juy = (py1 - u * py3) / p3;
+  S Jvx = (px2 - v * px3) / p3, Jvy = (py2 - v * py3) / p3;
+  S s11 = 1.0 + sigma_f * (Jux * Jux + Juy * Juy);
+  S s12 = sigma_f * (Jux * Jvx + Juy * Jvy);
+  S s22 = 1.0 + sigma_f * (Jvx * Jvx + Jvy * Jvy);
+  S det = s11 * s22 - s12 * s12;
+  S q = (s22 * u * u - 2.0 * s12 * u * v + s11 * v * v) / det;
+  q_val = val(q);
+  if (!(q_val < rc2)) return S(0.0);
+  hit = true;
+  return sqrt(1.0 / det) * exp(-0.5 * q);
+}
+
 template <class S>
 static void pixel_eval(double x, double y, const Rec<S>* recs, const std::vector<int>& cand,
                        const Cam& cam, const Opt& o, PixOut<S>& out, PixDiag* dg,
@@ -593,7 +646,8 @@ static void pixel_eval(double x, double y, const Rec<S>* recs, const std::vector
     bool hit;
     double q;
     S z(0.0);
-    S w = frag_weight(recs[i], x, y, rc2, hit, q, &z);
+    S w = o.mip == 1 ? frag_weight_pp(recs[i], x, y, rc2, o.sigma_f, hit, q, &z)
+                     : frag_weight(recs[i], x, y, rc2, hit, q, &z);
     if (std::isfinite(q)) cm = std::min(cm, std::fabs(q - rc2) / rc2);
     if (!hit) continue;
     fr.push_back({val(recs[i].zs), i, w, recs[i].ze, &recs[i], z});
@@ -717,9 +771,10 @@ int orc_brdf_lut(int n_nv, int n_r, int samples, double* out) {
 
 // FP32 binning reference.  P: the 7 parameter arrays (position, normal, tangent,
 // scale, albedo, roughness, metallic; [C][n] float32).  Outputs per surfel:
-// keep, z_start (float bits), inclusive tile rectangle.
+// keep, z_start (float bits), inclusive tile rectangle (tx0, ty0, tx1, ty1) and
+// (pixel_rect, nullable) the inclusive pixel rectangle (il, ih, jl, jh).
 int orc_bin_f32(const float* const* P, int n, const double* cam, const double* opt,
-                int* keep, uint32_t* zbits, int* rect) {
+                int* keep, uint32_t* zbits, int* rect, int* pixel_rect) {
   Cam c = unpack_cam(cam);
   Opt o = unpack_opt(opt);
   for (int i = 0; i < n; ++i) {
@@ -728,6 +783,10 @@ int orc_bin_f32(const float* const* P, int n, const double* cam, const double* o
     std::memcpy(&zbits[i], &b.zs, 4);
     rect[4 * i + 0] = b.tx0; rect[4 * i + 1] = b.ty0;
     rect[4 * i + 2] = b.tx1; rect[4 * i + 3] = b.ty1;
+    if (pixel_rect) {
+      pixel_rect[4 * i + 0] = b.il; pixel_rect[4 * i + 1] = b.ih;
+      pixel_rect[4 * i + 2] = b.jl; pixel_rect[4 * i + 3] = b.jh;
+    }
   }
   return 0;
 }
@@ -757,6 +816,7 @@ int orc_render(const float* const* P, int n, const double* cam, const double* op
     if (!bins[i].keep) continue;
     Surf<double> s = load_surf<double>(P, n, i, nullptr);
     preprocess(s, c, o, M, &md, &L, recs[i]);
+    set_rect(recs[i], bins[i]);
   }
   for (int i = 0; i < n; ++i)
     if (bins[i].keep) cand.push_back(i);
@@ -803,10 +863,12 @@ int orc_render_jvp(const float* const* P, int n, const double* const* V, const d
   MapsDual M{maps, dmaps};
 #pragma omp parallel for schedule(static)
   for (int i = 0; i < n; ++i) {
-    keep[i] = bin_f32(P, n, i, c, o).keep;
+    const BinOut bo = bin_f32(P, n, i, c, o);
+    keep[i] = bo.keep;
     if (!keep[i]) continue;
     Surf<Dual> s = load_surf<Dual>(P, n, i, V);
     preprocess(s, c, o, M, &md, &L, recs[i]);
+    set_rect(recs[i], bo);
   }
   for (int i = 0; i < n; ++i)
     if (keep[i]) cand.push_back(i);
@@ -845,10 +907,12 @@ int orc_render_grad(const float* const* P, int n, const double* cam, const doubl
   if (dmaps && He > 0) std::fill(dmaps, dmaps + md.total(), 0.0);
 #pragma omp parallel for schedule(static)
   for (int i = 0; i < n; ++i) {
-    keep[i] = bin_f32(P, n, i, c, o).keep;
+    const BinOut bo = bin_f32(P, n, i, c, o);
+    keep[i] = bo.keep;
     if (!keep[i]) continue;
     Surf<double> s = load_surf<double>(P, n, i, nullptr);
     preprocess(s, c, o, Md, &md, &L, recs[i]);
+    set_rect(recs[i], bo);
   }
   for (int i = 0; i < n; ++i)
     if (keep[i]) cand.push_back(i);
@@ -876,6 +940,7 @@ int orc_render_grad(const float* const* P, int n, const double* cam, const doubl
         Rec<Var>& v = vr[j];
         for (int a = 0; a < 3; ++a) { v.T1[a] = Var::leaf(r.T1[a]); v.T2[a] = Var::leaf(r.T2[a]); v.T4[a] = Var::leaf(r.T4[a]); }
         v.zs = Var(r.zs); v.ze = Var(r.ze);
+        for (int a = 0; a < 4; ++a) v.rect[a] = r.rect[a];
         for (int a = 0; a < 3; ++a) v.sinv[a] = Var::leaf(r.sinv[a]);
         v.nf = Var::leaf(r.nf);
         for (int a = 0; a < 3; ++a) v.col[a] = Var::leaf(r.col[a]);
@@ -987,10 +1052,12 @@ int orc_screen_grad(const float* const* P, int n, const double* cam, const doubl
   MapsD Md{maps};
 #pragma omp parallel for schedule(static)
   for (int i = 0; i < n; ++i) {
-    keep[i] = bin_f32(P, n, i, c, o).keep;
+    const BinOut bo = bin_f32(P, n, i, c, o);
+    keep[i] = bo.keep;
     if (!keep[i]) continue;
     Surf<double> s = load_surf<double>(P, n, i, nullptr);
     preprocess(s, c, o, Md, &md, &L, recs[i]);
+    set_rect(recs[i], bo);
   }
   for (int i = 0; i < n; ++i) {
     if (keep[i]) cand.push_back(i);
@@ -1017,6 +1084,7 @@ int orc_screen_grad(const float* const* P, int n, const double* cam, const doubl
         Rec<Var>& v = vr[j];
         for (int a = 0; a < 3; ++a) { v.T1[a] = Var::leaf(r.T1[a]); v.T2[a] = Var::leaf(r.T2[a]); v.T4[a] = Var::leaf(r.T4[a]); }
         v.zs = Var(r.zs); v.ze = Var(r.ze);
+        for (int a = 0; a < 4; ++a) v.rect[a] = r.rect[a];
         mip_filter(v, o.sigma_f);
         for (int a = 0; a < 3; ++a) v.col[a] = Var::leaf(r.col[a]);
       }
@@ -1066,9 +1134,11 @@ int orc_pixel_fragments(const float* const* P, int n, const double* cam, const d
   Lut L{lut, n_nv, n_r};
   MapsD M{maps};
   for (int i = 0; i < n; ++i) {
-    if (!bin_f32(P, n, i, c, o).keep) continue;
+    const BinOut bo = bin_f32(P, n, i, c, o);
+    if (!bo.keep) continue;
     Surf<double> s = load_surf<double>(P, n, i, nullptr);
     preprocess(s, c, o, M, &md, &L, recs[i]);
+    set_rect(recs[i], bo);
     cand.push_back(i);
   }
   PixOut<double> out;
