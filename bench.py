@@ -104,6 +104,9 @@ def main():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="eager steps only (for rocprofv3)")
+    ap.add_argument("--mip-ablation", action="store_true",
+                    help="forward time of the 4M-surfel checkerboard at 800x600 with no MIP filter, the "
+                         "centre-precomputed filter, the per-pixel Jacobian and 4x supersampling")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -121,6 +124,8 @@ def main():
     from paper_2605_05876_amd import autotune
 
     torch.cuda.set_device(0)
+    if args.mip_ablation:
+        return mip_ablation(args)
     t0 = time.perf_counter()
     w = g.make_config(args.config)
     log(f"[bench] workload {args.config}: {w.n_surfels} surfels, {len(w.cameras)} views, "
@@ -241,19 +246,90 @@ def main():
     torch.cuda.empty_cache()
 
     if not args.no_per_view:
+        # plain per-view launches (one launch chain per view, eager), and the same
+        # captured in a graph
         rp, stepp, _, bp = make("per_view")
         stepp()
         torch.cuda.synchronize()
-        msp = timed(stepp, args.steps, use_graph)
+        msp = timed(stepp, args.steps, False)
         out["per_view"] = {"value": round(n_pix / (msp * 1e-3) / 1e6, 2), "ms_per_step": round(msp, 4),
-                           "speedup_batched": round(msp / ms, 3)}
-        log(f"[bench] per-view{'+graph' if use_graph else ''}: {msp:.3f} ms/step")
+                           "launch": "per-view, eager", "speedup_batched": round(msp / ms, 3)}
+        log(f"[bench] per-view eager: {msp:.3f} ms/step")
+        if use_graph:
+            msg = timed(stepp, args.steps, True)
+            out["per_view"]["graph_ms_per_step"] = round(msg, 4)
+            log(f"[bench] per-view+graph: {msg:.3f} ms/step")
         del rp, stepp, bp
         torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(w, w.shade)
+    print(json.dumps(out), flush=True)
+
+
+def mip_ablation(args):
+    """Anti-aliasing comparison of Sec. 4.4.2 on its synthetic scene: forward time per
+    frame of a 4M-surfel checkerboard plane at 800x600 with (a) no MIP filter
+    (sigma_f = 0), (b) the centre-precomputed filter, (c) the per-pixel Jacobian and
+    (d) 4x supersampling (1600x1200 without the filter, then a 2x2 box filter)."""
+    import torch
+    import torch.nn.functional as F
+
+    import paper_2605_05876_amd as ss
+    import scenegen as g
+
+    t0 = time.perf_counter()
+    w = g.checkerboard_workload()
+    big = g.checkerboard_workload(width=1600, height=1200)
+    log(f"[mip] checkerboard: {w.n_surfels} surfels ({time.perf_counter() - t0:.1f} s to generate)")
+    batch = ss.batch_from_scenes(w.scenes, w.cameras)
+    batch_big = ss.batch_from_scenes(big.scenes, big.cameras)
+    sigma = 0.1
+    cases = {"none": (batch, dict(sigma_f=0.0)), "centre": (batch, dict(sigma_f=sigma)),
+             "per_pixel": (batch, dict(sigma_f=sigma, mip="pixel")), "ssaa4x": (batch_big, dict(sigma_f=0.0))}
+    out = {"metric": "forward ms/frame, 4M-surfel checkerboard plane, 800x600", "unit": "ms",
+           "higher_is_better": False, "dtype": "f32", "data": "synthetic", "steps": args.steps,
+           "config": {"workload": "ground plane 2000^2 lattice over [-10,10]^2, checker 0.2, camera at "
+                                  "(0,-10.6,0.45) looking at the origin, 45 deg vertical FOV",
+                      "sigma_f": sigma},
+           "paper_ms_context": {"none": 42, "centre": 50, "per_pixel": 65, "ssaa4x": 87}}
+    images = {}
+    for name, (b, kw) in cases.items():
+        r = ss.Renderer(ss.Options(shade="albedo", **kw))
+        r.reserve(b)
+        img = torch.empty((b.n_pixels, 3), device="cuda")
+        alpha = torch.empty((b.n_pixels,), device="cuda")
+        cam = b.cameras[0]
+
+        def step():
+            r.forward(b, out=(img, alpha, None))
+            if name == "ssaa4x":
+                x = img.view(cam.height, cam.width, 3).permute(2, 0, 1)[None]
+                return F.avg_pool2d(x, 2)
+            return img
+        step()
+        torch.cuda.synchronize()
+        assert r.poll()["status"] == 0
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            res = step()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(e0.elapsed_time(e1) / args.steps, 3)
+        res = res.reshape(3, -1).t() if name == "ssaa4x" else res
+        images[name] = res.reshape(-1, 3).float().cpu()
+        log(f"[mip] {name}: {out[name]:.3f} ms/frame")
+        del r
+        torch.cuda.empty_cache()
+    # how far each filtered image is from the supersampled one (a quality context)
+    ref = images["ssaa4x"]
+    out["rms_vs_ssaa4x"] = {k: round(float((v - ref).pow(2).mean().sqrt()), 5) for k, v in images.items()
+                            if k != "ssaa4x"}
     print(json.dumps(out), flush=True)
 
 

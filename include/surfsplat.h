@@ -86,6 +86,11 @@ typedef struct ss_options {
   int32_t depth_stats; /* 1: reserve per-layer depth statistics (8 bytes x 16 layers
                           per pixel) so that forwards may output the
                           depth-consolidation term (ss_outputs.cons)            */
+  int32_t mip;         /* 0: centre-precomputed MIP filter (Sec. 3.3.2, default);
+                          1: per-pixel Jacobian (Sec. 3.3.1): J = d(u,v)/d(x,y) at
+                          every intersection, support = the binning rectangle of the
+                          centre filter intersected with rho^2 < r_cut^2.  Forward
+                          only: ss_render_backward returns SS_ERR_UNSUPPORTED     */
 } ss_options;
 
 typedef struct ss_camera {

@@ -5,7 +5,8 @@ include/surfsplat.h); `surfsplat` is its ctypes binding and the
 torch.autograd.Function around it.
 """
 from .surfsplat import (Batch, Options, Renderer, SurfsplatError, SurfelRenderFunction,  # noqa: F401
-                        load_library, make_brdf_lut, render, PARAMS)
+                        load_library, make_brdf_lut, render, PARAMS, SS_OK, SS_ERR_INVALID_ARG, SS_ERR_HIP,
+                        SS_ERR_CAPACITY, SS_ERR_STATE, SS_ERR_UNSUPPORTED, SS_ERR_NOMEM)
 
 
 def batch_from_scenes(scenes, cameras, device="cuda", with_envmap=None):

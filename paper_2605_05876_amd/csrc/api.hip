@@ -125,6 +125,7 @@ ss_status check_options(const ss_options* o) {
     return SS_ERR_UNSUPPORTED;
   if (o->launch != SS_LAUNCH_BATCHED && o->launch != SS_LAUNCH_PER_VIEW) return SS_ERR_INVALID_ARG;
   if (o->depth_stats != 0 && o->depth_stats != 1) return SS_ERR_INVALID_ARG;
+  if (o->mip != 0 && o->mip != 1) return SS_ERR_INVALID_ARG;
   return SS_OK;
 }
 
@@ -196,6 +197,7 @@ Params make_params(const ss_context* c) {
   p.lut_r = c->lut_r;
   p.ss_grad = 0;
   p.cons = 0;
+  p.mip = c->opt.mip;
   return p;
 }
 
@@ -483,6 +485,7 @@ ss_status ss_default_options(ss_options* o) {
   o->launch = SS_LAUNCH_BATCHED;
   o->persistent = 1;
   o->depth_stats = 0;
+  o->mip = 0;
   return SS_OK;
 }
 
@@ -621,6 +624,7 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
                              const ss_grads* gr, ss_stream stream) {
   if (!c || !gin || !gin->d_image || !gr) return SS_ERR_INVALID_ARG;
   SS_TRY(check_batch(c, b));
+  if (c->opt.mip != 0) return SS_ERR_UNSUPPORTED;
   if (!c->fwd_valid || signature(c, b) != c->fwd_sig) return SS_ERR_STATE;
   if ((gin->d_cons || gin->d_depth) && !c->fwd_cons) return SS_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;

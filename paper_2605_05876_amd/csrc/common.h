@@ -59,6 +59,7 @@ struct Params {
   int lut_nv, lut_r;
   int ss_grad;  // backward: accumulate the screen-space gradient statistic in slot G_SS
   int cons;     // forward: depth statistics (eq:cons_loss, depth image); backward: their adjoint
+  int mip;      // 0: centre-precomputed MIP filter; 1: per-pixel Jacobian (forward only)
 };
 
 // ---------------------------------------------------------------- FP32 binning
@@ -181,6 +182,41 @@ __device__ __forceinline__ void frag_eval(const float* rec, int px, int py, floa
   f.cov = f.N < r2 * s2;
   f.q = f.N * __builtin_amdgcn_rcpf(s2);
   f.w = rec[R_NF] * __expf(-0.5f * f.q);
+}
+
+// Per-pixel-Jacobian variant of the MIP filter (Sec. 3.3.1): J = d(u,v)/d(x,y)
+// at this pixel's intersection.  With u = J_c d / s (J_c = M^{-1} at the
+// centre, s = 1 + a.d), J = (J_c / s)(I - d a^T / s) and its inverse is
+// M_p = s (I + d a^T) M_c, so with B = M_c M_c^T = Q^{-1} - sigma_f I and
+// S = M_p M_p^T + sigma_f I:  rho^2 = u^T (I + sigma_f J J^T)^{-1} u = s^2 d^T S^{-1} d
+// and n_f = sqrt(det(M_p M_p^T) / det S) = sqrt(s^6 det B / det S), where
+// det B = n_f(centre)^2 / det Q avoids the cancellation in Q^{-1} - sigma_f I.
+// The support is the binning rectangle intersected with rho^2 < r^2.
+__device__ __forceinline__ void frag_eval_pp(const float* rec, int px, int py, float r2, float sigma,
+                                             FragEval& f) {
+  const int rx = __float_as_int(rec[R_RX]), ry = __float_as_int(rec[R_RY]);
+  const int il = rx & 0xffff, ih = rx >> 16, jl = ry & 0xffff, jh = ry >> 16;
+  f.dx = ((float)(px - il) + 0.5f) - rec[R_X0];
+  f.dy = ((float)(py - jl) + 0.5f) - rec[R_Y0];
+  const float a3 = rec[R_A3], b3 = rec[R_B3];
+  f.s = __builtin_fmaf(a3, f.dx, __builtin_fmaf(b3, f.dy, 1.0f));
+  const float qxx = rec[R_QXX], qxy = 0.5f * rec[R_QXY2], qyy = rec[R_QYY];
+  const float iq = 1.f / (qxx * qyy - qxy * qxy);
+  const float B11 = qyy * iq - sigma, B12 = -qxy * iq, B22 = qxx * iq - sigma;
+  const float P11 = 1.f + f.dx * a3, P12 = f.dx * b3, P21 = f.dy * a3, P22 = 1.f + f.dy * b3;
+  const float X11 = P11 * B11 + P12 * B12, X12 = P11 * B12 + P12 * B22;
+  const float X21 = P21 * B11 + P22 * B12, X22 = P21 * B12 + P22 * B22;
+  const float s2 = f.s * f.s;
+  const float S11 = s2 * (X11 * P11 + X12 * P12) + sigma;
+  const float S12 = s2 * (X11 * P21 + X12 * P22);
+  const float S22 = s2 * (X21 * P21 + X22 * P22) + sigma;
+  const float detS = S11 * S22 - S12 * S12;
+  f.N = s2 * (S22 * f.dx * f.dx - 2.f * S12 * f.dx * f.dy + S11 * f.dy * f.dy);
+  const bool in_rect = px >= il && px <= ih && py >= jl && py <= jh;
+  f.cov = in_rect && f.s > 0.f && detS > 0.f && f.N < r2 * detS;
+  f.q = f.N / detS;
+  const float nfc = rec[R_NF];
+  f.w = sqrtf(s2 * s2 * s2 * nfc * nfc * iq / detS) * __expf(-0.5f * f.q);
 }
 
 __device__ __forceinline__ int view_of_tile(const ViewDev* views, int nv, int tile) {

@@ -82,15 +82,18 @@ __device__ __forceinline__ bool ellipse_meets(const float4 q0, const float4 q1, 
 }
 
 // Wave-level compaction of a chunk of up to 64 staged records: lane j tests
-// record c0 + j against the wave's sub-tile (rectangle, then ellipse); the
-// ballot is the (wave-uniform) set of records this wave visits, in list order.
+// record c0 + j against the wave's sub-tile (rectangle, then, for the centre
+// MIP filter, the ellipse); the ballot is the (wave-uniform) set of records
+// this wave visits, in list order.
+template <bool ELLIPSE = true>
 __device__ __forceinline__ uint64_t chunk_mask(const float4* lds, int c0, int cnt, int lane, int sx0,
                                                int sy0, float r2) {
   const int j = c0 + lane;
   bool ov = false;
   if (j < cnt) {
     const float4 q3 = lds[4 * j + 3];
-    ov = rect_meets(q3, sx0, sy0) && ellipse_meets(lds[4 * j], lds[4 * j + 1], q3, sx0, sy0, r2);
+    ov = rect_meets(q3, sx0, sy0);
+    if constexpr (ELLIPSE) ov = ov && ellipse_meets(lds[4 * j], lds[4 * j + 1], q3, sx0, sy0, r2);
   }
   return __ballot(ov);
 }
@@ -145,7 +148,8 @@ __device__ __forceinline__ float layer_norm(int shade, float W, float C0, float 
 // per-pixel depth-consolidation term and composited depth (each output
 // nullable).  Depths are accumulated relative to the layer's first fragment,
 // so the variance does not cancel against z^2.
-template <int TW, int TH, bool CONS>
+// PPX: per-pixel-Jacobian MIP filter instead of the centre-precomputed one.
+template <int TW, int TH, bool CONS, bool PPX>
 __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     const ViewDev* __restrict__ views, int n_views, int tile_begin, int n_items,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
@@ -185,13 +189,16 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
       __syncthreads();
       for (int c0 = 0; c0 < cnt; c0 += 64) {
         if (__ballot(!done) == 0ull) break;
-        uint64_t m = chunk_mask(lds, c0, cnt, lane, sx0, sy0, r2);
+        uint64_t m = chunk_mask<!PPX>(lds, c0, cnt, lane, sx0, sy0, r2);
         while (m) {
           const int j = c0 + __builtin_ctzll(m);
           m &= m - 1;
           const float* rec = reinterpret_cast<const float*>(lds + 4 * j);
           FragEval f;
-          frag_eval(rec, px, py, r2, f);
+          if constexpr (PPX)
+            frag_eval_pp(rec, px, py, r2, prm.sigma_f, f);
+          else
+            frag_eval(rec, px, py, r2, f);
           if (!f.cov || done) continue;
           if (Wg > 0.f && rec[R_ZS] > zmax) {
             // gap: finalise the layer (Shepard-normalised colour, coverage opacity)
@@ -627,14 +634,18 @@ static hipError_t fwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vi
                         const Params& prm, int B, float* image, float* alpha, uint8_t* nlo,
                         uint8_t* nli, float4* stats, float2* stats2, float* cons, float* depth,
                         int* queue, const int* order, int pers) {
-  if (prm.cons)
-    hipLaunchKernelGGL((raster_forward_kernel<TW, TH, true>), grid, dim3(TW * TH), lds, st, views, nv, tb, ni,
-                       ranges, vals, recs, prm, B, image, alpha, nlo, nli, stats, stats2, cons, depth, queue,
-                       order, pers);
-  else
-    hipLaunchKernelGGL((raster_forward_kernel<TW, TH, false>), grid, dim3(TW * TH), lds, st, views, nv, tb,
-                       ni, ranges, vals, recs, prm, B, image, alpha, nlo, nli, stats, stats2, cons, depth,
-                       queue, order, pers);
+#define SS_FWD_V(CV, PV)                                                                                 \
+  hipLaunchKernelGGL((raster_forward_kernel<TW, TH, CV, PV>), grid, dim3(TW * TH), lds, st, views, nv, tb, ni, \
+                     ranges, vals, recs, prm, B, image, alpha, nlo, nli, stats, stats2, cons, depth, queue,    \
+                     order, pers)
+  if (prm.mip == 1) {
+    if (prm.cons) SS_FWD_V(true, true);
+    else SS_FWD_V(false, true);
+  } else {
+    if (prm.cons) SS_FWD_V(true, false);
+    else SS_FWD_V(false, false);
+  }
+#undef SS_FWD_V
   return hipGetLastError();
 }
 

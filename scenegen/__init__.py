@@ -374,6 +374,23 @@ def plane_scene(n_side: int, spacing: float, scale: float, z: float = 0.0, exten
                  _f32(np.full(n, 0.5)), _f32(np.zeros(n)))
 
 
+def checkerboard_workload(n_side: int = 2000, extent: float = 10.0, square: float = 0.2,
+                          width: int = 800, height: int = 600, eye=(0.0, -10.6, 0.45),
+                          target=(0.0, 0.0, 0.0)) -> "Workload":
+    """Anti-aliasing test scene: a ground plane z = 0 sampled on an n_side^2 lattice
+    over [-extent, extent]^2 (4M surfels by default), isotropic scale = spacing,
+    black/white checkerboard albedo of the given square size, seen from a low
+    camera so that the plane recedes to the horizon (minification from ~0.1 to
+    many surfels per pixel within one frame)."""
+    spacing = 2.0 * extent / n_side
+    sc = plane_scene(n_side, spacing, spacing, color=(0.0, 0.0, 0.0))
+    x, y = sc.position[0].astype(np.float64), sc.position[1].astype(np.float64)
+    white = (np.floor(x / square) + np.floor(y / square)).astype(np.int64) % 2 == 0
+    sc.albedo = _f32(np.tile(white.astype(np.float64), (3, 1)))
+    cam = look_at_camera(eye, width, height, target=target)
+    return Workload("checkerboard", [sc], [cam], "albedo")
+
+
 CONFIG_NAMES = ["C1", "C2", "C3", "C4", "C5"]
 
 

@@ -28,7 +28,8 @@ MAX_MASKED = 1e-3
 
 def oracle_options(O, opts):
     return O.Options(r_cut=opts.r_cut, gamma=opts.gamma, sigma_f=opts.sigma_f, k_max=opts.k_max,
-                     shade=opts.shade, tile_w=opts.tile_w, tile_h=opts.tile_h)
+                     shade=opts.shade, tile_w=opts.tile_w, tile_h=opts.tile_h,
+                     mip=getattr(opts, "mip", "centre"))
 
 
 def oracle_maps(O, scenes, shade):

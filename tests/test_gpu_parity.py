@@ -416,6 +416,28 @@ def test_normal_image_parity(O, ss):
     assert max(errs.values()) <= GRAD_REL_L2, errs
 
 
+# ---------------------------------------------------------------- per-pixel MIP variant
+@pytest.mark.parametrize("case", ["checkerboard", "C1_sigma0.5"])
+def test_per_pixel_mip_forward_parity(O, ss, case):
+    """Sec. 3.3.1 variant (Jacobian at every intersection) against the oracle with the
+    image protocol; its backward is refused."""
+    if case == "checkerboard":
+        w = g.checkerboard_workload(n_side=240, extent=3.0, square=0.15, width=96, height=72,
+                                    eye=(0.0, -3.2, 0.35))
+        kw = dict(sigma_f=0.1)
+    else:
+        w = g.make_config("C1")
+        kw = dict(sigma_f=0.5)
+    rep = _forward_case(O, ss, w.scenes, w.cameras, "albedo", lambda c, v: all_pix(c), mip="pixel", **kw)
+    assert_image_parity(rep)
+    r = ss.Renderer(ss.Options(mip="pixel", **kw))
+    b = ss.batch_from_scenes(w.scenes, w.cameras)
+    r.forward(b)
+    with pytest.raises(ss.SurfsplatError) as e:
+        r.backward(b, torch.zeros((b.n_pixels, 3), device="cuda"))
+    assert e.value.status == ss.SS_ERR_UNSUPPORTED
+
+
 # ---------------------------------------------------------------- tables, invariances, edges
 def test_brdf_lut_matches_oracle(O, ss):
     lut = ss.make_brdf_lut(64, 64, 1024).cpu().numpy()
