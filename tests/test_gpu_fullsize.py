@@ -47,7 +47,7 @@ def sample(cam, k, seed):
     return np.unique(np.stack([xs, ys], 1), axis=0).astype(np.int32)
 
 
-@pytest.mark.parametrize("name,k", [("C3", 96), ("C5", 24)])
+@pytest.mark.parametrize("name,k", [("C3", 96), ("C5", 64)])
 def test_fullsize_sampled_parity(O, ss, name, k):
     w = g.make_config(name)
     opts = bench_options(ss, name, w.shade)
