@@ -273,10 +273,11 @@ ss_status prepare_env(ss_context* c, const ss_batch* b, hipStream_t st) {
     const long long lv_n = o;
     long long d = 0;
     for (int l = 0; l < 7; ++l) { e.doff[l] = d; d += 3LL * e.lh[l] * e.lw[l]; }
-    // privatise the irradiance level and the smallest specular levels in LDS
+    // privatise the irradiance level and the specular levels, smallest first,
+    // in LDS while they fit
     for (int l = 0; l < 7; ++l) e.loc_off[l] = -1;
     e.loc_total = 0;
-    for (int l : {6, 5, 4, 3, 2, 1}) {
+    for (int l : {6, 5, 4, 3, 2, 1, 0}) {
       const int n = 3 * e.lh[l] * e.lw[l];
       if (e.loc_total + n > kLocalMapFloats) break;
       e.loc_off[l] = e.loc_total;

@@ -247,9 +247,13 @@ hipError_t launch_brdf_lut(float* lut, int n_nv, int n_r, int samples, hipStream
 hipError_t launch_preprocess(const float* const P[7], long long N, const ViewDev* views, int v0,
                              int v1, int max_surf, const Params& prm, float* recs,
                              uint32_t* counts, hipStream_t st);
-constexpr int kBackwardBlocks = 512;       // blocks of the surfel adjoint (per scene)
-constexpr int kBackwardThreads = 512;      // threads per block of the surfel adjoint
-constexpr int kLocalMapFloats = 16384;     // LDS budget for privatised environment levels
+constexpr int kBackwardBlocks = 256;       // blocks of the shading adjoint (per scene): one per CU
+constexpr int kBackwardThreads = 1024;     // threads per block of the shading adjoint
+// LDS budget for privatised environment levels (156 KiB of the 160 KiB per
+// CU): with a 128 x 256 map it holds every level but the map itself, so only
+// lookups of the sharpest level fall back to global atomics, which are the
+// expensive part of the shading adjoint.
+constexpr int kLocalMapFloats = 39936;
 constexpr int kReduceSplit = 32;           // first-stage chunks of the partial reduction
 int backward_blocks(long long n_items);
 hipError_t launch_shade_backward(const float* const P[7], long long N, const ViewDev* views,

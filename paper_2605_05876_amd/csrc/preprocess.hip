@@ -11,6 +11,21 @@
 
 namespace ss {
 
+// Address-space-qualified views of the environment levels: the level pointers
+// come from the view descriptors at run time, so without the qualifier every
+// texel load and gradient atomic would be a FLAT instruction (and atomics into
+// the LDS-privatised levels would take the FLAT path instead of ds_add_f32).
+typedef const __attribute__((address_space(1))) float gmem_cf32;
+typedef __attribute__((address_space(1))) float gmem_f32;
+typedef __attribute__((address_space(3))) float lds_f32;
+
+__device__ __forceinline__ void grad_add(lds_f32* p, float x) {
+  __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void grad_add(gmem_f32* p, float x) {
+  __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------- shading
 // NaN maps to 0 so that table indices stay in range
 __device__ inline float clamp01(float x) { return !(x >= 0.f) ? 0.f : (x > 1.f ? 1.f : x); }
@@ -40,11 +55,12 @@ __device__ inline void latlong_coords(const float d[3], int H, int W, LatLong& L
   L.th = th; L.ph = ph; L.rho = rho;
   L.den = rho * rho + d[2] * d[2];
 }
-__device__ inline void latlong_fetch(const float* m, int W, const LatLong& L, float out[3]) {
-  const float* t00 = m + 3 * (L.r0 * W + L.c0);
-  const float* t01 = m + 3 * (L.r0 * W + L.c1);
-  const float* t10 = m + 3 * (L.r1 * W + L.c0);
-  const float* t11 = m + 3 * (L.r1 * W + L.c1);
+__device__ inline void latlong_fetch(const float* mp, int W, const LatLong& L, float out[3]) {
+  gmem_cf32* m = (gmem_cf32*)mp;
+  gmem_cf32* t00 = m + 3 * (L.r0 * W + L.c0);
+  gmem_cf32* t01 = m + 3 * (L.r0 * W + L.c1);
+  gmem_cf32* t10 = m + 3 * (L.r1 * W + L.c0);
+  gmem_cf32* t11 = m + 3 * (L.r1 * W + L.c1);
   for (int c = 0; c < 3; ++c)
     out[c] = (1.f - L.fa) * ((1.f - L.fb) * t00[c] + L.fb * t01[c]) +
              L.fa * ((1.f - L.fb) * t10[c] + L.fb * t11[c]);
@@ -104,9 +120,11 @@ __device__ inline void shade_forward(const ViewDev& v, const Params& P, const fl
 
 // One bilinear lat-long lookup with its adjoint: returns the value, scatters
 // g (the gradient of the looked-up value, known up front) into the texels of
-// dm (may be null) and adds the gradient with respect to the direction d to gd.
-__device__ inline void latlong_lookup_adjoint(const float* m, float* dm, int H, int W, const float d[3],
+// dm (LDS or global) and adds the gradient with respect to the direction d to gd.
+template <class DST>
+__device__ inline void latlong_lookup_adjoint(const float* mp, DST* dm, int H, int W, const float d[3],
                                               const float g[3], float val[3], float gd[3]) {
+  gmem_cf32* m = (gmem_cf32*)mp;
   LatLong L;
   latlong_coords(d, H, W, L);
   const int o00 = 3 * (L.r0 * W + L.c0), o01 = 3 * (L.r0 * W + L.c1);
@@ -119,11 +137,11 @@ __device__ inline void latlong_lookup_adjoint(const float* m, float* dm, int H, 
     val[c] = w00 * v00 + w01 * v01 + w10 * v10 + w11 * v11;
     ga += g[c] * ((1.f - L.fb) * (v10 - v00) + L.fb * (v11 - v01));
     gb += g[c] * ((1.f - L.fa) * (v01 - v00) + L.fa * (v11 - v10));
-    if (dm != nullptr && g[c] != 0.f) {
-      atomicAdd(dm + o00 + c, g[c] * w00);
-      atomicAdd(dm + o01 + c, g[c] * w01);
-      atomicAdd(dm + o10 + c, g[c] * w10);
-      atomicAdd(dm + o11 + c, g[c] * w11);
+    if (g[c] != 0.f) {
+      grad_add(dm + o00 + c, g[c] * w00);
+      grad_add(dm + o01 + c, g[c] * w01);
+      grad_add(dm + o10 + c, g[c] * w10);
+      grad_add(dm + o11 + c, g[c] * w11);
     }
   }
   const float gth = ga * ((float)H / kPi);
@@ -139,11 +157,16 @@ __device__ inline void latlong_lookup_adjoint(const float* m, float* dm, int H, 
 }
 
 // Adjoint of shade_forward: given g = dL/dcol, accumulates into g_p, g_nh,
-// g_rho, g_rough, g_metal and scatters texel gradients into dst[l].  Each
-// lookup's adjoint needs only quantities known before the lookup, so the three
-// lookups are processed one after the other (few live registers).
-__device__ inline float* level_grad_ptr(const ViewDev& v, const float* sm, const int loc_off[7], int l) {
-  return loc_off[l] >= 0 ? const_cast<float*>(sm) + loc_off[l] : v.dlvl[l];
+// g_rho, g_rough, g_metal and scatters texel gradients into level l's LDS
+// copy (loc_off[l] >= 0) or its global gradient map.  Each lookup's adjoint
+// needs only quantities known before the lookup, so the three lookups are
+// processed one after the other (few live registers).
+__device__ inline void level_lookup_adjoint(const ViewDev& v, const float* sm, const int loc_off[7], int l,
+                                            const float d[3], const float g[3], float val[3], float gd[3]) {
+  if (loc_off[l] >= 0)
+    latlong_lookup_adjoint(v.lvl[l], (lds_f32*)sm + loc_off[l], v.lh[l], v.lw[l], d, g, val, gd);
+  else
+    latlong_lookup_adjoint(v.lvl[l], (gmem_f32*)v.dlvl[l], v.lh[l], v.lw[l], d, g, val, gd);
 }
 
 __device__ inline void shade_backward(const ViewDev& v, const Params& P, const float p[3],
@@ -176,7 +199,7 @@ __device__ inline void shade_backward(const ViewDev& v, const Params& P, const f
   {
     float gLd[3], Ld[3];
     for (int c = 0; c < 3; ++c) gLd[c] = g[c] * kd[c] * rho[c];
-    latlong_lookup_adjoint(v.lvl[6], level_grad_ptr(v, sm, loc_off, 6), v.lh[6], v.lw[6], nh, gLd, Ld, g_nh);
+    level_lookup_adjoint(v, sm, loc_off, 6, nh, gLd, Ld, g_nh);
     for (int c = 0; c < 3; ++c) {
       const float gkd = g[c] * rho[c] * Ld[c];
       g_rho[c] += g[c] * kd[c] * Ld[c];
@@ -190,7 +213,7 @@ __device__ inline void shade_backward(const ViewDev& v, const Params& P, const f
     const float wt = side ? tl : 1.f - tl;
     float gX[3], X[3];
     for (int c = 0; c < 3; ++c) gX[c] = wt * gLs[c];
-    latlong_lookup_adjoint(v.lvl[l], level_grad_ptr(v, sm, loc_off, l), v.lh[l], v.lw[l], rd, gX, X, grd);
+    level_lookup_adjoint(v, sm, loc_off, l, rd, gX, X, grd);
     for (int c = 0; c < 3; ++c) {
       const float Ls = wt * X[c];
       gF0[c] += g[c] * Ls * beta[0];
@@ -412,7 +435,7 @@ __device__ inline bool record_has_grad(const float* grad, long long r, float gr[
   return any;
 }
 
-__global__ void __launch_bounds__(kBackwardThreads, 4) shade_backward_kernel(
+__global__ void __launch_bounds__(kBackwardThreads, 1) shade_backward_kernel(
     PPtrs PP, long long N, const ViewDev* __restrict__ views, SceneViews sv, Params prm,
     const float* __restrict__ grad, float* __restrict__ sg, LocalMaps lm, float* __restrict__ partial) {
   extern __shared__ float sm[];
@@ -634,6 +657,14 @@ hipError_t launch_shade_backward(const float* const P[7], long long N, const Vie
   lm.total = local_total;
   for (int l = 0; l < 7; ++l) lm.off[l] = local_total > 0 ? local_off[l] : -1;
   const int nb = backward_blocks((long long)n_surf * n_scene_views);
+  static bool lds_attr = false;  // allow the privatised levels beyond the default dynamic-LDS limit
+  if (!lds_attr) {
+    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&shade_backward_kernel),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        kLocalMapFloats * (int)sizeof(float));
+    if (ea != hipSuccess) return ea;
+    lds_attr = true;
+  }
   hipLaunchKernelGGL(shade_backward_kernel, dim3(nb), dim3(kBackwardThreads),
                      (size_t)local_total * sizeof(float), st, PP, N, views, sv, prm, grad, sg, lm,
                      partial);
