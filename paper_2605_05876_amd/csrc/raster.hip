@@ -1,12 +1,18 @@
 // Tile rasterizer, forward and backward (Alg. 1, eq:shepard, eq:alpha,
 // eq:compositing, App. A.1).
 //
-// A block owns one tile of TW x TH pixels; each wave64 owns an 8 x 8 sub-tile,
-// one pixel per lane.  The tile's sorted records are staged through LDS in
-// batches (one 64-byte record per surfel, coalesced gathers by the whole
-// block); every wave first tests the record's pixel rectangle against its own
-// sub-tile (wave-uniform skip), then each lane evaluates the MIP-filtered
-// weight and runs the interval-merging grouping of Alg. 1.
+// A block owns one tile of TW x TH pixels; each wave64 owns an 8 x 8 sub-tile
+// and each of its four 16-lane rows a 4 x 4 quadrant of it, one pixel per
+// lane.  The tile's sorted records are staged through LDS in batches (one
+// 64-byte record per surfel, coalesced gathers by the whole block).  For each
+// chunk of 64 staged records every lane tests one record against the wave's
+// sub-tile (pixel rectangle, then the acceptance ellipse).  The forward walks
+// the resulting wave-wide mask: every lane evaluates each surviving record.
+// The backward, whose per-record step is heavier (gradients and a reduction),
+// splits the mask per quadrant: each row walks its own records, so a wave step
+// evaluates up to four different records, each on the 16 pixels it may cover,
+// and reduces them row by row.  Either way each lane visits every covering
+// record in list order, as Alg. 1 requires.
 //
 // Forward: per pixel it writes the image, alpha, the layer count and each
 // layer's (W_k, C_k) (unnormalised), at most K_max of them.
@@ -15,29 +21,33 @@
 // suffix sums, and re-walks the tile front to back with the identical
 // per-fragment evaluation and grouping decisions.  Per fragment it forms
 // dL/dw and dL/dc, maps them to the record's 11 parameters, reduces them over
-// the wave with cross-lane shuffles and issues one atomic add per value per
-// wave.
+// each row with cross-lane DPP moves and issues one atomic add per value per
+// row.
 #include "common.h"
 
 namespace ss {
 
+// Lane -> pixel: wave w owns the 8 x 8 sub-tile (w % (TW/8), w / (TW/8)); row
+// r = lane / 16 owns its quadrant (r % 2, r / 2); lane 4 y + x of the row owns
+// pixel (x, y) of the quadrant.
 template <int TW, int TH>
 __device__ __forceinline__ void pixel_of_thread(int t, int tile_x, int tile_y, int& lx, int& ly,
                                                 int& sx0, int& sy0) {
-  const int lane = t & 63, wave = t >> 6;
+  const int lane = t & 63, wave = t >> 6, row = lane >> 4, l16 = lane & 15;
   constexpr int WX = TW / 8;
   const int wx = wave % WX, wy = wave / WX;
-  lx = wx * 8 + (lane & 7);
-  ly = wy * 8 + (lane >> 3);
+  lx = wx * 8 + (row & 1) * 4 + (l16 & 3);
+  ly = wy * 8 + (row >> 1) * 4 + (l16 >> 2);
   sx0 = tile_x * TW + wx * 8;
   sy0 = tile_y * TH + wy * 8;
 }
 
-// Does the record's pixel rectangle meet the 8 x 8 sub-tile at (sx0, sy0)?
-__device__ __forceinline__ bool rect_meets(const float4 q, int sx0, int sy0) {
+// Does the record's pixel rectangle meet the S x S box at (bx, by)?
+template <int S>
+__device__ __forceinline__ bool rect_meets(const float4 q, int bx, int by) {
   const int rx = __float_as_int(q.x), ry = __float_as_int(q.y);
   const int il = rx & 0xffff, ih = rx >> 16, jl = ry & 0xffff, jh = ry >> 16;
-  return !(ih < sx0 || il > sx0 + 7 || jh < sy0 || jl > sy0 + 7);
+  return !(ih < bx || il > bx + S - 1 || jh < by || jl > by + S - 1);
 }
 
 __device__ __forceinline__ void load_batch(float4* lds, const uint32_t* __restrict__ vals,
@@ -50,18 +60,19 @@ __device__ __forceinline__ void load_batch(float4* lds, const uint32_t* __restri
   }
 }
 
-// Can the acceptance ellipse of a record reach a pixel centre of the 8 x 8
-// sub-tile at (sx0, sy0)?  Conservative: with d the pixel offset from the
-// centre, rho^2 = d^T Q d / s^2 >= min_box(d^T Q d) / max_box(s)^2, where the
-// minimum of the convex quadratic over the box is 0 when the centre is inside
-// and otherwise lies on one of its edges (1-D minimum, clamped), and s is
-// linear so its maximum is at a corner.  A 1e-3 margin keeps the test far from
-// the per-pixel FP32 cutoff decision.
+// Can the acceptance ellipse of a record reach a pixel centre of the S x S box
+// at (bx, by)?  Conservative: with d the pixel offset from the centre,
+// rho^2 = d^T Q d / s^2 >= min_box(d^T Q d) / max_box(s)^2, where the minimum of
+// the convex quadratic over the box is 0 when the centre is inside and
+// otherwise lies on one of its edges (1-D minimum, clamped), and s is linear so
+// its maximum is at a corner.  A 1e-3 margin keeps the test far from the
+// per-pixel FP32 cutoff decision.
+template <int S>
 __device__ __forceinline__ bool ellipse_meets(const float4 q0, const float4 q1, const float4 q3,
-                                              int sx0, int sy0, float r2) {
+                                              int bx, int by, float r2) {
   const int il = __float_as_int(q3.x) & 0xffff, jl = __float_as_int(q3.y) & 0xffff;
-  const float x0 = (float)(sx0 - il) + 0.5f - q0.x, x1 = x0 + 7.f;
-  const float y0 = (float)(sy0 - jl) + 0.5f - q0.y, y1 = y0 + 7.f;
+  const float x0 = (float)(bx - il) + 0.5f - q0.x, x1 = x0 + (float)(S - 1);
+  const float y0 = (float)(by - jl) + 0.5f - q0.y, y1 = y0 + (float)(S - 1);
   const float qxx = q0.z, qxy = 0.5f * q0.w, qyy = q1.x, a3 = q1.y, b3 = q1.z;
   const float s00 = 1.f + a3 * x0 + b3 * y0, s01 = 1.f + a3 * x0 + b3 * y1;
   const float s10 = 1.f + a3 * x1 + b3 * y0, s11 = 1.f + a3 * x1 + b3 * y1;
@@ -81,10 +92,18 @@ __device__ __forceinline__ bool ellipse_meets(const float4 q0, const float4 q1, 
   return !(nmin >= r2 * smax * smax * 1.001f);
 }
 
-// Wave-level compaction of a chunk of up to 64 staged records: lane j tests
-// record c0 + j against the wave's sub-tile (rectangle, then, for the centre
-// MIP filter, the ellipse); the ballot is the (wave-uniform) set of records
-// this wave visits, in list order.
+// The masks are wave-uniform; saying so keeps them (and the loop over them)
+// in scalar registers even though the loop body branches per lane.
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Wave-level compaction of a chunk of up to 64 staged records (forward): lane
+// j tests record c0 + j against the wave's sub-tile (rectangle, then, for the
+// centre MIP filter, the ellipse); the ballot is the (wave-uniform) set of
+// records the whole wave visits, in list order.
 template <bool ELLIPSE = true>
 __device__ __forceinline__ uint64_t chunk_mask(const float4* lds, int c0, int cnt, int lane, int sx0,
                                                int sy0, float r2) {
@@ -92,10 +111,46 @@ __device__ __forceinline__ uint64_t chunk_mask(const float4* lds, int c0, int cn
   bool ov = false;
   if (j < cnt) {
     const float4 q3 = lds[4 * j + 3];
-    ov = rect_meets(q3, sx0, sy0);
-    if constexpr (ELLIPSE) ov = ov && ellipse_meets(lds[4 * j], lds[4 * j + 1], q3, sx0, sy0, r2);
+    ov = rect_meets<8>(q3, sx0, sy0);
+    if constexpr (ELLIPSE) ov = ov && ellipse_meets<8>(lds[4 * j], lds[4 * j + 1], q3, sx0, sy0, r2);
   }
-  return __ballot(ov);
+  return uniform64(__ballot(ov));
+}
+
+// Row-level compaction (backward): after the sub-tile test, lane j tests
+// record c0 + j's rectangle against the four quadrants; m[r] is the
+// (wave-uniform) set of records row r visits, in list order.  (Ellipse tests
+// per quadrant cost more than the steps they save.)
+__device__ __forceinline__ void chunk_masks(const float4* lds, int c0, int cnt, int lane, int sx0, int sy0,
+                                            float r2, uint64_t m[4]) {
+  const int j = c0 + lane;
+  bool o0 = false, o1 = false, o2 = false, o3 = false;
+  if (j < cnt) {
+    const float4 q3 = lds[4 * j + 3];
+    if (rect_meets<8>(q3, sx0, sy0) && ellipse_meets<8>(lds[4 * j], lds[4 * j + 1], q3, sx0, sy0, r2)) {
+      o0 = rect_meets<4>(q3, sx0, sy0);
+      o1 = rect_meets<4>(q3, sx0 + 4, sy0);
+      o2 = rect_meets<4>(q3, sx0, sy0 + 4);
+      o3 = rect_meets<4>(q3, sx0 + 4, sy0 + 4);
+    }
+  }
+  m[0] = uniform64(__ballot(o0));
+  m[1] = uniform64(__ballot(o1));
+  m[2] = uniform64(__ballot(o2));
+  m[3] = uniform64(__ballot(o3));
+}
+
+// One step of the row walks: every row takes the next record of its mask
+// (scalar).  Returns this lane's record (chunk index), -1 when its row has no
+// record left.
+__device__ __forceinline__ int next_records(uint64_t m[4], int row) {
+  int jr[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    jr[r] = m[r] ? (int)__builtin_ctzll(m[r]) : -1;
+    m[r] = uniform64(m[r] & (m[r] - 1));
+  }
+  return row == 0 ? jr[0] : (row == 1 ? jr[1] : (row == 2 ? jr[2] : jr[3]));
 }
 
 __device__ __forceinline__ int next_item(int* queue, int persistent, int& s_item, int iter) {
@@ -264,61 +319,66 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
 }
 
 // ---------------------------------------------------------------- backward
-// Sum of x over the 16 lanes of each row, left in every lane of the row
-// (quad xor 1, quad xor 2, half-row mirror, row mirror).
-__device__ __forceinline__ float row_sum16(float x) {
+// Row-wise transposed reductions: the four 16-lane rows of the wave reduce
+// their own values independently (each row carries one record).  A stage
+// pairs value a (kept by the lanes whose stage bit is 0) with value b (kept by
+// the others): each lane adds its partner's copy across the row (mirror) or
+// half-row (half mirror), halving the number of live values; a quad sum
+// finishes.  Only DPP moves, no LDS.
+__device__ __forceinline__ float dpp_row_mirror(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float dpp_half_mirror(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float quad_sum(float x) {
   x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
   x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
-  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xF, 0xF, false));
-  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xF, 0xF, false));
   return x;
 }
 
-// Reduces 12 per-lane values over the wave with a transposed butterfly:
-// permlane32_swap pairs (g_i, g_{i+6}) so lanes 0-31 carry value i and lanes
-// 32-63 value i+6; permlane16_swap pairs (s_i, s_{i+3}) so row r carries value
-// i + 3r; a row sum finishes.  Lane 16r + k (k < 3) returns the total of value
-// 3r + k in *vidx, other lanes -1.  Needs all 64 lanes active.
-__device__ __forceinline__ float wave_reduce12(const float g[12], int lane, int* vidx) {
+// 12 values per row: stage 1 (row mirror, lane bit 3) pairs (g_i, g_{i+6}),
+// stage 2 (half mirror, lane bit 2) pairs (s_i, s_{i+3}); then quad q of the
+// row holds values i + 3q.  Lane 4q + k (k < 3) of a row returns the row total
+// of value 3q + k in *vidx, other lanes -1.
+__device__ __forceinline__ float row_reduce12(const float g[12], int lane, int* vidx) {
+  const bool h8 = (lane & 8) != 0, h4 = (lane & 4) != 0;
   float s[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(g[i]), __float_as_uint(g[i + 6]),
-                                                    false, false);
-    s[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    const float keep = h8 ? g[i + 6] : g[i], send = h8 ? g[i] : g[i + 6];
+    s[i] = keep + dpp_row_mirror(send);
   }
-  float t3[3];
+  float t[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(s[i]), __float_as_uint(s[i + 3]),
-                                                    false, false);
-    t3[i] = row_sum16(__uint_as_float(r[0]) + __uint_as_float(r[1]));
+    const float keep = h4 ? s[i + 3] : s[i], send = h4 ? s[i] : s[i + 3];
+    t[i] = quad_sum(keep + dpp_half_mirror(send));
   }
-  const int row = lane >> 4, k = lane & 15;
-  *vidx = k < 3 ? 3 * row + k : -1;
-  return k == 0 ? t3[0] : (k == 1 ? t3[1] : t3[2]);
+  const int q = (lane >> 2) & 3, k = lane & 3;
+  *vidx = k < 3 ? 3 * q + k : -1;
+  return k == 0 ? t[0] : (k == 1 ? t[1] : t[2]);
 }
 
-// Same for 16 values: permlane32_swap pairs (g_i, g_{i+8}), permlane16_swap
-// pairs (s_i, s_{i+4}), row sum; lane 16r + k (k < 4) returns value 4r + k.
-__device__ __forceinline__ float wave_reduce16(const float g[16], int lane, int* vidx) {
+// 16 values per row: pairs (g_i, g_{i+8}), then (s_i, s_{i+4}); lane 4q + k of a
+// row returns value 4q + k.
+__device__ __forceinline__ float row_reduce16(const float g[16], int lane, int* vidx) {
+  const bool h8 = (lane & 8) != 0, h4 = (lane & 4) != 0;
   float s[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(g[i]), __float_as_uint(g[i + 8]),
-                                                    false, false);
-    s[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    const float keep = h8 ? g[i + 8] : g[i], send = h8 ? g[i] : g[i + 8];
+    s[i] = keep + dpp_row_mirror(send);
   }
-  float t4[4];
+  float t[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(s[i]), __float_as_uint(s[i + 4]),
-                                                    false, false);
-    t4[i] = row_sum16(__uint_as_float(r[0]) + __uint_as_float(r[1]));
+    const float keep = h4 ? s[i + 4] : s[i], send = h4 ? s[i] : s[i + 4];
+    t[i] = quad_sum(keep + dpp_half_mirror(send));
   }
-  const int row = lane >> 4, k = lane & 15;
-  *vidx = k < 4 ? 4 * row + k : -1;
-  return k == 0 ? t4[0] : (k == 1 ? t4[1] : (k == 2 ? t4[2] : t4[3]));
+  const int q = (lane >> 2) & 3, k = lane & 3;
+  *vidx = 4 * q + k;
+  return k == 0 ? t[0] : (k == 1 ? t[1] : (k == 2 ? t[2] : t[3]));
 }
 
 // Per-layer coefficients of the backward.  The layer's composited value is
@@ -404,8 +464,11 @@ __device__ inline void cons_coef(const float4* __restrict__ st, const float2* __
 // SS: also accumulate the densification statistic in slot G_SS.
 // CONS: add the adjoint of the depth statistics (loss weights d_cons on the
 // consolidation term, d_depth on the composited depth; either may be null).
+// Occupancy target: 5 waves per SIMD (up to 102 VGPRs per lane), 4 with the
+// extra statistics.
 template <int TW, int TH, bool SS, bool CONS>
-__global__ void __launch_bounds__(TW* TH, (SS || CONS) ? 4 : 8) raster_backward_kernel(
+__global__ void __launch_bounds__(TW* TH)
+__attribute__((amdgpu_waves_per_eu((SS || CONS) ? 4 : 5))) raster_backward_kernel(
     const ViewDev* __restrict__ views, int n_views, int tile_begin, int n_items,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float* __restrict__ recs, Params prm, int B, const float* __restrict__ d_image,
@@ -419,7 +482,7 @@ __global__ void __launch_bounds__(TW* TH, (SS || CONS) ? 4 : 8) raster_backward_
   extern __shared__ float4 lds[];
   __shared__ int s_item;
   constexpr int NT = TW * TH;
-  const int t = threadIdx.x, lane = t & 63;
+  const int t = threadIdx.x, lane = t & 63, row = lane >> 4;
   const float r2 = prm.r2, kappa = prm.kappa;
   const int kmax = prm.k_max;
   for (int iter = 0;; ++iter) {
@@ -483,16 +546,17 @@ __global__ void __launch_bounds__(TW* TH, (SS || CONS) ? 4 : 8) raster_backward_
       __syncthreads();
       for (int c0 = 0; c0 < cnt; c0 += 64) {
         if (__ballot(!done) == 0ull) break;
-        uint64_t m = chunk_mask(lds, c0, cnt, lane, sx0, sy0, r2);
-        while (m) {
-          const int j = c0 + __builtin_ctzll(m);
-          m &= m - 1;
-          const float* rec = reinterpret_cast<const float*>(lds + 4 * j);
+        uint64_t m[4];
+        chunk_masks(lds, c0, cnt, lane, sx0, sy0, r2, m);
+        while ((m[0] | m[1] | m[2] | m[3]) != 0ull) {
+          const int jl = next_records(m, row);
+          // idle rows read a valid record and contribute nothing
+          const float* rec = reinterpret_cast<const float*>(lds + 4 * (c0 + (jl < 0 ? 0 : jl)));
           FragEval f;
           frag_eval(rec, px, py, r2, f);
           bool contrib = false;
           float gw = 0.f, gcs = 0.f, gz = 0.f, zf = 0.f;
-          if (f.cov && !done) {
+          if (jl >= 0 && f.cov && !done) {
             bool live = true;
             if (Wg > 0.f && rec[R_ZS] > zmax) {
               // next layer: the forward flushed layer k here
@@ -526,10 +590,13 @@ __global__ void __launch_bounds__(TW* TH, (SS || CONS) ? 4 : 8) raster_backward_
             }
           }
           if (__ballot(contrib) == 0ull) continue;
-          // d(rho^2)/d(record) for q = d^T Q d / s^2, s = 1 + a3 dx + b3 dy
-          const float is = __builtin_amdgcn_rcpf(f.s), is2 = is * is;
-          const float gq = -0.5f * f.w * gw;
-          const float dx = f.dx, dy = f.dy, q = f.q;
+          // d(rho^2)/d(record) for q = d^T Q d / s^2, s = 1 + a3 dx + b3 dy.  Lanes that
+          // do not contribute have gw = gcs = gz = 0; zeroing their 1/s, q and w (which
+          // may be infinite off the ellipse) makes every value below exactly 0 there.
+          const float is = contrib ? __builtin_amdgcn_rcpf(f.s) : 0.f, is2 = is * is;
+          const float fw = contrib ? f.w : 0.f;
+          const float gq = -0.5f * fw * gw;
+          const float dx = f.dx, dy = f.dy, q = contrib ? f.q : 0.f;
           const float qxx = rec[R_QXX], qxy2 = rec[R_QXY2], qyy = rec[R_QYY];
           float g[RW];
           g[G_X0] = -gq * ((2.f * qxx * dx + qxy2 * dy) * is2 - 2.f * q * rec[R_A3] * is);
@@ -539,7 +606,7 @@ __global__ void __launch_bounds__(TW* TH, (SS || CONS) ? 4 : 8) raster_backward_
           g[G_QYY] = gq * dy * dy * is2;
           g[G_A3] = -2.f * gq * q * dx * is;
           g[G_B3] = -2.f * gq * q * dy * is;
-          g[G_NF] = gw * f.w * __builtin_amdgcn_rcpf(rec[R_NF]);
+          g[G_NF] = gw * fw * __builtin_amdgcn_rcpf(rec[R_NF]);
           g[G_CR] = gcs * L.G0;
           g[G_CG] = gcs * L.G1;
           g[G_CB] = gcs * L.G2;
@@ -565,7 +632,7 @@ __global__ void __launch_bounds__(TW* TH, (SS || CONS) ? 4 : 8) raster_backward_
             const float p1 = a3 * (1.f - sg * qxx) - b3 * sg * qxy;
             const float p2 = b3 * (1.f - sg * qyy) - a3 * sg * qxy;
             const float gab = a3 * g[G_A3] + b3 * g[G_B3];
-            const float gnf = sg * gw * f.w;  // n_f dL/dn_f sigma_f
+            const float gnf = sg * gw * fw;  // n_f dL/dn_f sigma_f
             const float gx = g[G_X0] - 2.f * (qxx * p1 * g[G_QXX] + (qxx * p2 + qxy * p1) * g[G_QXY2] +
                                               qxy * p2 * g[G_QYY]) -
                              a3 * gab + gnf * (a3 * qxx + b3 * qxy);
@@ -574,14 +641,12 @@ __global__ void __launch_bounds__(TW* TH, (SS || CONS) ? 4 : 8) raster_backward_
                              b3 * gab + gnf * (a3 * qxy + b3 * qyy);
             g[kNGrad] = sqrtf(gx * gx + gy * gy);
           }
-#pragma unroll
-          for (int q2 = 0; q2 < RW; ++q2) g[q2] = contrib ? g[q2] : 0.f;
           int vidx;
           float tot;
           if constexpr (RW == 12)
-            tot = wave_reduce12(g, lane, &vidx);
+            tot = row_reduce12(g, lane, &vidx);
           else
-            tot = wave_reduce16(g, lane, &vidx);
+            tot = row_reduce16(g, lane, &vidx);
           if (vidx >= 0 && vidx < NV && tot != 0.f) {
             // reduced index -> gradient slot (the extras are packed after the 11)
             const int slot = vidx < kNGrad ? vidx : (vidx == NV - 1 && CONS ? (int)G_TZ : (int)G_SS);
