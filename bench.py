@@ -104,6 +104,9 @@ def main():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="eager steps only (for rocprofv3)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="sweep tile shape x LDS batch on --config, store the best in the autotune cache "
+                         "(and print the sweep as one JSON line)")
     ap.add_argument("--mip-ablation", action="store_true",
                     help="forward time of the 4M-surfel checkerboard at 800x600 with no MIP filter, the "
                          "centre-precomputed filter, the per-pixel Jacobian and 4x supersampling")
@@ -126,6 +129,8 @@ def main():
     torch.cuda.set_device(0)
     if args.mip_ablation:
         return mip_ablation(args)
+    if args.autotune:
+        return run_autotune(args)
     t0 = time.perf_counter()
     w = g.make_config(args.config)
     log(f"[bench] workload {args.config}: {w.n_surfels} surfels, {len(w.cameras)} views, "
@@ -266,6 +271,43 @@ def main():
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(w, w.shade)
     print(json.dumps(out), flush=True)
+
+
+def run_autotune(args):
+    """Time one fwd+bwd step per (tile, LDS batch) candidate; keep the fastest."""
+    import numpy as np
+    import torch
+
+    import paper_2605_05876_amd as ss
+    import scenegen as g
+    from paper_2605_05876_amd import autotune
+
+    w = g.make_config(args.config)
+    batch = ss.batch_from_scenes(w.scenes, w.cameras)
+    n = batch.n_pixels
+    rng = np.random.default_rng(0)
+    G = torch.from_numpy(rng.normal(size=(n, 3)).astype(np.float32)).cuda()
+    Ga = torch.from_numpy(rng.normal(size=n).astype(np.float32)).cuda()
+    keep = []
+
+    def make_step(tw, th, lb):
+        keep.clear()
+        torch.cuda.empty_cache()
+        r = ss.Renderer(ss.Options(shade=w.shade, tile_w=tw, tile_h=th, lds_batch=lb))
+        r.reserve(batch)
+        out = (torch.empty((n, 3), device="cuda"), torch.empty(n, device="cuda"), None)
+        grads = {k: torch.empty_like(batch.params[k]) for k in ss.PARAMS}
+        if batch.envmaps is not None:
+            grads["envmap"] = [torch.empty_like(e) for e in batch.envmaps]
+        keep.append((r, out, grads))
+
+        def step():
+            r.forward(batch, out=out)
+            r.backward(batch, G, Ga, grads=grads)
+        return step
+    best = autotune.tune(args.config, batch, make_step, steps=max(3, args.steps), log=log)
+    print(json.dumps({"autotune": args.config, "best": best,
+                      "cache": autotune.lookup(args.config)}), flush=True)
 
 
 def mip_ablation(args):
