@@ -54,7 +54,7 @@ struct Group {
 
 struct SceneEnv {
   int He = 0, We = 0;
-  DevBuf dirs, lv, Z /* output-texel table (R, 1/Z) of levels 1..6 */, dlv;
+  DevBuf dirs, lv, Z /* output-texel table (R, 1/Z) of levels 1..6 */, dlv, part /* prefilter partials */;
   int lh[7], lw[7];
   long long off[7];   // float offsets of levels 1..6 in lv
   long long doff[7];  // float offsets of levels 0..6 in dlv
@@ -287,6 +287,7 @@ ss_status prepare_env(ss_context* c, const ss_batch* b, hipStream_t st) {
     SS_HIP(ensure(e.lv, lv_n * sizeof(float)));
     SS_HIP(ensure(e.dlv, d * sizeof(float)));
     SS_HIP(ensure(e.Z, (size_t)(lv_n / 3 + 1) * 4 * sizeof(float)));
+    SS_HIP(ensure(e.part, (size_t)envmap_prefilter_chunks(He, We) * (size_t)lv_n * sizeof(float)));
     if (e.He != He || e.We != We || !e.dirs.p) {
       SS_HIP(ensure(e.dirs, (size_t)He * We * 4 * sizeof(float)));
       SS_HIP(launch_envmap_dirs(P<float>(e.dirs), He, We, st));
@@ -306,7 +307,7 @@ ss_status run_envmap_prefilter(ss_context* c, const ss_batch* b, hipStream_t st)
     out[0] = nullptr;
     for (int l = 1; l < 7; ++l) out[l] = P<float>(e.lv) + e.off[l];
     SS_HIP(launch_envmap_prefilter(b->envmap[s], e.He, e.We, P<float>(e.dirs), P<float>(e.Z), out,
-                                   e.lh, e.lw, st));
+                                   e.lh, e.lw, P<float>(e.part), st));
   }
   return SS_OK;
 }
@@ -465,7 +466,7 @@ size_t workspace_bytes(const ss_context* c) {
   size_t s = c->views_d.n + c->recs.n + c->counts.n + c->offsets.n + c->scan_tmp.n + c->keys.n +
              c->vals.n + c->keys2.n + c->vals2.n + c->hist.n + c->ranges.n + c->nl.n + c->stats.n +
              c->grad.n + c->misc.n + c->lut.n + c->partial.n + c->sg.n + c->order.n + c->stats2.n;
-  for (const SceneEnv& e : c->env) s += e.dirs.n + e.lv.n + e.Z.n + e.dlv.n;
+  for (const SceneEnv& e : c->env) s += e.dirs.n + e.lv.n + e.Z.n + e.dlv.n + e.part.n;
   return s;
 }
 
@@ -508,7 +509,7 @@ ss_status ss_destroy(ss_context* c) {
                     &c->vals, &c->keys2, &c->vals2, &c->hist, &c->ranges, &c->nl, &c->stats,
                     &c->grad, &c->misc, &c->lut, &c->partial, &c->sg, &c->order, &c->stats2};
   for (DevBuf* b : bufs) release(*b);
-  for (SceneEnv& e : c->env) { release(e.dirs); release(e.lv); release(e.Z); release(e.dlv); }
+  for (SceneEnv& e : c->env) { release(e.dirs); release(e.lv); release(e.Z); release(e.dlv); release(e.part); }
   for (auto& pe : c->prof_ev) { c->ev_pool.push_back(pe.second.first); c->ev_pool.push_back(pe.second.second); }
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;

@@ -236,9 +236,12 @@ hipError_t launch_fill_f32(float* p, float v, long long n, hipStream_t st);
 hipError_t launch_envmap_dirs(float* dirs, int H, int W, hipStream_t st);
 hipError_t launch_envmap_out_dirs(int He, int We, const float* in_dirs, const int lh[7],
                                   const int lw[7], float* out_dirs, hipStream_t st);
+constexpr int kEnvChunksMax = 32;  // input chunks of the environment prefilter
+int envmap_prefilter_chunks(int He, int We);
+// part: scratch of envmap_prefilter_chunks(He, We) x (texels of levels 1..6) x 3 floats
 hipError_t launch_envmap_prefilter(const float* E, int He, int We, const float* in_dirs,
                                    const float* out_dirs, float* const lvl_out[7], const int lh[7],
-                                   const int lw[7], hipStream_t st);
+                                   const int lw[7], float* part, hipStream_t st);
 hipError_t launch_envmap_adjoint(const float* const dlvl[7], const int lh[7], const int lw[7],
                                  const float* out_dirs, int He, int We, const float* in_dirs,
                                  float* dE, hipStream_t st);

@@ -44,11 +44,12 @@ hipError_t launch_envmap_dirs(float* dirs, int H, int W, hipStream_t st) {
 }
 
 __device__ inline float ggx_weight(float c, float alpha) {
-  // D(mu; alpha) max(0, c) with mu^2 = (1 + c)/2
+  // D(mu; alpha) max(0, c) with mu^2 = (1 + c)/2 (hardware reciprocal: the
+  // weights enter normalised sums)
   float a2 = alpha * alpha;
   float mu2 = 0.5f * (1.f + c);
   float t = mu2 * (a2 - 1.f) + 1.f;
-  return a2 / (kPi * t * t) * c;
+  return a2 * (1.f / kPi) * __builtin_amdgcn_rcpf(t * t) * c;
 }
 
 struct LevelSet {
@@ -93,55 +94,97 @@ __global__ void __launch_bounds__(256) envmap_out_dirs_kernel(int nt, const floa
   if (threadIdx.x == 0) out_dirs[o] = make_float4(R[0], R[1], R[2], l < 6 ? 1.f / red[0] : 1.f / kPi);
 }
 
-// One block per output texel of levels 1..6; threads stride over the input
-// texels, then a block reduction.
-__global__ void __launch_bounds__(256) envmap_prefilter_kernel(const float* __restrict__ E, int nt,
-                                                               const float4* __restrict__ dirs,
+// Prefilter, stage 1.  Block (x, y): 256 consecutive output texels of levels
+// 1..6 (one per thread) against input chunk y.  The chunk's texels are staged
+// through LDS 256 at a time (every thread then reads the same entry: a
+// broadcast), so each input texel is fetched once per 256 outputs instead of
+// once per output.  A staged batch whose latitude band lies beyond the
+// hemisphere of every output direction of the wave (angular distance above
+// pi/2 + 1e-3, so the cosine is clearly negative in FP32) adds nothing and is
+// skipped.  Partial sums go to part[y][o][3]; stage 2 adds the chunks in a
+// fixed order.
+__global__ void __launch_bounds__(256) envmap_prefilter_kernel(const float* __restrict__ E, int He, int We,
+                                                               int chunk, const float4* __restrict__ dirs,
                                                                const float4* __restrict__ out_dirs,
-                                                               LevelSet L) {
-  __shared__ float red[3][256];
-  const int o = blockIdx.x;
-  const int l = level_of(L.first, o);
-  const int k = o - L.first[l];
-  const float4 R = out_dirs[o];
+                                                               int n_out, LevelSet L, float* __restrict__ part) {
+  __shared__ float4 sd[256];
+  __shared__ float se[3 * 256];
+  const int nt = He * We;
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  const bool live = o < n_out;
+  const int oo = live ? o : n_out - 1;
+  const int l = level_of(L.first, oo);
+  const float4 R = out_dirs[oo];
+  const float alpha = (float)(l * l) / 25.f;
+  const float thR = acosf(fminf(fmaxf(R.z, -1.f), 1.f));
+  const int t0 = blockIdx.y * chunk, t1 = min(t0 + chunk, nt);
   float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
-  if (l == 6) {
-    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
-      const float4 d = dirs[t];
-      const float c = R.x * d.x + R.y * d.y + R.z * d.z;
-      if (c <= 0.f) continue;
-      const float kk = c * d.w;
-      acc0 += E[3 * t] * kk;
-      acc1 += E[3 * t + 1] * kk;
-      acc2 += E[3 * t + 2] * kk;
-    }
-  } else {
-    const float alpha = (float)(l * l) / 25.f;
-    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
-      const float4 d = dirs[t];
-      const float c = R.x * d.x + R.y * d.y + R.z * d.z;
-      if (c <= 0.f) continue;
-      const float kk = ggx_weight(c, alpha) * d.w;
-      acc0 += E[3 * t] * kk;
-      acc1 += E[3 * t + 1] * kk;
-      acc2 += E[3 * t + 2] * kk;
-    }
-  }
-  red[0][threadIdx.x] = acc0;
-  red[1][threadIdx.x] = acc1;
-  red[2][threadIdx.x] = acc2;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s)
-      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+  for (int tb = t0; tb < t1; tb += 256) {
+    const int n = min(256, t1 - tb);
+    // latitude band of the batch (texel-centre angles of its first and last rows)
+    const float tha = kPi * ((float)(tb / We) + 0.5f) / (float)He;
+    const float thb = kPi * ((float)((tb + n - 1) / We) + 0.5f) / (float)He;
+    const float gap = fmaxf(fmaxf(tha - thR, thR - thb), 0.f);
+    const bool skip = __ballot(!(gap > 0.5f * kPi + 1e-3f)) == 0ull;
     __syncthreads();
+    if (threadIdx.x < n) {
+      const int t = tb + threadIdx.x;
+      sd[threadIdx.x] = dirs[t];
+      se[3 * threadIdx.x] = E[3 * t];
+      se[3 * threadIdx.x + 1] = E[3 * t + 1];
+      se[3 * threadIdx.x + 2] = E[3 * t + 2];
+    }
+    __syncthreads();
+    if (skip) continue;
+    if (l == 6) {
+      for (int i = 0; i < n; ++i) {
+        const float4 d = sd[i];
+        const float c = R.x * d.x + R.y * d.y + R.z * d.z;
+        if (c <= 0.f) continue;
+        const float kk = c * d.w;
+        acc0 += se[3 * i] * kk;
+        acc1 += se[3 * i + 1] * kk;
+        acc2 += se[3 * i + 2] * kk;
+      }
+    } else {
+      for (int i = 0; i < n; ++i) {
+        const float4 d = sd[i];
+        const float c = R.x * d.x + R.y * d.y + R.z * d.z;
+        if (c <= 0.f) continue;
+        const float kk = ggx_weight(c, alpha) * d.w;
+        acc0 += se[3 * i] * kk;
+        acc1 += se[3 * i + 1] * kk;
+        acc2 += se[3 * i + 2] * kk;
+      }
+    }
   }
-  if (threadIdx.x == 0) {
-    float* dst = L.out[l] + 3 * k;
-    dst[0] = red[0][0] * R.w;
-    dst[1] = red[1][0] * R.w;
-    dst[2] = red[2][0] * R.w;
+  if (live) {
+    float* dst = part + ((long long)blockIdx.y * n_out + o) * 3;
+    dst[0] = acc0;
+    dst[1] = acc1;
+    dst[2] = acc2;
   }
+}
+
+// Prefilter, stage 2: level texel = (sum over chunks) / Z.
+__global__ void __launch_bounds__(256) envmap_prefilter_sum_kernel(const float* __restrict__ part, int n_chunks,
+                                                                   int n_out, const float4* __restrict__ out_dirs,
+                                                                   LevelSet L) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_out) return;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+  for (int y = 0; y < n_chunks; ++y) {
+    const float* p = part + ((long long)y * n_out + o) * 3;
+    a0 += p[0];
+    a1 += p[1];
+    a2 += p[2];
+  }
+  const int l = level_of(L.first, o);
+  const float iz = out_dirs[o].w;
+  float* dst = L.out[l] + 3 * (o - L.first[l]);
+  dst[0] = a0 * iz;
+  dst[1] = a1 * iz;
+  dst[2] = a2 * iz;
 }
 
 static LevelSet make_levels(float* const lvl_out[7], const int lh[7], const int lw[7]) {
@@ -160,12 +203,26 @@ hipError_t launch_envmap_out_dirs(int He, int We, const float* in_dirs, const in
   return hipGetLastError();
 }
 
+int envmap_prefilter_chunks(int He, int We) {
+  // input chunks: enough blocks to fill the chip, at least 1024 texels each
+  const int nt = He * We;
+  int c = (nt + 2047) / 2048;
+  return c < 1 ? 1 : (c > kEnvChunksMax ? kEnvChunksMax : c);
+}
+
 hipError_t launch_envmap_prefilter(const float* E, int He, int We, const float* in_dirs,
                                    const float* out_dirs, float* const lvl_out[7], const int lh[7],
-                                   const int lw[7], hipStream_t st) {
+                                   const int lw[7], float* part, hipStream_t st) {
   LevelSet L = make_levels(lvl_out, lh, lw);
-  hipLaunchKernelGGL(envmap_prefilter_kernel, dim3(L.first[7]), dim3(256), 0, st, E, He * We,
+  const int n_out = L.first[7], nt = He * We;
+  const int nc = envmap_prefilter_chunks(He, We);
+  const int chunk = ((nt + nc - 1) / nc + 255) / 256 * 256;
+  hipLaunchKernelGGL(envmap_prefilter_kernel, dim3((n_out + 255) / 256, nc), dim3(256), 0, st, E, He, We, chunk,
                      reinterpret_cast<const float4*>(in_dirs),
+                     reinterpret_cast<const float4*>(out_dirs), n_out, L, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(envmap_prefilter_sum_kernel, dim3((n_out + 255) / 256), dim3(256), 0, st, part, nc, n_out,
                      reinterpret_cast<const float4*>(out_dirs), L);
   return hipGetLastError();
 }
@@ -178,6 +235,7 @@ hipError_t launch_envmap_prefilter(const float* E, int He, int We, const float* 
 struct DLevelSet {
   const float* g[7];
   int first[8];
+  int h[7], w[7];
 };
 
 __global__ void __launch_bounds__(256) envmap_adjoint_kernel(DLevelSet L, int nt,
@@ -191,7 +249,23 @@ __global__ void __launch_bounds__(256) envmap_adjoint_kernel(DLevelSet L, int nt
   float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
   int l = level_of(L.first, o_begin);
   float alpha = (float)(l * l) / 25.f;
-  for (int o = o_begin; o < o_end; ++o) {
+  // Latitude bands of the block's input texels and of the chunk's output texels
+  // (texel-centre angles; rows are monotone within a level).  When they are
+  // more than pi/2 + 1e-3 apart every cosine is clearly negative and the chunk
+  // adds nothing.
+  {
+    const int He = L.h[0], We = L.w[0];
+    const int ta = blockIdx.x * blockDim.x, tb = min(ta + (int)blockDim.x, nt) - 1;
+    const float ia = kPi * ((float)(ta / We) + 0.5f) / (float)He, ib = kPi * ((float)(tb / We) + 0.5f) / (float)He;
+    float oa = 4.f, ob = -1.f;
+    for (int lv = l; lv <= 6 && L.first[lv] < o_end; ++lv) {
+      const int k0 = max(o_begin, L.first[lv]) - L.first[lv], k1 = min(o_end, L.first[lv + 1]) - 1 - L.first[lv];
+      oa = fminf(oa, kPi * ((float)(k0 / L.w[lv]) + 0.5f) / (float)L.h[lv]);
+      ob = fmaxf(ob, kPi * ((float)(k1 / L.w[lv]) + 0.5f) / (float)L.h[lv]);
+    }
+    if (fmaxf(ia - ob, oa - ib) > 0.5f * kPi + 1e-3f) l = 7;  // nothing to add from this chunk
+  }
+  for (int o = o_begin; l <= 6 && o < o_end; ++o) {
     if (o >= L.first[l + 1]) {
       l = level_of(L.first, o);
       alpha = (float)(l * l) / 25.f;
@@ -224,6 +298,8 @@ hipError_t launch_envmap_adjoint(const float* const dlvl[7], const int lh[7], co
   L.first[1] = 0;
   for (int l = 0; l < 7; ++l) L.g[l] = dlvl[l];
   for (int l = 1; l <= 6; ++l) L.first[l + 1] = L.first[l] + lh[l] * lw[l];
+  for (int l = 0; l < 7; ++l) { L.h[l] = lh[l]; L.w[l] = lw[l]; }
+  L.h[0] = He; L.w[0] = We;
   const int nt = He * We;
   hipError_t e = launch_fill_f32(dE, 0.f, (long long)nt * 3, st);
   if (e != hipSuccess) return e;
