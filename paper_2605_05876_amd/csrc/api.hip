@@ -49,7 +49,7 @@ struct Group {
   int tile_base, n_tiles;
   long long rec_begin, rec_end;
   long long pair_base, pair_cap;
-  int key_bits;
+  int pair_passes;  // radix passes of the pair sort: 8-bit digits of the local tile index
 };
 
 struct SceneEnv {
@@ -82,9 +82,9 @@ struct ss_context {
   std::vector<Group> groups;
   std::vector<SceneEnv> env;
   DevBuf views_d, recs, counts, offsets, scan_tmp, keys, vals, keys2, vals2, hist, ranges, nl, stats,
-      grad, misc, partial, sg, order, stats2;
+      grad, misc, partial, sg, order, stats2, zkey, zkey2, zidx, zidx2, prect, zrect;
   std::vector<long long> soff;
-  long long scan_tmp_n = 0, pair_total = 0;
+  long long scan_tmp_n = 0, pair_total = 0, hist_n = 0;
   DevBuf lut;
   int lut_nv = 0, lut_r = 0;
   bool fwd_valid = false;
@@ -101,6 +101,7 @@ struct ss_context {
 namespace {
 
 constexpr int kMiscStatus = 0, kMiscQueue = 1, kMiscPairs = 8;
+constexpr int kMiscOrder = kMiscPairs + kMaxViews;  // 66 u32: tile-order bucket counts and cursors
 
 #define SS_HIP(x)                                                            \
   do {                                                                       \
@@ -323,7 +324,8 @@ ss_status run_preprocess(ss_context* c, const ss_batch* b, int v0, int v1, hipSt
   int ms = 0;
   for (int v = v0; v < v1; ++v) ms = c->views_h[v].n_surf > ms ? c->views_h[v].n_surf : ms;
   SS_HIP(launch_preprocess(pp, c->N, P<ViewDev>(c->views_d), v0, v1, ms, make_params(c),
-                           P<float>(c->recs), P<uint32_t>(c->counts), st));
+                           P<float>(c->recs), P<uint32_t>(c->counts), P<uint32_t>(c->zkey),
+                           P<uint2>(c->prect), st));
   return SS_OK;
 }
 
@@ -337,6 +339,44 @@ ss_status run_count_scan(ss_context* c, const Group& g, hipStream_t st) {
   }
   SS_HIP(launch_scan_u32(P<uint32_t>(c->counts) + g.rec_begin, P<uint32_t>(c->offsets) + g.rec_begin, n,
                          misc + kMiscPairs + gi, P<uint32_t>(c->scan_tmp), c->scan_tmp_n, st));
+  return SS_OK;
+}
+
+// Binning of one group (tile binning, Sec. 3.2.1): depth sort of the records,
+// slot ranges by a scan of their tile counts in that order, pair emission,
+// stable sort of the pairs by tile, tile ranges.  The sorted pairs end in
+// (keys, vals).
+ss_status run_binning(ss_context* c, const Group& g, int gi, hipStream_t st) {
+  uint32_t* misc = P<uint32_t>(c->misc);
+  const uint32_t* np = misc + kMiscPairs + gi;
+  int* status = reinterpret_cast<int*>(misc + kMiscStatus);
+  const long long n = g.rec_end - g.rec_begin;
+  if (n <= 0) {
+    SS_HIP(launch_fill_u32(misc + kMiscPairs + gi, 0u, 1, st));
+    SS_HIP(launch_fill_u32(P<uint32_t>(c->ranges) + 2LL * g.tile_base, 0u, 2LL * g.n_tiles, st));
+    return SS_OK;
+  }
+  uint32_t* zk = P<uint32_t>(c->zkey) + g.rec_begin;
+  uint32_t* zi = P<uint32_t>(c->zidx) + g.rec_begin;
+  uint2* zr = P<uint2>(c->zrect) + g.rec_begin;
+  SS_HIP(launch_radix_sort(zk, zi, P<uint32_t>(c->zkey2) + g.rec_begin, P<uint32_t>(c->zidx2) + g.rec_begin,
+                           true, (uint32_t)g.rec_begin, P<uint2>(c->prect), zr, nullptr, n, n, 4,
+                           P<uint32_t>(c->hist), c->hist_n, P<uint32_t>(c->scan_tmp), c->scan_tmp_n, st));
+  SS_HIP(launch_scan_rect_tiles(zr, c->opt.tile_w, c->opt.tile_h, P<uint32_t>(c->offsets) + g.rec_begin, n,
+                                misc + kMiscPairs + gi, P<uint32_t>(c->scan_tmp), c->scan_tmp_n, st));
+  // emit where an odd pass count leaves the sorted pairs in (keys, vals)
+  uint32_t* keys = P<uint32_t>(c->keys) + g.pair_base;
+  uint32_t* vals = P<uint32_t>(c->vals) + g.pair_base;
+  uint32_t* keys2 = P<uint32_t>(c->keys2) + g.pair_base;
+  uint32_t* vals2 = P<uint32_t>(c->vals2) + g.pair_base;
+  const bool odd = (g.pair_passes & 1) != 0;
+  SS_HIP(launch_emit_pairs(zi, zr, P<uint32_t>(c->offsets) + g.rec_begin, P<ViewDev>(c->views_d), g.v0, g.v1, n,
+                           c->opt.tile_w, c->opt.tile_h, odd ? keys2 : keys, odd ? vals2 : vals, g.pair_cap, status,
+                           st));
+  SS_HIP(launch_radix_sort(odd ? keys2 : keys, odd ? vals2 : vals, odd ? keys : keys2, odd ? vals : vals2, false, 0u,
+                           nullptr, nullptr, np, -1, g.pair_cap, g.pair_passes, P<uint32_t>(c->hist), c->hist_n,
+                           P<uint32_t>(c->scan_tmp), c->scan_tmp_n, st));
+  SS_HIP(launch_tile_ranges(keys, np, g.pair_cap, P<uint32_t>(c->ranges), g.tile_base, g.n_tiles, st));
   return SS_OK;
 }
 
@@ -372,10 +412,7 @@ ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
     for (int v = g.v0; v < g.v1; ++v) g.n_tiles += vh[v].tiles_x * vh[v].tiles_y;
     g.rec_begin = vh[g.v0].rec_off;
     g.rec_end = vh[g.v1 - 1].rec_off + vh[g.v1 - 1].n_surf;
-    int kb = 32 + bits_for((long long)g.tile_base + g.n_tiles);
-    int passes = (kb + 7) / 8;
-    if (passes & 1) ++passes;  // an even pass count leaves the result in the primary buffers
-    g.key_bits = 8 * passes;
+    g.pair_passes = g.n_tiles > 1 ? (bits_for(g.n_tiles) + 7) / 8 : 0;
     g.pair_base = 0;
     g.pair_cap = 0;
     c->groups.push_back(g);
@@ -385,7 +422,13 @@ ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
   SS_HIP(ensure(c->recs, (size_t)R * kRecFloats * sizeof(float)));
   SS_HIP(ensure(c->counts, (size_t)R * sizeof(uint32_t)));
   SS_HIP(ensure(c->offsets, (size_t)R * sizeof(uint32_t)));
-  SS_HIP(ensure(c->misc, (kMiscPairs + kMaxViews) * sizeof(uint32_t)));
+  SS_HIP(ensure(c->zkey, (size_t)R * sizeof(uint32_t)));
+  SS_HIP(ensure(c->zkey2, (size_t)R * sizeof(uint32_t)));
+  SS_HIP(ensure(c->zidx, (size_t)R * sizeof(uint32_t)));
+  SS_HIP(ensure(c->zidx2, (size_t)R * sizeof(uint32_t)));
+  SS_HIP(ensure(c->prect, (size_t)R * sizeof(uint2)));
+  SS_HIP(ensure(c->zrect, (size_t)R * sizeof(uint2)));
+  SS_HIP(ensure(c->misc, (kMiscOrder + 66) * sizeof(uint32_t)));
   c->scan_tmp_n = scan_tmp_size(R) + 16;
   SS_HIP(ensure(c->scan_tmp, (size_t)c->scan_tmp_n * sizeof(uint32_t)));
   SS_HIP(ensure(c->ranges, (size_t)2 * (c->n_tiles > 0 ? c->n_tiles : 1) * sizeof(uint32_t)));
@@ -415,13 +458,15 @@ ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
     maxcap = g.pair_cap > maxcap ? g.pair_cap : maxcap;
   }
   c->pair_total = base;
-  SS_HIP(ensure(c->keys, (size_t)base * sizeof(uint64_t)));
-  SS_HIP(ensure(c->keys2, (size_t)base * sizeof(uint64_t)));
+  SS_HIP(ensure(c->keys, (size_t)base * sizeof(uint32_t)));
+  SS_HIP(ensure(c->keys2, (size_t)base * sizeof(uint32_t)));
   SS_HIP(ensure(c->vals, (size_t)base * sizeof(uint32_t)));
   SS_HIP(ensure(c->vals2, (size_t)base * sizeof(uint32_t)));
-  const long long nblocks = (maxcap + 2047) / 2048;
-  SS_HIP(ensure(c->hist, (size_t)256 * nblocks * sizeof(uint32_t)));
-  const long long need_scan = scan_tmp_size(256 * nblocks > R ? 256 * nblocks : R) + 16;
+  long long maxrec = 0;
+  for (const Group& g : c->groups) maxrec = g.rec_end - g.rec_begin > maxrec ? g.rec_end - g.rec_begin : maxrec;
+  c->hist_n = radix_hist_size(maxcap) > radix_hist_size(maxrec) ? radix_hist_size(maxcap) : radix_hist_size(maxrec);
+  SS_HIP(ensure(c->hist, (size_t)c->hist_n * sizeof(uint32_t)));
+  const long long need_scan = scan_tmp_size(c->hist_n > R ? c->hist_n : R) + 16;
   if (need_scan > c->scan_tmp_n) {
     c->scan_tmp_n = need_scan;
     SS_HIP(ensure(c->scan_tmp, (size_t)need_scan * sizeof(uint32_t)));
@@ -465,7 +510,8 @@ enum { ST_ENV = 0, ST_PRE, ST_BIN, ST_RFWD, ST_RBWD, ST_PREBWD, ST_ENVBWD };
 size_t workspace_bytes(const ss_context* c) {
   size_t s = c->views_d.n + c->recs.n + c->counts.n + c->offsets.n + c->scan_tmp.n + c->keys.n +
              c->vals.n + c->keys2.n + c->vals2.n + c->hist.n + c->ranges.n + c->nl.n + c->stats.n +
-             c->grad.n + c->misc.n + c->lut.n + c->partial.n + c->sg.n + c->order.n + c->stats2.n;
+             c->grad.n + c->misc.n + c->lut.n + c->partial.n + c->sg.n + c->order.n + c->stats2.n + c->zkey.n +
+             c->zkey2.n + c->zidx.n + c->zidx2.n + c->prect.n + c->zrect.n;
   for (const SceneEnv& e : c->env) s += e.dirs.n + e.lv.n + e.Z.n + e.dlv.n + e.part.n;
   return s;
 }
@@ -507,7 +553,8 @@ ss_status ss_destroy(ss_context* c) {
   if (c->used) (void)hipStreamSynchronize(c->last_stream);
   DevBuf* bufs[] = {&c->views_d, &c->recs, &c->counts, &c->offsets, &c->scan_tmp, &c->keys,
                     &c->vals, &c->keys2, &c->vals2, &c->hist, &c->ranges, &c->nl, &c->stats,
-                    &c->grad, &c->misc, &c->lut, &c->partial, &c->sg, &c->order, &c->stats2};
+                    &c->grad, &c->misc, &c->lut, &c->partial, &c->sg, &c->order, &c->stats2,
+                    &c->zkey, &c->zkey2, &c->zidx, &c->zidx2, &c->prect, &c->zrect};
   for (DevBuf* b : bufs) release(*b);
   for (SceneEnv& e : c->env) { release(e.dirs); release(e.lv); release(e.Z); release(e.dlv); release(e.part); }
   for (auto& pe : c->prof_ev) { c->ev_pool.push_back(pe.second.first); c->ev_pool.push_back(pe.second.second); }
@@ -582,27 +629,13 @@ ss_status ss_render(ss_context* c, const ss_batch* b, const ss_outputs* out, ss_
     SS_TRY(run_preprocess(c, b, g.v0, g.v1, st));
     prof_end(c, t0, ST_PRE, st);
     t0 = prof_begin(c, st);
-    SS_TRY(run_count_scan(c, g, st));
-    int ms = 0;
-    for (int v = g.v0; v < g.v1; ++v) ms = c->views_h[v].n_surf > ms ? c->views_h[v].n_surf : ms;
-    const uint32_t* np = misc + kMiscPairs + gi;
-    uint64_t* keys = P<uint64_t>(c->keys) + g.pair_base;
+    SS_TRY(run_binning(c, g, (int)gi, st));
     uint32_t* vals = P<uint32_t>(c->vals) + g.pair_base;
-    SS_HIP(launch_emit_pairs(P<float>(c->recs), P<uint32_t>(c->offsets),
-                             P<ViewDev>(c->views_d), g.v0, g.v1, ms, c->opt.tile_w, c->opt.tile_h,
-                             keys, vals, np, g.pair_cap, status, st));
-    (void)ms;
-    bool in_tmp = false;
-    SS_HIP(launch_radix_sort(keys, vals, P<uint64_t>(c->keys2) + g.pair_base,
-                             P<uint32_t>(c->vals2) + g.pair_base, np, g.pair_cap, g.key_bits,
-                             P<uint32_t>(c->hist), P<uint32_t>(c->scan_tmp), c->scan_tmp_n, st,
-                             &in_tmp));
-    if (in_tmp) return SS_ERR_HIP;  // even pass counts by construction
-    SS_HIP(launch_tile_ranges(keys, np, g.pair_cap, P<uint32_t>(c->ranges), g.tile_base, g.n_tiles, st));
     int* order = nullptr;
     if (c->opt.persistent) {
       order = P<int>(c->order) + g.tile_base;
-      SS_HIP(launch_tile_order(P<uint32_t>(c->ranges), g.tile_base, g.n_tiles, order, st));
+      SS_HIP(launch_tile_order(P<uint32_t>(c->ranges), g.tile_base, g.n_tiles, order,
+                               misc + kMiscOrder, st));
     }
     prof_end(c, t0, ST_BIN, st);
     SS_HIP(launch_fill_u32(misc + kMiscQueue, 0u, 1, st));
@@ -756,13 +789,13 @@ __global__ void extract_records_kernel(const float* recs, long long R, uint32_t*
     rect[4 * r + 3] = ry >> 16;
   }
 }
-__global__ void copy_pairs_kernel(const uint64_t* k, const uint32_t* v, long long n, uint64_t tile_base,
-                                  uint64_t* ko, uint32_t* vo) {
+// Pair keys as (global tile << 32) | bits of the record's z_start.
+__global__ void copy_pairs_kernel(const uint32_t* k, const uint32_t* v, long long n, uint64_t tile_base,
+                                  const float* recs, uint64_t* ko, uint32_t* vo) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (ko) ko[i] = k[i];
+  if (ko) ko[i] = ((tile_base + k[i]) << 32) | (uint64_t)__float_as_uint(recs[(long long)v[i] * kRecFloats + R_ZS]);
   if (vo) vo[i] = v[i];
-  (void)tile_base;
 }
 __global__ void copy_ranges_kernel(const uint32_t* r, int n, uint32_t add, uint32_t* o) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -792,8 +825,8 @@ extern "C" ss_status ss_debug_binning(ss_context* c, uint32_t* rec_zbits, int32_
     const long long n = np[gi];
     if ((pair_keys || pair_vals) && n > 0)
       hipLaunchKernelGGL(copy_pairs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                         P<uint64_t>(c->keys) + g.pair_base, P<uint32_t>(c->vals) + g.pair_base, n,
-                         (uint64_t)g.tile_base, pair_keys ? pair_keys + done : nullptr,
+                         P<uint32_t>(c->keys) + g.pair_base, P<uint32_t>(c->vals) + g.pair_base, n,
+                         (uint64_t)g.tile_base, P<float>(c->recs), pair_keys ? pair_keys + done : nullptr,
                          pair_vals ? pair_vals + done : nullptr);
     if (tile_ranges && g.n_tiles > 0)
       hipLaunchKernelGGL(copy_ranges_kernel, dim3((g.n_tiles + 255) / 256), dim3(256), 0, st,

@@ -1,10 +1,18 @@
-// Tile binning (Sec. 3.2.1, Fig. 1 stage 3): exclusive scan of per-record tile
-// counts, emission of (key, value) pairs with key = global tile << 32 | bits of
-// z_start (z_start > 0 after the cull, so the float bits order like the
-// values) and value = record index, a stable LSD radix sort over the key bits
-// in use, and per-tile [start, end) ranges.  Each record emits in its own slot
-// range in row-major tile order and records are ordered by (view, surfel), so
-// the sorted order within a tile is (z_start, record): deterministic.
+// Tile binning (Sec. 3.2.1, Fig. 1 stage 3).  Order within a tile is by
+// (z_start, record index): deterministic, and the order the oracle defines.
+// Instead of one sort over (tile, z_start) keys of every pair, the records are
+// sorted first and the pairs second, both with 32-bit keys:
+//   1. the group's records are radix sorted by the bits of z_start (positive
+//      after the cull, so the float bits order like the values; culled
+//      records carry 0xffffffff and sort last) with their index as value;
+//   2. an exclusive scan of the per-record tile counts, taken in that order,
+//      gives each record its slot range;
+//   3. each record emits (tile, record) pairs into its slots, tile relative to
+//      the group's first tile;
+//   4. a stable radix sort over the tile bits in use, then per-tile
+//      [start, end) ranges.
+// Both sorts are stable and the records enter step 1 in index order, so
+// within a tile the result is ordered by (z_start, record index).
 //
 // Every kernel reads the data-dependent pair count from device memory and is
 // sized by the reserved capacity on the host, so the whole sequence can be
@@ -41,8 +49,29 @@ hipError_t launch_fill_f32(float* p, float v, long long n, hipStream_t st) {
 
 // ---------------------------------------------------------------- scan
 // Exclusive scan of u32 in three kernels: block sums, scan of the block sums
-// (one block), per-block scan plus carry.  Blocks hold 1024 elements.
-constexpr int kScanBlock = 1024;
+// (one block), per-block scan plus carry.  Blocks of 256 threads hold
+// kScanBlock elements.  The scanned sequence is a plain array or the tile
+// counts of record rectangles.  Reads are clamped into range rather than
+// branched round, so a thread's loads are all in flight at once.
+constexpr int kScanPer = 16;
+constexpr int kScanBlock = 256 * kScanPer;
+
+struct ScanPlain {
+  const uint32_t* in;
+  __device__ uint32_t operator()(long long i) const { return in[i]; }
+};
+// Tiles covered by a record's pixel rectangle (il | ih << 16, jl | jh << 16);
+// zero for an empty one (a culled record).
+struct ScanRectTiles {
+  const uint2* rect;
+  int tw, th;
+  __device__ uint32_t operator()(long long i) const {
+    const uint2 q = rect[i];
+    const int il = (int)(q.x & 0xffffu), ih = (int)(q.x >> 16), jl = (int)(q.y & 0xffffu), jh = (int)(q.y >> 16);
+    if (il > ih || jl > jh) return 0u;
+    return (uint32_t)((ih / tw - il / tw + 1) * (jh / th - jl / th + 1));
+  }
+};
 
 __device__ inline uint32_t block_exclusive_scan_256(uint32_t v, uint32_t* sh, uint32_t* total) {
   // sh: 256 + 8 entries of LDS
@@ -63,13 +92,16 @@ __device__ inline uint32_t block_exclusive_scan_256(uint32_t v, uint32_t* sh, ui
   return base + x - v;
 }
 
-__global__ void __launch_bounds__(256) scan_reduce_kernel(const uint32_t* in, long long n, uint32_t* sums) {
+template <class F>
+__global__ void __launch_bounds__(256) scan_reduce_kernel(F f, long long n, uint32_t* sums) {
   __shared__ uint32_t sh[264];
   long long base = (long long)blockIdx.x * kScanBlock;
   uint32_t s = 0;
-  for (int k = 0; k < 4; ++k) {
-    long long i = base + k * 256 + threadIdx.x;
-    if (i < n) s += in[i];
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const long long i = base + k * 256 + threadIdx.x;
+    const uint32_t x = f(i < n ? i : n - 1);
+    s += i < n ? x : 0u;
   }
   uint32_t tot;
   block_exclusive_scan_256(s, sh, &tot);
@@ -90,198 +122,426 @@ __global__ void __launch_bounds__(256) scan_sums_kernel(uint32_t* sums, long lon
   if (threadIdx.x == 0 && total) *total = carry;
 }
 
-__global__ void __launch_bounds__(256) scan_apply_kernel(const uint32_t* in, uint32_t* out, long long n,
-                                                         const uint32_t* sums) {
+// In place is fine: a block reads all its elements before writing any.  Loads
+// and stores are coalesced; LDS (rows padded against bank conflicts) turns
+// them into kScanPer consecutive elements per thread and back.
+template <class F>
+__global__ void __launch_bounds__(256) scan_apply_kernel(F f, uint32_t* out, long long n, const uint32_t* sums) {
+  constexpr int kRow = kScanPer + 1;
   __shared__ uint32_t sh[264];
-  long long base = (long long)blockIdx.x * kScanBlock;
-  // thread t owns 4 consecutive elements
-  uint32_t v[4], s = 0;
-  for (int k = 0; k < 4; ++k) {
-    long long i = base + threadIdx.x * 4 + k;
-    v[k] = i < n ? in[i] : 0u;
-    s += v[k];
+  __shared__ uint32_t tv[256 * kRow];
+  const int t = threadIdx.x;
+  const long long base = (long long)blockIdx.x * kScanBlock;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const int j = k * 256 + t;
+    const long long i = base + j;
+    const uint32_t x = f(i < n ? i : n - 1);
+    tv[(j / kScanPer) * kRow + j % kScanPer] = i < n ? x : 0u;
   }
+  __syncthreads();
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) s += tv[t * kRow + k];
   uint32_t ex = block_exclusive_scan_256(s, sh, nullptr) + sums[blockIdx.x];
-  for (int k = 0; k < 4; ++k) {
-    long long i = base + threadIdx.x * 4 + k;
-    if (i < n) out[i] = ex;
-    ex += v[k];
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const uint32_t x = tv[t * kRow + k];
+    tv[t * kRow + k] = ex;
+    ex += x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const int j = k * 256 + t;
+    const long long i = base + j;
+    if (i < n) out[i] = tv[(j / kScanPer) * kRow + j % kScanPer];
   }
 }
 
 long long scan_tmp_size(long long n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
 
-hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint32_t* total,
-                           uint32_t* tmp, long long tmp_n, hipStream_t st) {
+template <class F>
+static hipError_t scan_with(F f, uint32_t* out, long long n, uint32_t* total, uint32_t* tmp, long long tmp_n,
+                            hipStream_t st) {
   long long nb = (n + kScanBlock - 1) / kScanBlock;
   if (nb <= 0 || nb > tmp_n) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, st, in, n, tmp);
+  hipLaunchKernelGGL(scan_reduce_kernel<F>, dim3((unsigned)nb), dim3(256), 0, st, f, n, tmp);
   hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, st, tmp, nb, total);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(256), 0, st, in, out, n, tmp);
+  hipLaunchKernelGGL(scan_apply_kernel<F>, dim3((unsigned)nb), dim3(256), 0, st, f, out, n, tmp);
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- emission
-__global__ void __launch_bounds__(256) emit_kernel(const float* __restrict__ recs, const uint32_t* __restrict__ offsets,
-                                                   const ViewDev* __restrict__ views, int v0, int tile_w,
-                                                   int tile_h, uint64_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ vals, const uint32_t* n_pairs,
-                                                   long long cap, int* status) {
-  const ViewDev& v = views[v0 + blockIdx.y];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= v.n_surf) return;
-  const long long r = v.rec_off + i;
-  const float4 q = reinterpret_cast<const float4*>(recs + r * kRecFloats)[3];
-  const int rx = __float_as_int(q.x), ry = __float_as_int(q.y);
-  const int il = rx & 0xffff, ih = rx >> 16, jl = ry & 0xffff, jh = ry >> 16;
-  if (il > ih || jl > jh) return;
-  const int tx0 = il / tile_w, tx1 = ih / tile_w, ty0 = jl / tile_h, ty1 = jh / tile_h;
-  const uint32_t zb = (uint32_t)__float_as_int(q.z);
-  long long o = offsets[r];
-  const long long need = o + (long long)(tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-  if (need > cap || need > (long long)*n_pairs) {
-    *status = 3;  // SS_ERR_CAPACITY
-    return;
-  }
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      const uint64_t tile = (uint64_t)(v.tile_base + ty * v.tiles_x + tx);
-      keys[o] = (tile << 32) | zb;
-      vals[o] = (uint32_t)r;
-      ++o;
-    }
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint32_t* total, uint32_t* tmp,
+                           long long tmp_n, hipStream_t st) {
+  return scan_with(ScanPlain{in}, out, n, total, tmp, tmp_n, st);
 }
 
-hipError_t launch_emit_pairs(const float* recs, const uint32_t* offsets, const ViewDev* views,
-                             int v0, int v1, int max_surf, int tile_w, int tile_h,
-                             uint64_t* keys, uint32_t* vals, const uint32_t* n_pairs,
-                             long long cap, int* status, hipStream_t st) {
-  if (v1 <= v0 || max_surf <= 0) return hipSuccess;
-  dim3 grid((max_surf + 255) / 256, v1 - v0);
-  hipLaunchKernelGGL(emit_kernel, grid, dim3(256), 0, st, recs, offsets, views, v0, tile_w, tile_h,
-                     keys, vals, n_pairs, cap, status);
+hipError_t launch_scan_rect_tiles(const uint2* rect, int tile_w, int tile_h, uint32_t* out, long long n,
+                                  uint32_t* total, uint32_t* tmp, long long tmp_n, hipStream_t st) {
+  return scan_with(ScanRectTiles{rect, tile_w, tile_h}, out, n, total, tmp, tmp_n, st);
+}
+
+// ---------------------------------------------------------------- emission
+// Position i of the depth-sorted record list (record order[i], pixel rectangle
+// rect[i]) emits its pairs into slots offsets[i] on, in row-major order of its
+// tile rectangle.  The records of a block fill one contiguous slot range; it is
+// staged in LDS in windows of kEmitWindow slots and written out coalesced.
+constexpr int kEmitThreads = 256;
+constexpr int kEmitWindow = 2048;
+
+__global__ void __launch_bounds__(kEmitThreads) emit_kernel(const uint32_t* __restrict__ order,
+                                                            const uint2* __restrict__ rect,
+                                                            const uint32_t* __restrict__ offsets,
+                                                            const ViewDev* __restrict__ views, int v0, int nv,
+                                                            int tile_w, int tile_h, long long n_rec,
+                                                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                            long long cap, int* status) {
+  __shared__ long long roff[kMaxViews];
+  __shared__ int tbase[kMaxViews], tilesx[kMaxViews];
+  __shared__ uint32_t sk[kEmitWindow], sv[kEmitWindow];
+  __shared__ long long span[2];
+  const int t = threadIdx.x;
+  if (t < nv) {
+    const ViewDev& v = views[v0 + t];
+    roff[t] = v.rec_off;
+    tbase[t] = v.tile_base - views[v0].tile_base;
+    tilesx[t] = v.tiles_x;
+  }
+  const long long i0 = (long long)blockIdx.x * kEmitThreads;
+  const long long i1 = i0 + kEmitThreads < n_rec ? i0 + kEmitThreads : n_rec;
+  if (t == 0) {
+    span[0] = offsets[i0];
+    span[1] = 0;
+  }
+  __syncthreads();
+  const long long i = i0 + t;
+  uint32_t r = 0u;
+  long long o = 0, cnt = 0;
+  int tx0 = 0, ty0 = 0, nx = 1, tb = 0, tx = 0;
+  if (i < i1) {
+    r = order[i];
+    o = offsets[i];
+    const uint2 q = rect[i];
+    const int il = (int)(q.x & 0xffffu), ih = (int)(q.x >> 16), jl = (int)(q.y & 0xffffu), jh = (int)(q.y >> 16);
+    if (il <= ih && jl <= jh) {
+      int lo = 0, hi = nv - 1;  // the view holding record r: last one with rec_off <= r
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (roff[mid] <= (long long)r) lo = mid;
+        else hi = mid - 1;
+      }
+      tx0 = il / tile_w;
+      ty0 = jl / tile_h;
+      nx = ih / tile_w - tx0 + 1;
+      cnt = (long long)nx * (jh / tile_h - ty0 + 1);
+      tb = tbase[lo];
+      tx = tilesx[lo];
+      if (o + cnt > cap) *status = 3;  // SS_ERR_CAPACITY; every slot below cap is still written
+    }
+    if (i == i1 - 1) span[1] = o + cnt;
+  }
+  __syncthreads();
+  const long long s0 = span[0], s1 = span[1] < cap ? span[1] : cap;
+  for (long long w = s0; w < s1; w += kEmitWindow) {
+    const long long we = w + kEmitWindow < s1 ? w + kEmitWindow : s1;
+    const long long a = o > w ? o : w, e = o + cnt < we ? o + cnt : we;
+    if (a < e) {
+      int j = (int)(a - o);
+      int dy = j / nx, dx = j - dy * nx;
+      for (long long s = a; s < e; ++s) {
+        sk[s - w] = (uint32_t)(tb + (ty0 + dy) * tx + tx0 + dx);
+        sv[s - w] = r;
+        if (++dx == nx) {
+          dx = 0;
+          ++dy;
+        }
+      }
+    }
+    __syncthreads();
+    for (long long s = w + t; s < we; s += kEmitThreads) {
+      keys[s] = sk[s - w];
+      vals[s] = sv[s - w];
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_emit_pairs(const uint32_t* order, const uint2* rect, const uint32_t* offsets,
+                             const ViewDev* views, int v0, int v1, long long n_rec, int tile_w, int tile_h,
+                             uint32_t* keys, uint32_t* vals, long long cap, int* status, hipStream_t st) {
+  if (v1 <= v0 || n_rec <= 0) return hipSuccess;
+  if (v1 - v0 > kMaxViews) return hipErrorInvalidValue;
+  const long long nb = (n_rec + kEmitThreads - 1) / kEmitThreads;
+  hipLaunchKernelGGL(emit_kernel, dim3((unsigned)nb), dim3(kEmitThreads), 0, st, order, rect, offsets, views, v0,
+                     v1 - v0, tile_w, tile_h, n_rec, keys, vals, cap, status);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- radix sort
-// LSD, 8-bit digits.  A block owns kSortItems consecutive pairs; the scatter
-// ranks equal digits stably with wave64 ballots (a match-any over the 8 digit
-// bits) and per-wave digit counts in LDS.
-constexpr int kSortThreads = 256;
-constexpr int kSortRounds = 8;
-constexpr int kSortItems = kSortThreads * kSortRounds;
+// Stable LSD radix sort of 32-bit keys carrying 32-bit values, 8-bit digits,
+// reduce-then-scan.  The input is cut into chunks of kRadixItems pairs; each
+// workgroup owns a contiguous run of chunks, each of its waves a contiguous
+// 1/8 of a chunk, so workgroup, chunk and wave order are the input order.
+// Per pass: the histogram kernel writes each workgroup's digit counts
+// digit-major (hist[digit * groups + group]), one exclusive scan of that array
+// gives every workgroup the global start of each digit's run, and the scatter
+// kernel walks its chunks in order: it ranks each pair stably inside the chunk
+// (wave64 match-any over the digit bits, per-wave running digit counts),
+// stages the chunk in LDS in digit order and writes every digit's run of the
+// chunk to consecutive addresses after the runs of the chunks before it.
+constexpr int kRadixThreads = 512;
+constexpr int kRadixWaves = kRadixThreads / 64;
+constexpr int kRadixRounds = 16;
+constexpr int kRadixPerWave = 64 * kRadixRounds;
+constexpr int kRadixItems = kRadixThreads * kRadixRounds;
+constexpr int kRadixMaxGroups = 1 << 20;
 
-__global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const uint64_t* __restrict__ keys,
-                                                                  const uint32_t* n_pairs, int shift,
-                                                                  uint32_t* __restrict__ hist, int nblocks) {
-  __shared__ uint32_t cnt[256];
-  cnt[threadIdx.x] = 0;
-  __syncthreads();
-  const long long n = *n_pairs;
-  const long long base = (long long)blockIdx.x * kSortItems;
-  for (int k = 0; k < kSortRounds; ++k) {
-    long long i = base + k * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[(uint32_t)(keys[i] >> shift) & 255u], 1u);
-  }
-  __syncthreads();
-  hist[(long long)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+struct RadixGrid {
+  int groups, chunks_per_group;
+};
+static RadixGrid radix_grid(long long cap) {
+  const long long chunks = (cap + kRadixItems - 1) / kRadixItems;
+  RadixGrid g;
+  g.chunks_per_group = (int)((chunks + kRadixMaxGroups - 1) / kRadixMaxGroups);
+  if (g.chunks_per_group < 1) g.chunks_per_group = 1;
+  g.groups = (int)((chunks + g.chunks_per_group - 1) / g.chunks_per_group);
+  if (g.groups < 1) g.groups = 1;
+  return g;
+}
+long long radix_hist_size(long long cap) { return 256LL * radix_grid(cap).groups; }
+
+__device__ inline long long radix_count(const uint32_t* n_dev, long long n_fixed, long long cap) {
+  const long long n = n_fixed >= 0 ? n_fixed : (long long)*n_dev;
+  return n < cap ? n : cap;
 }
 
-__global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
-    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, const uint32_t* n_pairs, int shift, const uint32_t* __restrict__ hist,
-    int nblocks) {
-  __shared__ uint32_t base_d[256];
-  __shared__ uint32_t wc[4][256];
+// Lanes of the wave holding the same 8-bit digit as this one, among live lanes.
+__device__ inline uint64_t match_digit(uint32_t d, bool live) {
+  uint64_t m = __ballot(live);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bb = __ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+__device__ inline uint64_t lanes_below() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull) >> (64 - lane);
+}
+
+__global__ void __launch_bounds__(kRadixThreads) radix_hist_kernel(const uint32_t* __restrict__ keys,
+                                                                   const uint32_t* n_dev, long long n_fixed,
+                                                                   long long cap, int shift, int cpg,
+                                                                   uint32_t* __restrict__ hist) {
+  // 4 sub-histograms per wave (by lane & 3) cut same-address conflicts of the
+  // LDS atomics on skewed digits; rows padded to 257 to put them in other banks
+  constexpr int kSub = 4, kRow = 257;
+  __shared__ uint32_t wh[kRadixWaves * kSub * kRow];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const long long n = *n_pairs;
-  const long long base = (long long)blockIdx.x * kSortItems;
-  if (base >= n) return;
-  base_d[t] = hist[(long long)t * nblocks + blockIdx.x];
-  for (int w = 0; w < 4; ++w) wc[w][t] = 0;
+  uint32_t* my = wh + (wave * kSub + (lane & (kSub - 1))) * kRow;
+  for (int i = t; i < kRadixWaves * kSub * kRow; i += kRadixThreads) wh[i] = 0u;
   __syncthreads();
-  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-  for (int k = 0; k < kSortRounds; ++k) {
-    const long long i = base + k * kSortThreads + t;
-    const bool live = i < n;
-    uint64_t key = 0;
-    uint32_t val = 0, d = 0;
-    if (live) {
-      key = kin[i];
-      val = vin[i];
-      d = (uint32_t)(key >> shift) & 255u;
+  const long long n = radix_count(n_dev, n_fixed, cap);
+  for (int c = 0; c < cpg; ++c) {
+    const long long b0 = ((long long)blockIdx.x * cpg + c) * kRadixItems;
+    if (b0 >= n) break;
+    const long long base = b0 + (long long)wave * kRadixPerWave + lane;
+    // loads clamped into range (n > b0 >= 0), not branched round, so all are in flight at once
+    uint32_t d[kRadixRounds];
+#pragma unroll
+    for (int k = 0; k < kRadixRounds; ++k) {
+      const long long i = base + 64 * k;
+      d[k] = (keys[i < n ? i : n - 1] >> shift) & 255u;
     }
-    uint64_t mask = __ballot(live);
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      mask &= bit ? bb : ~bb;
-    }
-    const int rank = __popcll(mask & lt);
-    const int cnt = __popcll(mask);
-    const bool leader = live && rank == 0;
-    if (leader) wc[wave][d] = (uint32_t)cnt;
-    __syncthreads();
-    if (live) {
-      uint32_t off = base_d[d] + (uint32_t)rank;
-      for (int w = 0; w < wave; ++w) off += wc[w][d];
-      kout[off] = key;
-      vout[off] = val;
-    }
-    __syncthreads();
-    if (leader) {
-      atomicAdd(&base_d[d], (uint32_t)cnt);
-      wc[wave][d] = 0;
-    }
-    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRadixRounds; ++k)
+      if (base + 64 * k < n) atomicAdd(&my[d[k]], 1u);
+  }
+  __syncthreads();
+  if (t < 256) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int w = 0; w < kRadixWaves * kSub; ++w) s += wh[w * kRow + t];
+    hist[(long long)t * gridDim.x + blockIdx.x] = s;
   }
 }
 
-hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp,
-                             const uint32_t* n_pairs, long long cap, int key_bits, uint32_t* hist,
-                             uint32_t* scan_tmp, long long scan_tmp_n, hipStream_t st,
-                             bool* result_in_tmp) {
-  const int nblocks = (int)((cap + kSortItems - 1) / kSortItems);
-  uint64_t* ka = keys;
-  uint32_t* va = vals;
-  uint64_t* kb = keys_tmp;
-  uint32_t* vb = vals_tmp;
-  bool in_tmp = false;
-  for (int shift = 0; shift < key_bits; shift += 8) {
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(nblocks), dim3(kSortThreads), 0, st, ka, n_pairs,
-                       shift, hist, nblocks);
-    hipError_t e = launch_scan_u32(hist, hist, (long long)256 * nblocks, nullptr, scan_tmp,
-                                   scan_tmp_n, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblocks), dim3(kSortThreads), 0, st, ka, va, kb, vb,
-                       n_pairs, shift, hist, nblocks);
-    uint64_t* tk = ka; ka = kb; kb = tk;
-    uint32_t* tv = va; va = vb; vb = tv;
-    in_tmp = !in_tmp;
+// IOTA: the input values are val0 + (input position), vin is not read.
+// GATHER: also writes gout[dst] = gsrc[value] (the last pass of a sort whose
+// values index gsrc).
+template <bool IOTA, bool GATHER>
+__global__ void __launch_bounds__(kRadixThreads) radix_scatter_kernel(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t val0,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint2* __restrict__ gsrc,
+    uint2* __restrict__ gout, const uint32_t* n_dev, long long n_fixed, long long cap, int shift, int cpg,
+    const uint32_t* __restrict__ hist) {
+  __shared__ uint32_t woff[kRadixWaves][256];  // per-wave digit counts, then chunk-local run starts
+  __shared__ uint32_t loc[256];                // chunk-local start of each digit
+  __shared__ uint32_t run[256];                // global start of each digit's run of this chunk
+  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t sk[kRadixItems];
+  __shared__ uint32_t sv[kRadixItems];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const long long n = radix_count(n_dev, n_fixed, cap);
+  if (t < 256) run[t] = hist[(long long)t * gridDim.x + blockIdx.x];
+  const uint64_t lt = lanes_below();
+  for (int c = 0; c < cpg; ++c) {
+    const long long b0 = ((long long)blockIdx.x * cpg + c) * kRadixItems;
+    if (b0 >= n) break;
+    for (int i = t; i < kRadixWaves * 256; i += kRadixThreads) (&woff[0][0])[i] = 0u;
+    const long long base = b0 + (long long)wave * kRadixPerWave + lane;
+    // loads clamped into range (n > b0 >= 0), not branched round, so all are in flight at once
+    uint32_t key[kRadixRounds], val[kRadixRounds];
+#pragma unroll
+    for (int k = 0; k < kRadixRounds; ++k) {
+      const long long i = base + 64 * k;
+      const long long ic = i < n ? i : n - 1;
+      key[k] = kin[ic];
+      val[k] = IOTA ? val0 + (uint32_t)i : vin[ic];
+    }
+    __syncthreads();
+    // stable rank of each pair among the wave's pairs of its digit
+    uint32_t pre[kRadixRounds];
+#pragma unroll
+    for (int k = 0; k < kRadixRounds; ++k) {
+      const bool live = base + 64 * k < n;
+      const uint32_t d = (key[k] >> shift) & 255u;
+      const uint64_t m = match_digit(d, live);
+      const uint32_t r = (uint32_t)__popcll(m & lt);
+      const uint32_t cw = woff[wave][d];
+      pre[k] = cw + r;
+      __builtin_amdgcn_wave_barrier();
+      if (live && r == 0) woff[wave][d] = cw + (uint32_t)__popcll(m);
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // digit totals -> exclusive scan over digits -> per-wave run starts
+    uint32_t tot = 0, incl = 0;
+    if (t < 256) {
+#pragma unroll
+      for (int w = 0; w < kRadixWaves; ++w) {
+        const uint32_t x = woff[w][t];
+        woff[w][t] = tot;
+        tot += x;
+      }
+      incl = tot;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+      }
+      if (lane == 63) wsum[wave] = incl;
+    }
+    __syncthreads();
+    if (t < 256) {
+      uint32_t ex = incl - tot;
+      for (int w = 0; w < wave; ++w) ex += wsum[w];
+      loc[t] = ex;
+#pragma unroll
+      for (int w = 0; w < kRadixWaves; ++w) woff[w][t] += ex;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRadixRounds; ++k) {
+      if (base + 64 * k < n) {
+        const uint32_t p = woff[wave][(key[k] >> shift) & 255u] + pre[k];
+        sk[p] = key[k];
+        sv[p] = val[k];
+      }
+    }
+    __syncthreads();
+    const int cnt = (int)(n - b0 < kRadixItems ? n - b0 : kRadixItems);
+#pragma unroll 4
+    for (int p = t; p < cnt; p += kRadixThreads) {
+      const uint32_t k = sk[p];
+      const uint32_t d = (k >> shift) & 255u;
+      const uint32_t dst = run[d] + ((uint32_t)p - loc[d]);
+      const uint32_t v = sv[p];
+      kout[dst] = k;
+      vout[dst] = v;
+      if (GATHER) gout[dst] = gsrc[v];
+    }
+    __syncthreads();
+    if (t < 256) run[t] += tot;
   }
-  *result_in_tmp = in_tmp;
+}
+
+hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
+                             bool iota, uint32_t val0, const uint2* gsrc, uint2* gout,
+                             const uint32_t* n_dev, long long n_fixed, long long cap, int passes,
+                             uint32_t* hist, long long hist_n, uint32_t* scan_tmp, long long scan_tmp_n,
+                             hipStream_t st) {
+  if (passes <= 0 || cap <= 0) return hipSuccess;
+  const RadixGrid rg = radix_grid(cap);
+  if (256LL * rg.groups > hist_n) return hipErrorInvalidValue;
+  uint32_t *ka = keys, *va = vals, *kb = keys_tmp, *vb = vals_tmp;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(rg.groups), dim3(kRadixThreads), 0, st, ka, n_dev, n_fixed, cap,
+                       shift, rg.chunks_per_group, hist);
+    hipError_t e = launch_scan_u32(hist, hist, 256LL * rg.groups, nullptr, scan_tmp, scan_tmp_n, st);
+    if (e != hipSuccess) return e;
+    const bool io = iota && p == 0, ga = gsrc && p == passes - 1;
+#define SS_SCATTER(I, G)                                                                                     \
+  hipLaunchKernelGGL((radix_scatter_kernel<I, G>), dim3(rg.groups), dim3(kRadixThreads), 0, st, ka, va, val0, \
+                     kb, vb, gsrc, gout, n_dev, n_fixed, cap, shift, rg.chunks_per_group, hist)
+    if (io && ga) SS_SCATTER(true, true);
+    else if (io) SS_SCATTER(true, false);
+    else if (ga) SS_SCATTER(false, true);
+    else SS_SCATTER(false, false);
+#undef SS_SCATTER
+    uint32_t* tk = ka; ka = kb; kb = tk;
+    uint32_t* tv = va; va = vb; vb = tv;
+  }
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- ranges
-__global__ void tile_ranges_kernel(const uint64_t* __restrict__ keys, const uint32_t* n_pairs,
-                                   long long cap, uint32_t* __restrict__ ranges) {
-  const long long n = *n_pairs;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n && i < cap;
-       i += (long long)gridDim.x * blockDim.x) {
-    const uint32_t tile = (uint32_t)(keys[i] >> 32);
-    if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != tile) ranges[2 * (long long)tile] = (uint32_t)i;
-    if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != tile) ranges[2 * (long long)tile + 1] = (uint32_t)(i + 1);
+// keys: sorted tile indices relative to tile_begin.  A block stages
+// kRangeItems keys and one neighbour on each side in LDS (coalesced loads,
+// clamped into range) and marks where the tile changes.
+constexpr int kRangeItems = 2048;
+
+__global__ void __launch_bounds__(256) tile_ranges_kernel(const uint32_t* __restrict__ keys, const uint32_t* n_pairs,
+                                                          long long cap, int tile_begin,
+                                                          uint32_t* __restrict__ ranges) {
+  __shared__ uint32_t sk[kRangeItems + 2];
+  const long long n = (long long)*n_pairs < cap ? (long long)*n_pairs : cap;
+  const long long b0 = (long long)blockIdx.x * kRangeItems;
+  if (b0 >= n) return;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kRangeItems / 256; ++k) {
+    const long long i = b0 + k * 256 + t;
+    sk[1 + k * 256 + t] = keys[i < n ? i : n - 1];
+  }
+  if (t == 0) sk[0] = keys[b0 > 0 ? b0 - 1 : 0];
+  if (t == 1) sk[kRangeItems + 1] = keys[b0 + kRangeItems < n ? b0 + kRangeItems : n - 1];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kRangeItems / 256; ++k) {
+    const int j = k * 256 + t;
+    const long long i = b0 + j;
+    if (i < n) {
+      const uint32_t key = sk[1 + j];
+      const long long g = (long long)tile_begin + key;
+      if (i == 0 || sk[j] != key) ranges[2 * g] = (uint32_t)i;
+      if (i == n - 1 || sk[2 + j] != key) ranges[2 * g + 1] = (uint32_t)(i + 1);
+    }
   }
 }
 
-hipError_t launch_tile_ranges(const uint64_t* keys, const uint32_t* n_pairs, long long cap,
+hipError_t launch_tile_ranges(const uint32_t* keys, const uint32_t* n_pairs, long long cap,
                               uint32_t* ranges, int tile_begin, int n_tiles, hipStream_t st) {
   hipError_t e = launch_fill_u32(ranges + 2LL * tile_begin, 0u, 2LL * n_tiles, st);
   if (e != hipSuccess) return e;
-  long long b = (cap + 255) / 256;
-  unsigned nb = (unsigned)(b < 8192 ? (b > 0 ? b : 1) : 8192);
-  hipLaunchKernelGGL(tile_ranges_kernel, dim3(nb), dim3(256), 0, st, keys, n_pairs, cap, ranges);
+  const long long b = (cap + kRangeItems - 1) / kRangeItems;
+  if (b <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tile_ranges_kernel, dim3((unsigned)b), dim3(256), 0, st, keys, n_pairs, cap, tile_begin, ranges);
   return hipGetLastError();
 }
 

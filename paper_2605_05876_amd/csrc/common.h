@@ -249,7 +249,7 @@ hipError_t launch_brdf_lut(float* lut, int n_nv, int n_r, int samples, hipStream
 
 hipError_t launch_preprocess(const float* const P[7], long long N, const ViewDev* views, int v0,
                              int v1, int max_surf, const Params& prm, float* recs,
-                             uint32_t* counts, hipStream_t st);
+                             uint32_t* counts, uint32_t* zkey, uint2* prect, hipStream_t st);
 constexpr int kBackwardBlocks = 256;       // blocks of the shading adjoint (per scene): one per CU
 constexpr int kBackwardThreads = 1024;     // threads per block of the shading adjoint
 // LDS budget for privatised environment levels (156 KiB of the 160 KiB per
@@ -269,21 +269,33 @@ hipError_t launch_geometry_backward(const float* const P[7], long long N, const 
                                     const float* sg, float* const G[7], const float* recs,
                                     float* ss_out, int* vis_out, hipStream_t st);
 
-hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint32_t* total,
-                           uint32_t* tmp, long long tmp_n, hipStream_t st);
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint32_t* total, uint32_t* tmp,
+                           long long tmp_n, hipStream_t st);
+// Exclusive scan of the tile counts of record pixel rectangles (il | ih << 16, jl | jh << 16).
+hipError_t launch_scan_rect_tiles(const uint2* rect, int tile_w, int tile_h, uint32_t* out, long long n,
+                                  uint32_t* total, uint32_t* tmp, long long tmp_n, hipStream_t st);
 long long scan_tmp_size(long long n);
-hipError_t launch_emit_pairs(const float* recs, const uint32_t* offsets, const ViewDev* views,
-                             int v0, int v1, int max_surf, int tile_w, int tile_h,
-                             uint64_t* keys, uint32_t* vals, const uint32_t* n_pairs,
-                             long long cap, int* status, hipStream_t st);
-hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp,
-                             const uint32_t* n_pairs, long long cap, int key_bits, uint32_t* hist,
-                             uint32_t* scan_tmp, long long scan_tmp_n, hipStream_t st,
-                             bool* result_in_tmp);
-hipError_t launch_tile_ranges(const uint64_t* keys, const uint32_t* n_pairs, long long cap,
+hipError_t launch_emit_pairs(const uint32_t* order, const uint2* rect, const uint32_t* offsets,
+                             const ViewDev* views, int v0, int v1, long long n_rec, int tile_w, int tile_h,
+                             uint32_t* keys, uint32_t* vals, long long cap, int* status, hipStream_t st);
+// Stable radix sort of (key, value) pairs over the low 8 * passes key bits; the
+// result is in (keys, vals) for an even pass count, else in the tmp buffers.
+// Count: n_fixed when >= 0, else *n_dev (device), at most cap; cap sizes the
+// grid and the histogram (radix_hist_size(cap) entries).  iota: the first pass
+// takes val0 + position as values.  gsrc (optional): the last pass also writes
+// gout[i] = gsrc[value of sorted pair i].
+long long radix_hist_size(long long cap);
+hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
+                             bool iota, uint32_t val0, const uint2* gsrc, uint2* gout,
+                             const uint32_t* n_dev, long long n_fixed, long long cap, int passes,
+                             uint32_t* hist, long long hist_n, uint32_t* scan_tmp, long long scan_tmp_n,
+                             hipStream_t st);
+hipError_t launch_tile_ranges(const uint32_t* keys, const uint32_t* n_pairs, long long cap,
                               uint32_t* ranges, int tile_begin, int n_tiles, hipStream_t st);
 
-hipError_t launch_tile_order(const uint32_t* ranges, int tile_begin, int n_tiles, int* order, hipStream_t st);
+// scratch: 66 u32 of device memory (cleared by the call).
+hipError_t launch_tile_order(const uint32_t* ranges, int tile_begin, int n_tiles, int* order, uint32_t* scratch,
+                             hipStream_t st);
 hipError_t launch_raster_forward(const ViewDev* views, int n_views, int tile_begin, int tile_end,
                                  const uint32_t* ranges, const uint32_t* sorted_vals,
                                  const float* recs, const Params& prm, int lds_batch,

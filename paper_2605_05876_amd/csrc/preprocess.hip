@@ -345,7 +345,8 @@ struct PPtrs { const float* p[7]; };
 
 __global__ void __launch_bounds__(256) preprocess_kernel(PPtrs PP, long long N, const ViewDev* __restrict__ views,
                                                          int v0, Params prm, float* __restrict__ recs,
-                                                         uint32_t* __restrict__ counts) {
+                                                         uint32_t* __restrict__ counts,
+                                                         uint32_t* __restrict__ zkey, uint2* __restrict__ prect) {
   const int vi = v0 + blockIdx.y;
   const ViewDev& v = views[vi];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -359,6 +360,8 @@ __global__ void __launch_bounds__(256) preprocess_kernel(PPtrs PP, long long N, 
   float4* out = reinterpret_cast<float4*>(recs + r * kRecFloats);
   if (!o.keep) {
     counts[r] = 0u;
+    zkey[r] = 0xffffffffu;
+    prect[r] = make_uint2(1u, 0u);
     float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
     out[0] = z4; out[1] = z4; out[2] = z4;
     out[3] = make_float4(__int_as_float(1), __int_as_float(0), __int_as_float(0xffffffff), 0.f);
@@ -378,6 +381,8 @@ __global__ void __launch_bounds__(256) preprocess_kernel(PPtrs PP, long long N, 
   const int tw = prm.tile_w, th = prm.tile_h;
   const int tx0 = o.il / tw, tx1 = o.ih / tw, ty0 = o.jl / th, ty1 = o.jh / th;
   counts[r] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+  zkey[r] = __float_as_uint(o.zs);
+  prect[r] = make_uint2((uint32_t)(o.il | (o.ih << 16)), (uint32_t)(o.jl | (o.jh << 16)));
   out[0] = make_float4(g.x0r, g.y0r, g.Qxx, g.Qxy2);
   out[1] = make_float4(g.Qyy, g.a3, g.b3, g.nf);
   out[2] = make_float4(o.ze, col[0], col[1], col[2]);
@@ -387,12 +392,13 @@ __global__ void __launch_bounds__(256) preprocess_kernel(PPtrs PP, long long N, 
 
 hipError_t launch_preprocess(const float* const P[7], long long N, const ViewDev* views, int v0,
                              int v1, int max_surf, const Params& prm, float* recs,
-                             uint32_t* counts, hipStream_t st) {
+                             uint32_t* counts, uint32_t* zkey, uint2* prect, hipStream_t st) {
   if (v1 <= v0 || max_surf <= 0) return hipSuccess;
   PPtrs PP;
   for (int k = 0; k < 7; ++k) PP.p[k] = P[k];
   dim3 grid((max_surf + 255) / 256, v1 - v0);
-  hipLaunchKernelGGL(preprocess_kernel, grid, dim3(256), 0, st, PP, N, views, v0, prm, recs, counts);
+  hipLaunchKernelGGL(preprocess_kernel, grid, dim3(256), 0, st, PP, N, views, v0, prm, recs, counts, zkey,
+                     prect);
   return hipGetLastError();
 }
 

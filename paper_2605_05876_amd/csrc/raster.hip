@@ -662,33 +662,67 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS) ? 4 : 5))) raster_backward_kerne
 
 // ---------------------------------------------------------------- schedule
 // Longest-processing-time-first order of a group's tiles for the persistent
-// raster: counting sort by floor(log2(list length + 1)), descending.  The order
-// inside a bucket does not matter (it changes only which block renders a tile).
-__global__ void __launch_bounds__(1024) tile_order_kernel(const uint32_t* __restrict__ ranges, int tile_begin,
-                                                          int n_tiles, int* __restrict__ order) {
-  __shared__ int cnt[33], base[33];
-  if (threadIdx.x < 33) cnt[threadIdx.x] = 0;
-  __syncthreads();
-  for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) {
-    const uint32_t len = ranges[2 * (tile_begin + i) + 1] - ranges[2 * (tile_begin + i)];
-    atomicAdd(&cnt[32 - __clz(len + 1u)], 1);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int b = 32; b >= 0; --b) { base[b] = acc; acc += cnt[b]; }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) {
-    const uint32_t len = ranges[2 * (tile_begin + i) + 1] - ranges[2 * (tile_begin + i)];
-    const int pos = atomicAdd(&base[32 - __clz(len + 1u)], 1);
-    order[pos] = tile_begin + i;
-  }
+// raster: counting sort by bucket floor(log2(list length + 1)) + 1, descending.
+// Two kernels: bucket counts (LDS, then one global atomic per bucket and
+// block), then placement (each block reserves its run in every bucket with one
+// global atomic).  The order inside a bucket depends on block timing; it does
+// not matter (it changes only which block renders a tile).
+constexpr int kOrderThreads = 256;
+constexpr int kOrderBuckets = 33;
+
+__device__ inline int tile_bucket(const uint32_t* ranges, int tile) {
+  const uint32_t len = ranges[2 * tile + 1] - ranges[2 * tile];
+  return 32 - __clz(len + 1u);
 }
 
-hipError_t launch_tile_order(const uint32_t* ranges, int tile_begin, int n_tiles, int* order, hipStream_t st) {
+__global__ void __launch_bounds__(kOrderThreads) tile_bucket_count_kernel(const uint32_t* __restrict__ ranges,
+                                                                          int tile_begin, int n_tiles,
+                                                                          uint32_t* __restrict__ counts) {
+  __shared__ uint32_t lc[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) lc[threadIdx.x] = 0u;
+  __syncthreads();
+  const int i = blockIdx.x * kOrderThreads + threadIdx.x;
+  if (i < n_tiles) atomicAdd(&lc[tile_bucket(ranges, tile_begin + i)], 1u);
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets && lc[threadIdx.x]) atomicAdd(&counts[threadIdx.x], lc[threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(kOrderThreads) tile_place_kernel(const uint32_t* __restrict__ ranges,
+                                                                   int tile_begin, int n_tiles,
+                                                                   const uint32_t* __restrict__ counts,
+                                                                   uint32_t* __restrict__ cursor,
+                                                                   int* __restrict__ order) {
+  __shared__ uint32_t lc[kOrderBuckets], base[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) lc[threadIdx.x] = 0u;
+  __syncthreads();
+  const int i = blockIdx.x * kOrderThreads + threadIdx.x;
+  int b = 0;
+  uint32_t rank = 0u;
+  if (i < n_tiles) {
+    b = tile_bucket(ranges, tile_begin + i);
+    rank = atomicAdd(&lc[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets && lc[threadIdx.x]) {
+    uint32_t start = 0u;  // tiles in longer buckets come first
+    for (int k = kOrderBuckets - 1; k > (int)threadIdx.x; --k) start += counts[k];
+    base[threadIdx.x] = start + atomicAdd(&cursor[threadIdx.x], lc[threadIdx.x]);
+  }
+  __syncthreads();
+  if (i < n_tiles) order[base[b] + rank] = tile_begin + i;
+}
+
+// scratch: 2 * kOrderBuckets u32 (bucket counts and cursors), cleared here.
+hipError_t launch_tile_order(const uint32_t* ranges, int tile_begin, int n_tiles, int* order, uint32_t* scratch,
+                             hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, st, ranges, tile_begin, n_tiles, order);
+  hipError_t e = launch_fill_u32(scratch, 0u, 2 * kOrderBuckets, st);
+  if (e != hipSuccess) return e;
+  const unsigned nb = (unsigned)((n_tiles + kOrderThreads - 1) / kOrderThreads);
+  hipLaunchKernelGGL(tile_bucket_count_kernel, dim3(nb), dim3(kOrderThreads), 0, st, ranges, tile_begin, n_tiles,
+                     scratch);
+  hipLaunchKernelGGL(tile_place_kernel, dim3(nb), dim3(kOrderThreads), 0, st, ranges, tile_begin, n_tiles, scratch,
+                     scratch + kOrderBuckets, order);
   return hipGetLastError();
 }
 

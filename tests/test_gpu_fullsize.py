@@ -97,3 +97,72 @@ def test_fullsize_sampled_parity(O, ss, name, k):
         errs[f"envmap{i}"] = rel_l2(grads["envmap"][i].cpu().numpy(), dE)
     print(name, "backward", errs)
     assert max(errs.values()) <= GRAD_REL_L2, errs
+
+
+@pytest.mark.parametrize("name", ["C3"])
+def test_fullsize_binning_properties(O, ss, name):
+    """Tile lists at full size, where the oracle's per-record pair listing is too
+    slow: z_start bits and tile rectangles against the oracle's FP32 binning
+    (exact), then properties that fix the sorted pair list uniquely -- strictly
+    increasing (tile, z_start bits, record), every pair's tile inside its
+    record's rectangle, and each record's pair count equal to its rectangle's
+    tile count -- and per-tile ranges that delimit the runs of equal tiles."""
+    w = g.make_config(name)
+    opts = bench_options(ss, name, w.shade)
+    cams = w.cameras
+    r = ss.Renderer(opts)
+    b = ss.batch_from_scenes(w.scenes, cams)
+    r.forward(b)
+    assert r.poll()["status"] == 0
+    dbg = r.debug_binning(b)
+    zb = dbg["rec_zbits"].cpu().numpy().view(np.uint32)
+    keys = dbg["keys"].cpu().numpy().view(np.uint64)
+    vals = dbg["vals"].cpu().numpy().view(np.uint32).astype(np.int64)
+    ranges = dbg["ranges"].cpu().numpy().view(np.uint32).astype(np.int64)
+    oo = oracle_options(O, opts)
+    n_rec = sum(w.scenes[c.scene].n for c in cams)
+    trect = np.zeros((n_rec, 4), np.int64)
+    keep_all = np.zeros(n_rec, bool)
+    rec_off, tile_off, tiles_x = [], [], []
+    rec_base = tile_base = 0
+    for cam in cams:
+        sc = w.scenes[cam.scene]
+        keep, rz, rr = O.bin_f32(sc, cam, oo)
+        k = keep.astype(bool)
+        assert (zb[rec_base:rec_base + sc.n][k] == rz[k]).all(), "z_start bits differ"
+        trect[rec_base:rec_base + sc.n] = rr
+        keep_all[rec_base:rec_base + sc.n] = k
+        tx = -(-cam.width // opts.tile_w)
+        rec_off.append(rec_base)
+        tile_off.append(tile_base)
+        tiles_x.append(tx)
+        rec_base += sc.n
+        tile_base += tx * (-(-cam.height // opts.tile_h))
+    n = len(keys)
+    tile = (keys >> np.uint64(32)).astype(np.int64)
+    z = (keys & np.uint64(0xffffffff)).astype(np.uint32)
+    assert (z == zb[vals]).all()
+    assert keep_all[vals].all()
+    # strictly increasing (key, record): sorted, and no pair listed twice
+    dk = keys[1:] > keys[:-1]
+    eq = keys[1:] == keys[:-1]
+    assert (dk | (eq & (vals[1:] > vals[:-1]))).all()
+    # every pair's tile inside its record's tile rectangle
+    view = np.searchsorted(np.asarray(rec_off), vals, side="right") - 1
+    local = tile - np.asarray(tile_off)[view]
+    txs = np.asarray(tiles_x)[view]
+    px, py = local % txs, local // txs
+    rr = trect[vals]
+    assert ((px >= rr[:, 0]) & (px <= rr[:, 2]) & (py >= rr[:, 1]) & (py <= rr[:, 3])).all()
+    # as many pairs per record as its rectangle has tiles
+    area = np.where(keep_all, (trect[:, 2] - trect[:, 0] + 1) * (trect[:, 3] - trect[:, 1] + 1), 0)
+    assert (np.bincount(vals, minlength=n_rec) == area).all()
+    assert n == area.sum()
+    # ranges
+    cnt = np.bincount(tile, minlength=tile_base)
+    ends = np.cumsum(cnt)
+    starts = ends - cnt
+    nz = cnt > 0
+    assert (ranges[nz, 0] == starts[nz]).all() and (ranges[nz, 1] == ends[nz]).all()
+    assert (ranges[~nz] == 0).all()
+    print(name, "pairs", n, "records kept", int(keep_all.sum()), "of", n_rec)

@@ -81,17 +81,28 @@ def small_multiview():
 
 
 # ---------------------------------------------------------------- binning
-@pytest.mark.parametrize("case,tile", [("C1", (16, 16)), ("C1", (8, 8)), ("C2s", (16, 16)),
-                                       ("MV", (16, 8)), ("MV", (32, 16))])
-def test_binning_bit_exact(O, ss, case, tile):
+# Tile counts cover every pair-sort pass count: C1 16x16 and MV (one radix pass),
+# C1 8x8 (two), one 16x16 tile (none), BIG 8x8 with 69696 tiles (three); MV
+# per view sorts each view on its own.
+@pytest.mark.parametrize("case,tile,launch", [("C1", (16, 16), "batched"), ("C1", (8, 8), "batched"),
+                                              ("C2s", (16, 16), "batched"), ("MV", (16, 8), "batched"),
+                                              ("MV", (32, 16), "batched"), ("MV", (16, 8), "per_view"),
+                                              ("ONE_TILE", (16, 16), "batched"), ("BIG", (8, 8), "batched")])
+def test_binning_bit_exact(O, ss, case, tile, launch):
     if case == "C1":
         w = g.make_config("C1")
         scenes, cams, shade = w.scenes, w.cameras, "albedo"
     elif case == "C2s":
         (scenes, cams), shade = small_c2(), "splitsum"
+    elif case == "ONE_TILE":
+        (scenes, _), shade = small_multiview(), "albedo"
+        cams = [g.look_at_camera(np.array([0.3, -2.8, 0.9]), 16, 16)]
+    elif case == "BIG":
+        (scenes, _), shade = small_multiview(), "albedo"
+        cams = [g.look_at_camera(np.array([0.3, -2.8, 0.9]), 2112, 2112)]
     else:
         (scenes, cams), shade = small_multiview(), "splitsum"
-    opts = ss.Options(shade=shade, tile_w=tile[0], tile_h=tile[1])
+    opts = ss.Options(shade=shade, tile_w=tile[0], tile_h=tile[1], launch=launch)
     r, b, *_ = gpu_run(ss, scenes, cams, opts)
     dbg = r.debug_binning(b)
     zb = dbg["rec_zbits"].cpu().numpy().view(np.uint32)
@@ -531,4 +542,17 @@ def test_capacity_and_state_errors(ss):
         r.backward(b, torch.zeros((b.n_pixels, 3), device="cuda"))
     assert e.value.status == 4  # SS_ERR_STATE
     r.forward(b)
-    assert r.poll()["status"] == 0
+    d0 = r.poll()
+    assert d0["status"] == 0
+    # larger surfels with the same shapes: more pairs than the reserved capacity.
+    # The forward flags it (every slot below the capacity is still written, so
+    # nothing reads past it); after a reserve the same batch renders.
+    b.params["scale"].mul_(8.0)
+    r.forward(b)
+    d1 = r.poll()
+    assert d1["status"] == 3 and d1["n_pairs"] > d0["pair_capacity"], (d0, d1)  # SS_ERR_CAPACITY
+    r.reserve(b)
+    img, a = r.forward(b)[:2]
+    d2 = r.poll()
+    assert d2["status"] == 0 and d2["n_pairs"] == d1["n_pairs"], (d1, d2)
+    assert torch.isfinite(img).all() and torch.isfinite(a).all()
