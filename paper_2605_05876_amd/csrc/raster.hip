@@ -50,14 +50,27 @@ __device__ __forceinline__ bool rect_meets(const float4 q, int bx, int by) {
   return !(ih < bx || il > bx + S - 1 || jh < by || jl > by + S - 1);
 }
 
+// Stage records vals[b0 .. b0 + cnt) into LDS, 4 threads per record (one
+// float4 each).  (Loading all ids first and then all quarters keeps more
+// registers live across the walk and was slower.)
+template <int NT>
 __device__ __forceinline__ void load_batch(float4* lds, const uint32_t* __restrict__ vals,
-                                           const float* __restrict__ recs, uint32_t b0, int cnt,
-                                           int nthreads) {
-  // 4 threads per record, one float4 each
-  for (int j = threadIdx.x; j < cnt * 4; j += nthreads) {
+                                           const float* __restrict__ recs, uint32_t b0, int cnt) {
+  for (int j = threadIdx.x; j < cnt * 4; j += NT) {
     const uint32_t id = vals[b0 + (j >> 2)];
     lds[j] = reinterpret_cast<const float4*>(recs + (size_t)id * kRecFloats)[j & 3];
   }
+}
+
+// A staged record into registers: the four 16-byte LDS reads are issued
+// together, so the walk waits for LDS once per record instead of once for the
+// rectangle and again for the fields that depend on it.
+__device__ __forceinline__ void load_record(const float4* p, float rec[kRecFloats]) {
+  const float4 q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
+  rec[0] = q0.x; rec[1] = q0.y; rec[2] = q0.z; rec[3] = q0.w;
+  rec[4] = q1.x; rec[5] = q1.y; rec[6] = q1.z; rec[7] = q1.w;
+  rec[8] = q2.x; rec[9] = q2.y; rec[10] = q2.z; rec[11] = q2.w;
+  rec[12] = q3.x; rec[13] = q3.y; rec[14] = q3.z; rec[15] = q3.w;
 }
 
 // Can the acceptance ellipse of a record reach a pixel centre of the S x S box
@@ -240,7 +253,7 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     for (uint32_t b0 = start; b0 < end; b0 += (uint32_t)B) {
       if (__syncthreads_and(done)) break;
       const int cnt = (int)min((uint32_t)B, end - b0);
-      load_batch(lds, vals, recs, b0, cnt, NT);
+      load_batch<NT>(lds, vals, recs, b0, cnt);
       __syncthreads();
       for (int c0 = 0; c0 < cnt; c0 += 64) {
         if (__ballot(!done) == 0ull) break;
@@ -248,7 +261,8 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
         while (m) {
           const int j = c0 + __builtin_ctzll(m);
           m &= m - 1;
-          const float* rec = reinterpret_cast<const float*>(lds + 4 * j);
+          float rec[kRecFloats];
+          load_record(lds + 4 * j, rec);
           FragEval f;
           if constexpr (PPX)
             frag_eval_pp(rec, px, py, r2, prm.sigma_f, f);
@@ -542,7 +556,7 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS) ? 4 : 5))) raster_backward_kerne
     for (uint32_t b0 = start; b0 < end; b0 += (uint32_t)B) {
       if (__syncthreads_and(done)) break;
       const int cnt = (int)min((uint32_t)B, end - b0);
-      load_batch(lds, vals, recs, b0, cnt, NT);
+      load_batch<NT>(lds, vals, recs, b0, cnt);
       __syncthreads();
       for (int c0 = 0; c0 < cnt; c0 += 64) {
         if (__ballot(!done) == 0ull) break;
@@ -551,7 +565,8 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS) ? 4 : 5))) raster_backward_kerne
         while ((m[0] | m[1] | m[2] | m[3]) != 0ull) {
           const int jl = next_records(m, row);
           // idle rows read a valid record and contribute nothing
-          const float* rec = reinterpret_cast<const float*>(lds + 4 * (c0 + (jl < 0 ? 0 : jl)));
+          float rec[kRecFloats];
+          load_record(lds + 4 * (c0 + (jl < 0 ? 0 : jl)), rec);
           FragEval f;
           frag_eval(rec, px, py, r2, f);
           bool contrib = false;
