@@ -268,37 +268,43 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
             frag_eval_pp(rec, px, py, r2, prm.sigma_f, f);
           else
             frag_eval(rec, px, py, r2, f);
-          if (!f.cov || done) continue;
-          if (Wg > 0.f && rec[R_ZS] > zmax) {
-            // gap: finalise the layer (Shepard-normalised colour, coverage opacity)
-            const float a = -expm1f(-kappa * Wg), e = __expf(-kappa * Wg);
-            const float s = T * a * layer_norm(prm.shade, Wg, C0, C1, C2);
-            O0 += s * C0; O1 += s * C1; O2 += s * C2;
-            stats[pix * kMaxLayers + K] = make_float4(Wg, C0, C1, C2);
-            if constexpr (CONS) {
-              const float m = S1 / Wg;
-              stats2[pix * kMaxLayers + K] = make_float2(zr + m, S2 / Wg - m * m);
-              S1 = S2 = 0.f;
+          // (structured as nested branches rather than early continues: the
+          // compiler then keeps the step's reconvergence simple, which measured
+          // faster)
+          if (f.cov && !done) {
+            if (Wg > 0.f && rec[R_ZS] > zmax) {
+              // gap: finalise the layer (Shepard-normalised colour, coverage opacity)
+              const float a = -expm1f(-kappa * Wg), e = __expf(-kappa * Wg);
+              const float s = T * a * layer_norm(prm.shade, Wg, C0, C1, C2);
+              O0 += s * C0; O1 += s * C1; O2 += s * C2;
+              stats[pix * kMaxLayers + K] = make_float4(Wg, C0, C1, C2);
+              if constexpr (CONS) {
+                const float m = S1 / Wg;
+                stats2[pix * kMaxLayers + K] = make_float2(zr + m, S2 / Wg - m * m);
+                S1 = S2 = 0.f;
+              }
+              T *= e;
+              ++K;
+              C0 = C1 = C2 = 0.f;
+              Wg = 0.f;
+              zmax = 0.f;
+              if (K >= kmax) done = true;
             }
-            T *= e;
-            ++K;
-            C0 = C1 = C2 = 0.f;
-            Wg = 0.f;
-            zmax = 0.f;
-            if (K >= kmax) { done = true; continue; }
+            if (!done) {
+              if constexpr (CONS) {
+                const float z = frag_depth(rec, f);
+                if (Wg == 0.f) zr = z;
+                const float dz = z - zr;
+                S1 += f.w * dz;
+                S2 += f.w * dz * dz;
+              }
+              zmax = fmaxf(zmax, rec[R_ZE]);
+              C0 += f.w * rec[R_CR];
+              C1 += f.w * rec[R_CG];
+              C2 += f.w * rec[R_CB];
+              Wg += f.w;
+            }
           }
-          if constexpr (CONS) {
-            const float z = frag_depth(rec, f);
-            if (Wg == 0.f) zr = z;
-            const float dz = z - zr;
-            S1 += f.w * dz;
-            S2 += f.w * dz * dz;
-          }
-          zmax = fmaxf(zmax, rec[R_ZE]);
-          C0 += f.w * rec[R_CR];
-          C1 += f.w * rec[R_CG];
-          C2 += f.w * rec[R_CB];
-          Wg += f.w;
         }
       }
       __syncthreads();
