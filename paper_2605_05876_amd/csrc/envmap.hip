@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(256) envmap_prefilter_kernel(const float* __re
                                                                const float4* __restrict__ out_dirs,
                                                                int n_out, LevelSet L, float* __restrict__ part) {
   __shared__ float4 sd[256];
-  __shared__ float se[3 * 256];
+  __shared__ float4 se[256];  // (E, -): one 16-byte broadcast read per input texel
   const int nt = He * We;
   const int o = blockIdx.x * 256 + threadIdx.x;
   const bool live = o < n_out;
@@ -130,31 +130,32 @@ __global__ void __launch_bounds__(256) envmap_prefilter_kernel(const float* __re
     if (threadIdx.x < n) {
       const int t = tb + threadIdx.x;
       sd[threadIdx.x] = dirs[t];
-      se[3 * threadIdx.x] = E[3 * t];
-      se[3 * threadIdx.x + 1] = E[3 * t + 1];
-      se[3 * threadIdx.x + 2] = E[3 * t + 2];
+      se[threadIdx.x] = make_float4(E[3 * t], E[3 * t + 1], E[3 * t + 2], 0.f);
     }
     __syncthreads();
     if (skip) continue;
+    // texels behind the output direction (c <= 0) get weight 0 by a select,
+    // not a branch (lanes of a wave face different ways); adding the exact
+    // zero leaves the sums unchanged
     if (l == 6) {
+#pragma unroll 4
       for (int i = 0; i < n; ++i) {
-        const float4 d = sd[i];
+        const float4 d = sd[i], e = se[i];
         const float c = R.x * d.x + R.y * d.y + R.z * d.z;
-        if (c <= 0.f) continue;
-        const float kk = c * d.w;
-        acc0 += se[3 * i] * kk;
-        acc1 += se[3 * i + 1] * kk;
-        acc2 += se[3 * i + 2] * kk;
+        const float kk = c > 0.f ? c * d.w : 0.f;
+        acc0 += e.x * kk;
+        acc1 += e.y * kk;
+        acc2 += e.z * kk;
       }
     } else {
+#pragma unroll 4
       for (int i = 0; i < n; ++i) {
-        const float4 d = sd[i];
+        const float4 d = sd[i], e = se[i];
         const float c = R.x * d.x + R.y * d.y + R.z * d.z;
-        if (c <= 0.f) continue;
-        const float kk = ggx_weight(c, alpha) * d.w;
-        acc0 += se[3 * i] * kk;
-        acc1 += se[3 * i + 1] * kk;
-        acc2 += se[3 * i + 2] * kk;
+        const float kk = c > 0.f ? ggx_weight(c, alpha) * d.w : 0.f;
+        acc0 += e.x * kk;
+        acc1 += e.y * kk;
+        acc2 += e.z * kk;
       }
     }
   }
