@@ -64,9 +64,15 @@ __device__ __forceinline__ void load_batch(float4* lds, const uint32_t* __restri
 
 // A staged record into registers: the four 16-byte LDS reads are issued
 // together, so the walk waits for LDS once per record instead of once for the
-// rectangle and again for the fields that depend on it.
+// rectangle and again for the fields that depend on it.  NOW: an empty asm
+// takes all 16 values, so none of the reads can be sunk into the branches
+// that use them (faster in the forward walk, slower in the backward's).
+template <bool NOW = false>
 __device__ __forceinline__ void load_record(const float4* p, float rec[kRecFloats]) {
   const float4 q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
+  if constexpr (NOW)
+    asm volatile("" ::"v"(q0.x), "v"(q0.y), "v"(q0.z), "v"(q0.w), "v"(q1.x), "v"(q1.y), "v"(q1.z), "v"(q1.w),
+                 "v"(q2.x), "v"(q2.y), "v"(q2.z), "v"(q2.w), "v"(q3.x), "v"(q3.y), "v"(q3.z), "v"(q3.w));
   rec[0] = q0.x; rec[1] = q0.y; rec[2] = q0.z; rec[3] = q0.w;
   rec[4] = q1.x; rec[5] = q1.y; rec[6] = q1.z; rec[7] = q1.w;
   rec[8] = q2.x; rec[9] = q2.y; rec[10] = q2.z; rec[11] = q2.w;
@@ -262,7 +268,7 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
           const int j = c0 + __builtin_ctzll(m);
           m &= m - 1;
           float rec[kRecFloats];
-          load_record(lds + 4 * j, rec);
+          load_record<true>(lds + 4 * j, rec);
           FragEval f;
           if constexpr (PPX)
             frag_eval_pp(rec, px, py, r2, prm.sigma_f, f);
