@@ -167,7 +167,7 @@ __device__ inline void bin_geometry(const float p[3], const float n[3], const fl
 // raster kernels so that both take identical cutoff decisions: explicit fmaf
 // and a fixed order, independent of the surrounding code.
 struct FragEval {
-  float dx, dy, s, N, q, w;
+  float dx, dy, s, N, q, w, e;  // e = exp(-q/2), so w = n_f e
   bool cov;
 };
 __device__ __forceinline__ void frag_eval(const float* rec, int px, int py, float r2, FragEval& f) {
@@ -181,7 +181,8 @@ __device__ __forceinline__ void frag_eval(const float* rec, int px, int py, floa
   float s2 = f.s * f.s;
   f.cov = f.N < r2 * s2;
   f.q = f.N * __builtin_amdgcn_rcpf(s2);
-  f.w = rec[R_NF] * __expf(-0.5f * f.q);
+  f.e = __expf(-0.5f * f.q);
+  f.w = rec[R_NF] * f.e;
 }
 
 // Per-pixel-Jacobian variant of the MIP filter (Sec. 3.3.1): J = d(u,v)/d(x,y)
@@ -216,7 +217,8 @@ __device__ __forceinline__ void frag_eval_pp(const float* rec, int px, int py, f
   f.cov = in_rect && f.s > 0.f && detS > 0.f && f.N < r2 * detS;
   f.q = f.N / detS;
   const float nfc = rec[R_NF];
-  f.w = sqrtf(s2 * s2 * s2 * nfc * nfc * iq / detS) * __expf(-0.5f * f.q);
+  f.e = __expf(-0.5f * f.q);
+  f.w = sqrtf(s2 * s2 * s2 * nfc * nfc * iq / detS) * f.e;
 }
 
 __device__ __forceinline__ int view_of_tile(const ViewDev* views, int nv, int tile) {

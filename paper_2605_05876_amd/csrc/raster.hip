@@ -620,20 +620,23 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS) ? 4 : 5))) raster_backward_kerne
           // d(rho^2)/d(record) for q = d^T Q d / s^2, s = 1 + a3 dx + b3 dy.  Lanes that
           // do not contribute have gw = gcs = gz = 0; zeroing their 1/s, q and w (which
           // may be infinite off the ellipse) makes every value below exactly 0 there.
-          const float is = contrib ? __builtin_amdgcn_rcpf(f.s) : 0.f, is2 = is * is;
-          const float fw = contrib ? f.w : 0.f;
+          const float is = contrib ? __builtin_amdgcn_rcpf(f.s) : 0.f;
+          const float fw = contrib ? f.w : 0.f, fe = contrib ? f.e : 0.f;
           const float gq = -0.5f * fw * gw;
           const float dx = f.dx, dy = f.dy, q = contrib ? f.q : 0.f;
           const float qxx = rec[R_QXX], qxy2 = rec[R_QXY2], qyy = rec[R_QYY];
+          // u = gq / s^2 and v = -2 gq q / s factor every slot of the kernel shape
+          const float u = gq * is * is, vq = -2.f * gq * q * is;
+          const float ux = u * dx, uy = u * dy;
           float g[RW];
-          g[G_X0] = -gq * ((2.f * qxx * dx + qxy2 * dy) * is2 - 2.f * q * rec[R_A3] * is);
-          g[G_Y0] = -gq * ((qxy2 * dx + 2.f * qyy * dy) * is2 - 2.f * q * rec[R_B3] * is);
-          g[G_QXX] = gq * dx * dx * is2;
-          g[G_QXY2] = gq * dx * dy * is2;
-          g[G_QYY] = gq * dy * dy * is2;
-          g[G_A3] = -2.f * gq * q * dx * is;
-          g[G_B3] = -2.f * gq * q * dy * is;
-          g[G_NF] = gw * fw * __builtin_amdgcn_rcpf(rec[R_NF]);
+          g[G_X0] = -(2.f * qxx * ux + qxy2 * uy + rec[R_A3] * vq);
+          g[G_Y0] = -(qxy2 * ux + 2.f * qyy * uy + rec[R_B3] * vq);
+          g[G_QXX] = ux * dx;
+          g[G_QXY2] = ux * dy;
+          g[G_QYY] = uy * dy;
+          g[G_A3] = vq * dx;
+          g[G_B3] = vq * dy;
+          g[G_NF] = gw * fe;  // w / n_f
           g[G_CR] = gcs * L.G0;
           g[G_CG] = gcs * L.G1;
           g[G_CB] = gcs * L.G2;
