@@ -3,8 +3,9 @@
 //
 // Pipeline of ss_render on one stream:
 //   envmap levels (per scene, split-sum) -> preprocess + shade (per record)
-//   -> per group: scan of tile counts -> pair emission -> radix sort ->
-//   tile ranges -> raster forward.
+//   -> per group: depth sort of the records -> scan of their tile counts in
+//   that order -> pair emission -> stable sort of the pairs by tile -> tile
+//   ranges -> tile order -> raster forward.
 // A "group" is a run of views that share one pair list: one group holding
 // every view (batched launches) or one group per view (per-view launches).
 // ss_render_backward: raster backward (per group) -> preprocess/shade adjoint
