@@ -556,3 +556,70 @@ def test_capacity_and_state_errors(ss):
     d2 = r.poll()
     assert d2["status"] == 0 and d2["n_pairs"] == d1["n_pairs"], (d1, d2)
     assert torch.isfinite(img).all() and torch.isfinite(a).all()
+
+
+def test_graph_replay_matches_eager(ss):
+    """The whole forward+backward step captured once in a HIP graph and replayed: every
+    replay, with unrelated eager work and a synchronisation before it, gives the eager
+    images bit for bit and the eager gradients to rounding (atomic order)."""
+    scenes, cams = small_multiview()
+    r = ss.Renderer(ss.Options(shade="splitsum"))
+    b = ss.batch_from_scenes(scenes, cams)
+    r.reserve(b)
+    n_pix = b.n_pixels
+    rng = np.random.default_rng(5)
+    G = torch.from_numpy(rng.normal(size=(n_pix, 3)).astype(np.float32)).cuda()
+    Ga = torch.from_numpy(rng.normal(size=n_pix).astype(np.float32)).cuda()
+    img = torch.empty((n_pix, 3), device="cuda")
+    alpha = torch.empty((n_pix,), device="cuda")
+    nl = torch.empty((n_pix,), device="cuda", dtype=torch.uint8)
+    grads = {k: torch.empty_like(b.params[k]) for k in ss.PARAMS}
+    grads["envmap"] = [torch.empty_like(e) for e in b.envmaps]
+
+    def step():
+        r.forward(b, out=(img, alpha, nl))
+        r.backward(b, G, Ga, grads=grads)
+
+    def snapshot():
+        out = {"img": img.clone(), "alpha": alpha.clone(), "nl": nl.clone()}
+        out.update({k: grads[k].clone() for k in ss.PARAMS})
+        out["envmap"] = grads["envmap"][0].clone()
+        return out
+
+    step()
+    torch.cuda.synchronize()
+    assert r.poll()["status"] == 0
+    want = snapshot()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    cg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(cg):
+        step()
+    other = ss.Renderer(ss.Options())
+    w1 = g.make_config("C1")
+    b1 = ss.batch_from_scenes(w1.scenes, w1.cameras)
+    for rep in range(3):
+        # eager work between replays, on the same device: another renderer's forward
+        # and plain torch ops, then poison every output the graph must rewrite
+        other.forward(b1)
+        _ = torch.randn(1 << 20, device="cuda").sum().item()
+        img.fill_(float("nan"))
+        alpha.fill_(float("nan"))
+        nl.fill_(255)
+        for k in ss.PARAMS:
+            grads[k].fill_(float("nan"))
+        grads["envmap"][0].fill_(float("nan"))
+        torch.cuda.synchronize()
+        cg.replay()
+        torch.cuda.synchronize()
+        assert r.poll()["status"] == 0
+        got = snapshot()
+        for k in ("img", "alpha", "nl"):
+            assert torch.equal(got[k], want[k]), (rep, k)
+        for k in list(ss.PARAMS) + ["envmap"]:
+            a, e = got[k].double().cpu().numpy(), want[k].double().cpu().numpy()
+            assert np.isfinite(a).all() and rel_l2(a, e) < 1e-5, (rep, k, rel_l2(a, e))
