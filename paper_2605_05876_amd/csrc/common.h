@@ -253,7 +253,7 @@ hipError_t launch_preprocess(const float* const P[7], long long N, const ViewDev
                              int v1, int max_surf, const Params& prm, float* recs,
                              uint32_t* counts, uint32_t* zkey, uint2* prect, hipStream_t st);
 constexpr int kBackwardBlocks = 256;       // blocks of the shading adjoint (per scene): one per CU
-constexpr int kBackwardThreads = 1024;     // threads per block of the shading adjoint
+constexpr int kBackwardThreads = 512;      // threads per block of the shading adjoint
 // LDS budget for privatised environment levels (156 KiB of the 160 KiB per
 // CU): with a 128 x 256 map it holds every level but the map itself, so only
 // lookups of the sharpest level fall back to global atomics, which are the

@@ -18,6 +18,7 @@ namespace ss {
 typedef const __attribute__((address_space(1))) float gmem_cf32;
 typedef __attribute__((address_space(1))) float gmem_f32;
 typedef __attribute__((address_space(3))) float lds_f32;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
 __device__ __forceinline__ void grad_add(lds_f32* p, float x) {
   __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -118,142 +119,372 @@ __device__ inline void shade_forward(const ViewDev& v, const Params& P, const fl
   }
 }
 
-// One bilinear lat-long lookup with its adjoint: returns the value, scatters
-// g (the gradient of the looked-up value, known up front) into the texels of
-// dm (LDS or global) and adds the gradient with respect to the direction d to gd.
-template <class DST>
-__device__ inline void latlong_lookup_adjoint(const float* mp, DST* dm, int H, int W, const float d[3],
-                                              const float g[3], float val[3], float gd[3]) {
-  gmem_cf32* m = (gmem_cf32*)mp;
+// One bilinear lat-long lookup of the adjoint, split in stages so that a record
+// issues the texel loads of all its lookups before it waits for any of them,
+// and its gradient atomics only after its last load (a wave's memory counter
+// retires in issue order: a load issued after an atomic would wait for it).
+//   tap_setup:   coordinates, texel offsets and fractions;
+//   tap_fetch:   the 12 texel values;
+//   tap_adjoint: the looked-up value, and dL/dd added to gd for g = dL/dvalue;
+//   tap_scatter: g times the bilinear weights into the level's gradient map
+//                (its LDS copy when off >= 0, else global atomics).
+struct Tap {
+  int o00, o01, o10, o11;  // float offsets of the four texels
+  float fa, fb;            // bilinear fractions (row, column)
+  float hs, ws;            // H / pi and W / (2 pi)
+  float rho, den;          // for the derivative of the coordinates
+};
+__device__ inline void tap_setup(const float d[3], int H, int W, Tap& T) {
   LatLong L;
   latlong_coords(d, H, W, L);
-  const int o00 = 3 * (L.r0 * W + L.c0), o01 = 3 * (L.r0 * W + L.c1);
-  const int o10 = 3 * (L.r1 * W + L.c0), o11 = 3 * (L.r1 * W + L.c1);
-  const float w00 = (1.f - L.fa) * (1.f - L.fb), w01 = (1.f - L.fa) * L.fb;
-  const float w10 = L.fa * (1.f - L.fb), w11 = L.fa * L.fb;
-  float ga = 0.f, gb = 0.f;
+  T.o00 = 3 * (L.r0 * W + L.c0);
+  T.o01 = 3 * (L.r0 * W + L.c1);
+  T.o10 = 3 * (L.r1 * W + L.c0);
+  T.o11 = 3 * (L.r1 * W + L.c1);
+  T.fa = L.fa;
+  T.fb = L.fb;
+  T.hs = (float)H / kPi;
+  T.ws = (float)W / (2.f * kPi);
+  T.rho = L.rho;
+  T.den = L.den;
+}
+__device__ inline void tap_fetch(const float* mp, const Tap& T, float t[12]) {
+  gmem_cf32* m = (gmem_cf32*)mp;
+#pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const float v00 = m[o00 + c], v01 = m[o01 + c], v10 = m[o10 + c], v11 = m[o11 + c];
-    val[c] = w00 * v00 + w01 * v01 + w10 * v10 + w11 * v11;
-    ga += g[c] * ((1.f - L.fb) * (v10 - v00) + L.fb * (v11 - v01));
-    gb += g[c] * ((1.f - L.fa) * (v01 - v00) + L.fa * (v11 - v10));
-    if (g[c] != 0.f) {
-      grad_add(dm + o00 + c, g[c] * w00);
-      grad_add(dm + o01 + c, g[c] * w01);
-      grad_add(dm + o10 + c, g[c] * w10);
-      grad_add(dm + o11 + c, g[c] * w11);
-    }
+    t[4 * c + 0] = m[T.o00 + c];
+    t[4 * c + 1] = m[T.o01 + c];
+    t[4 * c + 2] = m[T.o10 + c];
+    t[4 * c + 3] = m[T.o11 + c];
   }
-  const float gth = ga * ((float)H / kPi);
-  const float gph = gb * ((float)W / (2.f * kPi));
-  if (L.rho > 1e-20f && L.den > 0.f) {
+}
+__device__ inline void tap_adjoint(const Tap& T, const float t[12], const float d[3], const float g[3],
+                                   float val[3], float gd[3]) {
+  const float w00 = (1.f - T.fa) * (1.f - T.fb), w01 = (1.f - T.fa) * T.fb;
+  const float w10 = T.fa * (1.f - T.fb), w11 = T.fa * T.fb;
+  float ga = 0.f, gb = 0.f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float v00 = t[4 * c], v01 = t[4 * c + 1], v10 = t[4 * c + 2], v11 = t[4 * c + 3];
+    val[c] = w00 * v00 + w01 * v01 + w10 * v10 + w11 * v11;
+    ga += g[c] * ((1.f - T.fb) * (v10 - v00) + T.fb * (v11 - v01));
+    gb += g[c] * ((1.f - T.fa) * (v01 - v00) + T.fa * (v11 - v10));
+  }
+  const float gth = ga * T.hs, gph = gb * T.ws;
+  if (T.rho > 1e-20f && T.den > 0.f) {
     // th = atan2(rho, z), ph = atan2(y, x), rho = sqrt(x^2 + y^2)
-    const float dth_drho = d[2] / L.den, dth_dz = -L.rho / L.den;
-    const float r2 = L.rho * L.rho;
-    gd[0] += gth * dth_drho * d[0] / L.rho - gph * d[1] / r2;
-    gd[1] += gth * dth_drho * d[1] / L.rho + gph * d[0] / r2;
+    const float dth_drho = d[2] / T.den, dth_dz = -T.rho / T.den;
+    const float r2 = T.rho * T.rho;
+    gd[0] += gth * dth_drho * d[0] / T.rho - gph * d[1] / r2;
+    gd[1] += gth * dth_drho * d[1] / T.rho + gph * d[0] / r2;
     gd[2] += gth * dth_dz;
   }
 }
-
-// Adjoint of shade_forward: given g = dL/dcol, accumulates into g_p, g_nh,
-// g_rho, g_rough, g_metal and scatters texel gradients into level l's LDS
-// copy (loc_off[l] >= 0) or its global gradient map.  Each lookup's adjoint
-// needs only quantities known before the lookup, so the three lookups are
-// processed one after the other (few live registers).
-__device__ inline void level_lookup_adjoint(const ViewDev& v, const float* sm, const int loc_off[7], int l,
-                                            const float d[3], const float g[3], float val[3], float gd[3]) {
-  if (loc_off[l] >= 0)
-    latlong_lookup_adjoint(v.lvl[l], (lds_f32*)sm + loc_off[l], v.lh[l], v.lw[l], d, g, val, gd);
-  else
-    latlong_lookup_adjoint(v.lvl[l], (gmem_f32*)v.dlvl[l], v.lh[l], v.lw[l], d, g, val, gd);
+// Texel gradients g times the bilinear weights.  Global maps take float
+// atomics.  Into an LDS copy, a float atomic add serialises the lanes of a
+// wave (about 3 cycles per lane on this part) while a 32-bit compare-and-swap
+// runs at close to the integer atomic rate: every lane first reads its twelve
+// words, then tries one compare-and-swap per word (new = old + x, the same
+// IEEE sum an atomic add forms), and only the lanes whose attempt lost a race
+// (another lane or wave wrote the word in between) fall back to the atomic add.
+__device__ __forceinline__ void tap_weights(const Tap& T, float w[4]) {
+  w[0] = (1.f - T.fa) * (1.f - T.fb);
+  w[1] = (1.f - T.fa) * T.fb;
+  w[2] = T.fa * (1.f - T.fb);
+  w[3] = T.fa * T.fb;
+}
+__device__ inline void tap_scatter_lds(lds_f32* dm, const Tap& T, const float g[3]) {
+  float w[4];
+  tap_weights(T, w);
+  const int o[4] = {T.o00, T.o01, T.o10, T.o11};
+  lds_u32* a[12];
+  float x[12];
+  uint32_t old[12];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[4 * c + k] = (lds_u32*)(dm + o[k] + c);
+      x[4 * c + k] = g[c] * w[k];
+    }
+#pragma unroll
+  for (int i = 0; i < 12; ++i)
+    old[i] = x[i] != 0.f ? __hip_atomic_load(a[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0u;
+  bool lost[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    lost[i] = false;
+    if (x[i] != 0.f) {
+      uint32_t e = old[i];
+      lost[i] = !__hip_atomic_compare_exchange_strong(a[i], &e, __float_as_uint(__uint_as_float(old[i]) + x[i]),
+                                                      __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 12; ++i)
+    if (lost[i]) grad_add((lds_f32*)a[i], x[i]);
+}
+// Texel gradients into a global map, by the whole wave: the lanes with a
+// global lookup are taken one at a time, and lanes 0..11 each add one of that
+// lookup's twelve values (tap k / 3, channel k % 3).  One atomic instruction
+// then covers the lookup's two runs of six consecutive floats (one or two
+// cache lines) instead of twelve instructions that each touch a different line
+// per lane: the L2 processes float atomics per (instruction, cache line), and
+// scattered ones ran at about 21 G lanes/s on this part.  Called by every lane
+// of the wave; `mine` says whether this lane has a lookup to scatter.
+__device__ inline void tap_scatter_global_wave(bool mine, float* dm, const Tap& T, const float g[3]) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int tap = lane / 3, c = lane - 3 * tap;
+  // (readfirstlane returns int: both halves go through uint32_t, so the low
+  // half is not sign-extended into the lanes 32..63 of the mask)
+  const uint64_t bal = __ballot(mine);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)bal);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(bal >> 32));
+  uint64_t m = ((uint64_t)hi << 32) | lo;
+  const uint64_t pd = (uint64_t)(uintptr_t)dm;
+  while (m) {
+    const int src = (int)__builtin_ctzll(m);
+    m &= m - 1;
+    const uint64_t base = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(pd >> 32), src) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)pd, src);
+    const int o0 = __builtin_amdgcn_readlane(T.o00, src), o1 = __builtin_amdgcn_readlane(T.o01, src);
+    const int o2 = __builtin_amdgcn_readlane(T.o10, src), o3 = __builtin_amdgcn_readlane(T.o11, src);
+    const float fa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(T.fa), src));
+    const float fb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(T.fb), src));
+    const float g0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g[0]), src));
+    const float g1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g[1]), src));
+    const float g2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g[2]), src));
+    if (lane < 12) {
+      const int o = tap == 0 ? o0 : (tap == 1 ? o1 : (tap == 2 ? o2 : o3));
+      const float wa = tap < 2 ? 1.f - fa : fa, wb = (tap & 1) ? fb : 1.f - fb;
+      const float x = (c == 0 ? g0 : (c == 1 ? g1 : g2)) * (wa * wb);
+      if (x != 0.f) grad_add((gmem_f32*)(uintptr_t)base + o + c, x);
+    }
+  }
 }
 
-__device__ inline void shade_backward(const ViewDev& v, const Params& P, const float p[3],
-                                      const float nh[3], const float rho[3], float rough,
-                                      float metal, const float g[3], const float* sm,
-                                      const int loc_off[7], float g_p[3], float g_nh[3],
-                                      float g_rho[3], float& g_rough, float& g_metal) {
-  float wv[3] = {v.cam_o[0] - p[0], v.cam_o[1] - p[1], v.cam_o[2] - p[2]};
-  const float wl = sqrtf(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
-  const float wo[3] = {wv[0] / wl, wv[1] / wl, wv[2] / wl};
-  const float nv = nh[0] * wo[0] + nh[1] * wo[1] + nh[2] * wo[2];
-  const float rd[3] = {2.f * nv * nh[0] - wo[0], 2.f * nv * nh[1] - wo[1], 2.f * nv * nh[2] - wo[2]};
-  const float rc = clamp01(rough);
+// The environment levels of one view as the shading adjoint sees them:
+// texels, gradient maps, sizes and the float offset of the level's LDS copy
+// (-1: not privatised).  Filled from wave-uniform values once per view; a lane
+// picks its specular level (0..5) with selects rather than an indexed load.
+struct LevelSet {
+  const float* lvl[7];
+  float* dlvl[7];
+  int lh[7], lw[7], off[7];
+};
+template <class T>
+__device__ __forceinline__ T pick_level(const T a[7], int l) {
+  T r = a[0];
+#pragma unroll
+  for (int i = 1; i < 6; ++i) r = l == i ? a[i] : r;
+  return r;
+}
+
+// Adjoint of shade_forward for one record, in three stages so that a thread
+// can keep two records in flight (the kernel's loop issues the loads of the
+// next record before the atomics of the current one; a wave's memory counter
+// retires in issue order, so a load issued after an atomic would wait for it):
+//   shade_load:    the record's 11 gradients and the surfel's parameters;
+//   shade_fetch:   directions, taps, and the loads of the BRDF table and of
+//                  the three environment lookups;
+//   shade_adjoint: g = dL/dcol through the split-sum colour to dL/d(position,
+//                  n_hat, albedo, roughness, metallic) and the texel gradients;
+//   shade_scatter: the texel gradients into the levels and the 11 surfel
+//                  gradients of the record into sg.
+struct PPtrs { const float* p[7]; };
+
+struct ShadeIn {
+  long long r, s;  // record and surfel; r < 0: none
+  float4 ga, gb, gc;  // the record's gradient slots 0..11
+  float p[3], n[3], rho[3], rough, metal;
+};
+struct ShadeSt {
+  long long r;  // < 0: no work (no record, or a record without gradient)
+  float g[3], rho[3], rough, metal;
+  float nh[3], wo[3], wl, nv, rd[3], tl, fx, fy;
+  int l0;
+  Tap Td, Ta, Tb;
+  float lt[8], td[12], ta[12], tb[12];
+};
+struct ShadeOut {
+  long long r;
+  int l0;
+  Tap Td, Ta, Tb;
+  float gLd[3], gXa[3], gXb[3];
+  float gp[3], gnh[3], grho[3], grough, gmetal;
+};
+
+__device__ inline void shade_load(const PPtrs& PP, long long N, const float* __restrict__ grad, long long r,
+                                  long long s, ShadeIn& in) {
+  in.r = r;
+  in.s = s;
+  if (r < 0) return;
+  const float4* g4 = reinterpret_cast<const float4*>(grad + r * kGradStride);
+  in.ga = g4[0];
+  in.gb = g4[1];
+  in.gc = g4[2];
+  for (int k = 0; k < 3; ++k) {
+    in.p[k] = PP.p[0][k * N + s];
+    in.n[k] = PP.p[1][k * N + s];
+    in.rho[k] = PP.p[4][k * N + s];
+  }
+  in.rough = PP.p[5][s];
+  in.metal = PP.p[6][s];
+}
+
+__device__ inline void shade_fetch(const LevelSet& LS, const float cam_o[3], const Params& P, const ShadeIn& in,
+                                   ShadeSt& S) {
+  S.r = -1;
+  if (in.r < 0) return;
+  const float gr[11] = {in.ga.x, in.ga.y, in.ga.z, in.ga.w, in.gb.x, in.gb.y,
+                        in.gb.z, in.gb.w, in.gc.x, in.gc.y, in.gc.z};
+  bool any = false;
+  for (int k = 0; k < kNGrad; ++k) any |= gr[k] != 0.f;
+  // a record with a gradient was rasterised, hence kept by the cull
+  if (!any) return;
+  S.r = in.r;
+  S.g[0] = gr[G_CR]; S.g[1] = gr[G_CG]; S.g[2] = gr[G_CB];
+  for (int c = 0; c < 3; ++c) S.rho[c] = in.rho[c];
+  S.rough = in.rough;
+  S.metal = in.metal;
+  const float nn = sqrtf(in.n[0] * in.n[0] + in.n[1] * in.n[1] + in.n[2] * in.n[2]);
+  for (int c = 0; c < 3; ++c) S.nh[c] = in.n[c] / nn;
+  const float wv[3] = {cam_o[0] - in.p[0], cam_o[1] - in.p[1], cam_o[2] - in.p[2]};
+  S.wl = sqrtf(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
+  for (int c = 0; c < 3; ++c) S.wo[c] = wv[c] / S.wl;
+  S.nv = S.nh[0] * S.wo[0] + S.nh[1] * S.wo[1] + S.nh[2] * S.wo[2];
+  for (int c = 0; c < 3; ++c) S.rd[c] = 2.f * S.nv * S.nh[c] - S.wo[c];
+  const float rc = clamp01(in.rough);
   const float lam = 5.f * rc;
-  const int l0 = min((int)floorf(lam), 4);
-  const float tl = lam - (float)l0;
-  const float nvc = clamp01(nv);
-  LutTap T;
+  S.l0 = min((int)floorf(lam), 4);
+  S.tl = lam - (float)S.l0;
+  const int l1 = S.l0 + 1;
+  // taps: irradiance level at n, the two specular levels at r_dir, BRDF table
+  tap_setup(S.nh, LS.lh[6], LS.lw[6], S.Td);
+  tap_setup(S.rd, pick_level(LS.lh, S.l0), pick_level(LS.lw, S.l0), S.Ta);
+  tap_setup(S.rd, pick_level(LS.lh, l1), pick_level(LS.lw, l1), S.Tb);
+  const float lx = clamp01(S.nv) * (float)(P.lut_nv - 1), ly = rc * (float)(P.lut_r - 1);
+  const int j0 = min((int)floorf(lx), P.lut_nv - 2), i0 = min((int)floorf(ly), P.lut_r - 2);
+  S.fx = lx - (float)j0;
+  S.fy = ly - (float)i0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    S.lt[4 * c + 0] = P.lut[(i0 * P.lut_nv + j0) * 2 + c];
+    S.lt[4 * c + 1] = P.lut[(i0 * P.lut_nv + j0 + 1) * 2 + c];
+    S.lt[4 * c + 2] = P.lut[((i0 + 1) * P.lut_nv + j0) * 2 + c];
+    S.lt[4 * c + 3] = P.lut[((i0 + 1) * P.lut_nv + j0 + 1) * 2 + c];
+  }
+  tap_fetch(LS.lvl[6], S.Td, S.td);
+  tap_fetch(pick_level(LS.lvl, S.l0), S.Ta, S.ta);
+  tap_fetch(pick_level(LS.lvl, l1), S.Tb, S.tb);
+}
+
+__device__ inline void shade_adjoint(const Params& P, const ShadeSt& S, ShadeOut& O) {
+  O.r = S.r;
+  O.l0 = 0;
+  if (S.r < 0) return;
+  O.l0 = S.l0;
+  O.Td = S.Td;
+  O.Ta = S.Ta;
+  O.Tb = S.Tb;
+  const float* g = S.g;
+  const float* rho = S.rho;
+  const float metal = S.metal, tl = S.tl, fx = S.fx, fy = S.fy, nv = S.nv;
   float beta[2];
-  lut_fetch(P, nvc, rc, T, beta);
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+    beta[c] = (1.f - fy) * ((1.f - fx) * S.lt[4 * c] + fx * S.lt[4 * c + 1]) +
+              fy * ((1.f - fx) * S.lt[4 * c + 2] + fx * S.lt[4 * c + 3]);
   float F0[3], kd[3], gLs[3], gF0[3];
   for (int c = 0; c < 3; ++c) {
     F0[c] = 0.04f * (1.f - metal) + rho[c] * metal;
     kd[c] = (1.f - F0[c]) * (1.f - metal);
     gLs[c] = g[c] * (F0[c] * beta[0] + beta[1]);
     gF0[c] = 0.f;
+    O.gLd[c] = g[c] * kd[c] * rho[c];
+    O.gXa[c] = (1.f - tl) * gLs[c];
+    O.gXb[c] = tl * gLs[c];
+    O.gp[c] = 0.f;
+    O.gnh[c] = 0.f;
+    O.grho[c] = 0.f;
   }
-  float gb1 = 0.f, gb2 = 0.f, gtl = 0.f, grd[3] = {0.f, 0.f, 0.f};
+  O.grough = 0.f;
+  O.gmetal = 0.f;
   // diffuse: L_d(n)
   {
-    float gLd[3], Ld[3];
-    for (int c = 0; c < 3; ++c) gLd[c] = g[c] * kd[c] * rho[c];
-    level_lookup_adjoint(v, sm, loc_off, 6, nh, gLd, Ld, g_nh);
+    float Ld[3];
+    tap_adjoint(S.Td, S.td, S.nh, O.gLd, Ld, O.gnh);
     for (int c = 0; c < 3; ++c) {
       const float gkd = g[c] * rho[c] * Ld[c];
-      g_rho[c] += g[c] * kd[c] * Ld[c];
+      O.grho[c] += g[c] * kd[c] * Ld[c];
       gF0[c] -= gkd * (1.f - metal);
-      g_metal -= gkd * (1.f - F0[c]);
+      O.gmetal -= gkd * (1.f - F0[c]);
     }
   }
   // specular: the two levels around lambda, weights (1 - t) and t
-  for (int side = 0; side < 2; ++side) {
-    const int l = l0 + side;
-    const float wt = side ? tl : 1.f - tl;
-    float gX[3], X[3];
-    for (int c = 0; c < 3; ++c) gX[c] = wt * gLs[c];
-    level_lookup_adjoint(v, sm, loc_off, l, rd, gX, X, grd);
+  float gb1 = 0.f, gb2 = 0.f, gtl = 0.f, grd[3] = {0.f, 0.f, 0.f};
+  {
+    float A[3], B[3];
+    tap_adjoint(S.Ta, S.ta, S.rd, O.gXa, A, grd);
+    tap_adjoint(S.Tb, S.tb, S.rd, O.gXb, B, grd);
     for (int c = 0; c < 3; ++c) {
-      const float Ls = wt * X[c];
+      const float Ls = (1.f - tl) * A[c] + tl * B[c];
       gF0[c] += g[c] * Ls * beta[0];
       gb1 += g[c] * Ls * F0[c];
       gb2 += g[c] * Ls;
-      gtl += (side ? 1.f : -1.f) * gLs[c] * X[c];
+      gtl += gLs[c] * (B[c] - A[c]);
     }
   }
   for (int c = 0; c < 3; ++c) {
-    g_metal += gF0[c] * (rho[c] - 0.04f);
-    g_rho[c] += gF0[c] * metal;
+    O.gmetal += gF0[c] * (rho[c] - 0.04f);
+    O.grho[c] += gF0[c] * metal;
   }
   float g_rc = 5.f * gtl;
   // BRDF table slopes
   float gnvc = 0.f;
-  {
-    const float* L = P.lut;
-    for (int c = 0; c < 2; ++c) {
-      const float t00 = L[(T.i0 * P.lut_nv + T.j0) * 2 + c];
-      const float t01 = L[(T.i0 * P.lut_nv + T.j0 + 1) * 2 + c];
-      const float t10 = L[((T.i0 + 1) * P.lut_nv + T.j0) * 2 + c];
-      const float t11 = L[((T.i0 + 1) * P.lut_nv + T.j0 + 1) * 2 + c];
-      const float dx = (1.f - T.fy) * (t01 - t00) + T.fy * (t11 - t10);
-      const float dy = (1.f - T.fx) * (t10 - t00) + T.fx * (t11 - t01);
-      const float gc = (c == 0) ? gb1 : gb2;
-      gnvc += gc * dx * (float)(P.lut_nv - 1);
-      g_rc += gc * dy * (float)(P.lut_r - 1);
-    }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const float t00 = S.lt[4 * c], t01 = S.lt[4 * c + 1], t10 = S.lt[4 * c + 2], t11 = S.lt[4 * c + 3];
+    const float dx = (1.f - fy) * (t01 - t00) + fy * (t11 - t10);
+    const float dy = (1.f - fx) * (t10 - t00) + fx * (t11 - t01);
+    const float gc = (c == 0) ? gb1 : gb2;
+    gnvc += gc * dx * (float)(P.lut_nv - 1);
+    g_rc += gc * dy * (float)(P.lut_r - 1);
   }
   float gnv = (nv >= 0.f && nv <= 1.f) ? gnvc : 0.f;
-  const float nhg = nh[0] * grd[0] + nh[1] * grd[1] + nh[2] * grd[2];
+  const float nhg = S.nh[0] * grd[0] + S.nh[1] * grd[1] + S.nh[2] * grd[2];
   gnv += 2.f * nhg;
   float gwo[3];
   for (int i = 0; i < 3; ++i) {
-    g_nh[i] += 2.f * nv * grd[i] + gnv * wo[i];
-    gwo[i] = -grd[i] + gnv * nh[i];
+    O.gnh[i] += 2.f * nv * grd[i] + gnv * S.wo[i];
+    gwo[i] = -grd[i] + gnv * S.nh[i];
   }
-  if (rough >= 0.f && rough <= 1.f) g_rough += g_rc;
-  const float wg = wo[0] * gwo[0] + wo[1] * gwo[1] + wo[2] * gwo[2];
-  for (int i = 0; i < 3; ++i) g_p[i] -= (gwo[i] - wo[i] * wg) / wl;
+  if (S.rough >= 0.f && S.rough <= 1.f) O.grough += g_rc;
+  const float wg = S.wo[0] * gwo[0] + S.wo[1] * gwo[1] + S.wo[2] * gwo[2];
+  for (int i = 0; i < 3; ++i) O.gp[i] -= (gwo[i] - S.wo[i] * wg) / S.wl;
+}
+
+// Called by every lane of the wave (the global maps are written cooperatively);
+// lanes without a record to scatter have O.r < 0.
+__device__ inline void shade_scatter(const LevelSet& LS, const ShadeOut& O, float* sm, float* __restrict__ sg) {
+  const bool act = O.r >= 0;
+  const int l1 = O.l0 + 1;
+  const int offs[3] = {LS.off[6], pick_level(LS.off, O.l0), pick_level(LS.off, l1)};
+  float* const gls[3] = {LS.dlvl[6], pick_level(LS.dlvl, O.l0), pick_level(LS.dlvl, l1)};
+  const Tap* taps[3] = {&O.Td, &O.Ta, &O.Tb};
+  const float* gs[3] = {O.gLd, O.gXa, O.gXb};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (act && offs[i] >= 0) tap_scatter_lds((lds_f32*)sm + offs[i], *taps[i], gs[i]);
+    tap_scatter_global_wave(act && offs[i] < 0, gls[i], *taps[i], gs[i]);
+  }
+  if (act) {
+    float4* out = reinterpret_cast<float4*>(sg + O.r * 12);
+    out[0] = make_float4(O.gp[0], O.gp[1], O.gp[2], O.gnh[0]);
+    out[1] = make_float4(O.gnh[1], O.gnh[2], O.grho[0], O.grho[1]);
+    out[2] = make_float4(O.grho[2], O.grough, O.gmetal, 0.f);
+  }
 }
 
 // ---------------------------------------------------------------- raster params
@@ -341,8 +572,6 @@ __device__ inline void load_surfel(const float* const* P, long long N, long long
   sv = P[3][N + s];
 }
 
-struct PPtrs { const float* p[7]; };
-
 __global__ void __launch_bounds__(256) preprocess_kernel(PPtrs PP, long long N, const ViewDev* __restrict__ views,
                                                          int v0, Params prm, float* __restrict__ recs,
                                                          uint32_t* __restrict__ counts,
@@ -407,7 +636,7 @@ struct GPtrs { float* p[7]; };
 
 // Surfel adjoint in two kernels.
 //   shade_backward_kernel (split-sum only): one thread per record, striding over
-//   the records of one scene.  The adjoint of the split-sum colour gives
+//   the records of one scene view by view.  The adjoint of the split-sum colour gives
 //   dL/d(position, n_hat, albedo, roughness, metallic) of that record (written
 //   to sg[r][12]) and the texel gradients of the environment levels: the small
 //   levels accumulate in a block-private LDS copy (written out as a per-block
@@ -447,31 +676,42 @@ __global__ void __launch_bounds__(kBackwardThreads, 1) shade_backward_kernel(
   extern __shared__ float sm[];
   for (int i = threadIdx.x; i < lm.total; i += blockDim.x) sm[i] = 0.f;
   __syncthreads();
-  const long long n_rec = (long long)sv.n * sv.n_surf;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_rec;
-       i += (long long)gridDim.x * blockDim.x) {
-    const int k = (int)(i / sv.n_surf);
-    const long long local = i - (long long)k * sv.n_surf;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  // a wave's lanes take consecutive records; the loop runs while the wave's
+  // first lane has a record, so every lane stays in it (the scatter into the
+  // global maps needs the whole wave)
+  const long long wave0 = (long long)blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+  const long long first = wave0 + (threadIdx.x & 63);
+  // the view loop is uniform, so the view's descriptor stays in scalar registers
+  for (int k = 0; k < sv.n; ++k) {
     const ViewDev& v = views[sv.idx[k]];
-    const long long r = v.rec_off + local, s = sv.surf_off + local;
-    float gr[12];
-    if (!record_has_grad(grad, r, gr)) continue;
-    // a record with a gradient was rasterised, hence kept by the cull; the
-    // shading needs only the position and the unit normal
-    const float p[3] = {PP.p[0][s], PP.p[0][N + s], PP.p[0][2 * N + s]};
-    const float n[3] = {PP.p[1][s], PP.p[1][N + s], PP.p[1][2 * N + s]};
-    const float nn = sqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-    const float nh[3] = {n[0] / nn, n[1] / nn, n[2] / nn};
-    const float rho[3] = {PP.p[4][s], PP.p[4][N + s], PP.p[4][2 * N + s]};
-    float gp[3] = {0.f, 0.f, 0.f}, gnh[3] = {0.f, 0.f, 0.f}, grho[3] = {0.f, 0.f, 0.f};
-    float grough = 0.f, gmetal = 0.f;
-    const float gcol[3] = {gr[G_CR], gr[G_CG], gr[G_CB]};
-    shade_backward(v, prm, p, nh, rho, PP.p[5][s], PP.p[6][s], gcol, sm, lm.off, gp, gnh, grho, grough,
-                   gmetal);
-    float4* out = reinterpret_cast<float4*>(sg + r * 12);
-    out[0] = make_float4(gp[0], gp[1], gp[2], gnh[0]);
-    out[1] = make_float4(gnh[1], gnh[2], grho[0], grho[1]);
-    out[2] = make_float4(grho[2], grough, gmetal, 0.f);
+    LevelSet LS;
+#pragma unroll
+    for (int l = 0; l < 7; ++l) {
+      LS.lvl[l] = v.lvl[l];
+      LS.dlvl[l] = v.dlvl[l];
+      LS.lh[l] = v.lh[l];
+      LS.lw[l] = v.lw[l];
+      LS.off[l] = lm.off[l];
+    }
+    const float cam_o[3] = {v.cam_o[0], v.cam_o[1], v.cam_o[2]};
+    const long long rec_off = v.rec_off, n = sv.n_surf;
+    auto rec = [&](long long local) { return local < n ? rec_off + local : -1ll; };
+    // two records in flight: the lookups of `local` are being loaded while the
+    // inputs of `local + stride` arrive
+    ShadeIn in;
+    ShadeSt S;
+    shade_load(PP, N, grad, rec(first), sv.surf_off + first, in);
+    shade_fetch(LS, cam_o, prm, in, S);
+    shade_load(PP, N, grad, rec(first + stride), sv.surf_off + first + stride, in);
+    for (long long w = wave0, local = first; w < n; w += stride, local += stride) {
+      ShadeOut O;
+      shade_adjoint(prm, S, O);
+      shade_fetch(LS, cam_o, prm, in, S);
+      const long long nx = local + 2 * stride;
+      shade_load(PP, N, grad, rec(nx), sv.surf_off + nx, in);
+      shade_scatter(LS, O, sm, sg);
+    }
   }
   if (lm.total > 0) {
     __syncthreads();
@@ -506,7 +746,8 @@ __global__ void __launch_bounds__(256) geometry_backward_kernel(
     float gr[12];
     // depth-consolidation term: gradient with respect to T4z = c'_z
     const float gtz = prm.cons ? grad[r * kGradStride + G_TZ] : 0.f;
-    if (!record_has_grad(grad, r, gr) && gtz == 0.f) continue;
+    const bool has = record_has_grad(grad, r, gr);
+    if (!has && gtz == 0.f) continue;
     Geo o;
     bin_geometry(p, n, t, su, sv, v, prm.r_cut, sig, o);
     if (!o.keep) continue;
@@ -518,7 +759,9 @@ __global__ void __launch_bounds__(256) geometry_backward_kernel(
       grho[0] += gr[G_CR]; grho[1] += gr[G_CG]; grho[2] += gr[G_CB];
     } else if (prm.shade == 2) {
       gnh[0] += gr[G_CR]; gnh[1] += gr[G_CG]; gnh[2] += gr[G_CB];
-    } else {
+    } else if (has) {
+      // sg holds the shading adjoint of the records with a gradient (the others
+      // have dL/dcol = 0)
       const float4* in = reinterpret_cast<const float4*>(sg + r * 12);
       const float4 a = in[0], b = in[1], c = in[2];
       gp[0] += a.x; gp[1] += a.y; gp[2] += a.z;
