@@ -281,10 +281,11 @@ __device__ __forceinline__ T pick_level(const T a[7], int l) {
   return r;
 }
 
-// Adjoint of shade_forward for one record, in three stages so that a thread
-// can keep two records in flight (the kernel's loop issues the loads of the
-// next record before the atomics of the current one; a wave's memory counter
-// retires in issue order, so a load issued after an atomic would wait for it):
+// Adjoint of shade_forward for one record, in stages: every load of a record
+// is issued before any of its atomics (a wave's memory counter retires in
+// issue order, so a load issued after an atomic would wait for it).  (Keeping
+// two records in flight, the loads of the next before the atomics of the
+// current one, measured no faster and needs more registers.)
 //   shade_load:    the record's 11 gradients and the surfel's parameters;
 //   shade_fetch:   directions, taps, and the loads of the BRDF table and of
 //                  the three environment lookups;
@@ -697,19 +698,13 @@ __global__ void __launch_bounds__(kBackwardThreads, 1) shade_backward_kernel(
     const float cam_o[3] = {v.cam_o[0], v.cam_o[1], v.cam_o[2]};
     const long long rec_off = v.rec_off, n = sv.n_surf;
     auto rec = [&](long long local) { return local < n ? rec_off + local : -1ll; };
-    // two records in flight: the lookups of `local` are being loaded while the
-    // inputs of `local + stride` arrive
-    ShadeIn in;
-    ShadeSt S;
-    shade_load(PP, N, grad, rec(first), sv.surf_off + first, in);
-    shade_fetch(LS, cam_o, prm, in, S);
-    shade_load(PP, N, grad, rec(first + stride), sv.surf_off + first + stride, in);
     for (long long w = wave0, local = first; w < n; w += stride, local += stride) {
+      ShadeIn in;
+      ShadeSt S;
       ShadeOut O;
-      shade_adjoint(prm, S, O);
+      shade_load(PP, N, grad, rec(local), sv.surf_off + local, in);
       shade_fetch(LS, cam_o, prm, in, S);
-      const long long nx = local + 2 * stride;
-      shade_load(PP, N, grad, rec(nx), sv.surf_off + nx, in);
+      shade_adjoint(prm, S, O);
       shade_scatter(LS, O, sm, sg);
     }
   }
