@@ -134,15 +134,16 @@ __global__ void __launch_bounds__(256) envmap_prefilter_kernel(const float* __re
     }
     __syncthreads();
     if (skip) continue;
-    // texels behind the output direction (c <= 0) get weight 0 by a select,
-    // not a branch (lanes of a wave face different ways); adding the exact
-    // zero leaves the sums unchanged
+    // texels behind the output direction (c <= 0) get weight exactly 0 through
+    // max(c, 0) (both weights carry a factor c), with no select or branch:
+    // lanes of a wave face different ways, and a branch let the compiler sink
+    // part of the staged reads into it and wait for LDS once per texel
     if (l == 6) {
 #pragma unroll 4
       for (int i = 0; i < n; ++i) {
         const float4 d = sd[i], e = se[i];
-        const float c = R.x * d.x + R.y * d.y + R.z * d.z;
-        const float kk = c > 0.f ? c * d.w : 0.f;
+        const float c = fmaxf(R.x * d.x + R.y * d.y + R.z * d.z, 0.f);
+        const float kk = c * d.w;
         acc0 += e.x * kk;
         acc1 += e.y * kk;
         acc2 += e.z * kk;
@@ -151,8 +152,8 @@ __global__ void __launch_bounds__(256) envmap_prefilter_kernel(const float* __re
 #pragma unroll 4
       for (int i = 0; i < n; ++i) {
         const float4 d = sd[i], e = se[i];
-        const float c = R.x * d.x + R.y * d.y + R.z * d.z;
-        const float kk = c > 0.f ? ggx_weight(c, alpha) * d.w : 0.f;
+        const float c = fmaxf(R.x * d.x + R.y * d.y + R.z * d.z, 0.f);
+        const float kk = ggx_weight(c, alpha) * d.w;
         acc0 += e.x * kk;
         acc1 += e.y * kk;
         acc2 += e.z * kk;
@@ -243,43 +244,66 @@ __global__ void __launch_bounds__(256) envmap_adjoint_kernel(DLevelSet L, int nt
                                                              const float4* __restrict__ dirs,
                                                              const float4* __restrict__ out_dirs,
                                                              float* __restrict__ dE, int chunk) {
+  __shared__ float4 sR[256], sG[256];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = t < nt;
   const float4 dt = live ? dirs[t] : make_float4(0.f, 0.f, 1.f, 0.f);
   const int o_begin = blockIdx.y * chunk, o_end = min(o_begin + chunk, L.first[7]);
-  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
-  int l = level_of(L.first, o_begin);
-  float alpha = (float)(l * l) / 25.f;
   // Latitude bands of the block's input texels and of the chunk's output texels
   // (texel-centre angles; rows are monotone within a level).  When they are
   // more than pi/2 + 1e-3 apart every cosine is clearly negative and the chunk
   // adds nothing.
+  bool skip;
   {
     const int He = L.h[0], We = L.w[0];
     const int ta = blockIdx.x * blockDim.x, tb = min(ta + (int)blockDim.x, nt) - 1;
     const float ia = kPi * ((float)(ta / We) + 0.5f) / (float)He, ib = kPi * ((float)(tb / We) + 0.5f) / (float)He;
     float oa = 4.f, ob = -1.f;
-    for (int lv = l; lv <= 6 && L.first[lv] < o_end; ++lv) {
+    for (int lv = level_of(L.first, o_begin); lv <= 6 && L.first[lv] < o_end; ++lv) {
       const int k0 = max(o_begin, L.first[lv]) - L.first[lv], k1 = min(o_end, L.first[lv + 1]) - 1 - L.first[lv];
       oa = fminf(oa, kPi * ((float)(k0 / L.w[lv]) + 0.5f) / (float)L.h[lv]);
       ob = fmaxf(ob, kPi * ((float)(k1 / L.w[lv]) + 0.5f) / (float)L.h[lv]);
     }
-    if (fmaxf(ia - ob, oa - ib) > 0.5f * kPi + 1e-3f) l = 7;  // nothing to add from this chunk
+    skip = fmaxf(ia - ob, oa - ib) > 0.5f * kPi + 1e-3f;
   }
-  for (int o = o_begin; l <= 6 && o < o_end; ++o) {
-    if (o >= L.first[l + 1]) {
-      l = level_of(L.first, o);
-      alpha = (float)(l * l) / 25.f;
+  // Stage the chunk's output texels through LDS (direction and 1/Z; gradient
+  // and alpha); the loops below then reads them as
+  // broadcasts, four texels' reads issued together, instead of a chain of
+  // dependent scalar loads per output texel.
+  if (!skip) {
+    const int o = o_begin + (int)threadIdx.x;
+    if (o < o_end) {
+      const int l = level_of(L.first, o);
+      const float* gg = L.g[l] + 3 * (o - L.first[l]);
+      sR[threadIdx.x] = out_dirs[o];
+      sG[threadIdx.x] = make_float4(gg[0], gg[1], gg[2], (float)(l * l) / 25.f);
     }
-    const float* gg = L.g[l] + 3 * (o - L.first[l]);
-    const float g0 = gg[0], g1 = gg[1], g2 = gg[2];
-    const float4 R = out_dirs[o];
-    const float c = R.x * dt.x + R.y * dt.y + R.z * dt.z;
-    if (c <= 0.f) continue;
-    const float kk = (l == 6 ? c : ggx_weight(c, alpha)) * dt.w * R.w;
-    acc0 += g0 * kk;
-    acc1 += g1 * kk;
-    acc2 += g2 * kk;
+  }
+  __syncthreads();
+  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+  if (!skip) {
+    // the specular levels come first in the flattened output order, the
+    // irradiance level last; weights are exactly 0 for c <= 0 through max(c, 0)
+    // (both carry a factor c), without a branch
+    const int n = o_end - o_begin, i6 = min(max(L.first[6] - o_begin, 0), n);
+#pragma unroll 4
+    for (int i = 0; i < i6; ++i) {
+      const float4 R = sR[i], G = sG[i];
+      const float c = fmaxf(R.x * dt.x + R.y * dt.y + R.z * dt.z, 0.f);
+      const float kk = ggx_weight(c, G.w) * dt.w * R.w;
+      acc0 += G.x * kk;
+      acc1 += G.y * kk;
+      acc2 += G.z * kk;
+    }
+#pragma unroll 4
+    for (int i = i6; i < n; ++i) {
+      const float4 R = sR[i], G = sG[i];
+      const float c = fmaxf(R.x * dt.x + R.y * dt.y + R.z * dt.z, 0.f);
+      const float kk = c * dt.w * R.w;
+      acc0 += G.x * kk;
+      acc1 += G.y * kk;
+      acc2 += G.z * kk;
+    }
   }
   if (!live) return;
   if (blockIdx.y == 0) {
