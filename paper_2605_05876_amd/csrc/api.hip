@@ -361,7 +361,9 @@ ss_status run_binning(ss_context* c, const Group& g, int gi, hipStream_t st) {
   uint32_t* zi = P<uint32_t>(c->zidx) + g.rec_begin;
   uint2* zr = P<uint2>(c->zrect) + g.rec_begin;
   SS_HIP(launch_radix_sort(zk, zi, P<uint32_t>(c->zkey2) + g.rec_begin, P<uint32_t>(c->zidx2) + g.rec_begin,
-                           true, (uint32_t)g.rec_begin, P<uint2>(c->prect), zr, nullptr, n, n, 4,
+                           true, (uint32_t)g.rec_begin, P<uint2>(c->prect), zr,
+                           // culled records: depth key 0xffffffff, empty rectangle (1, 0)
+                           0xffffffffu, make_uint2(1u, 0u), nullptr, n, n, 4,
                            P<uint32_t>(c->hist), c->hist_n, P<uint32_t>(c->scan_tmp), c->scan_tmp_n, st));
   SS_HIP(launch_scan_rect_tiles(zr, c->opt.tile_w, c->opt.tile_h, P<uint32_t>(c->offsets) + g.rec_begin, n,
                                 misc + kMiscPairs + gi, P<uint32_t>(c->scan_tmp), c->scan_tmp_n, st));
@@ -375,7 +377,7 @@ ss_status run_binning(ss_context* c, const Group& g, int gi, hipStream_t st) {
                            c->opt.tile_w, c->opt.tile_h, odd ? keys2 : keys, odd ? vals2 : vals, g.pair_cap, status,
                            st));
   SS_HIP(launch_radix_sort(odd ? keys2 : keys, odd ? vals2 : vals, odd ? keys : keys2, odd ? vals : vals2, false, 0u,
-                           nullptr, nullptr, np, -1, g.pair_cap, g.pair_passes, P<uint32_t>(c->hist), c->hist_n,
+                           nullptr, nullptr, 0u, make_uint2(0u, 0u), np, -1, g.pair_cap, g.pair_passes, P<uint32_t>(c->hist), c->hist_n,
                            P<uint32_t>(c->scan_tmp), c->scan_tmp_n, st));
   SS_HIP(launch_tile_ranges(keys, np, g.pair_cap, P<uint32_t>(c->ranges), g.tile_base, g.n_tiles, st));
   return SS_OK;

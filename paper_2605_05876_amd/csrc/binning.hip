@@ -372,13 +372,14 @@ __global__ void __launch_bounds__(kRadixThreads) radix_hist_kernel(const uint32_
 
 // IOTA: the input values are val0 + (input position), vin is not read.
 // GATHER: also writes gout[dst] = gsrc[value] (the last pass of a sort whose
-// values index gsrc).
+// values index gsrc), or gskip_val without reading gsrc where the key is
+// gskip_key (entries whose gathered value is known: culled records).
 template <bool IOTA, bool GATHER>
 __global__ void __launch_bounds__(kRadixThreads) radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t val0,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint2* __restrict__ gsrc,
-    uint2* __restrict__ gout, const uint32_t* n_dev, long long n_fixed, long long cap, int shift, int cpg,
-    const uint32_t* __restrict__ hist) {
+    uint2* __restrict__ gout, uint32_t gskip_key, uint2 gskip_val, const uint32_t* n_dev, long long n_fixed,
+    long long cap, int shift, int cpg, const uint32_t* __restrict__ hist) {
   __shared__ uint32_t woff[kRadixWaves][256];  // per-wave digit counts, then chunk-local run starts
   __shared__ uint32_t loc[256];                // chunk-local start of each digit
   __shared__ uint32_t run[256];                // global start of each digit's run of this chunk
@@ -463,7 +464,7 @@ __global__ void __launch_bounds__(kRadixThreads) radix_scatter_kernel(
       const uint32_t v = sv[p];
       kout[dst] = k;
       vout[dst] = v;
-      if (GATHER) gout[dst] = gsrc[v];
+      if (GATHER) gout[dst] = k == gskip_key ? gskip_val : gsrc[v];
     }
     __syncthreads();
     if (t < 256) run[t] += tot;
@@ -471,8 +472,8 @@ __global__ void __launch_bounds__(kRadixThreads) radix_scatter_kernel(
 }
 
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
-                             bool iota, uint32_t val0, const uint2* gsrc, uint2* gout,
-                             const uint32_t* n_dev, long long n_fixed, long long cap, int passes,
+                             bool iota, uint32_t val0, const uint2* gsrc, uint2* gout, uint32_t gskip_key,
+                             uint2 gskip_val, const uint32_t* n_dev, long long n_fixed, long long cap, int passes,
                              uint32_t* hist, long long hist_n, uint32_t* scan_tmp, long long scan_tmp_n,
                              hipStream_t st) {
   if (passes <= 0 || cap <= 0) return hipSuccess;
@@ -488,7 +489,7 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp,
     const bool io = iota && p == 0, ga = gsrc && p == passes - 1;
 #define SS_SCATTER(I, G)                                                                                     \
   hipLaunchKernelGGL((radix_scatter_kernel<I, G>), dim3(rg.groups), dim3(kRadixThreads), 0, st, ka, va, val0, \
-                     kb, vb, gsrc, gout, n_dev, n_fixed, cap, shift, rg.chunks_per_group, hist)
+                     kb, vb, gsrc, gout, gskip_key, gskip_val, n_dev, n_fixed, cap, shift, rg.chunks_per_group, hist)
     if (io && ga) SS_SCATTER(true, true);
     else if (io) SS_SCATTER(true, false);
     else if (ga) SS_SCATTER(false, true);

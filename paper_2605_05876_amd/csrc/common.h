@@ -285,11 +285,12 @@ hipError_t launch_emit_pairs(const uint32_t* order, const uint2* rect, const uin
 // Count: n_fixed when >= 0, else *n_dev (device), at most cap; cap sizes the
 // grid and the histogram (radix_hist_size(cap) entries).  iota: the first pass
 // takes val0 + position as values.  gsrc (optional): the last pass also writes
-// gout[i] = gsrc[value of sorted pair i].
+// gout[i] = gsrc[value of sorted pair i], or gskip_val where the key is
+// gskip_key (gsrc not read there).
 long long radix_hist_size(long long cap);
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
-                             bool iota, uint32_t val0, const uint2* gsrc, uint2* gout,
-                             const uint32_t* n_dev, long long n_fixed, long long cap, int passes,
+                             bool iota, uint32_t val0, const uint2* gsrc, uint2* gout, uint32_t gskip_key,
+                             uint2 gskip_val, const uint32_t* n_dev, long long n_fixed, long long cap, int passes,
                              uint32_t* hist, long long hist_n, uint32_t* scan_tmp, long long scan_tmp_n,
                              hipStream_t st);
 hipError_t launch_tile_ranges(const uint32_t* keys, const uint32_t* n_pairs, long long cap,
