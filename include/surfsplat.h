@@ -91,6 +91,12 @@ typedef struct ss_options {
                           every intersection, support = the binning rectangle of the
                           centre filter intersected with rho^2 < r_cut^2.  Forward
                           only: ss_render_backward returns SS_ERR_UNSUPPORTED     */
+  int32_t env_lds;     /* split-sum backward: floats of environment-level gradients
+                          the shading adjoint may accumulate in a block-private LDS
+                          copy (levels in the order irradiance, 5, 4, ..., 0, each
+                          only while it fits whole); the others take global atomics.
+                          -1 (default): as many as fit (39936 floats); 0: none.
+                          Results agree either way up to the order of float sums  */
 } ss_options;
 
 typedef struct ss_camera {

@@ -128,6 +128,7 @@ ss_status check_options(const ss_options* o) {
   if (o->launch != SS_LAUNCH_BATCHED && o->launch != SS_LAUNCH_PER_VIEW) return SS_ERR_INVALID_ARG;
   if (o->depth_stats != 0 && o->depth_stats != 1) return SS_ERR_INVALID_ARG;
   if (o->mip != 0 && o->mip != 1) return SS_ERR_INVALID_ARG;
+  if (o->env_lds < -1) return SS_ERR_INVALID_ARG;
   return SS_OK;
 }
 
@@ -281,7 +282,8 @@ ss_status prepare_env(ss_context* c, const ss_batch* b, hipStream_t st) {
     e.loc_total = 0;
     for (int l : {6, 5, 4, 3, 2, 1, 0}) {
       const int n = 3 * e.lh[l] * e.lw[l];
-      if (e.loc_total + n > kLocalMapFloats) break;
+      const int budget = c->opt.env_lds < 0 ? kLocalMapFloats : std::min(c->opt.env_lds, kLocalMapFloats);
+      if (e.loc_total + n > budget) break;
       e.loc_off[l] = e.loc_total;
       e.loc_total += n;
     }
@@ -537,6 +539,7 @@ ss_status ss_default_options(ss_options* o) {
   o->persistent = 1;
   o->depth_stats = 0;
   o->mip = 0;
+  o->env_lds = -1;
   return SS_OK;
 }
 

@@ -38,7 +38,8 @@ class ss_options(ctypes.Structure):
     _fields_ = [("r_cut", ctypes.c_float), ("k_max", ctypes.c_int32), ("gamma", ctypes.c_float),
                 ("sigma_f", ctypes.c_float), ("shade", ctypes.c_int32), ("tile_w", ctypes.c_int32),
                 ("tile_h", ctypes.c_int32), ("lds_batch", ctypes.c_int32), ("launch", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("depth_stats", ctypes.c_int32), ("mip", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("depth_stats", ctypes.c_int32), ("mip", ctypes.c_int32),
+                ("env_lds", ctypes.c_int32)]
 
 
 class ss_camera(ctypes.Structure):
@@ -146,12 +147,13 @@ class Options:
     persistent: bool = True
     depth_stats: bool = False   # allow forwards to output the eq:cons_loss term
     mip: str = "centre"         # "centre" (Sec. 3.3.2) | "pixel" (per-pixel Jacobian, forward only)
+    env_lds: int = -1           # split-sum backward: environment gradient floats kept in LDS (-1: all that fit)
 
     def to_c(self) -> ss_options:
         return ss_options(self.r_cut, self.k_max, self.gamma, self.sigma_f, SHADE[self.shade],
                           self.tile_w, self.tile_h, self.lds_batch, LAUNCH[self.launch],
                           1 if self.persistent else 0, 1 if self.depth_stats else 0,
-                          {"centre": 0, "pixel": 1}[self.mip])
+                          {"centre": 0, "pixel": 1}[self.mip], int(self.env_lds))
 
 
 def camera_to_c(cam) -> ss_camera:

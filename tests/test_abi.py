@@ -68,13 +68,16 @@ def test_host_argument_checks(lib):
     from paper_2605_05876_amd import surfsplat as s
     o = s.ss_options()
     assert lib.ss_default_options(ctypes.byref(o)) == 0
-    assert (o.r_cut, o.k_max, o.tile_w, o.tile_h) == (3.0, 16, 16, 16)
+    assert (o.r_cut, o.k_max, o.tile_w, o.tile_h, o.env_lds) == (3.0, 16, 16, 16, -1)
     ctx = ctypes.c_void_p()
     bad = s.ss_options.from_buffer_copy(o)
     bad.tile_w = 12
     assert lib.ss_create(ctypes.byref(bad), ctypes.byref(ctx)) == s.SS_ERR_UNSUPPORTED
     bad = s.ss_options.from_buffer_copy(o)
     bad.k_max = 17
+    assert lib.ss_create(ctypes.byref(bad), ctypes.byref(ctx)) == s.SS_ERR_INVALID_ARG
+    bad = s.ss_options.from_buffer_copy(o)
+    bad.env_lds = -2
     assert lib.ss_create(ctypes.byref(bad), ctypes.byref(ctx)) == s.SS_ERR_INVALID_ARG
     bad = s.ss_options.from_buffer_copy(o)
     bad.lds_batch = 100

@@ -257,6 +257,16 @@ def test_backward_parity_splitsum_full_image(O, ss):
     assert max(errs.values()) <= GRAD_REL_L2, errs
 
 
+@pytest.mark.parametrize("env_lds", [0, 6144])
+def test_backward_parity_splitsum_global_levels(O, ss, env_lds):
+    """Environment-level gradients through global atomics for every level (env_lds 0)
+    or for every level but the irradiance one (6144 floats): the wave-cooperative
+    global scatter of the shading adjoint for all three lookups, against the oracle."""
+    scenes, cams = small_c2()
+    errs = _backward_case(O, ss, scenes, cams, "splitsum", lambda c, v: all_pix(c), env_lds=env_lds)
+    assert max(errs.values()) <= GRAD_REL_L2, errs
+
+
 def test_backward_parity_multiview(O, ss):
     scenes, cams = small_multiview()
     errs = _backward_case(O, ss, scenes, cams, "splitsum", lambda c, v: all_pix(c), seed=3)
