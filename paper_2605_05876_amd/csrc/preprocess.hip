@@ -527,11 +527,15 @@ __device__ inline void raster_geometry_f64(const float pf[3], const float nf_[3]
                                            int il, int jl, RasterGeoF& out) {
   const double n0 = nf_[0], n1 = nf_[1], n2 = nf_[2];
   const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-  const double nh[3] = {n0 / nn, n1 / nn, n2 / nn};
+  // one FP64 division per denominator, then products (each FP64 division is a
+  // long instruction sequence; the results are rounded to FP32 once anyway)
+  const double inn = 1.0 / nn;
+  const double nh[3] = {n0 * inn, n1 * inn, n2 * inn};
   const double d = tf[0] * nh[0] + tf[1] * nh[1] + tf[2] * nh[2];
   double g[3] = {tf[0] - d * nh[0], tf[1] - d * nh[1], tf[2] - d * nh[2]};
   const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-  const double uh[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
+  const double ign = 1.0 / gn;
+  const double uh[3] = {g[0] * ign, g[1] * ign, g[2] * ign};
   const double vh[3] = {nh[1] * uh[2] - nh[2] * uh[1], nh[2] * uh[0] - nh[0] * uh[2],
                         nh[0] * uh[1] - nh[1] * uh[0]};
   const double su = su_, sv = sv_, sigma = sigma_;
@@ -542,24 +546,25 @@ __device__ inline void raster_geometry_f64(const float pf[3], const float nf_[3]
     up[i] = su * ((double)R[0] * uh[0] + (double)R[1] * uh[1] + (double)R[2] * uh[2]);
     vp[i] = sv * ((double)R[0] * vh[0] + (double)R[1] * vh[1] + (double)R[2] * vh[2]);
   }
-  const double z = cp[2], mx = cp[0] / z, my = cp[1] / z;
+  const double z = cp[2], iz = 1.0 / z, mx = cp[0] * iz, my = cp[1] * iz;
   const double fx = v.fx, fy = v.fy;
   const double x0 = fx * mx + (double)v.cx, y0 = fy * my + (double)v.cy;
-  const double M11 = fx * (up[0] - mx * up[2]) / z, M12 = fx * (vp[0] - mx * vp[2]) / z;
-  const double M21 = fy * (up[1] - my * up[2]) / z, M22 = fy * (vp[1] - my * vp[2]) / z;
-  const double g1 = up[2] / z, g2 = vp[2] / z;
+  const double M11 = fx * (up[0] - mx * up[2]) * iz, M12 = fx * (vp[0] - mx * vp[2]) * iz;
+  const double M21 = fy * (up[1] - my * up[2]) * iz, M22 = fy * (vp[1] - my * vp[2]) * iz;
+  const double g1 = up[2] * iz, g2 = vp[2] * iz;
   const double dm = M11 * M22 - M12 * M21;
   const double detA = dm * dm;
   const double K11 = M11 * M11 + M12 * M12, K12 = M11 * M21 + M12 * M22, K22 = M21 * M21 + M22 * M22;
   const double detB = detA + sigma * (K11 + K22) + sigma * sigma;
   out.x0r = (float)(x0 - (double)il);
   out.y0r = (float)(y0 - (double)jl);
-  out.Qxx = (float)((K22 + sigma) / detB);
-  out.Qxy2 = (float)(-2.0 * K12 / detB);
-  out.Qyy = (float)((K11 + sigma) / detB);
-  out.nf = (float)sqrt(detA / detB);
-  out.a3 = (float)((g2 * M21 - g1 * M22) / dm);
-  out.b3 = (float)((M12 * g1 - M11 * g2) / dm);
+  const double ib = 1.0 / detB, idm = 1.0 / dm;
+  out.Qxx = (float)((K22 + sigma) * ib);
+  out.Qxy2 = (float)(-2.0 * K12 * ib);
+  out.Qyy = (float)((K11 + sigma) * ib);
+  out.nf = (float)sqrt(detA * ib);
+  out.a3 = (float)((g2 * M21 - g1 * M22) * idm);
+  out.b3 = (float)((M12 * g1 - M11 * g2) * idm);
 }
 
 __device__ inline void load_surfel(const float* const* P, long long N, long long s, float p[3],
