@@ -93,6 +93,10 @@ struct ss_context {
   std::vector<long long> fwd_sig;
   hipStream_t last_stream = nullptr;  // may be the null stream
   bool used = false;                  // a stream call has been made
+  // second stream for the environment adjoint, overlapping the geometry adjoint
+  // (created on the first backward that uses it)
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // stage timing
   bool prof = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_ev;
@@ -565,6 +569,12 @@ ss_status ss_destroy(ss_context* c) {
   for (SceneEnv& e : c->env) { release(e.dirs); release(e.lv); release(e.Z); release(e.dlv); release(e.part); }
   for (auto& pe : c->prof_ev) { c->ev_pool.push_back(pe.second.first); c->ev_pool.push_back(pe.second.second); }
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+    (void)hipEventDestroy(c->fork_ev);
+    (void)hipEventDestroy(c->join_ev);
+  }
   delete c;
   return SS_OK;
 }
@@ -661,6 +671,20 @@ ss_status ss_render(ss_context* c, const ss_batch* b, const ss_outputs* out, ss_
   return SS_OK;
 }
 
+// Environment adjoint of every scene with a requested map gradient, on `st`.
+static ss_status envmap_backward(ss_context* c, const ss_grads* gr, hipStream_t st) {
+  if (c->opt.shade != SS_SHADE_SPLITSUM || !gr->d_envmap) return SS_OK;
+  for (int s = 0; s < c->n_scenes; ++s) {
+    if (!gr->d_envmap[s]) continue;
+    SceneEnv& e = c->env[s];
+    const float* dl[7];
+    for (int l = 0; l < 7; ++l) dl[l] = P<float>(e.dlv) + e.doff[l];
+    SS_HIP(launch_envmap_adjoint(dl, e.lh, e.lw, P<float>(e.Z), e.He, e.We, P<float>(e.dirs),
+                                 gr->d_envmap[s], st));
+  }
+  return SS_OK;
+}
+
 ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in* gin,
                              const ss_grads* gr, ss_stream stream) {
   if (!c || !gin || !gin->d_image || !gr) return SS_ERR_INVALID_ARG;
@@ -712,22 +736,33 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
                                    P<float>(c->partial), lg, prm, P<float>(c->grad), P<float>(c->sg), st));
     }
   }
+  // The environment adjoint reads only the level gradients that the shading
+  // adjoint wrote, as does the geometry adjoint its record gradients: with stage
+  // timing off it runs on a second stream beside the geometry adjoint and is
+  // joined back into `st` before this call returns.
+  const bool fork = c->opt.shade == SS_SHADE_SPLITSUM && gr->d_envmap && !c->prof;
+  if (fork) {
+    if (!c->side) {
+      SS_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+      SS_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+      SS_HIP(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    }
+    SS_HIP(hipEventRecord(c->fork_ev, st));
+    SS_HIP(hipStreamWaitEvent(c->side, c->fork_ev, 0));
+    SS_TRY(envmap_backward(c, gr, c->side));
+    SS_HIP(hipEventRecord(c->join_ev, c->side));
+  }
   SS_HIP(launch_geometry_backward(pp, c->N, P<ViewDev>(c->views_d), c->n_views, prm, P<float>(c->grad),
                                   P<float>(c->sg), G, P<float>(c->recs), gr->screen_grad,
                                   gr->visible_views, st));
   prof_end(c, t1, ST_PREBWD, st);
-  t1 = prof_begin(c, st);
-  if (c->opt.shade == SS_SHADE_SPLITSUM && gr->d_envmap) {
-    for (int s = 0; s < c->n_scenes; ++s) {
-      if (!gr->d_envmap[s]) continue;
-      SceneEnv& e = c->env[s];
-      const float* dl[7];
-      for (int l = 0; l < 7; ++l) dl[l] = P<float>(e.dlv) + e.doff[l];
-      SS_HIP(launch_envmap_adjoint(dl, e.lh, e.lw, P<float>(e.Z), e.He, e.We, P<float>(e.dirs),
-                                   gr->d_envmap[s], st));
-    }
+  if (fork) {
+    SS_HIP(hipStreamWaitEvent(st, c->join_ev, 0));
+  } else {
+    t1 = prof_begin(c, st);
+    SS_TRY(envmap_backward(c, gr, st));
+    prof_end(c, t1, ST_ENVBWD, st);
   }
-  prof_end(c, t1, ST_ENVBWD, st);
   return SS_OK;
 }
 
