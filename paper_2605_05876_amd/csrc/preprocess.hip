@@ -3,10 +3,12 @@
 // Forward (one thread per record): the binning decision (cull, depth interval,
 // pixel rectangle; Sec. 3.1, Sec. 3.2.1, App. A.1), the centre-precomputed MIP
 // kernel (Sec. 3.3.2) in projective form, and the split-sum colour (eq:ibl).
-// Backward (one thread per surfel, looping over the views of its scene): the
-// chain rule from the 11 record gradients written by the raster backward to
-// position, normal, tangent, scale, albedo, roughness and metallic, plus texel
-// gradients of the environment levels (atomics into small maps).
+// Backward: the adjoint of the split-sum colour per record (one thread per
+// record; texel gradients into block-private LDS copies of the environment
+// levels that fit, wave-cooperative global atomics for the others), then the
+// chain rule per surfel (one thread per surfel, looping over the views of its
+// scene) from the 11 record gradients written by the raster backward to
+// position, normal, tangent, scale, albedo, roughness and metallic.
 #include "common.h"
 
 namespace ss {
