@@ -128,8 +128,8 @@ __device__ inline void shade_forward(const ViewDev& v, const Params& P, const fl
 //   tap_setup:   coordinates, texel offsets and fractions;
 //   tap_fetch:   the 12 texel values;
 //   tap_adjoint: the looked-up value, and dL/dd added to gd for g = dL/dvalue;
-//   tap_scatter: g times the bilinear weights into the level's gradient map
-//                (its LDS copy when off >= 0, else global atomics).
+//   tap_scatter_lds / tap_scatter_global_wave: g times the bilinear weights
+//                into the level's LDS copy, or its global gradient map.
 struct Tap {
   int o00, o01, o10, o11;  // float offsets of the four texels
   float fa, fb;            // bilinear fractions (row, column)
