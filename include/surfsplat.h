@@ -218,7 +218,11 @@ ss_status ss_reserve(ss_context* ctx, const ss_batch* batch, ss_stream stream, s
 ss_status ss_render(ss_context* ctx, const ss_batch* batch, const ss_outputs* out, ss_stream stream);
 
 /* Backward of the last ss_render on this context with the same batch.
- * Returns SS_ERR_STATE without a matching forward. */
+ * Returns SS_ERR_STATE without a matching forward.  With split-sum shading and
+ * environment gradients requested, the environment adjoint runs on a stream of
+ * the context, forked from `stream` and joined back into it by events before
+ * the call returns (a captured graph holds both branches); work queued on
+ * `stream` afterwards sees every output. */
 ss_status ss_render_backward(ss_context* ctx, const ss_batch* batch, const ss_grad_in* gin,
                              const ss_grads* grads, ss_stream stream);
 

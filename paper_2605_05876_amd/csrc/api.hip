@@ -94,7 +94,7 @@ struct ss_context {
   hipStream_t last_stream = nullptr;  // may be the null stream
   bool used = false;                  // a stream call has been made
   // second stream for the environment adjoint, overlapping the geometry adjoint
-  // (created on the first backward that uses it)
+  // (split-sum; created by the reserve)
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // stage timing
@@ -389,6 +389,16 @@ ss_status run_binning(ss_context* c, const Group& g, int gi, hipStream_t st) {
   return SS_OK;
 }
 
+// The second stream and its fork/join events of the backward (split-sum);
+// created by the reserve, outside any graph capture.
+static ss_status ensure_side(ss_context* c) {
+  if (c->side || c->opt.shade != SS_SHADE_SPLITSUM) return SS_OK;
+  SS_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  SS_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+  SS_HIP(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+  return SS_OK;
+}
+
 ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
   c->reserved = false;
   c->fwd_valid = false;
@@ -482,6 +492,7 @@ ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
   }
   c->sig = signature(c, b);
   c->reserved = true;
+  SS_TRY(ensure_side(c));
   return SS_OK;
 }
 
@@ -742,11 +753,7 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
   // joined back into `st` before this call returns.
   const bool fork = c->opt.shade == SS_SHADE_SPLITSUM && gr->d_envmap && !c->prof;
   if (fork) {
-    if (!c->side) {
-      SS_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-      SS_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
-      SS_HIP(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
-    }
+    SS_TRY(ensure_side(c));
     SS_HIP(hipEventRecord(c->fork_ev, st));
     SS_HIP(hipStreamWaitEvent(c->side, c->fork_ev, 0));
     SS_TRY(envmap_backward(c, gr, c->side));
