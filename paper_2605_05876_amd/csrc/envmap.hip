@@ -43,13 +43,17 @@ hipError_t launch_envmap_dirs(float* dirs, int H, int W, hipStream_t st) {
   return hipGetLastError();
 }
 
+// D(mu; alpha) c with mu^2 = (1 + c)/2 (hardware reciprocal: the weights enter
+// normalised sums).  With k = (alpha^2 - 1)/2 the denominator
+// t = 1 + mu^2 (alpha^2 - 1) is one fused multiply-add, c k + (k + 1);
+// ggx_scaled leaves out the factor alpha^2 / pi.
+__device__ __forceinline__ float ggx_scaled(float c, float k) {
+  const float t = __builtin_fmaf(c, k, k + 1.f);
+  return __builtin_amdgcn_rcpf(t * t) * c;
+}
 __device__ inline float ggx_weight(float c, float alpha) {
-  // D(mu; alpha) max(0, c) with mu^2 = (1 + c)/2 (hardware reciprocal: the
-  // weights enter normalised sums)
-  float a2 = alpha * alpha;
-  float mu2 = 0.5f * (1.f + c);
-  float t = mu2 * (a2 - 1.f) + 1.f;
-  return a2 * (1.f / kPi) * __builtin_amdgcn_rcpf(t * t) * c;
+  const float a2 = alpha * alpha;
+  return a2 * (1.f / kPi) * ggx_scaled(c, 0.5f * (a2 - 1.f));
 }
 
 struct LevelSet {
@@ -267,7 +271,7 @@ __global__ void __launch_bounds__(256) envmap_adjoint_kernel(DLevelSet L, int nt
     skip = fmaxf(ia - ob, oa - ib) > 0.5f * kPi + 1e-3f;
   }
   // Stage the chunk's output texels through LDS (direction and 1/Z; gradient
-  // and alpha); the loops below then reads them as
+  // and the GGX constant); the loops below then reads them as
   // broadcasts, four texels' reads issued together, instead of a chain of
   // dependent scalar loads per output texel.
   if (!skip) {
@@ -275,8 +279,12 @@ __global__ void __launch_bounds__(256) envmap_adjoint_kernel(DLevelSet L, int nt
     if (o < o_end) {
       const int l = level_of(L.first, o);
       const float* gg = L.g[l] + 3 * (o - L.first[l]);
-      sR[threadIdx.x] = out_dirs[o];
-      sG[threadIdx.x] = make_float4(gg[0], gg[1], gg[2], (float)(l * l) / 25.f);
+      // specular levels: k = (alpha^2 - 1)/2 in w, and alpha^2 / pi folded into 1/Z
+      const float alpha = (float)(l * l) / 25.f, a2 = alpha * alpha;
+      float4 R = out_dirs[o];
+      if (l < 6) R.w *= a2 * (1.f / kPi);
+      sR[threadIdx.x] = R;
+      sG[threadIdx.x] = make_float4(gg[0], gg[1], gg[2], 0.5f * (a2 - 1.f));
     }
   }
   __syncthreads();
@@ -290,7 +298,7 @@ __global__ void __launch_bounds__(256) envmap_adjoint_kernel(DLevelSet L, int nt
     for (int i = 0; i < i6; ++i) {
       const float4 R = sR[i], G = sG[i];
       const float c = fmaxf(R.x * dt.x + R.y * dt.y + R.z * dt.z, 0.f);
-      const float kk = ggx_weight(c, G.w) * dt.w * R.w;
+      const float kk = ggx_scaled(c, G.w) * dt.w * R.w;
       acc0 += G.x * kk;
       acc1 += G.y * kk;
       acc2 += G.z * kk;
