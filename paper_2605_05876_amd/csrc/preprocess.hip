@@ -43,8 +43,9 @@ __device__ inline void latlong_coords(const float d[3], int H, int W, LatLong& L
   float th = atan2f(rho, d[2]);
   float ph = atan2f(d[1], d[0]);
   if (ph < 0.f) ph += 2.f * kPi;
-  float a = th * ((float)H / kPi) - 0.5f;
-  float b = ph * ((float)W / (2.f * kPi)) - 0.5f;
+  // texel scales as products with constant reciprocals (no division per lookup)
+  float a = th * ((float)H * (1.f / kPi)) - 0.5f;
+  float b = ph * ((float)W * (0.5f / kPi)) - 0.5f;
   if (!(a == a)) a = 0.f;  // NaN direction: any in-range texel
   if (!(b == b)) b = 0.f;
   float a0 = floorf(a), b0 = floorf(b);
@@ -93,7 +94,8 @@ __device__ inline void shade_forward(const ViewDev& v, const Params& P, const fl
                                      float metal, float col[3]) {
   float wv[3] = {v.cam_o[0] - p[0], v.cam_o[1] - p[1], v.cam_o[2] - p[2]};
   float wl = sqrtf(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
-  float wo[3] = {wv[0] / wl, wv[1] / wl, wv[2] / wl};
+  const float iwl = 1.f / wl;
+  float wo[3] = {wv[0] * iwl, wv[1] * iwl, wv[2] * iwl};
   LatLong Li;
   latlong_coords(nh, v.lh[6], v.lw[6], Li);
   float Ld[3];
@@ -145,8 +147,8 @@ __device__ inline void tap_setup(const float d[3], int H, int W, Tap& T) {
   T.o11 = 3 * (L.r1 * W + L.c1);
   T.fa = L.fa;
   T.fb = L.fb;
-  T.hs = (float)H / kPi;
-  T.ws = (float)W / (2.f * kPi);
+  T.hs = (float)H * (1.f / kPi);
+  T.ws = (float)W * (0.5f / kPi);
   T.rho = L.rho;
   T.den = L.den;
 }
@@ -355,7 +357,8 @@ __device__ inline void shade_fetch(const LevelSet& LS, const float cam_o[3], con
   for (int c = 0; c < 3; ++c) S.nh[c] = in.n[c] / nn;
   const float wv[3] = {cam_o[0] - in.p[0], cam_o[1] - in.p[1], cam_o[2] - in.p[2]};
   S.wl = sqrtf(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
-  for (int c = 0; c < 3; ++c) S.wo[c] = wv[c] / S.wl;
+  const float iwl = 1.f / S.wl;
+  for (int c = 0; c < 3; ++c) S.wo[c] = wv[c] * iwl;
   S.nv = S.nh[0] * S.wo[0] + S.nh[1] * S.wo[1] + S.nh[2] * S.wo[2];
   for (int c = 0; c < 3; ++c) S.rd[c] = 2.f * S.nv * S.nh[c] - S.wo[c];
   const float rc = clamp01(in.rough);
