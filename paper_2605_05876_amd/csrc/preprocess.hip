@@ -177,10 +177,11 @@ __device__ inline void tap_adjoint(const Tap& T, const float t[12], const float 
   const float gth = ga * T.hs, gph = gb * T.ws;
   if (T.rho > 1e-20f && T.den > 0.f) {
     // th = atan2(rho, z), ph = atan2(y, x), rho = sqrt(x^2 + y^2)
-    const float dth_drho = d[2] / T.den, dth_dz = -T.rho / T.den;
-    const float r2 = T.rho * T.rho;
-    gd[0] += gth * dth_drho * d[0] / T.rho - gph * d[1] / r2;
-    gd[1] += gth * dth_drho * d[1] / T.rho + gph * d[0] / r2;
+    const float iden = 1.f / T.den, irho = 1.f / T.rho;
+    const float dth_drho = d[2] * iden, dth_dz = -T.rho * iden;
+    const float a = gth * dth_drho * irho, b = gph * irho * irho;
+    gd[0] += a * d[0] - b * d[1];
+    gd[1] += a * d[1] + b * d[0];
     gd[2] += gth * dth_dz;
   }
 }
