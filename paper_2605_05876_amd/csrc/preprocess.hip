@@ -469,7 +469,8 @@ __device__ inline void shade_adjoint(const Params& P, const ShadeSt& S, ShadeOut
   }
   if (S.rough >= 0.f && S.rough <= 1.f) O.grough += g_rc;
   const float wg = S.wo[0] * gwo[0] + S.wo[1] * gwo[1] + S.wo[2] * gwo[2];
-  for (int i = 0; i < 3; ++i) O.gp[i] -= (gwo[i] - S.wo[i] * wg) / S.wl;
+  const float iwl = 1.f / S.wl;
+  for (int i = 0; i < 3; ++i) O.gp[i] -= (gwo[i] - S.wo[i] * wg) * iwl;
 }
 
 // Called by every lane of the wave (the global maps are written cooperatively);
@@ -779,13 +780,14 @@ __global__ void __launch_bounds__(256) geometry_backward_kernel(
     const float detB = g.detB, dm = o.dm;
     const float gQxx = gr[G_QXX], gQxy = 2.f * gr[G_QXY2], gQyy = gr[G_QYY];
     const float gnf = gr[G_NF], ga3 = gr[G_A3], gb3 = gr[G_B3];
-    float gdetB = -(gQxx * g.Qxx + gQxy * g.Qxy + gQyy * g.Qyy) / detB;
+    const float ib = 1.f / detB;  // one reciprocal per denominator, then products
+    float gdetB = -(gQxx * g.Qxx + gQxy * g.Qxy + gQyy * g.Qyy) * ib;
     float gdetA = 0.f;
     if (g.nf > 0.f) {
-      gdetB += -gnf * g.nf / (2.f * detB);
-      gdetA += gnf / (2.f * g.nf * detB);
+      gdetB += -gnf * g.nf * (0.5f * ib);
+      gdetA += gnf * (0.5f * ib) / g.nf;
     }
-    float gK22 = gQxx / detB, gK12 = -gQxy / detB, gK11 = gQyy / detB;
+    float gK22 = gQxx * ib, gK12 = -gQxy * ib, gK11 = gQyy * ib;
     gdetA += gdetB;
     const float gtrA = sig * gdetB;
     gK11 += gtrA;
@@ -840,7 +842,8 @@ __global__ void __launch_bounds__(256) geometry_backward_kernel(
     // u_hat = g / |g|
     float ug = o.uh[0] * guh[0] + o.uh[1] * guh[1] + o.uh[2] * guh[2];
     float gg[3];
-    for (int j = 0; j < 3; ++j) gg[j] = (guh[j] - o.uh[j] * ug) / o.gn;
+    const float ign = 1.f / o.gn;
+    for (int j = 0; j < 3; ++j) gg[j] = (guh[j] - o.uh[j] * ug) * ign;
     // g = t - (t.n_hat) n_hat
     float ngg = o.nh[0] * gg[0] + o.nh[1] * gg[1] + o.nh[2] * gg[2];
     for (int j = 0; j < 3; ++j) {
@@ -849,7 +852,8 @@ __global__ void __launch_bounds__(256) geometry_backward_kernel(
     }
     // n_hat = n / |n|
     float ng = o.nh[0] * gnh[0] + o.nh[1] * gnh[1] + o.nh[2] * gnh[2];
-    for (int j = 0; j < 3; ++j) gn[j] += (gnh[j] - o.nh[j] * ng) / o.nn;
+    const float inn = 1.f / o.nn;
+    for (int j = 0; j < 3; ++j) gn[j] += (gnh[j] - o.nh[j] * ng) * inn;
   }
   if (ss_out) ss_out[s] = ss_sum;
   if (vis_out) vis_out[s] = n_vis;
