@@ -215,10 +215,11 @@ __device__ __forceinline__ void frag_eval_pp(const float* rec, int px, int py, f
   f.N = s2 * (S22 * f.dx * f.dx - 2.f * S12 * f.dx * f.dy + S11 * f.dy * f.dy);
   const bool in_rect = px >= il && px <= ih && py >= jl && py <= jh;
   f.cov = in_rect && f.s > 0.f && detS > 0.f && f.N < r2 * detS;
-  f.q = f.N / detS;
+  const float idetS = 1.f / detS;  // one division for both uses
+  f.q = f.N * idetS;
   const float nfc = rec[R_NF];
   f.e = __expf(-0.5f * f.q);
-  f.w = sqrtf(s2 * s2 * s2 * nfc * nfc * iq / detS) * f.e;
+  f.w = sqrtf(s2 * s2 * s2 * nfc * nfc * iq * idetS) * f.e;
 }
 
 __device__ __forceinline__ int view_of_tile(const ViewDev* views, int nv, int tile) {
