@@ -9,6 +9,7 @@ Functions follow the paper section by section (see oracle.cpp):
   * `envmap_adjoint`    -- transpose of that linear map
   * `brdf_lut`          -- split-sum (beta1, beta2) table (eq:ibl)
   * `bin_f32`           -- FP32 cull / depth key / tile rectangle (Sec. 3.2.1, App. A.1)
+  * `records`           -- FP64 per-surfel quantities, FP64 cull rule and FP32 binning
   * `sorted_pairs`      -- reference tile lists sorted by (tile, z_start, record)
   * `render`            -- brute-force forward per pixel (Sec. 3.1-3.5, Alg. 1)
   * `render_jvp`        -- exact directional derivative (dual numbers)
@@ -51,7 +52,8 @@ def lib():
         L.orc_brdf_lut.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.orc_bin_f32.argtypes = [fpp, ctypes.c_int, dp, dp, ip, ctypes.POINTER(ctypes.c_uint32), ip, ip]
         L.orc_render.argtypes = [fpp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp,
-                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, dp, dp, ip, dp, dp]
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, dp, dp, ip, dp, dp, ip, dp]
+        L.orc_records.argtypes = [fpp, ctypes.c_int, dp, dp, dp]
         L.orc_render_jvp.argtypes = [fpp, ctypes.c_int, fpp, dp, dp, dp, dp, ctypes.c_int, ctypes.c_int,
                                      dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, dp, dp, dp]
         L.orc_render_grad.argtypes = [fpp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp,
@@ -214,7 +216,11 @@ def _maps_lut(maps, lut, He, We):
 
 def render(scene, cam, opt: Options, pix, maps=None, lut=None, env_hw=(0, 0)):
     """Forward at the listed pixels pix [K][2] (integer x, y); `cons` is the
-    per-pixel depth-consolidation term of eq:cons_loss."""
+    per-pixel depth-consolidation term of eq:cons_loss; `viol` the covering
+    fragments (FP64 decisions) that the FP32 binning misses (culled surfel, or
+    pixel outside its rectangle); `pp_drop`, `pp_drop_w` the count and weight sum
+    of the fragments the per-pixel MIP filter would accept outside that
+    rectangle (mip = "pixel" only)."""
     P = _Params(scene)
     pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 2)
     k = pix.shape[0]
@@ -227,12 +233,32 @@ def render(scene, cam, opt: Options, pix, maps=None, lut=None, env_hw=(0, 0)):
     viol = np.zeros(k, np.int32)
     cons = np.zeros(k, np.float64)
     depth = np.zeros(k, np.float64)
+    drop = np.zeros(k, np.int32)
+    drop_w = np.zeros(k, np.float64)
     c, o = pack_camera(cam), opt.pack()
     lib().orc_render(P.pp, P.n, _dptr(c), _dptr(o), _dptr(maps), He, We, _dptr(lut),
                      lut.shape[1], lut.shape[0], k, _iptr(pix), _dptr(img), _dptr(alpha),
-                     _iptr(nl), _dptr(cm), _dptr(gm), _iptr(viol), _dptr(cons), _dptr(depth))
+                     _iptr(nl), _dptr(cm), _dptr(gm), _iptr(viol), _dptr(cons), _dptr(depth), _iptr(drop),
+                     _dptr(drop_w))
     return dict(image=img, alpha=alpha, n_layers=nl, cut_margin=cm, gap_margin=gm, viol=viol, cons=cons,
-                depth=depth)
+                depth=depth, pp_drop=drop, pp_drop_w=drop_w)
+
+
+def records(scene, cam, opt: Options) -> dict:
+    """Per-surfel FP64 quantities of one view: T rows, depth interval, the MIP
+    filter (Sigma_mip^{-1}, Sigma_mip, n_f), the FP64 cull (keep64, margin =
+    (minimum depth over the acceptance ellipse - znear) / c'_z) and the FP32
+    binning (keep32, inclusive pixel rectangle il, ih, jl, jh, and stage32: 0-2
+    culled (centre not beyond znear, degenerate projection, ellipse not entirely
+    beyond znear), 3 empty rectangle, 4 kept)."""
+    P = _Params(scene)
+    out = np.zeros((P.n, 26), np.float64)
+    c, o = pack_camera(cam), opt.pack()
+    lib().orc_records(P.pp, P.n, _dptr(c), _dptr(o), _dptr(out))
+    return dict(T1=out[:, 0:3], T2=out[:, 3:6], T4=out[:, 6:9], zs=out[:, 9], ze=out[:, 10],
+                sinv=out[:, 11:14], sig=out[:, 14:17], nf=out[:, 17], keep64=out[:, 18] > 0,
+                margin=out[:, 19], keep32=out[:, 20] > 0, rect=out[:, 21:25].astype(np.int64),
+                stage32=out[:, 25].astype(np.int64))
 
 
 def render_jvp(scene, cam, opt: Options, pix, direction: dict, maps=None, dmaps=None,

@@ -79,6 +79,7 @@ template <class S> struct Rec {
   S T1[3], T2[3], T4[3];
   S zs, ze;
   S sinv[3];  // Sigma_mip^{-1}: uu, uv, vv
+  S sig[3];   // Sigma_mip itself: uu, uv, vv
   S nf;
   S col[3];
   int rect[4] = {0, -1, 0, -1};  // FP32 binning pixel rectangle il, ih, jl, jh
@@ -374,6 +375,9 @@ static void mip_filter(Rec<S>& r, double sigma_f) {
   S s12 = sigma_f * (J11 * J21 + J12 * J22);
   S s22 = 1.0 + sigma_f * (J21 * J21 + J22 * J22);
   S dets = s11 * s22 - s12 * s12;
+  r.sig[0] = s11;
+  r.sig[1] = s12;
+  r.sig[2] = s22;
   r.sinv[0] = s22 / dets;
   r.sinv[1] = -s12 / dets;
   r.sinv[2] = s11 / dets;
@@ -468,6 +472,11 @@ static void preprocess(const Surf<S>& s, const Cam& cam, const Opt& o, const M& 
 // contraction, IEEE division and square root, sums left to right).  Outputs:
 // keep flag, z_start bits, inclusive tile rectangle, pixel rectangle.
 struct BinOut {
+  // stage reached: 0 culled (centre not beyond znear), 1 culled (degenerate
+  // projection, det A = 0), 2 culled (acceptance ellipse not entirely beyond
+  // znear), 3 empty pixel rectangle (off screen or between pixel centres),
+  // 4 kept
+  int stage;
   int keep;
   float zs;
   int tx0, ty0, tx1, ty1;  // inclusive tile rectangle (empty: keep = 0)
@@ -478,7 +487,7 @@ template <class S> static void set_rect(Rec<S>& r, const BinOut& b) {
 }
 
 static BinOut bin_f32(const float* const* P, int n, int i, const Cam& cd, const Opt& od) {
-  BinOut b{0, 0.f, 0, 0, -1, -1, 0, -1, 0, -1};
+  BinOut b{0, 0, 0.f, 0, 0, -1, -1, 0, -1, 0, -1};
   const float nx = P[1][i], ny = P[1][n + i], nz = P[1][2 * n + i];
   const float tx = P[2][i], ty = P[2][n + i], tz = P[2][2 * n + i];
   const float su = P[3][i], sv = P[3][n + i];
@@ -510,6 +519,7 @@ static BinOut bin_f32(const float* const* P, int n, int i, const Cam& cd, const 
   float ez = rcut * std::sqrt(upz * upz + vpz * vpz);
   b.zs = z - ez;
   if (!(z > znear)) return b;
+  b.stage = 1;
   float mx = cpx / z, my = cpy / z;
   float x0 = fx * mx + cx, y0 = fy * my + cy;
   float M11 = (fx * (upx - mx * upz)) / z, M12 = (fx * (vpx - mx * vpz)) / z;
@@ -518,6 +528,7 @@ static BinOut bin_f32(const float* const* P, int n, int i, const Cam& cd, const 
   float dm = M11 * M22 - M12 * M21;
   float detA = dm * dm;
   if (!(detA > 0.f)) return b;
+  b.stage = 2;
   float a = M11 * M11 + M21 * M21, bb = M11 * M12 + M21 * M22, c = M12 * M12 + M22 * M22;
   float S11 = detA + sigma * c, S12 = -(sigma * bb), S22 = detA + sigma * a;
   float Sg1 = S11 * g1 + S12 * g2, Sg2 = S12 * g1 + S22 * g2;
@@ -525,6 +536,7 @@ static BinOut bin_f32(const float* const* P, int n, int i, const Cam& cd, const 
   float r2 = rcut * rcut;
   float kz = 1.f - znear / z;
   if (!(r2 * gSg < detA * (kz * kz))) return b;
+  b.stage = 3;
   float den = detA - r2 * gSg;
   float SM1x = S11 * M11 + S12 * M12, SM1y = S12 * M11 + S22 * M12;
   float M1SM1 = M11 * SM1x + M12 * SM1y, M1Sg = M11 * Sg1 + M12 * Sg2;
@@ -542,11 +554,40 @@ static BinOut bin_f32(const float* const* P, int n, int i, const Cam& cd, const 
   il = std::max(il, 0.f); ih = std::min(ih, (float)(cd.W - 1));
   jl = std::max(jl, 0.f); jh = std::min(jh, (float)(cd.H - 1));
   if (!(il <= ih) || !(jl <= jh)) return b;
+  b.stage = 4;
   b.keep = 1;
   b.il = (int)il; b.ih = (int)ih; b.jl = (int)jl; b.jh = (int)jh;
   b.tx0 = (int)il / od.tile_w; b.tx1 = (int)ih / od.tile_w;
   b.ty0 = (int)jl / od.tile_h; b.ty1 = (int)jh / od.tile_h;
   return b;
+}
+
+// ------------------------------------------------------------ FP64 cull
+// The cull rule (the bounding-rectangle reading of App. A.1): a surfel is kept
+// when its whole MIP acceptance ellipse {u^T Sigma_mip^{-1} u < r_cut^2} lies
+// beyond the near plane, i.e. its projection is a bounded ellipse.  The
+// camera-space depth is linear along the surfel plane,
+// z(u, v) = c'_z + u t'_uz + v t'_vz, so its minimum over the ellipse is
+// c'_z - r_cut sqrt(t_z^T Sigma_mip t_z) with t_z = (t'_uz, t'_vz) (the support
+// function of an ellipse).  Evaluated in FP64 from the oracle's own T rows and
+// filter, independently of the FP32 binning decision.
+// margin: (minimum depth - znear) / c'_z.
+template <class S>
+static bool cull_keep64(const Rec<S>& r, double znear, double rcut, double* margin) {
+  const double z = val(r.T4[2]);
+  if (!(z > znear)) {
+    *margin = (z - znear) / std::max(std::fabs(z), 1e-300);
+    return false;
+  }
+  const double a = val(r.T4[0]), b = val(r.T4[1]);
+  const double q = a * a * val(r.sig[0]) + 2.0 * a * b * val(r.sig[1]) + b * b * val(r.sig[2]);
+  const double zmin = z - rcut * std::sqrt(q);
+  if (!std::isfinite(zmin)) {
+    *margin = -INFINITY;
+    return false;
+  }
+  *margin = (zmin - znear) / z;
+  return zmin > znear;
 }
 
 // ------------------------------------------------------------ per pixel
@@ -560,7 +601,9 @@ template <class S> struct Frag { double zs; int idx; S w; S ze; const Rec<S>* r;
 // depth: the composited layer depth sum_k T_k alpha_k z_k (alpha-weighted; the
 // background contributes nothing).
 template <class S> struct PixOut { S img[3]; S alpha; S cons; S depth; int nl; };
-struct PixDiag { double cut_margin, gap_margin; int viol; };
+// Fragments the per-pixel MIP filter accepts outside its support rectangle.
+struct Dropped { int n = 0; double w = 0.0; };
+struct PixDiag { double cut_margin = INFINITY, gap_margin = INFINITY; Dropped pp_drop; };
 
 // zf (nullable): camera-space depth of the ray-surfel intersection,
 // T4 . (u, v, 1) = c'_z + u t'_uz + v t'_vz.
@@ -595,15 +638,19 @@ static S frag_weight(const Rec<S>& r, double x, double y, double rc2, bool& hit,
 // Sigma_mip = I + sigma_f J J^T, q = u^T Sigma_mip^{-1} u, n_f = |Sigma_mip|^{-1/2}.
 // Reading: the support stays the FP32 binning rectangle of the centre filter
 // (the variant runs inside the same binning) intersected with q < r_cut^2.
+// dropped (nullable): counts (and sums the weights of) the fragments the
+// per-pixel filter accepts (q < r_cut^2) at pixels outside that rectangle, i.e.
+// the fragments this support reading removes.
 template <class S>
 static S frag_weight_pp(const Rec<S>& r, double x, double y, double rc2, double sigma_f, bool& hit,
-                        double& q_val, S* zf = nullptr) {
+                        double& q_val, S* zf = nullptr, Dropped* dropped = nullptr) {
   using std::sqrt;
   using std::exp;
   hit = false;
   q_val = INFINITY;
   const int px = (int)std::floor(x), py = (int)std::floor(y);
-  if (px < r.rect[0] || px > r.rect[1] || py < r.rect[2] || py > r.rect[3]) return S(0.0);
+  const bool in_rect = !(px < r.rect[0] || px > r.rect[1] || py < r.rect[2] || py > r.rect[3]);
+  if (!in_rect && !dropped) return S(0.0);
   S k[3], l[3];
   for (int i = 0; i < 3; ++i) { k[i] = x * r.T4[i] - r.T1[i]; l[i] = y * r.T4[i] - r.T2[i]; }
   S p1 = k[1] * l[2] - k[2] * l[1];
@@ -626,6 +673,13 @@ static S frag_weight_pp(const Rec<S>& r, double x, double y, double rc2, double 
   S s22 = 1.0 + sigma_f * (Jvx * Jvx + Jvy * Jvy);
   S det = s11 * s22 - s12 * s12;
   S q = (s22 * u * u - 2.0 * s12 * u * v + s11 * v * v) / det;
+  if (!in_rect) {
+    if (val(q) < rc2) {
+      ++dropped->n;
+      dropped->w += std::sqrt(1.0 / val(det)) * std::exp(-0.5 * val(q));
+    }
+    return S(0.0);
+  }
   q_val = val(q);
   if (!(q_val < rc2)) return S(0.0);
   hit = true;
@@ -646,7 +700,7 @@ static void pixel_eval(double x, double y, const Rec<S>* recs, const std::vector
     bool hit;
     double q;
     S z(0.0);
-    S w = o.mip == 1 ? frag_weight_pp(recs[i], x, y, rc2, o.sigma_f, hit, q, &z)
+    S w = o.mip == 1 ? frag_weight_pp(recs[i], x, y, rc2, o.sigma_f, hit, q, &z, dg ? &dg->pp_drop : nullptr)
                      : frag_weight(recs[i], x, y, rc2, hit, q, &z);
     if (std::isfinite(q)) cm = std::min(cm, std::fabs(q - rc2) / rc2);
     if (!hit) continue;
@@ -747,6 +801,42 @@ static Surf<S> load_surf(const float* const* P, int n, int i, const double* cons
   return s;
 }
 
+// Per-surfel quantities of one view: FP64 records of every surfel, the FP32
+// binning decision (kept for the comparison with the GPU binning and for the
+// support of the per-pixel MIP variant), the FP64 cull (keep) and the candidate
+// list = the surfels the FP64 cull keeps.  The FP32 decision does not choose
+// the candidates: a covering fragment of a surfel that it culls, or outside its
+// FP32 pixel rectangle, is a bounding-rectangle violation.
+template <class S, class M>
+static void prepare(const float* const* P, int n, const double* const* V, const Cam& c, const Opt& o,
+                    const M& maps, const MapDims* md, const Lut* L, std::vector<Rec<S>>& recs,
+                    std::vector<BinOut>& bins, std::vector<int>& keep, std::vector<int>& cand,
+                    std::vector<double>* margin = nullptr) {
+  recs.assign(n, Rec<S>());
+  bins.assign(n, BinOut{0, 0, 0.f, 0, 0, -1, -1, 0, -1, 0, -1});
+  keep.assign(n, 0);
+  if (margin) margin->assign(n, 0.0);
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < n; ++i) {
+    bins[i] = bin_f32(P, n, i, c, o);
+    Surf<S> s = load_surf<S>(P, n, i, V);
+    preprocess(s, c, o, maps, md, L, recs[i]);
+    set_rect(recs[i], bins[i]);
+    double m = 0.0;
+    keep[i] = cull_keep64(recs[i], c.znear, o.r_cut, &m) ? 1 : 0;
+    if (margin) (*margin)[i] = m;
+  }
+  cand.clear();
+  for (int i = 0; i < n; ++i)
+    if (keep[i]) cand.push_back(i);
+}
+
+// Is pixel (px, py) outside the FP32 binning of surfel i (culled, or outside
+// its inclusive pixel rectangle)?
+static bool outside_bin(const BinOut& b, int px, int py) {
+  return !b.keep || px < b.il || px > b.ih || py < b.jl || py > b.jh;
+}
+
 }  // namespace orc
 
 using namespace orc;
@@ -801,25 +891,17 @@ int orc_bin_f32(const float* const* P, int n, const double* cam, const double* o
 int orc_render(const float* const* P, int n, const double* cam, const double* opt,
                const double* maps, int He, int We, const double* lut, int n_nv, int n_r,
                int npix, const int* pix, double* img, double* alpha, int* nl,
-               double* cut_margin, double* gap_margin, int* viol, double* cons, double* depth) {
+               double* cut_margin, double* gap_margin, int* viol, double* cons, double* depth,
+               int* pp_drop, double* pp_drop_w) {
   Cam c = unpack_cam(cam);
   Opt o = unpack_opt(opt);
-  std::vector<Rec<double>> recs(n);
-  std::vector<BinOut> bins(n);
-  std::vector<int> cand;
+  std::vector<Rec<double>> recs;
+  std::vector<BinOut> bins;
+  std::vector<int> keep, cand;
   MapDims md(std::max(He, 4), std::max(We, 8));
   Lut L{lut, n_nv, n_r};
   MapsD M{maps};
-#pragma omp parallel for schedule(static)
-  for (int i = 0; i < n; ++i) {
-    bins[i] = bin_f32(P, n, i, c, o);
-    if (!bins[i].keep) continue;
-    Surf<double> s = load_surf<double>(P, n, i, nullptr);
-    preprocess(s, c, o, M, &md, &L, recs[i]);
-    set_rect(recs[i], bins[i]);
-  }
-  for (int i = 0; i < n; ++i)
-    if (bins[i].keep) cand.push_back(i);
+  prepare(P, n, nullptr, c, o, M, &md, &L, recs, bins, keep, cand);
 #pragma omp parallel for schedule(dynamic, 4)
   for (int k = 0; k < npix; ++k) {
     int px = pix[2 * k], py = pix[2 * k + 1];
@@ -828,11 +910,8 @@ int orc_render(const float* const* P, int n, const double* cam, const double* op
     std::vector<int> cov;
     pixel_eval(px + 0.5, py + 0.5, recs.data(), cand, c, o, out, &dg, &cov);
     int v = 0;
-    for (int i : cov) {
-      const BinOut& b = bins[i];
-      int tx = px / o.tile_w, ty = py / o.tile_h;
-      if (tx < b.tx0 || tx > b.tx1 || ty < b.ty0 || ty > b.ty1) ++v;
-    }
+    for (int i : cov)
+      if (outside_bin(bins[i], px, py)) ++v;
     for (int ch = 0; ch < 3; ++ch) img[3 * k + ch] = out.img[ch];
     alpha[k] = out.alpha;
     nl[k] = out.nl;
@@ -841,6 +920,8 @@ int orc_render(const float* const* P, int n, const double* cam, const double* op
     viol[k] = v;
     if (cons) cons[k] = out.cons;
     if (depth) depth[k] = out.depth;
+    if (pp_drop) pp_drop[k] = dg.pp_drop.n;
+    if (pp_drop_w) pp_drop_w[k] = dg.pp_drop.w;
   }
   return 0;
 }
@@ -856,22 +937,13 @@ int orc_render_jvp(const float* const* P, int n, const double* const* V, const d
                    double* depth_dot) {
   Cam c = unpack_cam(cam);
   Opt o = unpack_opt(opt);
-  std::vector<Rec<Dual>> recs(n);
-  std::vector<int> keep(n), cand;
+  std::vector<Rec<Dual>> recs;
+  std::vector<BinOut> bins;
+  std::vector<int> keep, cand;
   MapDims md(std::max(He, 4), std::max(We, 8));
   Lut L{lut, n_nv, n_r};
   MapsDual M{maps, dmaps};
-#pragma omp parallel for schedule(static)
-  for (int i = 0; i < n; ++i) {
-    const BinOut bo = bin_f32(P, n, i, c, o);
-    keep[i] = bo.keep;
-    if (!keep[i]) continue;
-    Surf<Dual> s = load_surf<Dual>(P, n, i, V);
-    preprocess(s, c, o, M, &md, &L, recs[i]);
-    set_rect(recs[i], bo);
-  }
-  for (int i = 0; i < n; ++i)
-    if (keep[i]) cand.push_back(i);
+  prepare(P, n, V, c, o, M, &md, &L, recs, bins, keep, cand);
 #pragma omp parallel for schedule(dynamic, 4)
   for (int k = 0; k < npix; ++k) {
     PixOut<Dual> out;
@@ -896,8 +968,9 @@ int orc_render_grad(const float* const* P, int n, const double* cam, const doubl
                     double* const* dP, double* dmaps, const double* dcons, const double* ddepth) {
   Cam c = unpack_cam(cam);
   Opt o = unpack_opt(opt);
-  std::vector<Rec<double>> recs(n);
-  std::vector<int> keep(n), cand;
+  std::vector<Rec<double>> recs;
+  std::vector<BinOut> bins;
+  std::vector<int> keep, cand;
   MapDims md(std::max(He, 4), std::max(We, 8));
   Lut L{lut, n_nv, n_r};
   MapsD Md{maps};
@@ -905,17 +978,7 @@ int orc_render_grad(const float* const* P, int n, const double* cam, const doubl
   for (int a = 0; a < 7; ++a)
     if (dP[a]) std::fill(dP[a], dP[a] + (size_t)csz[a] * n, 0.0);
   if (dmaps && He > 0) std::fill(dmaps, dmaps + md.total(), 0.0);
-#pragma omp parallel for schedule(static)
-  for (int i = 0; i < n; ++i) {
-    const BinOut bo = bin_f32(P, n, i, c, o);
-    keep[i] = bo.keep;
-    if (!keep[i]) continue;
-    Surf<double> s = load_surf<double>(P, n, i, nullptr);
-    preprocess(s, c, o, Md, &md, &L, recs[i]);
-    set_rect(recs[i], bo);
-  }
-  for (int i = 0; i < n; ++i)
-    if (keep[i]) cand.push_back(i);
+  prepare(P, n, nullptr, c, o, Md, &md, &L, recs, bins, keep, cand);
   // adjoint of each record: T1, T2, T4 (9), zs, ze (no gradient), sinv (3), nf, col (3)
   const int NR = 16;
   std::vector<double> drec((size_t)n * NR, 0.0);
@@ -1045,25 +1108,19 @@ int orc_screen_grad(const float* const* P, int n, const double* cam, const doubl
                     double* abs_sum, double* vec_sum, int* visible, const double* dcons) {
   Cam c = unpack_cam(cam);
   Opt o = unpack_opt(opt);
-  std::vector<Rec<double>> recs(n);
-  std::vector<int> keep(n), cand;
+  std::vector<Rec<double>> recs;
+  std::vector<BinOut> bins;
+  std::vector<int> keep, cand;
   MapDims md(std::max(He, 4), std::max(We, 8));
   Lut L{lut, n_nv, n_r};
   MapsD Md{maps};
-#pragma omp parallel for schedule(static)
+  prepare(P, n, nullptr, c, o, Md, &md, &L, recs, bins, keep, cand);
   for (int i = 0; i < n; ++i) {
-    const BinOut bo = bin_f32(P, n, i, c, o);
-    keep[i] = bo.keep;
-    if (!keep[i]) continue;
-    Surf<double> s = load_surf<double>(P, n, i, nullptr);
-    preprocess(s, c, o, Md, &md, &L, recs[i]);
-    set_rect(recs[i], bo);
-  }
-  for (int i = 0; i < n; ++i) {
-    if (keep[i]) cand.push_back(i);
     abs_sum[i] = 0.0;
     if (vec_sum) vec_sum[i] = vec_sum[(size_t)n + i] = 0.0;
-    if (visible) visible[i] = keep[i];
+    // the views a surfel "contributed" to: the binning decision (cull and a
+    // non-empty rectangle)
+    if (visible) visible[i] = bins[i].keep;
   }
 #pragma omp parallel
   {
@@ -1128,19 +1185,13 @@ int orc_pixel_fragments(const float* const* P, int n, const double* cam, const d
                         int* layer) {
   Cam c = unpack_cam(cam);
   Opt o = unpack_opt(opt);
-  std::vector<Rec<double>> recs(n);
-  std::vector<int> cand;
+  std::vector<Rec<double>> recs;
+  std::vector<BinOut> bins;
+  std::vector<int> keep, cand;
   MapDims md(std::max(He, 4), std::max(We, 8));
   Lut L{lut, n_nv, n_r};
   MapsD M{maps};
-  for (int i = 0; i < n; ++i) {
-    const BinOut bo = bin_f32(P, n, i, c, o);
-    if (!bo.keep) continue;
-    Surf<double> s = load_surf<double>(P, n, i, nullptr);
-    preprocess(s, c, o, M, &md, &L, recs[i]);
-    set_rect(recs[i], bo);
-    cand.push_back(i);
-  }
+  prepare(P, n, nullptr, c, o, M, &md, &L, recs, bins, keep, cand);
   PixOut<double> out;
   std::vector<int> cov, lay;
   std::vector<double> ws;
@@ -1153,6 +1204,40 @@ int orc_pixel_fragments(const float* const* P, int n, const double* cam, const d
     layer[j] = lay[j];
   }
   return (int)cov.size();
+}
+
+// Per-surfel records of one view (test access): 26 doubles per surfel:
+// T1 (3), T2 (3), T4 (3), z_start, z_end, Sigma_mip^{-1} (3), Sigma_mip (3), n_f,
+// FP64 keep, FP64 cull margin (see cull_keep64), FP32 keep, FP32 pixel
+// rectangle il, ih, jl, jh, FP32 binning stage (see BinOut).
+int orc_records(const float* const* P, int n, const double* cam, const double* opt, double* out) {
+  Cam c = unpack_cam(cam);
+  Opt o = unpack_opt(opt);
+  std::vector<Rec<double>> recs;
+  std::vector<BinOut> bins;
+  std::vector<int> keep, cand;
+  std::vector<double> margin;
+  MapDims md(4, 8);
+  std::vector<double> zero_maps(md.total(), 0.0), zero_lut(8, 0.0);
+  Lut L{zero_lut.data(), 2, 2};
+  MapsD M{zero_maps.data()};
+  Opt oa = o;
+  oa.shade = 0;  // geometry only
+  prepare(P, n, nullptr, c, oa, M, &md, &L, recs, bins, keep, cand, &margin);
+  for (int i = 0; i < n; ++i) {
+    double* d = out + (size_t)i * 26;
+    const Rec<double>& r = recs[i];
+    for (int a = 0; a < 3; ++a) { d[a] = r.T1[a]; d[3 + a] = r.T2[a]; d[6 + a] = r.T4[a]; }
+    d[9] = r.zs; d[10] = r.ze;
+    for (int a = 0; a < 3; ++a) { d[11 + a] = r.sinv[a]; d[14 + a] = r.sig[a]; }
+    d[17] = r.nf;
+    d[18] = keep[i];
+    d[19] = margin[i];
+    d[20] = bins[i].keep;
+    d[21] = bins[i].il; d[22] = bins[i].ih; d[23] = bins[i].jl; d[24] = bins[i].jh;
+    d[25] = bins[i].stage;
+  }
+  return 0;
 }
 
 }  // extern "C"

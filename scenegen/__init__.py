@@ -26,7 +26,9 @@ import numpy as np
 __all__ = [
     "Scene", "Camera", "Workload", "look_at_camera", "fibonacci_directions",
     "sphere_scene", "torus_scene", "superquadric_scene", "clustered_sphere_scene",
-    "lognormal_envmap", "make_config", "CONFIG_NAMES", "plane_scene",
+    "lognormal_envmap", "make_config", "CONFIG_NAMES", "plane_scene", "near_plane_workload",
+    "tie_planes_workload", "two_spheres_workload", "occluded_planes_workload", "thin_shell_workload",
+    "concat_scenes",
 ]
 
 
@@ -389,6 +391,144 @@ def checkerboard_workload(n_side: int = 2000, extent: float = 10.0, square: floa
     sc.albedo = _f32(np.tile(white.astype(np.float64), (3, 1)))
     cam = look_at_camera(eye, width, height, target=target)
     return Workload("checkerboard", [sc], [cam], "albedo")
+
+
+def concat_scenes(*scenes: Scene) -> Scene:
+    """One scene holding the surfels of several (in order); the envmap of the first."""
+    cat = lambda k: _f32(np.concatenate([np.asarray(getattr(s, k)) for s in scenes], axis=-1))
+    return Scene(cat("position"), cat("normal"), cat("tangent"), cat("scale"), cat("albedo"),
+                 cat("roughness"), cat("metallic"), scenes[0].envmap)
+
+
+def _axis_camera(width, height, f, znear=0.01, background=(0.0, 0.0, 0.0), eye=(0.0, 0.0, 0.0)):
+    """Pinhole camera at `eye` looking down +z (R = I)."""
+    R = np.eye(3)
+    return Camera(width, height, float(f), float(f), width / 2.0, height / 2.0, _f32(R),
+                  _f32(-np.asarray(eye, np.float64)), znear, tuple(background), 0)
+
+
+def near_plane_workload(seed: int = 61, n: int = 3000, width: int = 96, height: int = 80,
+                        f: float = 80.0, znear: float = 0.25) -> Workload:
+    """Surfels close to the camera: centres at depths U[0.6 znear, 6 znear] and
+    lateral positions up to 1.3x the half field of view, random orientations and
+    lognormal(ln 0.04, 0.5) scales, so that many straddle the near plane, lie
+    partly behind the camera or cross the image border.  SVBRDF and a 16 x 32
+    environment; camera at the origin looking down +z with the given znear."""
+    r_pos, r_nrm, r_ang, r_scl, r_mat, r_env = _rngs(seed, 6)
+    z = r_pos.uniform(0.6 * znear, 6.0 * znear, n)
+    hx, hy = 1.3 * (width / 2.0) / f, 1.3 * (height / 2.0) / f
+    x = r_pos.uniform(-hx, hx, n) * z
+    y = r_pos.uniform(-hy, hy, n) * z
+    nrm = r_nrm.normal(size=(3, n))
+    nrm /= np.linalg.norm(nrm, axis=0)
+    tan = _inplane_tangent(nrm, r_ang.uniform(0, math.pi, n))
+    scl = np.exp(r_scl.normal(math.log(0.04), 0.5, size=(2, n)))
+    alb, rough, metal = _svbrdf(r_mat, n)
+    sc = Scene(_f32(np.stack([x, y, z])), _f32(nrm), _f32(tan), _f32(scl), _f32(alb), _f32(rough), _f32(metal))
+    sc.envmap = lognormal_envmap(seed, 16, 32)
+    cam = _axis_camera(width, height, f, znear=znear, background=(0.1, 0.2, 0.3))
+    return Workload("near_plane", [sc], [cam], "splitsum")
+
+
+def tie_planes_workload(width: int = 80, height: int = 64, f: float = 90.0, spacing: float = 0.03,
+                        scale: float = 0.03, z: float = 2.0, gap: float = 0.5) -> Workload:
+    """Adversarial ties of the depth sort: camera at the origin looking down +z at
+    fronto-parallel surfels (normal -z, tangent +x), whose depth intervals have
+    zero extent, so every surfel of a plane has exactly the same z_start.  Two
+    interleaved lattices (red, and blue offset by half a spacing) share the plane
+    z; a green lattice at z + gap lies behind them."""
+    def lat(off, zz, col, half):
+        g = (np.arange(-half, half + 1)) * spacing + off
+        X, Y = np.meshgrid(g, g, indexing="ij")
+        k = X.size
+        pos = np.stack([X.ravel() * zz / z, Y.ravel() * zz / z, np.full(k, zz)])
+        nrm = np.tile(np.array([[0.0], [0.0], [-1.0]]), (1, k))
+        tan = np.tile(np.array([[1.0], [0.0], [0.0]]), (1, k))
+        alb = np.tile(np.asarray(col, np.float64)[:, None], (1, k))
+        return Scene(_f32(pos), _f32(nrm), _f32(tan), _f32(np.full((2, k), scale * zz / z)), _f32(alb),
+                     _f32(np.full(k, 0.5)), _f32(np.zeros(k)))
+    half = int(0.55 * width / f * z / spacing) + 1
+    sc = concat_scenes(lat(0.0, z, (1.0, 0.1, 0.1), half), lat(0.5 * spacing, z, (0.1, 0.1, 1.0), half),
+                       lat(0.25 * spacing, z + gap, (0.1, 1.0, 0.1), half))
+    return Workload("tie_planes", [sc], [_axis_camera(width, height, f)], "albedo")
+
+
+def _sphere_points(rng_pos, rng_ang, centre, radius, n):
+    p = rng_pos.normal(size=(3, n))
+    p /= np.linalg.norm(p, axis=0)
+    tan = _inplane_tangent(p, rng_ang.uniform(0, math.pi, n))
+    return np.asarray(centre, np.float64)[:, None] + radius * p, p, tan
+
+
+def two_spheres_workload(seed: int = 71, n_each: int = 20_000, width: int = 800, height: int = 600,
+                         scale: float = None, shade: str = "albedo") -> Workload:
+    """The inter-object edge scene of Sec. 4.4.3: two overlapping point-sampled
+    unit spheres, the rear one offset to the right, so that the front
+    silhouette, the rear silhouette and the overlap where the front sphere
+    occludes the rear one are all in view.  Radial normals; isotropic scale
+    about the mean surfel spacing (default 1.2 sqrt(4 pi / n_each)); a warm
+    front sphere and a cool rear one (uniform per-surfel albedo jitter).
+    Camera 45 deg vertical FOV, looking at the pair from distance 4.5."""
+    r = _rngs(seed, 6)
+    s = 1.2 * math.sqrt(4 * math.pi / n_each) if scale is None else scale
+    pa, na, ta = _sphere_points(r[0], r[1], (-0.35, 0.0, 0.0), 0.6, n_each)
+    pb, nb, tb = _sphere_points(r[2], r[3], (0.45, 0.5, 0.1), 0.6, n_each)
+    ca = np.clip(np.array([[0.9], [0.5], [0.2]]) + r[4].uniform(-0.1, 0.1, (3, n_each)), 0, 1)
+    cb = np.clip(np.array([[0.2], [0.4], [0.9]]) + r[5].uniform(-0.1, 0.1, (3, n_each)), 0, 1)
+    mk = lambda p, nn, t, c: Scene(_f32(p), _f32(nn), _f32(t), _f32(np.full((2, n_each), s)), _f32(c),
+                                   _f32(np.full(n_each, 0.4)), _f32(np.zeros(n_each)))
+    sc = concat_scenes(mk(pa, na, ta, ca), mk(pb, nb, tb, cb))
+    if shade == "splitsum":
+        sc.envmap = lognormal_envmap(seed, 16, 32)
+    cam = look_at_camera((0.0, -4.5, 0.3), width, height, target=(0.05, 0.25, 0.05))
+    return Workload("two_spheres", [sc], [cam], shade)
+
+
+def occluded_planes_workload(width: int = 72, height: int = 60, f: float = 80.0, seed: int = 81) -> Workload:
+    """A dense, opaque front plane (spacing s/3, accumulated weight far above the
+    opacity saturation) over a sparser second plane, both slightly tilted and
+    jittered, random albedo; the back plane is wider, so it is visible around the
+    front one."""
+    r = _rngs(seed, 4)
+    th = math.radians(10.0)
+
+    def plane(z, spacing, s, extent, rng):
+        g = np.arange(-extent, extent + 1e-9, spacing)
+        X, Y = np.meshgrid(g, g, indexing="ij")
+        k = X.size
+        X = X.ravel() + rng.uniform(-0.2, 0.2, k) * spacing
+        Y = Y.ravel() + rng.uniform(-0.2, 0.2, k) * spacing
+        pos = np.stack([X, Y * math.cos(th), z + Y * math.sin(th)])
+        nrm = np.tile(np.array([[0.0], [math.sin(th)], [-math.cos(th)]]), (1, k))
+        tan = np.tile(np.array([[1.0], [0.0], [0.0]]), (1, k))
+        return Scene(_f32(pos), _f32(nrm), _f32(tan), _f32(np.full((2, k), s)),
+                     _f32(rng.uniform(0, 1, (3, k))), _f32(np.full(k, 0.5)), _f32(np.zeros(k)))
+    front = plane(2.0, 0.01, 0.03, 0.5, r[0])
+    back = plane(2.6, 0.04, 0.04, 1.2, r[1])
+    cam = _axis_camera(width, height, f, background=(0.3, 0.3, 0.3))
+    return Workload("occluded_planes", [concat_scenes(front, back)], [cam], "albedo")
+
+
+def thin_shell_workload(width: int = 72, height: int = 60, f: float = 80.0, seed: int = 91,
+                        sep: float = 0.02) -> Workload:
+    """Two near-parallel tilted layers separated by `sep` along the view axis, less
+    than their surfels' depth extent (the thin-shell limitation of Sec. 5: the
+    interval merge fuses them into one layer), plus a third layer well behind;
+    lattice spacing about the surfel scale, random albedo."""
+    r = _rngs(seed, 3)
+    th = math.radians(35.0)
+
+    def layer(z, rng, off):
+        g = np.arange(-0.6, 0.6 + 1e-9, 0.025) + off
+        X, Y = np.meshgrid(g, g, indexing="ij")
+        k = X.size
+        pos = np.stack([X.ravel(), Y.ravel() * math.cos(th), z + Y.ravel() * math.sin(th)])
+        nrm = np.tile(np.array([[0.0], [math.sin(th)], [-math.cos(th)]]), (1, k))
+        tan = np.tile(np.array([[1.0], [0.0], [0.0]]), (1, k))
+        return Scene(_f32(pos), _f32(nrm), _f32(tan), _f32(np.full((2, k), 0.025)),
+                     _f32(rng.uniform(0, 1, (3, k))), _f32(np.full(k, 0.5)), _f32(np.zeros(k)))
+    sc = concat_scenes(layer(2.0, r[0], 0.0), layer(2.0 + sep, r[1], 0.0123), layer(2.5, r[2], 0.007))
+    return Workload("thin_shell", [sc], [_axis_camera(width, height, f)], "albedo")
 
 
 CONFIG_NAMES = ["C1", "C2", "C3", "C4", "C5"]

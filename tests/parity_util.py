@@ -7,10 +7,15 @@ Comparison protocol (FP32 GPU against the FP64 oracle):
   * pixels whose decision margin is small (cutoff |q - r^2|/r^2 < 1e-6, depth gap
     |z_start - z_max|/z_max < 1e-5) are excluded: FP32 and FP64 may
     legitimately take the other branch there; at most 0.1% of the pixels;
-  * pixels that are ill-conditioned in FP32 are excluded from the per-pixel
-    bound: those whose FP64 value moves by more than half that bound when the
-    FP32 surfel inputs are perturbed by 4 ulps (thin, edge-on ellipses without
-    the MIP prefilter); at most 1% of the pixels;
+  * a covering fragment (FP64 decisions) that the FP32 binning misses -- its
+    surfel culled, or the pixel outside its rectangle -- fails the comparison
+    (`viol`); nothing is masked for it;
+  * pixels that are ill-conditioned in FP32 -- whose FP64 value moves by more than
+    half the per-pixel bound when the FP32 surfel inputs are perturbed by 4 ulps
+    (thin, grazing ellipses) -- are held to a wider bound instead:
+    |d| <= bound + 2 c, with c the value's shift under that perturbation (an FP32
+    evaluation of the same decisions carries input-sized rounding errors, so its
+    error is of the order of c); each is reported;
   * gradients: relative L2 <= 1e-3 per parameter group, with dL/dimage zero on
     the excluded pixels.
 """
@@ -19,7 +24,7 @@ import numpy as np
 CUT_MARGIN = 1e-6
 GAP_MARGIN = 1e-5
 COND_ULPS = 4
-MAX_COND_MASKED = 1e-2
+COND_WIDEN = 2.0
 IMG_REL_L2 = 1e-4
 IMG_PIX = 1e-4
 GRAD_REL_L2 = 1e-3
@@ -67,7 +72,7 @@ def oracle_forward(O, scenes, cameras, opts, pix_per_view, maps, lut, conditioni
 
 
 def decision_ok(r):
-    return (r["cut_margin"] >= CUT_MARGIN) & (r["gap_margin"] >= GAP_MARGIN) & (r["viol"] == 0)
+    return (r["cut_margin"] >= CUT_MARGIN) & (r["gap_margin"] >= GAP_MARGIN)
 
 
 def pixel_index(cameras, v, pix):
@@ -80,11 +85,12 @@ def compare_images(cameras, pix_per_view, ref, img_gpu, alpha_gpu):
     img_gpu = np.asarray(img_gpu, np.float64)
     alpha_gpu = np.asarray(alpha_gpu, np.float64)
     refs, gots, masks, conds = [], [], [], []
-    n_masked = n_cut = n_gap = 0
+    n_masked = n_cut = n_gap = n_viol = 0
     n_total = 0
     for v, cam in enumerate(cameras):
         r = ref[v]
         ok = decision_ok(r)
+        n_viol += int(r["viol"].sum())
         idx = pixel_index(cameras, v, pix_per_view[v])
         refs.append(np.concatenate([r["image"], r["alpha"][:, None]], 1)[ok])
         gots.append(np.concatenate([img_gpu[idx], alpha_gpu[idx][:, None]], 1)[ok])
@@ -102,8 +108,11 @@ def compare_images(cameras, pix_per_view, ref, img_gpu, alpha_gpu):
     bound = IMG_PIX * np.maximum(np.abs(R), 1e-2 * np.abs(R).max())
     well = (Cd <= 0.5 * bound).all(1) if d.size else np.zeros(0, bool)
     n_cond = int((~well).sum())
-    ratio = np.where(well, (d / bound).max(1), 0.0) if d.size else np.zeros(0)
+    # per-pixel bound; ill-conditioned pixels against the wider bound + 2 c
+    wide = bound + COND_WIDEN * Cd
+    ratio = np.where(well, (d / bound).max(1), (d / wide).max(1)) if d.size else np.zeros(0)
     worst = float(ratio.max()) if d.size else 0.0
+    cond_ratio = float(ratio[~well].max()) if n_cond else 0.0
     # details of the worst compared pixels (for failure messages)
     info = []
     if d.size:
@@ -116,13 +125,14 @@ def compare_images(cameras, pix_per_view, ref, img_gpu, alpha_gpu):
             info.append(dict(pix=allpix[i].tolist(), ref=R[i].round(7).tolist(), got=G[i].round(7).tolist(),
                              ratio=round(float(ratio[i]), 3), cut=float(cm[i]), gap=float(gm[i]), nl=int(nl[i])))
     return dict(rel_l2=rel_l2, worst_pixel_ratio=worst, masked=n_masked, total=n_total,
-                masked_frac=n_masked / max(n_total, 1), masked_cut=n_cut, masked_gap=n_gap,
-                cond_masked=n_cond, cond_frac=n_cond / max(n_total, 1), worst=info), masks
+                masked_frac=n_masked / max(n_total, 1), masked_cut=n_cut, masked_gap=n_gap, viol=n_viol,
+                cond_pixels=n_cond, cond_frac=n_cond / max(n_total, 1), cond_worst_ratio=cond_ratio,
+                worst=info), masks
 
 
 def assert_image_parity(rep):
+    assert rep["viol"] == 0, rep
     assert rep["masked_frac"] <= MAX_MASKED, rep
-    assert rep["cond_frac"] <= MAX_COND_MASKED, rep
     assert rep["rel_l2"] <= IMG_REL_L2, rep
     assert rep["worst_pixel_ratio"] <= 1.0, rep
 
