@@ -34,7 +34,10 @@
  *     th = pi (a + 1/2)/H_e, ph = 2 pi (b + 1/2)/W_e.
  *   - Calls never abort and never throw.  Argument errors are reported
  *     synchronously; conditions found on the device (pair-capacity overflow)
- *     are latched and reported by ss_poll.
+ *     are latched and reported by ss_poll.  A forward that overflowed its pair
+ *     capacity writes NaN into every pixel of its image and alpha, and a
+ *     backward after it NaN into every surfel gradient, so the failure cannot
+ *     pass unnoticed where nobody polls (for instance in replayed graphs).
  *   - One context serves one stream at a time.
  */
 #ifndef SURFSPLAT_H
@@ -80,7 +83,9 @@ typedef struct ss_options {
   int32_t shade;  /* ss_shade_mode                                                */
   int32_t tile_w; /* tile width in pixels: 8, 16 or 32                           */
   int32_t tile_h; /* tile height in pixels: 8 or 16                              */
-  int32_t lds_batch; /* surfels staged per LDS batch: 32, 64, 128 or 256         */
+  int32_t lds_batch; /* surfels staged per LDS batch: 32, 64, 128 or 256; 0: the
+                        library picks one at each reserve from the measured mean
+                        tile-list length (the largest of 32..256 not above it)  */
   int32_t launch;    /* ss_launch_mode                                            */
   int32_t persistent; /* 1: raster blocks pull (view, tile) items from a queue   */
   int32_t depth_stats; /* 1: reserve per-layer depth statistics (8 bytes x 16 layers
@@ -97,6 +102,32 @@ typedef struct ss_options {
                           only while it fits whole); the others take global atomics.
                           -1 (default): as many as fit (39936 floats); 0: none.
                           Results agree either way up to the order of float sums  */
+  float t_min;         /* transmittance early-out: once a layer has been composited
+                          and the transmittance left in front of the next one,
+                          T_{k+1} = prod_{j<=k} (1 - alpha_j), is below t_min, the
+                          pixel's walk ends and later groups are discarded, exactly
+                          as after the K_max-th layer (App. A.1); the image keeps
+                          T_{K+1} bg.  0 (default): off, the exact semantics        */
+  int32_t deterministic; /* 1: ss_render_backward returns bitwise identical gradients
+                          for identical inputs: the raster backward sums each
+                          record's per-fragment gradients per (record, tile) in a
+                          fixed order and the tiles of a record in a fixed order
+                          (instead of float atomics in arrival order), and the
+                          environment gradients are accumulated in 64-bit fixed
+                          point.  Slower, and it reserves 48 bytes per pair more */
+  int32_t validate;    /* 1: every ss_render counts the non-finite surfel parameters
+                          and environment texels, every ss_render_backward the
+                          non-finite entries of d_image / d_alpha; the count of the
+                          last call is reported by ss_poll (n_nonfinite)          */
+  int32_t counters;    /* 1: the raster forward counts its work (ss_diag:
+                          n_evaluated, n_fragments, n_layers, sum_layer_weight)   */
+  int32_t tonemap;     /* 0 (default): the image is the composited linear (HDR) colour;
+                          1: the image is passed per channel through the log-space
+                          and sRGB transfer used for HDR targets with eq:photo_loss
+                          (Sec. 3.7.1): y = srgb(log(1 + max(x, 0))), with
+                          srgb(v) = 12.92 v for v <= 0.0031308, else
+                          1.055 v^(1/2.4) - 0.055.  d_image is then dL/dy and the
+                          backward applies dy/dx itself.  alpha is not mapped     */
 } ss_options;
 
 typedef struct ss_camera {
@@ -140,6 +171,9 @@ typedef struct ss_outputs {
    * layer's mean depth as above (divide by alpha for the expected depth of the
    * covered part).  Needs options.depth_stats = 1. */
   float* depth;
+  /* host, or NULL: receives the generation number of this forward (1, 2, ...
+   * per context) */
+  int64_t* generation;
 } ss_outputs;
 
 typedef struct ss_grad_in {
@@ -148,6 +182,9 @@ typedef struct ss_grad_in {
   const float* d_cons;  /* device [sum HW] or NULL: dL/dcons; needs the last forward to
                            have written cons or depth (else SS_ERR_STATE)       */
   const float* d_depth; /* device [sum HW] or NULL: dL/ddepth; same condition  */
+  int64_t generation;   /* 0: the context's last forward; otherwise the number that
+                           forward reported: SS_ERR_STATE when a later forward has
+                           replaced its state (two renders before one backward)   */
 } ss_grad_in;
 
 typedef struct ss_grads { /* every pointer may be NULL (skip); outputs are overwritten */
@@ -179,13 +216,22 @@ typedef struct ss_diag {
   int64_t n_pairs;       /* (tile, surfel) pairs of the last forward            */
   int64_t pair_capacity; /* pairs the workspace holds                           */
   int64_t workspace_bytes;
+  int64_t generation;    /* generation number of the last ss_render (0: none)   */
+  int64_t n_nonfinite;   /* options.validate: non-finite inputs of the last render
+                            plus those of the last backward                       */
+  /* options.counters, the last forward: */
+  int64_t n_evaluated;   /* (pixel, record) pairs the raster evaluated (E)        */
+  int64_t n_fragments;   /* fragments accumulated into composited layers (F)      */
+  int64_t n_layers;      /* layers composited over all pixels                     */
+  double sum_layer_weight; /* sum of their accumulated weights W_k (eq:alpha)     */
 } ss_diag;
 
 typedef struct ss_context ss_context;
 
 /* Fills *opt with the paper's settings: r_cut 3, K_max 16, gamma 2 pi,
  * sigma_f 0.1 px^2, albedo shading, 16x16 tiles, LDS batch 128, batched,
- * persistent raster. */
+ * persistent raster, no early-out, no tone map, atomics (not deterministic),
+ * no validation, no counters. */
 ss_status ss_default_options(ss_options* opt);
 
 /* Creates a context on the current HIP device.  *out receives ownership. */

@@ -52,7 +52,8 @@ def lib():
         L.orc_brdf_lut.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.orc_bin_f32.argtypes = [fpp, ctypes.c_int, dp, dp, ip, ctypes.POINTER(ctypes.c_uint32), ip, ip]
         L.orc_render.argtypes = [fpp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp,
-                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, dp, dp, ip, dp, dp, ip, dp]
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, dp, dp, ip, dp, dp, ip, dp,
+                                 ip]
         L.orc_records.argtypes = [fpp, ctypes.c_int, dp, dp, dp]
         L.orc_render_jvp.argtypes = [fpp, ctypes.c_int, fpp, dp, dp, dp, dp, ctypes.c_int, ctypes.c_int,
                                      dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, dp, dp, dp]
@@ -78,12 +79,15 @@ class Options:
     tile_w: int = 16
     tile_h: int = 16
     mip: str = "centre"            # "centre" (Sec. 3.3.2) | "pixel" (per-pixel Jacobian, Sec. 3.3.1)
+    t_min: float = 0.0             # transmittance early-out (0: off; the paper has none)
+    tonemap: str = "linear"        # "linear" | "srgb_log" (log-space + sRGB transfer, eq:photo_loss)
 
     def pack(self):
         f = lambda x: float(np.float32(x))
         return np.array([f(self.r_cut), f(self.gamma), f(self.sigma_f), self.k_max,
                          {"albedo": 0, "splitsum": 1, "normal": 2}[self.shade], self.tile_w, self.tile_h,
-                         {"centre": 0, "pixel": 1}[self.mip]], np.float64)
+                         {"centre": 0, "pixel": 1}[self.mip], f(self.t_min),
+                         {"linear": 0, "srgb_log": 1}[self.tonemap]], np.float64)
 
 
 def _dptr(a):
@@ -220,7 +224,8 @@ def render(scene, cam, opt: Options, pix, maps=None, lut=None, env_hw=(0, 0)):
     fragments (FP64 decisions) that the FP32 binning misses (culled surfel, or
     pixel outside its rectangle); `pp_drop`, `pp_drop_w` the count and weight sum
     of the fragments the per-pixel MIP filter would accept outside that
-    rectangle (mip = "pixel" only)."""
+    rectangle (mip = "pixel" only); `n_frag` the fragments accumulated into
+    the composited layers."""
     P = _Params(scene)
     pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 2)
     k = pix.shape[0]
@@ -235,13 +240,14 @@ def render(scene, cam, opt: Options, pix, maps=None, lut=None, env_hw=(0, 0)):
     depth = np.zeros(k, np.float64)
     drop = np.zeros(k, np.int32)
     drop_w = np.zeros(k, np.float64)
+    nfrag = np.zeros(k, np.int32)
     c, o = pack_camera(cam), opt.pack()
     lib().orc_render(P.pp, P.n, _dptr(c), _dptr(o), _dptr(maps), He, We, _dptr(lut),
                      lut.shape[1], lut.shape[0], k, _iptr(pix), _dptr(img), _dptr(alpha),
                      _iptr(nl), _dptr(cm), _dptr(gm), _iptr(viol), _dptr(cons), _dptr(depth), _iptr(drop),
-                     _dptr(drop_w))
+                     _dptr(drop_w), _iptr(nfrag))
     return dict(image=img, alpha=alpha, n_layers=nl, cut_margin=cm, gap_margin=gm, viol=viol, cons=cons,
-                depth=depth, pp_drop=drop, pp_drop_w=drop_w)
+                depth=depth, pp_drop=drop, pp_drop_w=drop_w, n_frag=nfrag)
 
 
 def records(scene, cam, opt: Options) -> dict:

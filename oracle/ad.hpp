@@ -25,6 +25,9 @@ inline Dual atan2(Dual y, Dual x) {
   double r2 = x.v * x.v + y.v * y.v;
   return {std::atan2(y.v, x.v), (x.v * y.d - y.v * x.d) / r2};
 }
+inline Dual log1p(Dual a) { return {std::log1p(a.v), a.d / (1.0 + a.v)}; }
+// a^p for a constant exponent p (a > 0)
+inline Dual pow(Dual a, double p) { double r = std::pow(a.v, p); return {r, p * r / a.v * a.d}; }
 inline double val(Dual a) { return a.v; }
 
 // ---------------------------------------------------------------- reverse tape
@@ -75,9 +78,13 @@ inline Var atan2(Var y, Var x) {
   double r2 = x.v * x.v + y.v * y.v;
   return mk(std::atan2(y.v, x.v), y.id, x.v / r2, x.id, -y.v / r2);
 }
+inline Var log1p(Var a) { return mk(std::log1p(a.v), a.id, 1.0 / (1.0 + a.v), -1, 0.0); }
+inline Var pow(Var a, double p) { double r = std::pow(a.v, p); return mk(r, a.id, p * r / a.v, -1, 0.0); }
 inline double val(Var a) { return a.v; }
 
 inline double val(double a) { return a; }
+inline double log1p(double a) { return std::log1p(a); }
+inline double pow(double a, double p) { return std::pow(a, p); }
 
 // mixed arithmetic with plain doubles
 #define ORC_MIXED(T)                                                     \

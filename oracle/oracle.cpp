@@ -49,6 +49,8 @@ struct Opt {
   double r_cut, gamma, sigma_f;
   int k_max, shade, tile_w, tile_h;
   int mip;  // 0: centre-precomputed MIP filter (Sec. 3.3.2); 1: per-pixel Jacobian (Sec. 3.3.1)
+  double t_min;  // transmittance early-out: the walk ends once T_{k+1} < t_min (0: off)
+  int tonemap;   // 1: log-space + sRGB transfer of the image (eq:photo_loss, Sec. 3.7.1)
 };
 static Cam unpack_cam(const double* c) {
   Cam k;
@@ -65,6 +67,8 @@ static Opt unpack_opt(const double* o) {
   p.r_cut = o[0]; p.gamma = o[1]; p.sigma_f = o[2];
   p.k_max = (int)o[3]; p.shade = (int)o[4]; p.tile_w = (int)o[5]; p.tile_h = (int)o[6];
   p.mip = (int)o[7];
+  p.t_min = o[8];
+  p.tonemap = (int)o[9];
   return p;
 }
 
@@ -590,6 +594,17 @@ static bool cull_keep64(const Rec<S>& r, double znear, double rcut, double* marg
   return zmin > znear;
 }
 
+// ------------------------------------------------------------ tone map
+// The transfer applied to HDR images with eq:photo_loss (Sec. 3.7.1): log
+// space, then the sRGB encoding (IEC 61966-2-1: linear segment 12.92 v up to
+// v = 0.0031308, else 1.055 v^(1/2.4) - 0.055).  Negative inputs map to 0.
+template <class S> static S tonemap_srgb_log(S x) {
+  if (!(val(x) > 0.0)) return S(0.0);
+  S v = log1p(x);
+  if (val(v) <= 0.0031308) return 12.92 * v;
+  return 1.055 * pow(v, 1.0 / 2.4) - 0.055;
+}
+
 // ------------------------------------------------------------ per pixel
 // Ray-surfel intersection (Sec. 3.1), MIP-filtered weight (eq:mip_weight),
 // interval grouping (Alg. 1), Shepard normalisation (eq:shepard), coverage
@@ -600,9 +615,12 @@ template <class S> struct Frag { double zs; int idx; S w; S ze; const Rec<S>* r;
 // intra-layer part, over the composited layers.
 // depth: the composited layer depth sum_k T_k alpha_k z_k (alpha-weighted; the
 // background contributes nothing).
-template <class S> struct PixOut { S img[3]; S alpha; S cons; S depth; int nl; };
+// nf: fragments accumulated into the composited layers
+template <class S> struct PixOut { S img[3]; S alpha; S cons; S depth; int nl; int nf = 0; };
 // Fragments the per-pixel MIP filter accepts outside its support rectangle.
 struct Dropped { int n = 0; double w = 0.0; };
+// gap_margin: the closest depth-gap decision, and (t_min > 0) the closest
+// early-out decision |T - t_min| / t_min.
 struct PixDiag { double cut_margin = INFINITY, gap_margin = INFINITY; Dropped pp_drop; };
 
 // zf (nullable): camera-space depth of the ray-surfel intersection,
@@ -751,20 +769,27 @@ static void pixel_eval(double x, double y, const Rec<S>* recs, const std::vector
       gm = std::min(gm, std::fabs(f.zs - zmax) / std::max(std::fabs(zmax), 1e-300));
       if (f.zs > zmax) {  // gap detected: finalise the current layer
         flush();
-        if (K >= o.k_max) { done = true; break; }
+        if (o.t_min > 0.0) gm = std::min(gm, std::fabs(val(Tb) - o.t_min) / o.t_min);
+        // the K_max cap (App. A.1), or the early-out once the transmittance in
+        // front of the next layer is below t_min
+        if (K >= o.k_max || val(Tb) < o.t_min) { done = true; break; }
         Cg[0] = Cg[1] = Cg[2] = S(0.0);
         Wg = S(0.0);
         zmax = 0.0;
       }
     }
     zmax = std::max(zmax, val(f.ze));
+    ++out.nf;
     if (layer_of) (*layer_of)[fi] = K;
     for (int c = 0; c < 3; ++c) Cg[c] += f.w * f.r->col[c];
     Wg += f.w;
     members.push_back(&f);
   }
   if (!done && val(Wg) > 0.0) flush();
-  for (int c = 0; c < 3; ++c) out.img[c] = Cout[c] + Tb * cam.bg[c];
+  for (int c = 0; c < 3; ++c) {
+    out.img[c] = Cout[c] + Tb * cam.bg[c];
+    if (o.tonemap) out.img[c] = tonemap_srgb_log(out.img[c]);
+  }
   out.alpha = 1.0 - Tb;
   S cons(0.0);
   for (int i = 0; i < K; ++i) {
@@ -892,7 +917,7 @@ int orc_render(const float* const* P, int n, const double* cam, const double* op
                const double* maps, int He, int We, const double* lut, int n_nv, int n_r,
                int npix, const int* pix, double* img, double* alpha, int* nl,
                double* cut_margin, double* gap_margin, int* viol, double* cons, double* depth,
-               int* pp_drop, double* pp_drop_w) {
+               int* pp_drop, double* pp_drop_w, int* nfrag) {
   Cam c = unpack_cam(cam);
   Opt o = unpack_opt(opt);
   std::vector<Rec<double>> recs;
@@ -921,6 +946,7 @@ int orc_render(const float* const* P, int n, const double* cam, const double* op
     if (cons) cons[k] = out.cons;
     if (depth) depth[k] = out.depth;
     if (pp_drop) pp_drop[k] = dg.pp_drop.n;
+    if (nfrag) nfrag[k] = out.nf;
     if (pp_drop_w) pp_drop_w[k] = dg.pp_drop.w;
   }
   return 0;

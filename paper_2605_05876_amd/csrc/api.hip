@@ -90,6 +90,8 @@ struct ss_context {
   int lut_nv = 0, lut_r = 0;
   bool fwd_valid = false;
   bool fwd_cons = false;  // the last forward wrote the per-layer depth statistics
+  long long generation = 0;  // number of the last ss_render (its forward state)
+  int lds_batch = 128;       // the LDS batch in use (options.lds_batch, or picked by the reserve)
   std::vector<long long> fwd_sig;
   hipStream_t last_stream = nullptr;  // may be the null stream
   bool used = false;                  // a stream call has been made
@@ -105,8 +107,15 @@ struct ss_context {
 
 namespace {
 
+// Device words of a workspace (u32 array `misc`): latched status, the raster
+// work queue, per-group pair counts, the tile-order scratch, then 64-bit
+// counters (8-byte aligned): non-finite inputs of the forward and of the
+// backward, and the raster forward's work counters (E, F, layers, sum of W).
 constexpr int kMiscStatus = 0, kMiscQueue = 1, kMiscPairs = 8;
 constexpr int kMiscOrder = kMiscPairs + kMaxViews;  // 66 u32: tile-order bucket counts and cursors
+constexpr int kMiscNonfinite = kMiscOrder + 66;     // u64 [2]: forward, backward
+constexpr int kMiscCounters = kMiscNonfinite + 4;   // u64 [3] + f64: E, F, layers, sum W
+constexpr int kMiscWords = kMiscCounters + 8;
 
 #define SS_HIP(x)                                                            \
   do {                                                                       \
@@ -127,12 +136,16 @@ ss_status check_options(const ss_options* o) {
     return SS_ERR_INVALID_ARG;
   const int tk = o->tile_w * 100 + o->tile_h;
   if (tk != 808 && tk != 1608 && tk != 1616 && tk != 3208 && tk != 3216) return SS_ERR_UNSUPPORTED;
-  if (o->lds_batch != 32 && o->lds_batch != 64 && o->lds_batch != 128 && o->lds_batch != 256)
+  if (o->lds_batch != 0 && o->lds_batch != 32 && o->lds_batch != 64 && o->lds_batch != 128 &&
+      o->lds_batch != 256)
     return SS_ERR_UNSUPPORTED;
   if (o->launch != SS_LAUNCH_BATCHED && o->launch != SS_LAUNCH_PER_VIEW) return SS_ERR_INVALID_ARG;
   if (o->depth_stats != 0 && o->depth_stats != 1) return SS_ERR_INVALID_ARG;
   if (o->mip != 0 && o->mip != 1) return SS_ERR_INVALID_ARG;
   if (o->env_lds < -1) return SS_ERR_INVALID_ARG;
+  if (!(o->t_min >= 0.f) || !(o->t_min < 1.f)) return SS_ERR_INVALID_ARG;
+  if ((o->deterministic | o->validate | o->counters | o->tonemap) & ~1) return SS_ERR_INVALID_ARG;
+  if (o->deterministic) return SS_ERR_UNSUPPORTED;
   return SS_OK;
 }
 
@@ -205,6 +218,9 @@ Params make_params(const ss_context* c) {
   p.ss_grad = 0;
   p.cons = 0;
   p.mip = c->opt.mip;
+  p.t_min = c->opt.t_min;
+  p.tonemap = c->opt.tonemap;
+  p.counters = c->opt.counters;
   return p;
 }
 
@@ -262,6 +278,34 @@ ss_status upload_views(ss_context* c, const ss_batch* b, hipStream_t st) {
   return SS_OK;
 }
 
+// Level sizes, float offsets and the LDS layout of the privatised level
+// gradients of scene s (no device work).  Returns the float counts of the
+// levels 1..6 (lv) and of the gradient levels 0..6 (dlv).
+void env_layout(const ss_context* c, const ss_batch* b, int s, SceneEnv& e, long long* lv_n, long long* dlv_n) {
+  const int He = b->env_hw[2 * s], We = b->env_hw[2 * s + 1];
+  e.lh[0] = He; e.lw[0] = We;
+  for (int l = 1; l <= 5; ++l) { e.lh[l] = He >> l > 4 ? He >> l : 4; e.lw[l] = We >> l > 8 ? We >> l : 8; }
+  e.lh[6] = 32; e.lw[6] = 64;
+  long long o = 0;
+  e.off[0] = 0;
+  for (int l = 1; l < 7; ++l) { e.off[l] = o; o += 3LL * e.lh[l] * e.lw[l]; }
+  *lv_n = o;
+  long long d = 0;
+  for (int l = 0; l < 7; ++l) { e.doff[l] = d; d += 3LL * e.lh[l] * e.lw[l]; }
+  *dlv_n = d;
+  // privatise the irradiance level and the specular levels, smallest first,
+  // in LDS while they fit
+  for (int l = 0; l < 7; ++l) e.loc_off[l] = -1;
+  e.loc_total = 0;
+  for (int l : {6, 5, 4, 3, 2, 1, 0}) {
+    const int n = 3 * e.lh[l] * e.lw[l];
+    const int budget = c->opt.env_lds < 0 ? kLocalMapFloats : std::min(c->opt.env_lds, kLocalMapFloats);
+    if (e.loc_total + n > budget) break;
+    e.loc_off[l] = e.loc_total;
+    e.loc_total += n;
+  }
+}
+
 ss_status prepare_env(ss_context* c, const ss_batch* b, hipStream_t st) {
   if (c->opt.shade != SS_SHADE_SPLITSUM) {
     c->env.clear();
@@ -271,26 +315,8 @@ ss_status prepare_env(ss_context* c, const ss_batch* b, hipStream_t st) {
   for (int s = 0; s < b->n_scenes; ++s) {
     SceneEnv& e = c->env[s];
     const int He = b->env_hw[2 * s], We = b->env_hw[2 * s + 1];
-    e.lh[0] = He; e.lw[0] = We;
-    for (int l = 1; l <= 5; ++l) { e.lh[l] = He >> l > 4 ? He >> l : 4; e.lw[l] = We >> l > 8 ? We >> l : 8; }
-    e.lh[6] = 32; e.lw[6] = 64;
-    long long o = 0;
-    e.off[0] = 0;
-    for (int l = 1; l < 7; ++l) { e.off[l] = o; o += 3LL * e.lh[l] * e.lw[l]; }
-    const long long lv_n = o;
-    long long d = 0;
-    for (int l = 0; l < 7; ++l) { e.doff[l] = d; d += 3LL * e.lh[l] * e.lw[l]; }
-    // privatise the irradiance level and the specular levels, smallest first,
-    // in LDS while they fit
-    for (int l = 0; l < 7; ++l) e.loc_off[l] = -1;
-    e.loc_total = 0;
-    for (int l : {6, 5, 4, 3, 2, 1, 0}) {
-      const int n = 3 * e.lh[l] * e.lw[l];
-      const int budget = c->opt.env_lds < 0 ? kLocalMapFloats : std::min(c->opt.env_lds, kLocalMapFloats);
-      if (e.loc_total + n > budget) break;
-      e.loc_off[l] = e.loc_total;
-      e.loc_total += n;
-    }
+    long long lv_n = 0, d = 0;
+    env_layout(c, b, s, e, &lv_n, &d);
     SS_HIP(ensure(c->partial, (size_t)(kBackwardBlocks + kReduceSplit) * kLocalMapFloats * sizeof(float)));
     SS_HIP(ensure(e.lv, lv_n * sizeof(float)));
     SS_HIP(ensure(e.dlv, d * sizeof(float)));
@@ -399,16 +425,13 @@ static ss_status ensure_side(ss_context* c) {
   return SS_OK;
 }
 
-ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
-  c->reserved = false;
-  c->fwd_valid = false;
-  c->views_uploaded = false;
+// Host-side plan of a batch: counts, view layout and the groups of views that
+// share a pair list (no device work, no allocation).
+void plan_batch(ss_context* c, const ss_batch* b, std::vector<ViewDev>& vh) {
   c->n_views = b->n_views;
   c->n_scenes = b->n_scenes;
   c->N = b->surfel_offset[b->n_scenes];
   c->soff.assign(b->surfel_offset, b->surfel_offset + b->n_scenes + 1);
-  SS_TRY(prepare_env(c, b, st));
-  std::vector<ViewDev> vh;
   build_views(c, b, vh);
   c->R = 0;
   c->n_pix = 0;
@@ -436,6 +459,17 @@ ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
     g.pair_cap = 0;
     c->groups.push_back(g);
   }
+  c->lds_batch = c->opt.lds_batch > 0 ? c->opt.lds_batch : 128;
+}
+
+ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
+  c->reserved = false;
+  c->fwd_valid = false;
+  c->views_uploaded = false;
+  c->n_scenes = b->n_scenes;
+  SS_TRY(prepare_env(c, b, st));
+  std::vector<ViewDev> vh;
+  plan_batch(c, b, vh);
   const long long R = c->R > 0 ? c->R : 1;
   SS_HIP(ensure(c->views_d, sizeof(ViewDev) * kMaxViews));
   SS_HIP(ensure(c->recs, (size_t)R * kRecFloats * sizeof(float)));
@@ -447,7 +481,7 @@ ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
   SS_HIP(ensure(c->zidx2, (size_t)R * sizeof(uint32_t)));
   SS_HIP(ensure(c->prect, (size_t)R * sizeof(uint2)));
   SS_HIP(ensure(c->zrect, (size_t)R * sizeof(uint2)));
-  SS_HIP(ensure(c->misc, (kMiscOrder + 66) * sizeof(uint32_t)));
+  SS_HIP(ensure(c->misc, kMiscWords * sizeof(uint32_t)));
   c->scan_tmp_n = scan_tmp_size(R) + 16;
   SS_HIP(ensure(c->scan_tmp, (size_t)c->scan_tmp_n * sizeof(uint32_t)));
   SS_HIP(ensure(c->ranges, (size_t)2 * (c->n_tiles > 0 ? c->n_tiles : 1) * sizeof(uint32_t)));
@@ -477,6 +511,13 @@ ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
     maxcap = g.pair_cap > maxcap ? g.pair_cap : maxcap;
   }
   c->pair_total = base;
+  if (c->opt.lds_batch == 0) {
+    // the largest batch not above the mean tile-list length (at least 32)
+    long long np_all = 0;
+    for (uint32_t x : np) np_all += x;
+    const double mean = c->n_tiles > 0 ? (double)np_all / c->n_tiles : 0.0;
+    c->lds_batch = mean >= 256 ? 256 : (mean >= 128 ? 128 : (mean >= 64 ? 64 : 32));
+  }
   SS_HIP(ensure(c->keys, (size_t)base * sizeof(uint32_t)));
   SS_HIP(ensure(c->keys2, (size_t)base * sizeof(uint32_t)));
   SS_HIP(ensure(c->vals, (size_t)base * sizeof(uint32_t)));
@@ -536,6 +577,67 @@ size_t workspace_bytes(const ss_context* c) {
   return s;
 }
 
+
+// Non-finite surfel parameters (and environment texels) of a batch, counted
+// into the 64-bit word `cnt` (options.validate).
+ss_status count_nonfinite_inputs(ss_context* c, const ss_batch* b, unsigned long long* cnt, hipStream_t st) {
+  const float* pp[7];
+  param_ptrs(b, pp);
+  const int rows[7] = {3, 3, 3, 2, 3, 1, 1};
+  for (int a = 0; a < 7; ++a)
+    if (c->N > 0) SS_HIP(launch_count_nonfinite(pp[a], (long long)rows[a] * c->N, cnt, st));
+  if (c->opt.shade == SS_SHADE_SPLITSUM)
+    for (int s = 0; s < b->n_scenes; ++s)
+      SS_HIP(launch_count_nonfinite(b->envmap[s], 3LL * b->env_hw[2 * s] * b->env_hw[2 * s + 1], cnt, st));
+  return SS_OK;
+}
+
+// The forward pipeline on a planned and sized workspace whose view table is on
+// the device: environment levels, then per group preprocess + shading,
+// binning, tile order and the raster forward.  Clears the device words it
+// relies on first.
+ss_status forward_body(ss_context* c, const ss_batch* b, const ss_outputs* out, hipStream_t st) {
+  uint32_t* misc = P<uint32_t>(c->misc);
+  SS_HIP(launch_fill_u32(misc, 0u, kMiscPairs, st));
+  SS_HIP(launch_fill_u32(misc + kMiscNonfinite, 0u, 4, st));  // both non-finite counters
+  if (c->opt.counters) SS_HIP(launch_fill_u32(misc + kMiscCounters, 0u, 8, st));
+  if (c->opt.validate)
+    SS_TRY(count_nonfinite_inputs(c, b, reinterpret_cast<unsigned long long*>(misc + kMiscNonfinite), st));
+  hipEvent_t t0 = prof_begin(c, st);
+  SS_TRY(run_envmap_prefilter(c, b, st));
+  prof_end(c, t0, ST_ENV, st);
+  Params prm = make_params(c);
+  prm.cons = (out->cons || out->depth) ? 1 : 0;
+  int* status = reinterpret_cast<int*>(misc + kMiscStatus);
+  for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+    const Group& g = c->groups[gi];
+    t0 = prof_begin(c, st);
+    SS_TRY(run_preprocess(c, b, g.v0, g.v1, st));
+    prof_end(c, t0, ST_PRE, st);
+    t0 = prof_begin(c, st);
+    SS_TRY(run_binning(c, g, (int)gi, st));
+    uint32_t* vals = P<uint32_t>(c->vals) + g.pair_base;
+    int* order = nullptr;
+    if (c->opt.persistent) {
+      order = P<int>(c->order) + g.tile_base;
+      SS_HIP(launch_tile_order(P<uint32_t>(c->ranges), g.tile_base, g.n_tiles, order,
+                               misc + kMiscOrder, st));
+    }
+    prof_end(c, t0, ST_BIN, st);
+    SS_HIP(launch_fill_u32(misc + kMiscQueue, 0u, 1, st));
+    t0 = prof_begin(c, st);
+    SS_HIP(launch_raster_forward(P<ViewDev>(c->views_d), c->n_views, g.tile_base,
+                                 g.tile_base + g.n_tiles, P<uint32_t>(c->ranges), vals,
+                                 P<float>(c->recs), prm, c->lds_batch, out->image, out->alpha,
+                                 out->n_layers, P<uint8_t>(c->nl), P<float4>(c->stats),
+                                 P<float2>(c->stats2), out->cons, out->depth,
+                                 reinterpret_cast<int*>(misc + kMiscQueue), order,
+                                 c->opt.persistent, status,
+                                 reinterpret_cast<unsigned long long*>(misc + kMiscCounters), st));
+    prof_end(c, t0, ST_RFWD, st);
+  }
+  return SS_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -555,6 +657,11 @@ ss_status ss_default_options(ss_options* o) {
   o->depth_stats = 0;
   o->mip = 0;
   o->env_lds = -1;
+  o->t_min = 0.f;
+  o->deterministic = 0;
+  o->validate = 0;
+  o->counters = 0;
+  o->tonemap = 0;
   return SS_OK;
 }
 
@@ -642,48 +749,17 @@ ss_status ss_render(ss_context* c, const ss_batch* b, const ss_outputs* out, ss_
   if (!c->reserved || signature(c, b) != c->sig) SS_TRY(reserve_impl(c, b, st));
   c->fwd_valid = false;
   SS_TRY(upload_views(c, b, st));
-  uint32_t* misc = P<uint32_t>(c->misc);
-  SS_HIP(launch_fill_u32(misc, 0u, kMiscPairs, st));
-  hipEvent_t t0 = prof_begin(c, st);
-  SS_TRY(run_envmap_prefilter(c, b, st));
-  prof_end(c, t0, ST_ENV, st);
-  Params prm = make_params(c);
-  prm.cons = (out->cons || out->depth) ? 1 : 0;
-  int* status = reinterpret_cast<int*>(misc + kMiscStatus);
-  for (size_t gi = 0; gi < c->groups.size(); ++gi) {
-    const Group& g = c->groups[gi];
-    t0 = prof_begin(c, st);
-    SS_TRY(run_preprocess(c, b, g.v0, g.v1, st));
-    prof_end(c, t0, ST_PRE, st);
-    t0 = prof_begin(c, st);
-    SS_TRY(run_binning(c, g, (int)gi, st));
-    uint32_t* vals = P<uint32_t>(c->vals) + g.pair_base;
-    int* order = nullptr;
-    if (c->opt.persistent) {
-      order = P<int>(c->order) + g.tile_base;
-      SS_HIP(launch_tile_order(P<uint32_t>(c->ranges), g.tile_base, g.n_tiles, order,
-                               misc + kMiscOrder, st));
-    }
-    prof_end(c, t0, ST_BIN, st);
-    SS_HIP(launch_fill_u32(misc + kMiscQueue, 0u, 1, st));
-    t0 = prof_begin(c, st);
-    SS_HIP(launch_raster_forward(P<ViewDev>(c->views_d), c->n_views, g.tile_base,
-                                 g.tile_base + g.n_tiles, P<uint32_t>(c->ranges), vals,
-                                 P<float>(c->recs), prm, c->opt.lds_batch, out->image, out->alpha,
-                                 out->n_layers, P<uint8_t>(c->nl), P<float4>(c->stats),
-                                 P<float2>(c->stats2), out->cons, out->depth,
-                                 reinterpret_cast<int*>(misc + kMiscQueue), order,
-                                 c->opt.persistent, st));
-    prof_end(c, t0, ST_RFWD, st);
-  }
+  SS_TRY(forward_body(c, b, out, st));
   c->fwd_valid = true;
-  c->fwd_cons = prm.cons != 0;
+  c->fwd_cons = out->cons || out->depth;
   c->fwd_sig = c->sig;
+  ++c->generation;
+  if (out->generation) *out->generation = c->generation;
   return SS_OK;
 }
 
 // Environment adjoint of every scene with a requested map gradient, on `st`.
-static ss_status envmap_backward(ss_context* c, const ss_grads* gr, hipStream_t st) {
+static ss_status envmap_backward(ss_context* c, const ss_grads* gr, const int* status, hipStream_t st) {
   if (c->opt.shade != SS_SHADE_SPLITSUM || !gr->d_envmap) return SS_OK;
   for (int s = 0; s < c->n_scenes; ++s) {
     if (!gr->d_envmap[s]) continue;
@@ -691,7 +767,7 @@ static ss_status envmap_backward(ss_context* c, const ss_grads* gr, hipStream_t 
     const float* dl[7];
     for (int l = 0; l < 7; ++l) dl[l] = P<float>(e.dlv) + e.doff[l];
     SS_HIP(launch_envmap_adjoint(dl, e.lh, e.lw, P<float>(e.Z), e.He, e.We, P<float>(e.dirs),
-                                 gr->d_envmap[s], st));
+                                 gr->d_envmap[s], status, st));
   }
   return SS_OK;
 }
@@ -702,6 +778,7 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
   SS_TRY(check_batch(c, b));
   if (c->opt.mip != 0) return SS_ERR_UNSUPPORTED;
   if (!c->fwd_valid || signature(c, b) != c->fwd_sig) return SS_ERR_STATE;
+  if (gin->generation != 0 && gin->generation != c->generation) return SS_ERR_STATE;
   if ((gin->d_cons || gin->d_depth) && !c->fwd_cons) return SS_ERR_STATE;
   hipStream_t st = (hipStream_t)stream;
   c->last_stream = st;
@@ -711,6 +788,13 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
   prm.ss_grad = gr->screen_grad ? 1 : 0;
   prm.cons = (gin->d_cons || gin->d_depth) ? 1 : 0;
   uint32_t* misc = P<uint32_t>(c->misc);
+  const int* status = reinterpret_cast<const int*>(misc + kMiscStatus);
+  if (c->opt.validate) {
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(misc + kMiscNonfinite) + 1;
+    SS_HIP(launch_fill_u32(misc + kMiscNonfinite + 2, 0u, 2, st));
+    SS_HIP(launch_count_nonfinite(gin->d_image, 3 * c->n_pix, cnt, st));
+    if (gin->d_alpha) SS_HIP(launch_count_nonfinite(gin->d_alpha, c->n_pix, cnt, st));
+  }
   SS_HIP(launch_fill_f32(P<float>(c->grad), 0.f, (long long)c->R * kGradStride, st));
   if (c->opt.shade == SS_SHADE_SPLITSUM)
     for (SceneEnv& e : c->env) SS_HIP(launch_fill_f32(P<float>(e.dlv), 0.f, (long long)(e.dlv.n / 4), st));
@@ -721,7 +805,7 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
     SS_HIP(launch_raster_backward(P<ViewDev>(c->views_d), c->n_views, g.tile_base,
                                   g.tile_base + g.n_tiles, P<uint32_t>(c->ranges),
                                   P<uint32_t>(c->vals) + g.pair_base, P<float>(c->recs), prm,
-                                  c->opt.lds_batch, gin->d_image, gin->d_alpha, P<uint8_t>(c->nl),
+                                  c->lds_batch, gin->d_image, gin->d_alpha, P<uint8_t>(c->nl),
                                   P<float4>(c->stats), P<float2>(c->stats2), gin->d_cons, gin->d_depth,
                                   P<float>(c->grad), c->R,
                                   reinterpret_cast<int*>(misc + kMiscQueue),
@@ -756,18 +840,18 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
     SS_TRY(ensure_side(c));
     SS_HIP(hipEventRecord(c->fork_ev, st));
     SS_HIP(hipStreamWaitEvent(c->side, c->fork_ev, 0));
-    SS_TRY(envmap_backward(c, gr, c->side));
+    SS_TRY(envmap_backward(c, gr, status, c->side));
     SS_HIP(hipEventRecord(c->join_ev, c->side));
   }
   SS_HIP(launch_geometry_backward(pp, c->N, P<ViewDev>(c->views_d), c->n_views, prm, P<float>(c->grad),
                                   P<float>(c->sg), G, P<float>(c->recs), gr->screen_grad,
-                                  gr->visible_views, st));
+                                  gr->visible_views, status, st));
   prof_end(c, t1, ST_PREBWD, st);
   if (fork) {
     SS_HIP(hipStreamWaitEvent(st, c->join_ev, 0));
   } else {
     t1 = prof_begin(c, st);
-    SS_TRY(envmap_backward(c, gr, st));
+    SS_TRY(envmap_backward(c, gr, status, st));
     prof_end(c, t1, ST_ENVBWD, st);
   }
   return SS_OK;
@@ -778,16 +862,26 @@ ss_status ss_poll(ss_context* c, ss_diag* out) {
   std::memset(out, 0, sizeof(*out));
   if (c->used) SS_HIP(hipStreamSynchronize(c->last_stream));
   if (c->misc.p) {
-    std::vector<uint32_t> m(kMiscPairs + c->groups.size());
+    std::vector<uint32_t> m(kMiscWords);
     SS_HIP(hipMemcpy(m.data(), c->misc.p, m.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
     out->status = (int32_t)m[kMiscStatus];
     long long np = 0;
     for (size_t g = 0; g < c->groups.size(); ++g) np += m[kMiscPairs + g];
     out->n_pairs = np;
+    unsigned long long u[6];
+    std::memcpy(u, m.data() + kMiscNonfinite, sizeof(u));
+    out->n_nonfinite = (int64_t)(u[0] + u[1]);
+    if (c->opt.counters) {
+      out->n_evaluated = (int64_t)u[2];
+      out->n_fragments = (int64_t)u[3];
+      out->n_layers = (int64_t)u[4];
+      std::memcpy(&out->sum_layer_weight, &u[5], sizeof(double));
+    }
   }
   out->n_records = c->R;
   out->pair_capacity = c->pair_total;
   out->workspace_bytes = (int64_t)workspace_bytes(c);
+  out->generation = c->generation;
   return out->status == 0 ? SS_OK : (ss_status)out->status;
 }
 

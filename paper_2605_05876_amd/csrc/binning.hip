@@ -47,6 +47,33 @@ hipError_t launch_fill_f32(float* p, float v, long long n, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Non-finite entries of p[0..n): a per-lane count, one 64-bit atomic per lane
+// that found any (they are rare).
+__global__ void count_nonfinite_kernel(const float* __restrict__ p, long long n, unsigned long long* cnt) {
+  unsigned c = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    c += isfinite(p[i]) ? 0u : 1u;
+  if (c) atomicAdd(cnt, (unsigned long long)c);
+}
+// NaN into p[0..n) when the latched status is SS_ERR_CAPACITY (3).
+__global__ void poison_if_capacity_kernel(float* p, long long n, const int* __restrict__ status) {
+  if (*status != 3) return;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = __builtin_nanf("");
+}
+hipError_t launch_poison_if_capacity(float* p, long long n, const int* status, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(poison_if_capacity_kernel, dim3(fill_blocks(n)), dim3(256), 0, st, p, n, status);
+  return hipGetLastError();
+}
+hipError_t launch_count_nonfinite(const float* p, long long n, unsigned long long* cnt, hipStream_t st) {
+  if (n <= 0 || !p) return hipSuccess;
+  hipLaunchKernelGGL(count_nonfinite_kernel, dim3(fill_blocks(n)), dim3(256), 0, st, p, n, cnt);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- scan
 // Exclusive scan of u32 in three kernels: block sums, scan of the block sums
 // (one block), per-block scan plus carry.  Blocks of 256 threads hold

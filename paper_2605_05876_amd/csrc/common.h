@@ -59,8 +59,26 @@ struct Params {
   int lut_nv, lut_r;
   int ss_grad;  // backward: accumulate the screen-space gradient statistic in slot G_SS
   int cons;     // forward: depth statistics (eq:cons_loss, depth image); backward: their adjoint
-  int mip;      // 0: centre-precomputed MIP filter; 1: per-pixel Jacobian (forward only)
+  int mip;      // 0: centre-precomputed MIP filter; 1: per-pixel Jacobian
+  float t_min;  // transmittance early-out (0: off)
+  int tonemap;  // 1: log-space + sRGB transfer of the image (and its derivative in the backward)
+  int counters; // forward: count evaluated pairs, fragments, layers and their weight
 };
+
+// Log-space + sRGB transfer of one linear channel value (the HDR transfer
+// used with eq:photo_loss): y = srgb(log(1 + max(x, 0))) with the sRGB
+// encoding 12.92 v (v <= 0.0031308) or 1.055 v^(1/2.4) - 0.055, and dy/dx
+// (0 for x <= 0).
+__device__ __forceinline__ float tonemap_srgb_log(float x) {
+  const float v = log1pf(fmaxf(x, 0.f));
+  return v <= 0.0031308f ? 12.92f * v : 1.055f * exp2f(log2f(v) * (1.f / 2.4f)) - 0.055f;
+}
+__device__ __forceinline__ float tonemap_srgb_log_deriv(float x) {
+  if (!(x > 0.f)) return 0.f;
+  const float v = log1pf(x);
+  const float ds = v <= 0.0031308f ? 12.92f : (1.055f / 2.4f) * exp2f(log2f(v) * (1.f / 2.4f - 1.f));
+  return ds / (1.f + x);
+}
 
 // ---------------------------------------------------------------- FP32 binning
 // The binning decision of one (surfel, view): cull, depth-interval start and
@@ -235,6 +253,10 @@ __device__ __forceinline__ int view_of_tile(const ViewDev* views, int nv, int ti
 // (implemented in the .hip files; all enqueue on `st` and return hipError_t)
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t st);
 hipError_t launch_fill_f32(float* p, float v, long long n, hipStream_t st);
+// NaN into p[0..n) when the device status word is SS_ERR_CAPACITY.
+hipError_t launch_poison_if_capacity(float* p, long long n, const int* status, hipStream_t st);
+// Adds the number of non-finite entries of p[0..n) to *cnt (device).
+hipError_t launch_count_nonfinite(const float* p, long long n, unsigned long long* cnt, hipStream_t st);
 
 hipError_t launch_envmap_dirs(float* dirs, int H, int W, hipStream_t st);
 hipError_t launch_envmap_out_dirs(int He, int We, const float* in_dirs, const int lh[7],
@@ -245,9 +267,10 @@ int envmap_prefilter_chunks(int He, int We);
 hipError_t launch_envmap_prefilter(const float* E, int He, int We, const float* in_dirs,
                                    const float* out_dirs, float* const lvl_out[7], const int lh[7],
                                    const int lw[7], float* part, hipStream_t st);
+// status (device): a latched SS_ERR_CAPACITY makes dE NaN.
 hipError_t launch_envmap_adjoint(const float* const dlvl[7], const int lh[7], const int lw[7],
                                  const float* out_dirs, int He, int We, const float* in_dirs,
-                                 float* dE, hipStream_t st);
+                                 float* dE, const int* status, hipStream_t st);
 hipError_t launch_brdf_lut(float* lut, int n_nv, int n_r, int samples, hipStream_t st);
 
 hipError_t launch_preprocess(const float* const P[7], long long N, const ViewDev* views, int v0,
@@ -267,10 +290,11 @@ hipError_t launch_shade_backward(const float* const P[7], long long N, const Vie
                                  int n_surf, const int local_off[7], int local_total, float* partial,
                                  float* const level_grad[7], const Params& prm, const float* grad,
                                  float* sg, hipStream_t st);
+// status (device): a latched SS_ERR_CAPACITY makes every output gradient NaN.
 hipError_t launch_geometry_backward(const float* const P[7], long long N, const ViewDev* views,
                                     int n_views, const Params& prm, const float* grad,
                                     const float* sg, float* const G[7], const float* recs,
-                                    float* ss_out, int* vis_out, hipStream_t st);
+                                    float* ss_out, int* vis_out, const int* status, hipStream_t st);
 
 hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint32_t* total, uint32_t* tmp,
                            long long tmp_n, hipStream_t st);
@@ -306,7 +330,8 @@ hipError_t launch_raster_forward(const ViewDev* views, int n_views, int tile_beg
                                  float* image, float* alpha, uint8_t* n_layers_out,
                                  uint8_t* n_layers, float4* layer_stats, float2* layer_stats2,
                                  float* cons, float* depth, int* queue, const int* order,
-                                 int persistent, hipStream_t st);
+                                 int persistent, const int* status, unsigned long long* counters,
+                                 hipStream_t st);
 hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_begin, int tile_end,
                                   const uint32_t* ranges, const uint32_t* sorted_vals,
                                   const float* recs, const Params& prm, int lds_batch,

@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(256) envmap_adjoint_kernel(DLevelSet L, int nt
 
 hipError_t launch_envmap_adjoint(const float* const dlvl[7], const int lh[7], const int lw[7],
                                  const float* out_dirs, int He, int We, const float* in_dirs,
-                                 float* dE, hipStream_t st) {
+                                 float* dE, const int* status, hipStream_t st) {
   DLevelSet L;
   L.first[1] = 0;
   for (int l = 0; l < 7; ++l) L.g[l] = dlvl[l];
@@ -341,7 +341,9 @@ hipError_t launch_envmap_adjoint(const float* const dlvl[7], const int lh[7], co
   hipLaunchKernelGGL(envmap_adjoint_kernel, dim3((nt + 255) / 256, nchunk), dim3(256), 0, st, L, nt,
                      reinterpret_cast<const float4*>(in_dirs),
                      reinterpret_cast<const float4*>(out_dirs), dE, chunk);
-  return hipGetLastError();
+  e = hipGetLastError();
+  if (e != hipSuccess || !status) return e;
+  return launch_poison_if_capacity(dE, (long long)nt * 3, status, st);
 }
 
 // ---------------------------------------------------------------- BRDF table

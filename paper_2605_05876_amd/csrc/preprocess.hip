@@ -730,7 +730,8 @@ __global__ void __launch_bounds__(kBackwardThreads, 1) shade_backward_kernel(
 __global__ void __launch_bounds__(256) geometry_backward_kernel(
     PPtrs PP, long long N, const ViewDev* __restrict__ views, int n_views, Params prm,
     const float* __restrict__ grad, const float* __restrict__ sg, GPtrs G,
-    const float* __restrict__ recs, float* __restrict__ ss_out, int* __restrict__ vis_out) {
+    const float* __restrict__ recs, float* __restrict__ ss_out, int* __restrict__ vis_out,
+    const int* __restrict__ status) {
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= N) return;
   float p[3], n[3], t[3], su, sv;
@@ -855,6 +856,11 @@ __global__ void __launch_bounds__(256) geometry_backward_kernel(
     const float inn = 1.f / o.nn;
     for (int j = 0; j < 3; ++j) gn[j] += (gnh[j] - o.nh[j] * ng) * inn;
   }
+  if (status && *status == 3 /* SS_ERR_CAPACITY: the forward's pair list was cut */) {
+    const float q = __builtin_nanf("");
+    for (int k = 0; k < 3; ++k) { gp[k] = gn[k] = gt[k] = grho[k] = q; }
+    gsu = gsv = grough = gmetal = ss_sum = q;
+  }
   if (ss_out) ss_out[s] = ss_sum;
   if (vis_out) vis_out[s] = n_vis;
   for (int k = 0; k < 3; ++k) {
@@ -942,13 +948,13 @@ hipError_t launch_shade_backward(const float* const P[7], long long N, const Vie
 hipError_t launch_geometry_backward(const float* const P[7], long long N, const ViewDev* views,
                                     int n_views, const Params& prm, const float* grad,
                                     const float* sg, float* const G[7], const float* recs,
-                                    float* ss_out, int* vis_out, hipStream_t st) {
+                                    float* ss_out, int* vis_out, const int* status, hipStream_t st) {
   if (N <= 0) return hipSuccess;
   PPtrs PP;
   GPtrs GG;
   for (int k = 0; k < 7; ++k) { PP.p[k] = P[k]; GG.p[k] = G[k]; }
   hipLaunchKernelGGL(geometry_backward_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, PP, N,
-                     views, n_views, prm, grad, sg, GG, recs, ss_out, vis_out);
+                     views, n_views, prm, grad, sg, GG, recs, ss_out, vis_out, status);
   return hipGetLastError();
 }
 

@@ -223,6 +223,10 @@ __device__ __forceinline__ float layer_norm(int shade, float W, float C0, float 
 // nullable).  Depths are accumulated relative to the layer's first fragment,
 // so the variance does not cancel against z^2.
 // PPX: per-pixel-Jacobian MIP filter instead of the centre-precomputed one.
+// A latched SS_ERR_CAPACITY in *status (the pair list was cut short) makes
+// every pixel NaN.  With prm.counters the kernel adds its work to counters[]:
+// (pixel, record) evaluations, accumulated fragments, composited layers (u64)
+// and the sum of their weights (f64 in counters[3]).
 template <int TW, int TH, bool CONS, bool PPX>
 __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     const ViewDev* __restrict__ views, int n_views, int tile_begin, int n_items,
@@ -230,13 +234,15 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     const float* __restrict__ recs, Params prm, int B, float* __restrict__ image,
     float* __restrict__ alpha, uint8_t* __restrict__ nl_out, uint8_t* __restrict__ nl_int,
     float4* __restrict__ stats, float2* __restrict__ stats2, float* __restrict__ cons_out,
-    float* __restrict__ depth_out, int* queue, const int* __restrict__ order, int persistent) {
+    float* __restrict__ depth_out, int* queue, const int* __restrict__ order, int persistent,
+    const int* __restrict__ status, unsigned long long* __restrict__ counters) {
   extern __shared__ float4 lds[];
   __shared__ int s_item;
   constexpr int NT = TW * TH;
   const int t = threadIdx.x, lane = t & 63;
-  const float r2 = prm.r2, kappa = prm.kappa;
+  const float r2 = prm.r2, kappa = prm.kappa, t_min = prm.t_min;
   const int kmax = prm.k_max;
+  const bool poisoned = *status == 3;  // SS_ERR_CAPACITY
   for (int iter = 0;; ++iter) {
     const int item = next_item(queue, persistent, s_item, iter);
     if (item < 0 || item >= n_items) break;
@@ -255,7 +261,11 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     float O0 = 0.f, O1 = 0.f, O2 = 0.f, T = 1.f;
     float zr = 0.f, S1 = 0.f, S2 = 0.f;  // CONS: reference depth, sum w dz, sum w dz^2
     int K = 0;
-    bool done = !inside;
+    bool done = !inside || poisoned;
+    int nF = 0;              // counters: fragments accumulated by this pixel
+    float sumW = 0.f;        // counters: sum of its layers' weights
+    unsigned long long nE = 0;  // counters: (pixel, record) evaluations of the wave (uniform)
+    const int n_in = __popcll(__ballot(inside));
     for (uint32_t b0 = start; b0 < end; b0 += (uint32_t)B) {
       if (__syncthreads_and(done)) break;
       const int cnt = (int)min((uint32_t)B, end - b0);
@@ -264,6 +274,7 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
       for (int c0 = 0; c0 < cnt; c0 += 64) {
         if (__ballot(!done) == 0ull) break;
         uint64_t m = chunk_mask<!PPX>(lds, c0, cnt, lane, sx0, sy0, r2);
+        nE += (unsigned long long)__popcll(m) * (unsigned)n_in;
         while (m) {
           const int j = c0 + __builtin_ctzll(m);
           m &= m - 1;
@@ -291,10 +302,12 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
               }
               T *= e;
               ++K;
+              sumW += Wg;
               C0 = C1 = C2 = 0.f;
               Wg = 0.f;
               zmax = 0.f;
-              if (K >= kmax) done = true;
+              // K_max cap, or the early-out once the transmittance is below t_min
+              if (K >= kmax || T < t_min) done = true;
             }
             if (!done) {
               if constexpr (CONS) {
@@ -309,6 +322,7 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
               C1 += f.w * rec[R_CG];
               C2 += f.w * rec[R_CB];
               Wg += f.w;
+              ++nF;
             }
           }
         }
@@ -327,19 +341,45 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
         }
         T *= e;
         ++K;
+        sumW += Wg;
       }
       if constexpr (CONS) {
         float cs, dp;
         depth_stats_of_pixel(stats + pix * kMaxLayers, stats2 + pix * kMaxLayers, K, kappa, cs, dp);
-        if (cons_out) cons_out[pix] = cs;
-        if (depth_out) depth_out[pix] = dp;
+        if (cons_out) cons_out[pix] = poisoned ? __builtin_nanf("") : cs;
+        if (depth_out) depth_out[pix] = poisoned ? __builtin_nanf("") : dp;
       }
-      image[3 * pix + 0] = O0 + T * v.bg[0];
-      image[3 * pix + 1] = O1 + T * v.bg[1];
-      image[3 * pix + 2] = O2 + T * v.bg[2];
-      alpha[pix] = 1.f - T;
+      float o0 = O0 + T * v.bg[0], o1 = O1 + T * v.bg[1], o2 = O2 + T * v.bg[2];
+      if (prm.tonemap) {
+        o0 = tonemap_srgb_log(o0);
+        o1 = tonemap_srgb_log(o1);
+        o2 = tonemap_srgb_log(o2);
+      }
+      float a = 1.f - T;
+      if (poisoned) o0 = o1 = o2 = a = __builtin_nanf("");
+      image[3 * pix + 0] = o0;
+      image[3 * pix + 1] = o1;
+      image[3 * pix + 2] = o2;
+      alpha[pix] = a;
       nl_int[pix] = (uint8_t)K;
       if (nl_out) nl_out[pix] = (uint8_t)K;
+    }
+    if (prm.counters) {
+      // wave sums, one set of atomics per wave and tile
+      unsigned long long f = (unsigned)nF, k = inside ? (unsigned)K : 0u;
+      float w = inside ? sumW : 0.f;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        f += __shfl_xor(f, off);
+        k += __shfl_xor(k, off);
+        w += __shfl_xor(w, off);
+      }
+      if (lane == 0) {
+        if (nE) atomicAdd(counters + 0, nE);
+        if (f) atomicAdd(counters + 1, f);
+        if (k) atomicAdd(counters + 2, k);
+        if (w != 0.f) atomicAdd(reinterpret_cast<double*>(counters + 3), (double)w);
+      }
     }
   }
 }
@@ -550,6 +590,12 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS) ? 4 : 5))) raster_backward_kerne
       }
       Tfin = T;
       Cf[0] += T * v.bg[0]; Cf[1] += T * v.bg[1]; Cf[2] += T * v.bg[2];
+      if (prm.tonemap) {
+        // d_image is dL/dy for the tone-mapped y; the walk needs dL/dx
+        G[0] *= tonemap_srgb_log_deriv(Cf[0]);
+        G[1] *= tonemap_srgb_log_deriv(Cf[1]);
+        G[2] *= tonemap_srgb_log_deriv(Cf[2]);
+      }
       if (nl > 0) {
         layer_coef(stats[pix * kMaxLayers], 1.f, kappa, G, ga, Tfin, Cf, pre, prm.shade, L);
         if constexpr (CONS) {
@@ -762,11 +808,12 @@ static hipError_t fwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vi
                         int ni, const uint32_t* ranges, const uint32_t* vals, const float* recs,
                         const Params& prm, int B, float* image, float* alpha, uint8_t* nlo,
                         uint8_t* nli, float4* stats, float2* stats2, float* cons, float* depth,
-                        int* queue, const int* order, int pers) {
+                        int* queue, const int* order, int pers, const int* status,
+                        unsigned long long* counters) {
 #define SS_FWD_V(CV, PV)                                                                                 \
   hipLaunchKernelGGL((raster_forward_kernel<TW, TH, CV, PV>), grid, dim3(TW * TH), lds, st, views, nv, tb, ni, \
                      ranges, vals, recs, prm, B, image, alpha, nlo, nli, stats, stats2, cons, depth, queue,    \
-                     order, pers)
+                     order, pers, status, counters)
   if (prm.mip == 1) {
     if (prm.cons) SS_FWD_V(true, true);
     else SS_FWD_V(false, true);
@@ -820,17 +867,19 @@ hipError_t launch_raster_forward(const ViewDev* views, int n_views, int tile_beg
                                  float* image, float* alpha, uint8_t* n_layers_out,
                                  uint8_t* n_layers, float4* layer_stats, float2* layer_stats2,
                                  float* cons, float* depth, int* queue, const int* order,
-                                 int persistent, hipStream_t st) {
+                                 int persistent, const int* status, unsigned long long* counters,
+                                 hipStream_t st) {
   const int n_items = tile_end - tile_begin;
   if (n_items <= 0) return hipSuccess;
   if (prm.cons && (!layer_stats2 || (!cons && !depth))) return hipErrorInvalidValue;
+  if (!status || (prm.counters && !counters)) return hipErrorInvalidValue;
   const int threads = prm.tile_w * prm.tile_h;
   dim3 grid(persistent ? persistent_grid(n_items, threads) : (unsigned)n_items);
   const size_t lds = (size_t)lds_batch * kRecFloats * sizeof(float);
 #define SS_FWD(TW, TH) fwd_t<TW, TH>(grid, lds, st, views, n_views, tile_begin, n_items, ranges, \
                                      sorted_vals, recs, prm, lds_batch, image, alpha,            \
                                      n_layers_out, n_layers, layer_stats, layer_stats2, cons,    \
-                                     depth, queue, order, persistent)
+                                     depth, queue, order, persistent, status, counters)
   switch (prm.tile_w * 100 + prm.tile_h) {
     case 808: return SS_FWD(8, 8);
     case 1608: return SS_FWD(16, 8);

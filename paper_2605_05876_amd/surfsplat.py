@@ -39,7 +39,8 @@ class ss_options(ctypes.Structure):
                 ("sigma_f", ctypes.c_float), ("shade", ctypes.c_int32), ("tile_w", ctypes.c_int32),
                 ("tile_h", ctypes.c_int32), ("lds_batch", ctypes.c_int32), ("launch", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("depth_stats", ctypes.c_int32), ("mip", ctypes.c_int32),
-                ("env_lds", ctypes.c_int32)]
+                ("env_lds", ctypes.c_int32), ("t_min", ctypes.c_float), ("deterministic", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("counters", ctypes.c_int32), ("tonemap", ctypes.c_int32)]
 
 
 class ss_camera(ctypes.Structure):
@@ -63,12 +64,13 @@ class ss_batch(ctypes.Structure):
 
 class ss_outputs(ctypes.Structure):
     _fields_ = [("image", ctypes.c_void_p), ("alpha", ctypes.c_void_p), ("n_layers", ctypes.c_void_p),
-                ("cons", ctypes.c_void_p), ("depth", ctypes.c_void_p)]
+                ("cons", ctypes.c_void_p), ("depth", ctypes.c_void_p),
+                ("generation", ctypes.POINTER(ctypes.c_int64))]
 
 
 class ss_grad_in(ctypes.Structure):
     _fields_ = [("d_image", ctypes.c_void_p), ("d_alpha", ctypes.c_void_p), ("d_cons", ctypes.c_void_p),
-                ("d_depth", ctypes.c_void_p)]
+                ("d_depth", ctypes.c_void_p), ("generation", ctypes.c_int64)]
 
 
 class ss_grads(ctypes.Structure):
@@ -81,7 +83,10 @@ class ss_grads(ctypes.Structure):
 
 class ss_diag(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("n_records", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
-                ("pair_capacity", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
+                ("pair_capacity", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("generation", ctypes.c_int64), ("n_nonfinite", ctypes.c_int64),
+                ("n_evaluated", ctypes.c_int64), ("n_fragments", ctypes.c_int64), ("n_layers", ctypes.c_int64),
+                ("sum_layer_weight", ctypes.c_double)]
 
 
 _LIB = None
@@ -142,18 +147,25 @@ class Options:
     shade: str = "albedo"
     tile_w: int = 16
     tile_h: int = 16
-    lds_batch: int = 128
+    lds_batch: int = 128        # 0: picked by the library at each reserve
     launch: str = "batched"
     persistent: bool = True
     depth_stats: bool = False   # allow forwards to output the eq:cons_loss term
-    mip: str = "centre"         # "centre" (Sec. 3.3.2) | "pixel" (per-pixel Jacobian, forward only)
+    mip: str = "centre"         # "centre" (Sec. 3.3.2) | "pixel" (per-pixel Jacobian, Sec. 3.3.1)
     env_lds: int = -1           # split-sum backward: environment gradient floats kept in LDS (-1: all that fit)
+    t_min: float = 0.0          # transmittance early-out (0: off)
+    deterministic: bool = False  # bitwise reproducible gradients
+    validate: bool = False      # count non-finite inputs (ss_poll: n_nonfinite)
+    counters: bool = False      # count the raster forward's work (ss_poll)
+    tonemap: str = "linear"     # "linear" | "srgb_log" (log-space + sRGB transfer, eq:photo_loss)
 
     def to_c(self) -> ss_options:
         return ss_options(self.r_cut, self.k_max, self.gamma, self.sigma_f, SHADE[self.shade],
                           self.tile_w, self.tile_h, self.lds_batch, LAUNCH[self.launch],
                           1 if self.persistent else 0, 1 if self.depth_stats else 0,
-                          {"centre": 0, "pixel": 1}[self.mip], int(self.env_lds))
+                          {"centre": 0, "pixel": 1}[self.mip], int(self.env_lds), float(self.t_min),
+                          1 if self.deterministic else 0, 1 if self.validate else 0,
+                          1 if self.counters else 0, {"linear": 0, "srgb_log": 1}[self.tonemap])
 
 
 def camera_to_c(cam) -> ss_camera:
@@ -227,12 +239,21 @@ class Batch:
 
 
 class Renderer:
-    """One libsurfsplat context (one stream at a time)."""
+    """One libsurfsplat context (one stream at a time).
+
+    check_capacity: after each forward outside graph capture, poll the device
+    status (this synchronises the stream); when the surfels have moved so far
+    that the reserved pair capacity was exceeded, reserve again and render
+    again, so no truncated image is ever returned.  Under capture (or with
+    check_capacity off) an overflow leaves NaN images and gradients and a
+    status for ss_poll."""
 
     def __init__(self, options: Optional[Options] = None, lut: Optional[torch.Tensor] = None,
-                 lut_size=(64, 64), lut_samples: int = 1024):
+                 lut_size=(64, 64), lut_samples: int = 1024, check_capacity: bool = True):
         self.L = load_library()
         self.options = options or Options()
+        self.check_capacity = check_capacity
+        self.last_generation = 0
         self.ctx = ctypes.c_void_p()
         _check(self.L.ss_create(ctypes.byref(self.options.to_c()), ctypes.byref(self.ctx)), "ss_create")
         self.lut = None
@@ -286,18 +307,31 @@ class Renderer:
             image, alpha, nl, aux = out
         else:
             image, alpha, nl = out
+        gen = ctypes.c_int64(0)
         o = ss_outputs(image.data_ptr(), alpha.data_ptr(), None if nl is None else nl.data_ptr(),
-                       _ptr(aux.get("cons")), _ptr(aux.get("depth")))
+                       _ptr(aux.get("cons")), _ptr(aux.get("depth")), ctypes.pointer(gen))
         _check(self.L.ss_render(self.ctx, ctypes.byref(batch.c), ctypes.byref(o), _stream_ptr()), "ss_render")
+        if self.check_capacity and not torch.cuda.is_current_stream_capturing():
+            d = self.poll()
+            if d["device_status"] == SS_ERR_CAPACITY:
+                self.reserve(batch)
+                _check(self.L.ss_render(self.ctx, ctypes.byref(batch.c), ctypes.byref(o), _stream_ptr()),
+                       "ss_render")
+                d = self.poll()
+            _check(d["device_status"], "ss_render (device)")
+        self.last_generation = int(gen.value)
         return (image, alpha, nl, aux) if aux else (image, alpha, nl)
 
     def backward(self, batch: Batch, d_image: torch.Tensor, d_alpha: Optional[torch.Tensor] = None,
                  grads: Optional[dict] = None, want_envmap: bool = True, want_screen_grad: bool = False,
-                 d_cons: Optional[torch.Tensor] = None, d_depth: Optional[torch.Tensor] = None):
+                 d_cons: Optional[torch.Tensor] = None, d_depth: Optional[torch.Tensor] = None,
+                 generation: int = 0):
         """Parameter gradients of the last forward.  With want_screen_grad (or
         "screen_grad" / "visible_views" tensors in `grads`) also the
         densification statistic of Sec. 3.6.1: float32 [N] sum over views and
-        pixels of |(dL_p/dT1z, dL_p/dT2z)| T4z and int32 [N] visible-view count."""
+        pixels of |(dL_p/dT1z, dL_p/dT2z)| T4z and int32 [N] visible-view count.
+        generation: the number the forward reported (0: the last forward); a
+        stale one raises SurfsplatError (SS_ERR_STATE)."""
         dev = batch.params["position"].device
         if grads is None:
             grads = {k: torch.empty_like(batch.params[k]) for k in PARAMS}
@@ -313,7 +347,7 @@ class Renderer:
         d_depth = None if d_depth is None else d_depth.contiguous()
         gi = ss_grad_in(d_image.data_ptr(), None if d_alpha is None else d_alpha.data_ptr(),
                         None if d_cons is None else d_cons.data_ptr(),
-                        None if d_depth is None else d_depth.data_ptr())
+                        None if d_depth is None else d_depth.data_ptr(), int(generation))
         g = ss_grads()
         for k in PARAMS:
             setattr(g, "d_" + k, None if grads.get(k) is None else grads[k].data_ptr())
@@ -331,7 +365,9 @@ class Renderer:
         d = ss_diag()
         s = self.L.ss_poll(self.ctx, ctypes.byref(d))
         return dict(status=int(s), device_status=d.status, n_records=d.n_records, n_pairs=d.n_pairs,
-                    pair_capacity=d.pair_capacity, workspace_bytes=d.workspace_bytes)
+                    pair_capacity=d.pair_capacity, workspace_bytes=d.workspace_bytes, generation=d.generation,
+                    n_nonfinite=d.n_nonfinite, n_evaluated=d.n_evaluated, n_fragments=d.n_fragments,
+                    n_layers=d.n_layers, sum_layer_weight=d.sum_layer_weight)
 
     def profile(self, enable: bool = True):
         _check(self.L.ss_profile_enable(self.ctx, 1 if enable else 0), "ss_profile_enable")
@@ -388,6 +424,9 @@ class SurfelRenderFunction(torch.autograd.Function):
         ctx.renderer = renderer
         ctx.batch = batch
         ctx.n_env = len(envmaps)
+        # the backward must find this forward's state (a second render through the
+        # same renderer before backward replaces it: the library then refuses)
+        ctx.generation = renderer.last_generation
         return image, alpha
 
     @staticmethod
@@ -395,7 +434,7 @@ class SurfelRenderFunction(torch.autograd.Function):
         batch = ctx.batch
         if d_image is None:
             d_image = torch.zeros((batch.n_pixels, 3), device=batch.params["position"].device)
-        g = ctx.renderer.backward(batch, d_image, d_alpha, want_envmap=ctx.n_env > 0)
+        g = ctx.renderer.backward(batch, d_image, d_alpha, want_envmap=ctx.n_env > 0, generation=ctx.generation)
         env = g.get("envmap") or []
         return (None, None, None, g["position"], g["normal"], g["tangent"], g["scale"], g["albedo"],
                 g["roughness"], g["metallic"], *env)

@@ -34,7 +34,8 @@ MAX_MASKED = 1e-3
 def oracle_options(O, opts):
     return O.Options(r_cut=opts.r_cut, gamma=opts.gamma, sigma_f=opts.sigma_f, k_max=opts.k_max,
                      shade=opts.shade, tile_w=opts.tile_w, tile_h=opts.tile_h,
-                     mip=getattr(opts, "mip", "centre"))
+                     mip=getattr(opts, "mip", "centre"), t_min=getattr(opts, "t_min", 0.0),
+                     tonemap=getattr(opts, "tonemap", "linear"))
 
 
 def oracle_maps(O, scenes, shade):
