@@ -59,7 +59,9 @@ typedef enum ss_status {
   SS_ERR_CAPACITY = 3,    /* pair capacity too small; ss_reserve and call again  */
   SS_ERR_STATE = 4,       /* call out of order (backward without forward, ...)   */
   SS_ERR_UNSUPPORTED = 5, /* an option value this build does not implement       */
-  SS_ERR_NOMEM = 6        /* device allocation failed                            */
+  SS_ERR_NOMEM = 6,       /* device allocation failed                            */
+  SS_ERR_STATIC_LIMIT = 7 /* the batch does not fit the fixed workspace of
+                             ss_render_static                                   */
 } ss_status;
 
 typedef enum ss_shade_mode {
@@ -172,7 +174,7 @@ typedef struct ss_outputs {
    * covered part).  Needs options.depth_stats = 1. */
   float* depth;
   /* host, or NULL: receives the generation number of this forward (1, 2, ...
-   * per context) */
+   * per context); ss_render_static writes 0 (it leaves no state for a backward) */
   int64_t* generation;
 } ss_outputs;
 
@@ -224,6 +226,10 @@ typedef struct ss_diag {
   int64_t n_fragments;   /* fragments accumulated into composited layers (F)      */
   int64_t n_layers;      /* layers composited over all pixels                     */
   double sum_layer_weight; /* sum of their accumulated weights W_k (eq:alpha)     */
+  /* the last ss_render_static on the current device (any context): */
+  int32_t static_status; /* its latched status (SS_OK or SS_ERR_CAPACITY)        */
+  int64_t static_pairs;  /* its (tile, surfel) pair count                        */
+  int64_t static_pair_capacity;
 } ss_diag;
 
 typedef struct ss_context ss_context;
@@ -274,6 +280,25 @@ ss_status ss_render_backward(ss_context* ctx, const ss_batch* batch, const ss_gr
 
 /* Synchronises the context's last stream and reports the latched status. */
 ss_status ss_poll(ss_context* ctx, ss_diag* out);
+
+/* Allocation-free forward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same computation as ss_render, with every buffer of its
+ * workspace taken from one fixed device array of SS_STATIC_SCRATCH_BYTES per
+ * GPU (held by each GPU the library runs on until the process ends) instead of
+ * the context's workspace: it calls no allocating routine and does not
+ * synchronise.  The context supplies only its options and BRDF table, and its
+ * own forward state is left as it was (a backward still refers to the last
+ * ss_render).  Limits: batched launch mode (else SS_ERR_UNSUPPORTED); records,
+ * pixels, tiles and environment levels must fit the array with room for at
+ * least 4096 pairs, else SS_ERR_STATIC_LIMIT before any device work.  The
+ * pair capacity is what the array has left; an overflow latches
+ * SS_ERR_CAPACITY (ss_poll: static_status) and the image and alpha are NaN.
+ * Every call on a GPU shares that GPU's array and clears what must start at
+ * zero; calls that overlap in time on one GPU (two streams, two threads)
+ * race and their results are undefined. */
+#define SS_STATIC_SCRATCH_BYTES (32u << 20)
+ss_status ss_render_static(ss_context* ctx, const ss_batch* batch, const ss_outputs* out, ss_stream stream);
 
 /* Test access to the last forward's binning: record keys (depth-interval start
  * bits, or 0xffffffff when culled), per-record pixel rectangles (int32

@@ -6,7 +6,8 @@ torch.autograd.Function around it.
 """
 from .surfsplat import (Batch, Options, Renderer, SurfsplatError, SurfelRenderFunction,  # noqa: F401
                         load_library, make_brdf_lut, render, PARAMS, SS_OK, SS_ERR_INVALID_ARG, SS_ERR_HIP,
-                        SS_ERR_CAPACITY, SS_ERR_STATE, SS_ERR_UNSUPPORTED, SS_ERR_NOMEM)
+                        SS_ERR_CAPACITY, SS_ERR_STATE, SS_ERR_UNSUPPORTED, SS_ERR_NOMEM,
+                        SS_ERR_STATIC_LIMIT, STATIC_SCRATCH_BYTES)
 
 
 def batch_from_scenes(scenes, cameras, device="cuda", with_envmap=None):

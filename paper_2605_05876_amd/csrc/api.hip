@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -638,6 +639,99 @@ ss_status forward_body(ss_context* c, const ss_batch* b, const ss_outputs* out, 
   }
   return SS_OK;
 }
+
+// ---------------------------------------------------------------- fixed workspace
+// The workspace of ss_render_static: one file-scope device array per GPU (the
+// code object's global segment, held until the process ends).  Host code
+// never uses the name `scratch` as an address: it is a host-side stand-in.
+// Each device's own address comes from hipGetSymbolAddress, taken once per
+// device with that device current, and only that address reaches kernels.
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+long long g_static_cap[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[SS_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+// Address of the current device's copy of `scratch`.
+ss_status static_scratch(void** out, int* dev_out) {
+  int dev = 0;
+  SS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return SS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    SS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return SS_ERR_HIP;
+    g_static_ptr[dev] = p;
+  }
+  *out = g_static_ptr[dev];
+  *dev_out = dev;
+  return SS_OK;
+}
+
+// Buffers cut in order from one region (256-byte aligned); `ok` turns false
+// once a request does not fit.
+struct Carver {
+  char* base;
+  size_t cap;
+  size_t used = 0;
+  bool ok = true;
+  void take(DevBuf& b, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    const size_t off = (used + 255) & ~size_t(255);
+    if (!ok || off > cap || bytes > cap - off) {
+      ok = false;
+      b.p = nullptr;
+      b.n = 0;
+      return;
+    }
+    b.p = base + off;
+    b.n = bytes;
+    used = off + bytes;
+  }
+};
+
+// View descriptors travel as kernel arguments (no host-to-device copy, so the
+// call also works under graph capture), kViewsPerStore at a time.
+constexpr int kViewsPerStore = 8;
+struct ViewStore {
+  ViewDev v[kViewsPerStore];
+  int n;
+};
+static_assert(sizeof(ViewStore) <= 3072, "view store exceeds the kernel-argument budget");
+__global__ void store_views_kernel(ViewStore src, ViewDev* dst) {
+  const int words = src.n * (int)(sizeof(ViewDev) / sizeof(uint32_t));
+  for (int i = threadIdx.x; i < words; i += blockDim.x)
+    reinterpret_cast<uint32_t*>(dst)[i] = reinterpret_cast<const uint32_t*>(src.v)[i];
+}
+
+// ss_poll's view of the last ss_render_static on the current device: the
+// status and pair-count words sit at the start of the array.
+ss_status static_poll(ss_diag* out) {
+  int dev = 0;
+  SS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return SS_OK;
+  void* p = nullptr;
+  long long cap = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    p = g_static_ptr[dev];
+    cap = g_static_cap[dev];
+  }
+  if (!p || cap == 0) return SS_OK;
+  SS_HIP(hipDeviceSynchronize());
+  uint32_t m[kMiscPairs + 1];
+  SS_HIP(hipMemcpy(m, p, sizeof(m), hipMemcpyDeviceToHost));
+  out->static_status = (int32_t)m[kMiscStatus];
+  out->static_pairs = m[kMiscPairs];
+  out->static_pair_capacity = cap;
+  return SS_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -882,6 +976,7 @@ ss_status ss_poll(ss_context* c, ss_diag* out) {
   out->pair_capacity = c->pair_total;
   out->workspace_bytes = (int64_t)workspace_bytes(c);
   out->generation = c->generation;
+  SS_TRY(static_poll(out));
   return out->status == 0 ? SS_OK : (ss_status)out->status;
 }
 
@@ -915,6 +1010,109 @@ ss_status ss_profile_read(ss_context* c, double* ms, int64_t* count) {
 }
 
 }  // extern "C"
+
+
+// Allocation-free forward: the workspace of one batched group is carved from
+// the current device's `scratch` (status words first), the pair capacity is
+// whatever is left, and the pipeline is forward_body, as in ss_render.
+extern "C" ss_status ss_render_static(ss_context* c, const ss_batch* b, const ss_outputs* out,
+                                      ss_stream stream) {
+  if (!c || !out || !out->image || !out->alpha) return SS_ERR_INVALID_ARG;
+  if ((out->cons || out->depth) && !c->opt.depth_stats) return SS_ERR_INVALID_ARG;
+  SS_TRY(check_batch(c, b));
+  if (c->opt.shade == SS_SHADE_SPLITSUM && !c->lut.p) return SS_ERR_STATE;
+  if (c->opt.launch != SS_LAUNCH_BATCHED) return SS_ERR_UNSUPPORTED;
+  void* base = nullptr;
+  int dev = 0;
+  SS_TRY(static_scratch(&base, &dev));
+  hipStream_t st = (hipStream_t)stream;
+  // a workspace over the array; nothing below allocates device memory, and
+  // none of its buffers is ever released
+  ss_context w;
+  w.opt = c->opt;
+  w.lut = c->lut;
+  w.lut_nv = c->lut_nv;
+  w.lut_r = c->lut_r;
+  Carver cv{static_cast<char*>(base), (size_t)SS_STATIC_SCRATCH_BYTES};
+  cv.take(w.misc, kMiscWords * sizeof(uint32_t));
+  if (c->opt.shade == SS_SHADE_SPLITSUM) {
+    w.env.resize(b->n_scenes);
+    for (int s = 0; s < b->n_scenes; ++s) {
+      SceneEnv& e = w.env[s];
+      const int He = b->env_hw[2 * s], We = b->env_hw[2 * s + 1];
+      long long lv_n = 0, dlv_n = 0;
+      env_layout(&w, b, s, e, &lv_n, &dlv_n);
+      cv.take(e.lv, lv_n * sizeof(float));
+      cv.take(e.Z, (size_t)(lv_n / 3 + 1) * 4 * sizeof(float));
+      cv.take(e.part, (size_t)envmap_prefilter_chunks(He, We) * (size_t)lv_n * sizeof(float));
+      cv.take(e.dirs, (size_t)He * We * 4 * sizeof(float));
+      e.He = He;
+      e.We = We;
+    }
+  }
+  std::vector<ViewDev> vh;
+  plan_batch(&w, b, vh);
+  const long long R = w.R > 0 ? w.R : 1;
+  const long long npix = w.n_pix > 0 ? w.n_pix : 1, ntiles = w.n_tiles > 0 ? w.n_tiles : 1;
+  cv.take(w.views_d, sizeof(ViewDev) * b->n_views);
+  cv.take(w.recs, (size_t)R * kRecFloats * sizeof(float));
+  for (DevBuf* d : {&w.counts, &w.offsets, &w.zkey, &w.zkey2, &w.zidx, &w.zidx2})
+    cv.take(*d, (size_t)R * sizeof(uint32_t));
+  cv.take(w.prect, (size_t)R * sizeof(uint2));
+  cv.take(w.zrect, (size_t)R * sizeof(uint2));
+  cv.take(w.ranges, (size_t)2 * ntiles * sizeof(uint32_t));
+  cv.take(w.order, (size_t)ntiles * sizeof(int));
+  cv.take(w.nl, (size_t)npix);
+  cv.take(w.stats, (size_t)npix * kMaxLayers * sizeof(float4));
+  if (c->opt.depth_stats) cv.take(w.stats2, (size_t)npix * kMaxLayers * sizeof(float2));
+  if (!cv.ok) return SS_ERR_STATIC_LIMIT;
+  // pairs (keys and values, double-buffered): what is left after the sort's
+  // histogram and scan scratch for that capacity
+  Group& g = w.groups[0];
+  const long long nrec = g.rec_end - g.rec_begin;
+  const size_t left = cv.cap - ((cv.used + 255) & ~size_t(255));
+  auto hist_for = [&](long long cp) {
+    return radix_hist_size(cp) > radix_hist_size(nrec) ? radix_hist_size(cp) : radix_hist_size(nrec);
+  };
+  auto need = [&](long long cp) {
+    const long long h = hist_for(cp), sc = scan_tmp_size(h > R ? h : R) + 16;
+    return (size_t)(16 * cp + 4 * h + 4 * sc) + 8 * 256;
+  };
+  long long cap = (long long)(left / 16);
+  while (cap > 0 && need(cap) > left) cap -= cap / 64 > 0 ? cap / 64 : 1;
+  if (cap < 4096) return SS_ERR_STATIC_LIMIT;
+  g.pair_base = 0;
+  g.pair_cap = cap;
+  w.pair_total = cap;
+  w.hist_n = hist_for(cap);
+  w.scan_tmp_n = scan_tmp_size(w.hist_n > R ? w.hist_n : R) + 16;
+  for (DevBuf* d : {&w.keys, &w.keys2, &w.vals, &w.vals2}) cv.take(*d, (size_t)cap * sizeof(uint32_t));
+  cv.take(w.hist, (size_t)w.hist_n * sizeof(uint32_t));
+  cv.take(w.scan_tmp, (size_t)w.scan_tmp_n * sizeof(uint32_t));
+  if (!cv.ok) return SS_ERR_STATIC_LIMIT;
+  // view table (its map pointers point into the array), direction tables
+  for (int v0 = 0; v0 < b->n_views; v0 += kViewsPerStore) {
+    ViewStore vs;
+    std::memset(&vs, 0, sizeof(vs));
+    vs.n = b->n_views - v0 < kViewsPerStore ? b->n_views - v0 : kViewsPerStore;
+    for (int i = 0; i < vs.n; ++i) vs.v[i] = vh[v0 + i];
+    hipLaunchKernelGGL(store_views_kernel, dim3(1), dim3(256), 0, st, vs, P<ViewDev>(w.views_d) + v0);
+    SS_HIP(hipGetLastError());
+  }
+  w.views_h = vh;
+  w.views_uploaded = true;
+  for (SceneEnv& e : w.env) {
+    SS_HIP(launch_envmap_dirs(P<float>(e.dirs), e.He, e.We, st));
+    SS_HIP(launch_envmap_out_dirs(e.He, e.We, P<float>(e.dirs), e.lh, e.lw, P<float>(e.Z), st));
+  }
+  SS_TRY(forward_body(&w, b, out, st));
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    g_static_cap[dev] = cap;
+  }
+  if (out->generation) *out->generation = 0;
+  return SS_OK;
+}
 
 // ---------------------------------------------------------------- test access
 namespace {
@@ -992,6 +1190,7 @@ extern "C" const char* ss_status_str(ss_status s) {
     case SS_ERR_STATE: return "call out of order";
     case SS_ERR_UNSUPPORTED: return "unsupported option";
     case SS_ERR_NOMEM: return "device allocation failed";
+    case SS_ERR_STATIC_LIMIT: return "batch exceeds the fixed workspace of ss_render_static";
   }
   return "unknown status";
 }

@@ -17,13 +17,15 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsurfsplat.so")
 
-SS_OK, SS_ERR_INVALID_ARG, SS_ERR_HIP, SS_ERR_CAPACITY, SS_ERR_STATE, SS_ERR_UNSUPPORTED, SS_ERR_NOMEM = range(7)
+(SS_OK, SS_ERR_INVALID_ARG, SS_ERR_HIP, SS_ERR_CAPACITY, SS_ERR_STATE, SS_ERR_UNSUPPORTED, SS_ERR_NOMEM,
+ SS_ERR_STATIC_LIMIT) = range(8)
 SHADE = {"albedo": 0, "splitsum": 1, "normal": 2}
 LAUNCH = {"batched": 0, "per_view": 1}
 
 EXPORTED = ["ss_default_options", "ss_create", "ss_destroy", "ss_set_options", "ss_brdf_lut",
             "ss_set_brdf_lut", "ss_reserve", "ss_render", "ss_render_backward", "ss_poll",
-            "ss_debug_binning", "ss_profile_enable", "ss_profile_read", "ss_status_str"]
+            "ss_render_static", "ss_debug_binning", "ss_profile_enable", "ss_profile_read", "ss_status_str"]
+STATIC_SCRATCH_BYTES = 32 << 20  # SS_STATIC_SCRATCH_BYTES
 STAGES = ["envmap", "preprocess", "binning", "raster_forward", "raster_backward",
           "preprocess_backward", "envmap_backward"]
 
@@ -86,7 +88,8 @@ class ss_diag(ctypes.Structure):
                 ("pair_capacity", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("generation", ctypes.c_int64), ("n_nonfinite", ctypes.c_int64),
                 ("n_evaluated", ctypes.c_int64), ("n_fragments", ctypes.c_int64), ("n_layers", ctypes.c_int64),
-                ("sum_layer_weight", ctypes.c_double)]
+                ("sum_layer_weight", ctypes.c_double), ("static_status", ctypes.c_int32),
+                ("static_pairs", ctypes.c_int64), ("static_pair_capacity", ctypes.c_int64)]
 
 
 _LIB = None
@@ -113,6 +116,7 @@ def load_library(path: str = LIB_PATH):
     L.ss_render_backward.argtypes = [vp, ctypes.POINTER(ss_batch), ctypes.POINTER(ss_grad_in),
                                      ctypes.POINTER(ss_grads), vp]
     L.ss_poll.argtypes = [vp, ctypes.POINTER(ss_diag)]
+    L.ss_render_static.argtypes = [vp, ctypes.POINTER(ss_batch), ctypes.POINTER(ss_outputs), vp]
     L.ss_debug_binning.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int64), vp]
     L.ss_profile_enable.argtypes = [vp, ctypes.c_int32]
@@ -322,6 +326,23 @@ class Renderer:
         self.last_generation = int(gen.value)
         return (image, alpha, nl, aux) if aux else (image, alpha, nl)
 
+    def render_static(self, batch: Batch, out=None, want_layers: bool = False):
+        """Forward through ss_render_static (no device allocation in the library:
+        the workspace is its fixed per-GPU array).  Returns image, alpha and the
+        layer counts (if want_layers); `out` may pass (image, alpha, n_layers)."""
+        dev = batch.params["position"].device
+        if out is None:
+            image = torch.empty((batch.n_pixels, 3), device=dev, dtype=torch.float32)
+            alpha = torch.empty((batch.n_pixels,), device=dev, dtype=torch.float32)
+            nl = torch.empty((batch.n_pixels,), device=dev, dtype=torch.uint8) if want_layers else None
+        else:
+            image, alpha, nl = out
+        o = ss_outputs(image.data_ptr(), alpha.data_ptr(), None if nl is None else nl.data_ptr(), None, None,
+                       None)
+        _check(self.L.ss_render_static(self.ctx, ctypes.byref(batch.c), ctypes.byref(o), _stream_ptr()),
+               "ss_render_static")
+        return image, alpha, nl
+
     def backward(self, batch: Batch, d_image: torch.Tensor, d_alpha: Optional[torch.Tensor] = None,
                  grads: Optional[dict] = None, want_envmap: bool = True, want_screen_grad: bool = False,
                  d_cons: Optional[torch.Tensor] = None, d_depth: Optional[torch.Tensor] = None,
@@ -367,7 +388,8 @@ class Renderer:
         return dict(status=int(s), device_status=d.status, n_records=d.n_records, n_pairs=d.n_pairs,
                     pair_capacity=d.pair_capacity, workspace_bytes=d.workspace_bytes, generation=d.generation,
                     n_nonfinite=d.n_nonfinite, n_evaluated=d.n_evaluated, n_fragments=d.n_fragments,
-                    n_layers=d.n_layers, sum_layer_weight=d.sum_layer_weight)
+                    n_layers=d.n_layers, sum_layer_weight=d.sum_layer_weight, static_status=d.static_status,
+                    static_pairs=d.static_pairs, static_pair_capacity=d.static_pair_capacity)
 
     def profile(self, enable: bool = True):
         _check(self.L.ss_profile_enable(self.ctx, 1 if enable else 0), "ss_profile_enable")

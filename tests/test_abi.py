@@ -97,6 +97,7 @@ def test_host_argument_checks(lib):
     assert lib.ss_create(ctypes.byref(o), ctypes.byref(ctx)) == 0
     # null batch / outputs are rejected before any device work
     assert lib.ss_render(ctx, None, None, None) == s.SS_ERR_INVALID_ARG
+    assert lib.ss_render_static(ctx, None, None, None) == s.SS_ERR_INVALID_ARG
     assert lib.ss_render_backward(ctx, None, None, None, None) == s.SS_ERR_INVALID_ARG
     b = s.ss_batch()
     b.n_scenes = 1
@@ -120,3 +121,4 @@ def test_host_argument_checks(lib):
     assert lib.ss_render_backward(ctx, ctypes.byref(b), ctypes.byref(gin), ctypes.byref(gr), None) == s.SS_ERR_STATE
     assert lib.ss_destroy(ctx) == 0
     assert lib.ss_status_str(3).decode().startswith("pair capacity")
+    assert "ss_render_static" in lib.ss_status_str(7).decode()
