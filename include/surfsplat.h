@@ -96,8 +96,8 @@ typedef struct ss_options {
   int32_t mip;         /* 0: centre-precomputed MIP filter (Sec. 3.3.2, default);
                           1: per-pixel Jacobian (Sec. 3.3.1): J = d(u,v)/d(x,y) at
                           every intersection, support = the binning rectangle of the
-                          centre filter intersected with rho^2 < r_cut^2.  Forward
-                          only: ss_render_backward returns SS_ERR_UNSUPPORTED     */
+                          centre filter intersected with rho^2 < r_cut^2; the
+                          backward differentiates the per-pixel filter as well   */
   int32_t env_lds;     /* split-sum backward: floats of environment-level gradients
                           the shading adjoint may accumulate in a block-private LDS
                           copy (levels in the order irradiance, 5, 4, ..., 0, each

@@ -870,7 +870,6 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
                              const ss_grads* gr, ss_stream stream) {
   if (!c || !gin || !gin->d_image || !gr) return SS_ERR_INVALID_ARG;
   SS_TRY(check_batch(c, b));
-  if (c->opt.mip != 0) return SS_ERR_UNSUPPORTED;
   if (!c->fwd_valid || signature(c, b) != c->fwd_sig) return SS_ERR_STATE;
   if (gin->generation != 0 && gin->generation != c->generation) return SS_ERR_STATE;
   if ((gin->d_cons || gin->d_depth) && !c->fwd_cons) return SS_ERR_STATE;

@@ -59,7 +59,7 @@ struct Params {
   int lut_nv, lut_r;
   int ss_grad;  // backward: accumulate the screen-space gradient statistic in slot G_SS
   int cons;     // forward: depth statistics (eq:cons_loss, depth image); backward: their adjoint
-  int mip;      // 0: centre-precomputed MIP filter; 1: per-pixel Jacobian
+  int mip;      // 0: centre-precomputed MIP filter; 1: per-pixel Jacobian (forward and backward)
   float t_min;  // transmittance early-out (0: off)
   int tonemap;  // 1: log-space + sRGB transfer of the image (and its derivative in the backward)
   int counters; // forward: count evaluated pairs, fragments, layers and their weight
@@ -238,6 +238,70 @@ __device__ __forceinline__ void frag_eval_pp(const float* rec, int px, int py, f
   const float nfc = rec[R_NF];
   f.e = __expf(-0.5f * f.q);
   f.w = sqrtf(s2 * s2 * s2 * nfc * nfc * iq * idetS) * f.e;
+}
+
+// Adjoint of frag_eval_pp's weight for one fragment: G = w dL/dw (0 for a
+// fragment that contributes nothing), written as dL/d(record field) into
+// g[G_X0 .. G_NF].  With iq = 1/det Q, B = Q^{-1} - sigma_f I, P = I + d a^T,
+// H = P B P^T and S = s^2 H + sigma_f I (the quantities of frag_eval_pp),
+//   log w = log n_f + 3 log s + (log iq - log det S)/2 - q/2,
+//   q = s^2 (S22 dx^2 - 2 S12 dx dy + S11 dy^2) / det S,
+// and the adjoint of H = P B P^T is dL/dP = 2 Gam P B, dL/dB = P^T Gam P with
+// Gam the symmetric matrix of dL/dH (off-diagonal halved).  A lane with
+// G = 0 evaluates the chain at d = 0 so every output is an exact zero.
+__device__ inline void frag_grad_pp(const float* rec, int px, int py, float sigma, float G, bool live,
+                                    float* g) {
+  const int il = __float_as_int(rec[R_RX]) & 0xffff, jl = __float_as_int(rec[R_RY]) & 0xffff;
+  const float dx = live ? ((float)(px - il) + 0.5f) - rec[R_X0] : 0.f;
+  const float dy = live ? ((float)(py - jl) + 0.5f) - rec[R_Y0] : 0.f;
+  const float a3 = rec[R_A3], b3 = rec[R_B3];
+  const float s = __builtin_fmaf(a3, dx, __builtin_fmaf(b3, dy, 1.0f));
+  const float qxx = rec[R_QXX], qxy = 0.5f * rec[R_QXY2], qyy = rec[R_QYY];
+  const float iq = 1.f / (qxx * qyy - qxy * qxy);
+  const float B11 = qyy * iq - sigma, B12 = -qxy * iq, B22 = qxx * iq - sigma;
+  const float P11 = 1.f + dx * a3, P12 = dx * b3, P21 = dy * a3, P22 = 1.f + dy * b3;
+  const float X11 = P11 * B11 + P12 * B12, X12 = P11 * B12 + P12 * B22;
+  const float X21 = P21 * B11 + P22 * B12, X22 = P21 * B12 + P22 * B22;
+  const float H11 = X11 * P11 + X12 * P12, H12 = X11 * P21 + X12 * P22, H22 = X21 * P21 + X22 * P22;
+  const float s2 = s * s;
+  const float S11 = s2 * H11 + sigma, S12 = s2 * H12, S22 = s2 * H22 + sigma;
+  const float idetS = 1.f / (S11 * S22 - S12 * S12);
+  const float Nn = S22 * dx * dx - 2.f * S12 * dx * dy + S11 * dy * dy;
+  const float q = s2 * Nn * idetS;
+  const float gq = -0.5f * G;                                 // dL/dq
+  const float gdet = -(0.5f * G + gq * q) * idetS;            // dL/d det S
+  const float gN = gq * s2 * idetS;                           // dL/dNn
+  float gs2 = gq * Nn * idetS;
+  float gdx = 2.f * gN * (S22 * dx - S12 * dy);
+  float gdy = 2.f * gN * (S11 * dy - S12 * dx);
+  const float gS11 = gN * dy * dy + gdet * S22;
+  const float gS22 = gN * dx * dx + gdet * S11;
+  const float gS12 = -2.f * (gN * dx * dy + gdet * S12);
+  gs2 += gS11 * H11 + gS12 * H12 + gS22 * H22;
+  const float T11 = s2 * gS11, T12 = 0.5f * s2 * gS12, T22 = s2 * gS22;  // Gam
+  const float gP11 = 2.f * (T11 * X11 + T12 * X21), gP12 = 2.f * (T11 * X12 + T12 * X22);
+  const float gP21 = 2.f * (T12 * X11 + T22 * X21), gP22 = 2.f * (T12 * X12 + T22 * X22);
+  const float Y11 = T11 * P11 + T12 * P21, Y12 = T11 * P12 + T12 * P22;
+  const float Y21 = T12 * P11 + T22 * P21, Y22 = T12 * P12 + T22 * P22;
+  const float gB11 = P11 * Y11 + P21 * Y21, gB12 = 2.f * (P11 * Y12 + P21 * Y22), gB22 = P12 * Y12 + P22 * Y22;
+  // B = Q^{-1} - sigma_f I with Q^{-1} = iq [[qyy, -qxy], [-qxy, qxx]]; iq = 1/det Q
+  float gqxx = gB22 * iq, gqyy = gB11 * iq, gqxy = -gB12 * iq;
+  const float t = -(gB11 * qyy - gB12 * qxy + gB22 * qxx) * iq * iq - 0.5f * G * iq;
+  gqxx += t * qyy;
+  gqyy += t * qxx;
+  gqxy -= 2.f * t * qxy;
+  // s = 1 + a . d, P = I + d a^T
+  const float gs = 3.f * G * __builtin_amdgcn_rcpf(s) + 2.f * s * gs2;
+  gdx += gP11 * a3 + gP12 * b3 + gs * a3;
+  gdy += gP21 * a3 + gP22 * b3 + gs * b3;
+  g[G_X0] = -gdx;
+  g[G_Y0] = -gdy;
+  g[G_QXX] = gqxx;
+  g[G_QXY2] = 0.5f * gqxy;
+  g[G_QYY] = gqyy;
+  g[G_A3] = gP11 * dx + gP21 * dy + gs * dx;
+  g[G_B3] = gP12 * dx + gP22 * dy + gs * dy;
+  g[G_NF] = G / rec[R_NF];
 }
 
 __device__ __forceinline__ int view_of_tile(const ViewDev* views, int nv, int tile) {

@@ -139,14 +139,19 @@ __device__ __forceinline__ uint64_t chunk_mask(const float4* lds, int c0, int cn
 // Row-level compaction (backward): after the sub-tile test, lane j tests
 // record c0 + j's rectangle against the four quadrants; m[r] is the
 // (wave-uniform) set of records row r visits, in list order.  (Ellipse tests
-// per quadrant cost more than the steps they save.)
+// per quadrant cost more than the steps they save.)  ELLIPSE: the sub-tile
+// test includes the centre filter's acceptance ellipse (not for the
+// per-pixel-Jacobian filter, whose acceptance set differs).
+template <bool ELLIPSE = true>
 __device__ __forceinline__ void chunk_masks(const float4* lds, int c0, int cnt, int lane, int sx0, int sy0,
                                             float r2, uint64_t m[4]) {
   const int j = c0 + lane;
   bool o0 = false, o1 = false, o2 = false, o3 = false;
   if (j < cnt) {
     const float4 q3 = lds[4 * j + 3];
-    if (rect_meets<8>(q3, sx0, sy0) && ellipse_meets<8>(lds[4 * j], lds[4 * j + 1], q3, sx0, sy0, r2)) {
+    bool meets = rect_meets<8>(q3, sx0, sy0);
+    if constexpr (ELLIPSE) meets = meets && ellipse_meets<8>(lds[4 * j], lds[4 * j + 1], q3, sx0, sy0, r2);
+    if (meets) {
       o0 = rect_meets<4>(q3, sx0, sy0);
       o1 = rect_meets<4>(q3, sx0 + 4, sy0);
       o2 = rect_meets<4>(q3, sx0, sy0 + 4);
@@ -530,11 +535,12 @@ __device__ inline void cons_coef(const float4* __restrict__ st, const float2* __
 // SS: also accumulate the densification statistic in slot G_SS.
 // CONS: add the adjoint of the depth statistics (loss weights d_cons on the
 // consolidation term, d_depth on the composited depth; either may be null).
+// PPX: the per-pixel-Jacobian MIP filter (frag_eval_pp and its adjoint).
 // Occupancy target: 5 waves per SIMD (up to 102 VGPRs per lane), 4 with the
-// extra statistics.
-template <int TW, int TH, bool SS, bool CONS>
+// extra statistics or the per-pixel filter.
+template <int TW, int TH, bool SS, bool CONS, bool PPX>
 __global__ void __launch_bounds__(TW* TH)
-__attribute__((amdgpu_waves_per_eu((SS || CONS) ? 4 : 5))) raster_backward_kernel(
+__attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backward_kernel(
     const ViewDev* __restrict__ views, int n_views, int tile_begin, int n_items,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float* __restrict__ recs, Params prm, int B, const float* __restrict__ d_image,
@@ -619,14 +625,17 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS) ? 4 : 5))) raster_backward_kerne
       for (int c0 = 0; c0 < cnt; c0 += 64) {
         if (__ballot(!done) == 0ull) break;
         uint64_t m[4];
-        chunk_masks(lds, c0, cnt, lane, sx0, sy0, r2, m);
+        chunk_masks<!PPX>(lds, c0, cnt, lane, sx0, sy0, r2, m);
         while ((m[0] | m[1] | m[2] | m[3]) != 0ull) {
           const int jl = next_records(m, row);
           // idle rows read a valid record and contribute nothing
           float rec[kRecFloats];
           load_record(lds + 4 * (c0 + (jl < 0 ? 0 : jl)), rec);
           FragEval f;
-          frag_eval(rec, px, py, r2, f);
+          if constexpr (PPX)
+            frag_eval_pp(rec, px, py, r2, prm.sigma_f, f);
+          else
+            frag_eval(rec, px, py, r2, f);
           bool contrib = false;
           float gw = 0.f, gcs = 0.f, gz = 0.f, zf = 0.f;
           if (jl >= 0 && f.cov && !done) {
@@ -671,18 +680,22 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS) ? 4 : 5))) raster_backward_kerne
           const float gq = -0.5f * fw * gw;
           const float dx = f.dx, dy = f.dy, q = contrib ? f.q : 0.f;
           const float qxx = rec[R_QXX], qxy2 = rec[R_QXY2], qyy = rec[R_QYY];
-          // u = gq / s^2 and v = -2 gq q / s factor every slot of the kernel shape
-          const float u = gq * is * is, vq = -2.f * gq * q * is;
-          const float ux = u * dx, uy = u * dy;
           float g[RW];
-          g[G_X0] = -(2.f * qxx * ux + qxy2 * uy + rec[R_A3] * vq);
-          g[G_Y0] = -(qxy2 * ux + 2.f * qyy * uy + rec[R_B3] * vq);
-          g[G_QXX] = ux * dx;
-          g[G_QXY2] = ux * dy;
-          g[G_QYY] = uy * dy;
-          g[G_A3] = vq * dx;
-          g[G_B3] = vq * dy;
-          g[G_NF] = gw * fe;  // w / n_f
+          if constexpr (PPX) {
+            frag_grad_pp(rec, px, py, prm.sigma_f, fw * gw, contrib, g);
+          } else {
+            // u = gq / s^2 and v = -2 gq q / s factor every slot of the kernel shape
+            const float u = gq * is * is, vq = -2.f * gq * q * is;
+            const float ux = u * dx, uy = u * dy;
+            g[G_X0] = -(2.f * qxx * ux + qxy2 * uy + rec[R_A3] * vq);
+            g[G_Y0] = -(qxy2 * ux + 2.f * qyy * uy + rec[R_B3] * vq);
+            g[G_QXX] = ux * dx;
+            g[G_QXY2] = ux * dy;
+            g[G_QYY] = uy * dy;
+            g[G_A3] = vq * dx;
+            g[G_B3] = vq * dy;
+            g[G_NF] = gw * fe;  // w / n_f
+          }
           g[G_CR] = gcs * L.G0;
           g[G_CG] = gcs * L.G1;
           g[G_CB] = gcs * L.G2;
@@ -831,9 +844,14 @@ static void bwd_launch(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vie
                        int B, const float* di, const float* da, const uint8_t* nli, const float4* stats,
                        const float2* stats2, const float* dcons, const float* ddepth, float* grad, long long R,
                        int* queue, const int* order, int pers) {
-  hipLaunchKernelGGL((raster_backward_kernel<TW, TH, SS, CONS>), grid, dim3(TW * TH), lds, st, views, nv, tb,
-                     ni, ranges, vals, recs, prm, B, di, da, nli, stats, stats2, dcons, ddepth, grad, R, queue,
-                     order, pers);
+  if (prm.mip == 1)
+    hipLaunchKernelGGL((raster_backward_kernel<TW, TH, SS, CONS, true>), grid, dim3(TW * TH), lds, st, views, nv,
+                       tb, ni, ranges, vals, recs, prm, B, di, da, nli, stats, stats2, dcons, ddepth, grad, R,
+                       queue, order, pers);
+  else
+    hipLaunchKernelGGL((raster_backward_kernel<TW, TH, SS, CONS, false>), grid, dim3(TW * TH), lds, st, views, nv,
+                       tb, ni, ranges, vals, recs, prm, B, di, da, nli, stats, stats2, dcons, ddepth, grad, R,
+                       queue, order, pers);
 }
 
 template <int TW, int TH>

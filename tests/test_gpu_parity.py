@@ -438,25 +438,35 @@ def test_normal_image_parity(O, ss):
 
 
 # ---------------------------------------------------------------- per-pixel MIP variant
-@pytest.mark.parametrize("case", ["checkerboard", "C1_sigma0.5"])
-def test_per_pixel_mip_forward_parity(O, ss, case):
-    """Sec. 3.3.1 variant (Jacobian at every intersection) against the oracle with the
-    image protocol; its backward is refused."""
+def _per_pixel_case(case):
     if case == "checkerboard":
         w = g.checkerboard_workload(n_side=240, extent=3.0, square=0.15, width=96, height=72,
                                     eye=(0.0, -3.2, 0.35))
-        kw = dict(sigma_f=0.1)
-    else:
+        return w.scenes, w.cameras, "albedo", dict(sigma_f=0.1)
+    if case == "C1_sigma0.5":
         w = g.make_config("C1")
-        kw = dict(sigma_f=0.5)
-    rep = _forward_case(O, ss, w.scenes, w.cameras, "albedo", lambda c, v: all_pix(c), mip="pixel", **kw)
+        return w.scenes, w.cameras, "albedo", dict(sigma_f=0.5)
+    scenes, cams = small_multiview()
+    return scenes, cams, "splitsum", dict(sigma_f=0.3)
+
+
+@pytest.mark.parametrize("case", ["checkerboard", "C1_sigma0.5"])
+def test_per_pixel_mip_forward_parity(O, ss, case):
+    """Sec. 3.3.1 variant (Jacobian at every intersection) against the oracle with the
+    image protocol."""
+    scenes, cams, shade, kw = _per_pixel_case(case)
+    rep = _forward_case(O, ss, scenes, cams, shade, lambda c, v: all_pix(c), mip="pixel", **kw)
     assert_image_parity(rep)
-    r = ss.Renderer(ss.Options(mip="pixel", **kw))
-    b = ss.batch_from_scenes(w.scenes, w.cameras)
-    r.forward(b)
-    with pytest.raises(ss.SurfsplatError) as e:
-        r.backward(b, torch.zeros((b.n_pixels, 3), device="cuda"))
-    assert e.value.status == ss.SS_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("case", ["checkerboard", "C1_sigma0.5", "multiview"])
+def test_per_pixel_mip_backward_parity(O, ss, case):
+    """Adjoint of the per-pixel-Jacobian filter (Sec. 3.3.1): dL/d(record) through the
+    pixel's own Sigma_mip and det, against the oracle's tape adjoint (relative L2 per
+    group, split-sum and the environment maps included for the multi-view case)."""
+    scenes, cams, shade, kw = _per_pixel_case(case)
+    errs = _backward_case(O, ss, scenes, cams, shade, lambda c, v: all_pix(c), mip="pixel", **kw)
+    assert max(errs.values()) <= GRAD_REL_L2, errs
 
 
 # ---------------------------------------------------------------- tables, invariances, edges

@@ -116,3 +116,48 @@ def test_per_pixel_support_reading_drops_little_weight(oracle_lib):
         assert r["pp_drop"].sum() > 0
         assert dropped / kept.sum() < 3e-3, (w.name, dropped, kept.sum())
         assert dropped / r["pp_drop"].sum() < 1e-3
+
+
+def test_per_pixel_jvp_matches_finite_differences(oracle_lib):
+    """Directional derivatives of the per-pixel variant against central differences
+    of its FP64 forward (Richardson-extrapolated; coordinates whose step flips a
+    decision are skipped)."""
+    from test_oracle_grad import _objective
+    O = oracle_lib
+    w = g.make_config("C1", n_scale=0.3, res_scale=0.375)
+    sc, cam = w.scenes[0], w.cameras[0]
+    opt = O.Options(sigma_f=0.4, mip="pixel")
+    pix = O.all_pixels(cam)
+    rng = np.random.default_rng(9)
+    G = rng.normal(size=(len(pix), 3))
+    ga = np.zeros(len(pix))
+    r0 = O.render_grad(sc, cam, opt, pix, G, None)
+    live = np.nonzero(np.abs(r0["position"]).sum(0) > 0)[0]
+    checked = 0
+    for k in ("position", "normal", "scale", "albedo"):
+        arr = getattr(sc, k)
+        for trial in range(6):
+            i = int(rng.choice(live))
+            row = int(rng.integers(0, arr.shape[0]))
+            p = float(arr[row, i])
+            v = {k: np.zeros(arr.shape)}
+            v[k][row, i] = 1.0
+            d = (G * O.render_jvp(sc, cam, opt, pix, v)["image_dot"]).sum()
+
+            def fd(h):
+                hi, lo = np.float32(p + h), np.float32(p - h)
+                arr[row, i] = hi
+                fp = _objective(O, sc, cam, opt, pix, G, ga, None, None, (0, 0))
+                arr[row, i] = lo
+                fm = _objective(O, sc, cam, opt, pix, G, ga, None, None, (0, 0))
+                arr[row, i] = np.float32(p)
+                return (fp - fm) / (float(hi) - float(lo))
+            h = 2e-3 * max(abs(p), 0.05)
+            f1, f2 = fd(h), fd(h / 2)
+            scale = max(abs(d), 1e-3 * np.abs(r0[k]).max(), 1e-8)
+            if abs(f1 - f2) > 2e-3 * scale:
+                continue
+            fr = (4 * f2 - f1) / 3
+            assert abs(fr - d) <= 2e-4 * scale + 1e-7, (k, row, i, fr, d)
+            checked += 1
+    assert checked >= 12
