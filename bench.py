@@ -24,6 +24,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32 (256 CUs at 2.4 GHz)
+# Algorithmic FP32 operations per covering fragment (an FMA counts 2, each
+# reciprocal or exponential 1), counted from the per-fragment formulas: the
+# evaluation (pixel offset, perspective denominator, quadratic form, cutoff,
+# weight: 20 + 2), the layer state (2), and in the backward the gradient of the
+# 11 record values (39 + 1) plus their per-record sums (11).
+FLOPS_PER_FRAGMENT = {"raster_forward": 30, "raster_backward": 75}
 WORKLOAD_DESC = {
     "C1": "4,096 surfels on the unit sphere, albedo shading, 1 view 128x128",
     "C2": "200k surfels on a displaced torus, split-sum, envmap 64x128, 1 view 512x512",
@@ -51,26 +58,60 @@ def algorithmic_bytes(stage, n_pairs, n_rec_vis, n_pix, mean_layers, n_surf):
     return None
 
 
-def measured_traffic(kernel, workload, tile, lds_batch):
-    """HBM bytes per launch of a raster kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, if it was taken on this workload and tile
-    setup with the current raster sources (else None)."""
+def raster_source_hash():
     import hashlib
-    root = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(root, "profiles", "hbm_traffic_raster_c3.md")
+    h = hashlib.sha256()
+    for f in ("paper_2605_05876_amd/csrc/raster.hip", "paper_2605_05876_amd/csrc/common.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_record(name, workload, tile, lds_batch):
+    """The JSON record at the end of profiles/<name>, if it was taken on this
+    workload and tile setup with the current raster sources (else None)."""
     try:
-        text = open(path).read()
+        text = open(os.path.join(ROOT, "profiles", name)).read()
         rec = json.loads(text.rsplit("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
         return None
-    h = hashlib.sha256()
-    for f in ("paper_2605_05876_amd/csrc/raster.hip", "paper_2605_05876_amd/csrc/common.h"):
-        with open(os.path.join(root, f), "rb") as fh:
-            h.update(fh.read())
-    if (rec.get("source_sha256") != h.hexdigest() or rec.get("workload") != workload
-            or rec.get("tile") != tile or rec.get("lds_batch") != lds_batch or kernel not in rec):
+    if (rec.get("source_sha256") != raster_source_hash() or rec.get("workload") != workload
+            or rec.get("tile") != tile or rec.get("lds_batch") != lds_batch):
         return None
-    return rec[kernel]["bytes_per_launch"]
+    return rec
+
+
+def measured_traffic(kernel, workload, tile, lds_batch):
+    """HBM bytes per launch of a raster kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (None when stale)."""
+    rec = committed_record("hbm_traffic_raster_c3.md", workload, tile, lds_batch)
+    return rec[kernel]["bytes_per_launch"] if rec and kernel in rec else None
+
+
+def measured_valu_busy(kernel, workload, tile, lds_batch):
+    """VALU issue fraction of a raster kernel from the committed instruction
+    counters (None when stale)."""
+    rec = committed_record("counters_raster_c3.md", workload, tile, lds_batch)
+    return rec[kernel]["valu_issue_busy"] if rec and kernel in rec else None
+
+
+def step_algorithmic_bytes(n_surf, n_rec, n_pairs, n_pix):
+    """HBM bytes one fwd+bwd step must move at least: parameters read twice and
+    their gradients written (192 per surfel), per (surfel, view) record its write,
+    its gradient write and read back (200), per pair the emission, sort, sorted id
+    and two reads of id + record (180), per pixel-view the image and alpha, their
+    gradients and the re-read state (56)."""
+    return 192 * n_surf + 200 * n_rec + 180 * n_pairs + 56 * n_pix
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(workload, opts_shade, budget_s=20.0):
@@ -113,10 +154,31 @@ def cpu_baseline(workload, opts_shade, budget_s=20.0):
     if opts_shade == "splitsum":
         O.envmap_adjoint(gr["maps"], *hw)
     dt = time.perf_counter() - t2
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = O.set_threads()
+    # the same per-pixel work on one thread, on a smaller sample (~budget/4)
+    O.set_threads(1)
+    k1 = int(max(16, min(k, (budget_s / 4) / max(per_px * cores, 1e-9))))
+    pix1 = pix[:k1]
+    t3 = time.perf_counter()
+    O.render(sc, cam, opt, pix1, maps=maps, lut=lut, env_hw=hw)
+    O.render_grad(sc, cam, opt, pix1, np.ones((k1, 3)), np.ones(k1), maps=maps, lut=lut, env_hw=hw)
+    dt1 = time.perf_counter() - t3
+    O.set_threads(cores)
     return {"value": k / dt / 1e6, "unit": "Mpixel-views/s", "cores": cores, "kind": "oracle",
+            "cpu": cpu_model(), "value_1thread": k1 / dt1 / 1e6,
             "sample": f"view 0 of the workload, {k} seeded pixels, all {sc.n} surfels, FP64 forward + "
-                      f"adjoint incl. environment prefilter and its adjoint; {dt:.1f} s"}
+                      f"adjoint incl. environment prefilter and its adjoint; {dt:.1f} s on {cores} threads; "
+                      f"1 thread: {k1} of those pixels (forward + adjoint, no environment) in {dt1:.1f} s"}
+
+
+def check_status(renderer, what):
+    """Polls the device status (synchronising); a latched error (a pair-capacity
+    overflow in a timed step) makes the run fail instead of reporting a rate of
+    truncated work."""
+    d = renderer.poll()
+    if d["device_status"] != 0 or d["status"] != 0:
+        raise RuntimeError(f"device status after {what}: {d}")
+    return d
 
 
 def main():
@@ -179,7 +241,8 @@ def main():
     Ga = torch.from_numpy(rng.normal(size=n_pix).astype(np.float32)).cuda()
 
     def make(launch):
-        r = ss.Renderer(ss.Options(**{**opts.__dict__, "launch": launch}))
+        # no poll inside timed steps: the device status is checked after each timed loop
+        r = ss.Renderer(ss.Options(**{**opts.__dict__, "launch": launch}), check_capacity=False)
         ws = r.reserve(batch)
         img = torch.empty((n_pix, 3), device="cuda")
         alpha = torch.empty((n_pix,), device="cuda")
@@ -243,6 +306,7 @@ def main():
     ms = timed(step, args.steps, use_graph)
     value = n_pix / (ms * 1e-3) / 1e6
     log(f"[bench] batched{'+graph' if use_graph else ''}: {ms:.3f} ms/step, {value:.1f} Mpixel-views/s")
+    check_status(r, "batched timed steps")
 
     # per-stage times (eager, HIP events on the library's stream)
     r.profile(True)
@@ -254,19 +318,53 @@ def main():
     stages = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
     per_step = {k: v[0] / max(1, max(3, min(args.steps, 10))) for k, v in prof.items()}
     log("[bench] stage ms/launch: " + ", ".join(f"{k} {v:.3f}" for k, v in stages.items()))
+    check_status(r, "stage-profiled steps")
     dom = max(("raster_forward", "raster_backward"), key=lambda k: per_step[k])
     nl_mean = float(bufs[2].float().mean().item())
-    counts_vis = None
+    # the work of one step, counted by the raster forward (options.counters)
+    rc = ss.Renderer(ss.Options(**{**opts.__dict__, "counters": True}), check_capacity=False)
+    rc.forward(batch)
+    dc = check_status(rc, "counted forward")
+    del rc
+    work = {"P_pairs": diag["n_pairs"], "F_fragments": dc["n_fragments"], "E_evaluated": dc["n_evaluated"],
+            "layers": dc["n_layers"], "W_mean": round(dc["sum_layer_weight"] / max(dc["n_layers"], 1), 3),
+            "layers_per_pixel": round(dc["n_layers"] / n_pix, 4),
+            "E_over_F": round(dc["n_evaluated"] / max(dc["n_fragments"], 1), 2)}
+    log(f"[bench] work: {work}")
+    t_dom = stages[dom] * 1e-3
     alg = algorithmic_bytes(dom, diag["n_pairs"], diag["n_records"], n_pix, nl_mean, w.n_surfels)
-    achieved = alg / (stages[dom] * 1e-3) / 1e9 if stages[dom] > 0 else 0.0
+    hbm_achieved = alg / t_dom / 1e9 if t_dom > 0 else 0.0
+    flops = FLOPS_PER_FRAGMENT[dom] * dc["n_fragments"]
+    alu_achieved = flops / t_dom / 1e12 if t_dom > 0 else 0.0
     traffic = measured_traffic(dom, args.config, f"{tw}x{th}", lb)
-    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-            "algorithmic_bytes_per_launch": int(alg), "launch_ms": round(stages[dom], 4),
-            "n_pairs": diag["n_pairs"], "mean_layers": round(nl_mean, 3)}
+    valu_busy = measured_valu_busy(dom, args.config, f"{tw}x{th}", lb)
+    # the binding resource: VALU issue (counters) against HBM (measured traffic,
+    # else the algorithmic bytes)
+    hbm_use = (traffic if traffic else alg) / t_dom / 1e9 / HBM_PEAK_GBS if t_dom > 0 else 0.0
+    alu_use = valu_busy if valu_busy is not None else alu_achieved / FP32_PEAK_TFLOPS
+    bound = "alu" if alu_use >= hbm_use else "hbm"
+    if bound == "alu":
+        roof = {"kernel": dom, "bound": "alu", "achieved": round(alu_achieved, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(alu_achieved / FP32_PEAK_TFLOPS, 5)}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(hbm_achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(hbm_achieved / HBM_PEAK_GBS, 5)}
+    roof.update({"traffic": traffic, "valu_issue_busy": valu_busy,
+                 "alu": {"algorithmic_flops_per_launch": int(flops),
+                         "flops_per_fragment": FLOPS_PER_FRAGMENT[dom],
+                         "achieved_TFLOPs": round(alu_achieved, 3),
+                         "frac": round(alu_achieved / FP32_PEAK_TFLOPS, 5)},
+                 "hbm": {"algorithmic_bytes_per_launch": int(alg), "achieved_GBps": round(hbm_achieved, 2),
+                         "frac": round(hbm_achieved / HBM_PEAK_GBS, 5)},
+                 "launch_ms": round(stages[dom], 4), "n_pairs": diag["n_pairs"],
+                 "mean_layers": round(nl_mean, 3)})
     if traffic:
         roof["traffic_over_algorithmic"] = round(traffic / alg, 3)
-        roof["traffic_GBps"] = round(traffic / (stages[dom] * 1e-3) / 1e9, 1)
+        roof["traffic_GBps"] = round(traffic / t_dom / 1e9, 1)
+    b_step = step_algorithmic_bytes(w.n_surfels, diag["n_records"], diag["n_pairs"], n_pix)
+    step_roof = {"algorithmic_bytes": int(b_step), "achieved_GBps": round(b_step / (ms * 1e-3) / 1e9, 1),
+                 "hbm_frac": round(b_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                 "hbm_ceiling_Mpixel_views_s": round(n_pix / (b_step / (HBM_PEAK_GBS * 1e9)) / 1e6, 1)}
 
     out = {"metric": "fwd+bwd Mpixel-views/s", "value": round(value, 2), "unit": "Mpixel-views/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
@@ -277,6 +375,8 @@ def main():
                       "tile": f"{tw}x{th}", "lds_batch": lb, "pixel_views": n_pix,
                       "surfels": w.n_surfels},
            "roofline": roof,
+           "step_roofline": step_roof,
+           "work": work,
            "stages_ms_per_step": {k: round(v, 4) for k, v in per_step.items()}}
     del r, step, bufs
     torch.cuda.empty_cache()
@@ -288,11 +388,23 @@ def main():
         stepp()
         torch.cuda.synchronize()
         msp = timed(stepp, args.steps, False)
+        check_status(rp, "per-view timed steps")
         out["per_view"] = {"value": round(n_pix / (msp * 1e-3) / 1e6, 2), "ms_per_step": round(msp, 4),
                            "launch": "per-view, eager", "speedup_batched": round(msp / ms, 3)}
         log(f"[bench] per-view eager: {msp:.3f} ms/step")
+        # where the per-view time goes: the same stages, summed over the views
+        rp.profile(True)
+        n_prof = max(3, min(args.steps, 10))
+        for _ in range(n_prof):
+            stepp()
+        pprof = rp.profile_read()
+        rp.profile(False)
+        out["per_view"]["stages_ms_per_step"] = {k: round(v[0] / n_prof, 4) for k, v in pprof.items()}
+        out["per_view"]["stage_launches_per_step"] = {k: v[1] // n_prof for k, v in pprof.items()}
+        log(f"[bench] per-view stages ms/step: {out['per_view']['stages_ms_per_step']}")
         if use_graph:
             msg = timed(stepp, args.steps, True)
+            check_status(rp, "per-view graph steps")
             out["per_view"]["graph_ms_per_step"] = round(msg, 4)
             log(f"[bench] per-view+graph: {msg:.3f} ms/step")
         del rp, stepp, bp

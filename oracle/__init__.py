@@ -50,6 +50,7 @@ def lib():
         L.orc_envmap.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp]
         L.orc_envmap_adjoint.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp]
         L.orc_brdf_lut.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_bin_f32.argtypes = [fpp, ctypes.c_int, dp, dp, ip, ctypes.POINTER(ctypes.c_uint32), ip, ip]
         L.orc_render.argtypes = [fpp, ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp,
                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, dp, dp, ip, dp, dp, ip, dp,
@@ -89,6 +90,11 @@ class Options:
                          {"centre": 0, "pixel": 1}[self.mip], f(self.t_min),
                          {"linear": 0, "srgb_log": 1}[self.tonemap]], np.float64)
 
+
+
+def set_threads(n: int = 0) -> int:
+    """OpenMP threads of the oracle's loops (n > 0 sets it); returns the count."""
+    return int(lib().orc_set_threads(int(n)))
 
 def _dptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))

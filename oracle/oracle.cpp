@@ -30,6 +30,8 @@
 #include <unordered_map>
 #include <vector>
 
+#include <omp.h>
+
 #include "ad.hpp"
 
 namespace orc {
@@ -879,6 +881,12 @@ int orc_envmap_adjoint(const double* dmaps, int He, int We, double* dE) {
   envmap_adjoint(dmaps, He, We, dE);
   return 0;
 }
+// Threads of the OpenMP loops (n > 0 sets it); returns the count in use.
+int orc_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+}
+
 int orc_brdf_lut(int n_nv, int n_r, int samples, double* out) {
   brdf_lut(n_nv, n_r, samples, out);
   return 0;

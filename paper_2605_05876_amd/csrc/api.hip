@@ -52,6 +52,7 @@ struct Group {
   long long rec_begin, rec_end;
   long long pair_base, pair_cap;
   int pair_passes;  // radix passes of the pair sort: 8-bit digits of the local tile index
+  long long mask_base, mask_n;  // the group's chunk slots of walk masks (WalkBufs)
 };
 
 struct SceneEnv {
@@ -84,7 +85,7 @@ struct ss_context {
   std::vector<Group> groups;
   std::vector<SceneEnv> env;
   DevBuf views_d, recs, counts, offsets, scan_tmp, keys, vals, keys2, vals2, hist, ranges, nl, stats,
-      grad, misc, partial, sg, order, stats2, zkey, zkey2, zidx, zidx2, prect, zrect;
+      grad, misc, partial, sg, order, stats2, zkey, zkey2, zidx, zidx2, prect, zrect, lpos, qmask;
   std::vector<long long> soff;
   long long scan_tmp_n = 0, pair_total = 0, hist_n = 0;
   DevBuf lut;
@@ -458,9 +459,31 @@ void plan_batch(ss_context* c, const ss_batch* b, std::vector<ViewDev>& vh) {
     g.pair_passes = g.n_tiles > 1 ? (bits_for(g.n_tiles) + 7) / 8 : 0;
     g.pair_base = 0;
     g.pair_cap = 0;
+    g.mask_base = 0;
+    g.mask_n = 0;
     c->groups.push_back(g);
   }
   c->lds_batch = c->opt.lds_batch > 0 ? c->opt.lds_batch : 128;
+}
+
+// Chunk slots of the walk masks for every group (after the pair capacities);
+// returns the number of 64-bit masks.
+long long layout_masks(ss_context* c) {
+  long long base = 0;
+  for (Group& g : c->groups) {
+    g.mask_base = base;
+    g.mask_n = mask_slots(g.pair_cap, g.n_tiles);
+    base += g.mask_n;
+  }
+  return base * (long long)(c->opt.tile_w * c->opt.tile_h / 16);
+}
+
+WalkBufs walk_bufs(ss_context* c, const Group& g) {
+  WalkBufs w;
+  w.pos = P<uint32_t>(c->lpos);
+  w.masks = P<uint64_t>(c->qmask);
+  w.mask_base = g.mask_base;
+  return w;
 }
 
 ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
@@ -489,6 +512,7 @@ ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
   SS_HIP(ensure(c->nl, (size_t)(c->n_pix > 0 ? c->n_pix : 1)));
   SS_HIP(ensure(c->order, (size_t)(c->n_tiles > 0 ? c->n_tiles : 1) * sizeof(int)));
   SS_HIP(ensure(c->stats, (size_t)(c->n_pix > 0 ? c->n_pix : 1) * kMaxLayers * sizeof(float4)));
+  SS_HIP(ensure(c->lpos, (size_t)(c->n_pix > 0 ? c->n_pix : 1) * kPosStride * sizeof(uint32_t)));
   if (c->opt.depth_stats)
     SS_HIP(ensure(c->stats2, (size_t)(c->n_pix > 0 ? c->n_pix : 1) * kMaxLayers * sizeof(float2)));
   SS_HIP(ensure(c->grad, (size_t)R * kGradStride * sizeof(float)));
@@ -519,6 +543,7 @@ ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
     const double mean = c->n_tiles > 0 ? (double)np_all / c->n_tiles : 0.0;
     c->lds_batch = mean >= 256 ? 256 : (mean >= 128 ? 128 : (mean >= 64 ? 64 : 32));
   }
+  SS_HIP(ensure(c->qmask, (size_t)layout_masks(c) * sizeof(uint64_t)));
   SS_HIP(ensure(c->keys, (size_t)base * sizeof(uint32_t)));
   SS_HIP(ensure(c->keys2, (size_t)base * sizeof(uint32_t)));
   SS_HIP(ensure(c->vals, (size_t)base * sizeof(uint32_t)));
@@ -573,7 +598,7 @@ size_t workspace_bytes(const ss_context* c) {
   size_t s = c->views_d.n + c->recs.n + c->counts.n + c->offsets.n + c->scan_tmp.n + c->keys.n +
              c->vals.n + c->keys2.n + c->vals2.n + c->hist.n + c->ranges.n + c->nl.n + c->stats.n +
              c->grad.n + c->misc.n + c->lut.n + c->partial.n + c->sg.n + c->order.n + c->stats2.n + c->zkey.n +
-             c->zkey2.n + c->zidx.n + c->zidx2.n + c->prect.n + c->zrect.n;
+             c->zkey2.n + c->zidx.n + c->zidx2.n + c->prect.n + c->zrect.n + c->lpos.n + c->qmask.n;
   for (const SceneEnv& e : c->env) s += e.dirs.n + e.lv.n + e.Z.n + e.dlv.n + e.part.n;
   return s;
 }
@@ -626,6 +651,10 @@ ss_status forward_body(ss_context* c, const ss_batch* b, const ss_outputs* out, 
     }
     prof_end(c, t0, ST_BIN, st);
     SS_HIP(launch_fill_u32(misc + kMiscQueue, 0u, 1, st));
+    const WalkBufs wb = walk_bufs(c, g);
+    // chunks the forward does not reach keep empty masks
+    SS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(wb.masks + g.mask_base * (c->opt.tile_w * c->opt.tile_h / 16)),
+                           0u, 2LL * g.mask_n * (c->opt.tile_w * c->opt.tile_h / 16), st));
     t0 = prof_begin(c, st);
     SS_HIP(launch_raster_forward(P<ViewDev>(c->views_d), c->n_views, g.tile_base,
                                  g.tile_base + g.n_tiles, P<uint32_t>(c->ranges), vals,
@@ -634,7 +663,7 @@ ss_status forward_body(ss_context* c, const ss_batch* b, const ss_outputs* out, 
                                  P<float2>(c->stats2), out->cons, out->depth,
                                  reinterpret_cast<int*>(misc + kMiscQueue), order,
                                  c->opt.persistent, status,
-                                 reinterpret_cast<unsigned long long*>(misc + kMiscCounters), st));
+                                 reinterpret_cast<unsigned long long*>(misc + kMiscCounters), wb, st));
     prof_end(c, t0, ST_RFWD, st);
   }
   return SS_OK;
@@ -776,7 +805,7 @@ ss_status ss_destroy(ss_context* c) {
   DevBuf* bufs[] = {&c->views_d, &c->recs, &c->counts, &c->offsets, &c->scan_tmp, &c->keys,
                     &c->vals, &c->keys2, &c->vals2, &c->hist, &c->ranges, &c->nl, &c->stats,
                     &c->grad, &c->misc, &c->lut, &c->partial, &c->sg, &c->order, &c->stats2,
-                    &c->zkey, &c->zkey2, &c->zidx, &c->zidx2, &c->prect, &c->zrect};
+                    &c->zkey, &c->zkey2, &c->zidx, &c->zidx2, &c->prect, &c->zrect, &c->lpos, &c->qmask};
   for (DevBuf* b : bufs) release(*b);
   for (SceneEnv& e : c->env) { release(e.dirs); release(e.lv); release(e.Z); release(e.dlv); release(e.part); }
   for (auto& pe : c->prof_ev) { c->ev_pool.push_back(pe.second.first); c->ev_pool.push_back(pe.second.second); }
@@ -903,7 +932,7 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
                                   P<float>(c->grad), c->R,
                                   reinterpret_cast<int*>(misc + kMiscQueue),
                                   c->opt.persistent ? P<int>(c->order) + g.tile_base : nullptr,
-                                  c->opt.persistent, st));
+                                  c->opt.persistent, walk_bufs(c, g), st));
     prof_end(c, t0, ST_RBWD, st);
   }
   const float* pp[7];
@@ -1063,6 +1092,7 @@ extern "C" ss_status ss_render_static(ss_context* c, const ss_batch* b, const ss
   cv.take(w.order, (size_t)ntiles * sizeof(int));
   cv.take(w.nl, (size_t)npix);
   cv.take(w.stats, (size_t)npix * kMaxLayers * sizeof(float4));
+  cv.take(w.lpos, (size_t)npix * kPosStride * sizeof(uint32_t));
   if (c->opt.depth_stats) cv.take(w.stats2, (size_t)npix * kMaxLayers * sizeof(float2));
   if (!cv.ok) return SS_ERR_STATIC_LIMIT;
   // pairs (keys and values, double-buffered): what is left after the sort's
@@ -1073,9 +1103,10 @@ extern "C" ss_status ss_render_static(ss_context* c, const ss_batch* b, const ss
   auto hist_for = [&](long long cp) {
     return radix_hist_size(cp) > radix_hist_size(nrec) ? radix_hist_size(cp) : radix_hist_size(nrec);
   };
+  const long long nq = c->opt.tile_w * c->opt.tile_h / 16;
   auto need = [&](long long cp) {
     const long long h = hist_for(cp), sc = scan_tmp_size(h > R ? h : R) + 16;
-    return (size_t)(16 * cp + 4 * h + 4 * sc) + 8 * 256;
+    return (size_t)(16 * cp + 4 * h + 4 * sc + 8 * nq * mask_slots(cp, g.n_tiles)) + 8 * 256;
   };
   long long cap = (long long)(left / 16);
   while (cap > 0 && need(cap) > left) cap -= cap / 64 > 0 ? cap / 64 : 1;
@@ -1088,6 +1119,7 @@ extern "C" ss_status ss_render_static(ss_context* c, const ss_batch* b, const ss
   for (DevBuf* d : {&w.keys, &w.keys2, &w.vals, &w.vals2}) cv.take(*d, (size_t)cap * sizeof(uint32_t));
   cv.take(w.hist, (size_t)w.hist_n * sizeof(uint32_t));
   cv.take(w.scan_tmp, (size_t)w.scan_tmp_n * sizeof(uint32_t));
+  cv.take(w.qmask, (size_t)layout_masks(&w) * sizeof(uint64_t));
   if (!cv.ok) return SS_ERR_STATIC_LIMIT;
   // view table (its map pointers point into the array), direction tables
   for (int v0 = 0; v0 < b->n_views; v0 += kViewsPerStore) {

@@ -31,6 +31,25 @@ enum GradField { G_X0 = 0, G_Y0, G_QXX, G_QXY2, G_QYY, G_A3, G_B3, G_NF, G_CR, G
 constexpr int kNGrad = 11;
 constexpr int kGradStride = 16;
 
+// What the raster forward leaves for the backward's walk, besides the
+// per-layer totals: per pixel the list position (within its group's pair list)
+// where each composited layer starts and, at index K, where its walk ended
+// (the fragment that would have opened layer K, or 0xffffffff when the list
+// ran out), kPosStride words per pixel; and per (tile, 32-record-aligned chunk
+// of its list, 4 x 4 quadrant) the 64-bit mask of the chunk's records with a
+// fragment accumulated in the quadrant.  Chunk slot of list position p in a
+// tile whose list starts at `start`: mask_base + start / 32 + (p - start) / 32 +
+// (tile - first tile of the group); distinct (tile, chunk) pairs get distinct
+// slots, and a group with pair capacity cap and n tiles needs
+// cap / 32 + n + 2 slots of (tile pixels / 16) masks.
+constexpr int kPosStride = 17;
+struct WalkBufs {
+  uint32_t* pos;
+  uint64_t* masks;
+  long long mask_base;  // first slot of the group
+};
+inline long long mask_slots(long long pair_cap, int n_tiles) { return pair_cap / 32 + n_tiles + 2; }
+
 // ---------------------------------------------------------------- views
 struct ViewDev {
   float fx, fy, cx, cy;
@@ -395,7 +414,7 @@ hipError_t launch_raster_forward(const ViewDev* views, int n_views, int tile_beg
                                  uint8_t* n_layers, float4* layer_stats, float2* layer_stats2,
                                  float* cons, float* depth, int* queue, const int* order,
                                  int persistent, const int* status, unsigned long long* counters,
-                                 hipStream_t st);
+                                 const WalkBufs& wb, hipStream_t st);
 hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_begin, int tile_end,
                                   const uint32_t* ranges, const uint32_t* sorted_vals,
                                   const float* recs, const Params& prm, int lds_batch,
@@ -403,6 +422,6 @@ hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_be
                                   const uint8_t* n_layers, const float4* layer_stats,
                                   const float2* layer_stats2, const float* d_cons,
                                   const float* d_depth, float* grad, long long R, int* queue,
-                                  const int* order, int persistent, hipStream_t st);
+                                  const int* order, int persistent, const WalkBufs& wb, hipStream_t st);
 
 }  // namespace ss

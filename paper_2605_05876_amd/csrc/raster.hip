@@ -136,47 +136,6 @@ __device__ __forceinline__ uint64_t chunk_mask(const float4* lds, int c0, int cn
   return uniform64(__ballot(ov));
 }
 
-// Row-level compaction (backward): after the sub-tile test, lane j tests
-// record c0 + j's rectangle against the four quadrants; m[r] is the
-// (wave-uniform) set of records row r visits, in list order.  (Ellipse tests
-// per quadrant cost more than the steps they save.)  ELLIPSE: the sub-tile
-// test includes the centre filter's acceptance ellipse (not for the
-// per-pixel-Jacobian filter, whose acceptance set differs).
-template <bool ELLIPSE = true>
-__device__ __forceinline__ void chunk_masks(const float4* lds, int c0, int cnt, int lane, int sx0, int sy0,
-                                            float r2, uint64_t m[4]) {
-  const int j = c0 + lane;
-  bool o0 = false, o1 = false, o2 = false, o3 = false;
-  if (j < cnt) {
-    const float4 q3 = lds[4 * j + 3];
-    bool meets = rect_meets<8>(q3, sx0, sy0);
-    if constexpr (ELLIPSE) meets = meets && ellipse_meets<8>(lds[4 * j], lds[4 * j + 1], q3, sx0, sy0, r2);
-    if (meets) {
-      o0 = rect_meets<4>(q3, sx0, sy0);
-      o1 = rect_meets<4>(q3, sx0 + 4, sy0);
-      o2 = rect_meets<4>(q3, sx0, sy0 + 4);
-      o3 = rect_meets<4>(q3, sx0 + 4, sy0 + 4);
-    }
-  }
-  m[0] = uniform64(__ballot(o0));
-  m[1] = uniform64(__ballot(o1));
-  m[2] = uniform64(__ballot(o2));
-  m[3] = uniform64(__ballot(o3));
-}
-
-// One step of the row walks: every row takes the next record of its mask
-// (scalar).  Returns this lane's record (chunk index), -1 when its row has no
-// record left.
-__device__ __forceinline__ int next_records(uint64_t m[4], int row) {
-  int jr[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    jr[r] = m[r] ? (int)__builtin_ctzll(m[r]) : -1;
-    m[r] = uniform64(m[r] & (m[r] - 1));
-  }
-  return row == 0 ? jr[0] : (row == 1 ? jr[1] : (row == 2 ? jr[2] : jr[3]));
-}
-
 __device__ __forceinline__ int next_item(int* queue, int persistent, int& s_item, int iter) {
   if (!persistent) return iter == 0 ? (int)blockIdx.x : -1;
   if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
@@ -222,6 +181,15 @@ __device__ __forceinline__ float layer_norm(int shade, float W, float C0, float 
   return shade == 2 ? rsqrtf(C0 * C0 + C1 * C1 + C2 * C2) : 1.f / W;
 }
 
+// OR over the 16 lanes of a row (DPP: quad swaps, half-row mirror, row mirror).
+__device__ __forceinline__ uint32_t row_or(uint32_t x) {
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false);
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false);
+  return x;
+}
+
 // ---------------------------------------------------------------- forward
 // CONS: also the per-layer depth statistics (mean, variance; stats2) and the
 // per-pixel depth-consolidation term and composited depth (each output
@@ -240,11 +208,13 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     float* __restrict__ alpha, uint8_t* __restrict__ nl_out, uint8_t* __restrict__ nl_int,
     float4* __restrict__ stats, float2* __restrict__ stats2, float* __restrict__ cons_out,
     float* __restrict__ depth_out, int* queue, const int* __restrict__ order, int persistent,
-    const int* __restrict__ status, unsigned long long* __restrict__ counters) {
+    const int* __restrict__ status, unsigned long long* __restrict__ counters, uint32_t* __restrict__ lpos,
+    uint64_t* __restrict__ qmask, long long mask_base) {
   extern __shared__ float4 lds[];
   __shared__ int s_item;
   constexpr int NT = TW * TH;
-  const int t = threadIdx.x, lane = t & 63;
+  constexpr int NQ = TW * TH / 16;  // 4 x 4 quadrants of the tile
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const float r2 = prm.r2, kappa = prm.kappa, t_min = prm.t_min;
   const int kmax = prm.k_max;
   const bool poisoned = *status == 3;  // SS_ERR_CAPACITY
@@ -267,10 +237,14 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     float zr = 0.f, S1 = 0.f, S2 = 0.f;  // CONS: reference depth, sum w dz, sum w dz^2
     int K = 0;
     bool done = !inside || poisoned;
+    // list position of the current layer's first fragment (0xffffffff: none yet)
+    uint32_t lstart = 0xffffffffu;
+    uint32_t* const lp = lpos + pix * kPosStride;
     int nF = 0;              // counters: fragments accumulated by this pixel
+    unsigned nE = 0;         // counters: records evaluated at this pixel
     float sumW = 0.f;        // counters: sum of its layers' weights
-    unsigned long long nE = 0;  // counters: (pixel, record) evaluations of the wave (uniform)
-    const int n_in = __popcll(__ballot(inside));
+    // this row's walk mask of chunk slot 0 of the tile (one writer lane per row)
+    uint64_t* const qrow = qmask + (mask_base + (start >> 5) + (tile - tile_begin)) * NQ + wave * 4 + (lane >> 4);
     for (uint32_t b0 = start; b0 < end; b0 += (uint32_t)B) {
       if (__syncthreads_and(done)) break;
       const int cnt = (int)min((uint32_t)B, end - b0);
@@ -279,9 +253,13 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
       for (int c0 = 0; c0 < cnt; c0 += 64) {
         if (__ballot(!done) == 0ull) break;
         uint64_t m = chunk_mask<!PPX>(lds, c0, cnt, lane, sx0, sy0, r2);
-        nE += (unsigned long long)__popcll(m) * (unsigned)n_in;
+        nE += inside ? (unsigned)__popcll(m) : 0u;
+        // the records of the chunk this pixel accumulated; OR-ed over each row of
+        // 16 lanes (a 4 x 4 quadrant) they are the backward's walk lists
+        uint32_t lm0 = 0u, lm1 = 0u;
         while (m) {
           const int j = c0 + __builtin_ctzll(m);
+          const uint64_t bit = m & (0ull - m);  // the record's bit in the chunk
           m &= m - 1;
           float rec[kRecFloats];
           load_record<true>(lds + 4 * j, rec);
@@ -300,6 +278,7 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
               const float s = T * a * layer_norm(prm.shade, Wg, C0, C1, C2);
               O0 += s * C0; O1 += s * C1; O2 += s * C2;
               stats[pix * kMaxLayers + K] = make_float4(Wg, C0, C1, C2);
+              lp[K] = lstart;
               if constexpr (CONS) {
                 const float m = S1 / Wg;
                 stats2[pix * kMaxLayers + K] = make_float2(zr + m, S2 / Wg - m * m);
@@ -311,10 +290,18 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
               C0 = C1 = C2 = 0.f;
               Wg = 0.f;
               zmax = 0.f;
-              // K_max cap, or the early-out once the transmittance is below t_min
-              if (K >= kmax || T < t_min) done = true;
+              lstart = 0xffffffffu;
+              // K_max cap, or the early-out once the transmittance is below t_min;
+              // the discarded fragment's list position ends the pixel's walk
+              if (K >= kmax || T < t_min) {
+                done = true;
+                lp[K] = b0 + (uint32_t)j;
+              }
             }
             if (!done) {
+              lstart = lstart == 0xffffffffu ? b0 + (uint32_t)j : lstart;
+              lm0 |= (uint32_t)bit;
+              lm1 |= (uint32_t)(bit >> 32);
               if constexpr (CONS) {
                 const float z = frag_depth(rec, f);
                 if (Wg == 0.f) zr = z;
@@ -331,6 +318,9 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
             }
           }
         }
+        lm0 = row_or(lm0);
+        lm1 = row_or(lm1);
+        if ((lane & 15) == 0) qrow[(long long)((b0 + (uint32_t)c0 - start) >> 5) * NQ] = ((uint64_t)lm1 << 32) | lm0;
       }
       __syncthreads();
     }
@@ -340,6 +330,7 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
         const float s = T * a * layer_norm(prm.shade, Wg, C0, C1, C2);
         O0 += s * C0; O1 += s * C1; O2 += s * C2;
         stats[pix * kMaxLayers + K] = make_float4(Wg, C0, C1, C2);
+        lp[K] = lstart;
         if constexpr (CONS) {
           const float m = S1 / Wg;
           stats2[pix * kMaxLayers + K] = make_float2(zr + m, S2 / Wg - m * m);
@@ -348,6 +339,7 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
         ++K;
         sumW += Wg;
       }
+      if (!done) lp[K] = 0xffffffffu;  // the walk ran to the end of the list
       if constexpr (CONS) {
         float cs, dp;
         depth_stats_of_pixel(stats + pix * kMaxLayers, stats2 + pix * kMaxLayers, K, kappa, cs, dp);
@@ -371,16 +363,17 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     }
     if (prm.counters) {
       // wave sums, one set of atomics per wave and tile
-      unsigned long long f = (unsigned)nF, k = inside ? (unsigned)K : 0u;
+      unsigned long long f = (unsigned)nF, k = inside ? (unsigned)K : 0u, e = nE;
       float w = inside ? sumW : 0.f;
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
         f += __shfl_xor(f, off);
         k += __shfl_xor(k, off);
+        e += __shfl_xor(e, off);
         w += __shfl_xor(w, off);
       }
       if (lane == 0) {
-        if (nE) atomicAdd(counters + 0, nE);
+        if (e) atomicAdd(counters + 0, e);
         if (f) atomicAdd(counters + 1, f);
         if (k) atomicAdd(counters + 2, k);
         if (w != 0.f) atomicAdd(reinterpret_cast<double*>(counters + 3), (double)w);
@@ -532,14 +525,37 @@ __device__ inline void cons_coef(const float4* __restrict__ st, const float2* __
   c.v = zk.y;
 }
 
+// Lane -> pixel of the backward.  A block owns a tile; wave i owns the tile's
+// 4 x 4 quadrant(s) numbered as in the forward (quadrant 4 w + r is row r of
+// forward wave w).  With up to 16 quadrants a wave owns one and all four rows
+// of 16 lanes hold its 16 pixels (R = 4 copies); 32 x 16 tiles (32 quadrants,
+// 16 waves) give each wave two, rows 0-1 and 2-3 (R = 2).  Row r of a wave
+// takes copy r % R of quadrant r / R.
+template <int TW, int TH>
+struct BwdMap {
+  static constexpr int NQ = TW * TH / 16;           // quadrants per tile
+  static constexpr int QW = NQ > 16 ? 2 : 1;        // quadrants per wave
+  static constexpr int NW = NQ / QW;                // waves per block
+  static constexpr int R = 4 / QW;                  // rows per quadrant
+  static constexpr int NT = NW * 64;                // threads per block
+};
+
 // SS: also accumulate the densification statistic in slot G_SS.
 // CONS: add the adjoint of the depth statistics (loss weights d_cons on the
 // consolidation term, d_depth on the composited depth; either may be null).
 // PPX: the per-pixel-Jacobian MIP filter (frag_eval_pp and its adjoint).
+//
+// The walk needs no gap tests: the forward recorded where each of a pixel's
+// layers starts in the tile list and where its walk ended, and per chunk and
+// quadrant which records had a fragment accumulated there.  A wave steps only
+// those records, R of them at a time (one per row); a lane's list positions
+// increase from step to step, so it advances its layer (transmittance, prefix
+// colour and the layer's coefficients, as in the forward's compositing order)
+// whenever a position reaches the next layer's start.
 // Occupancy target: 5 waves per SIMD (up to 102 VGPRs per lane), 4 with the
 // extra statistics or the per-pixel filter.
 template <int TW, int TH, bool SS, bool CONS, bool PPX>
-__global__ void __launch_bounds__(TW* TH)
+__global__ void __launch_bounds__((BwdMap<TW, TH>::NT))
 __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backward_kernel(
     const ViewDev* __restrict__ views, int n_views, int tile_begin, int n_items,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
@@ -547,16 +563,19 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
     const float* __restrict__ d_alpha, const uint8_t* __restrict__ nl_int,
     const float4* __restrict__ stats, const float2* __restrict__ stats2, const float* __restrict__ d_cons,
     const float* __restrict__ d_depth, float* __restrict__ grad, long long R, int* queue,
-    const int* __restrict__ order, int persistent) {
+    const int* __restrict__ order, int persistent, const uint32_t* __restrict__ lpos,
+    const uint64_t* __restrict__ qmask, long long mask_base) {
+  using M = BwdMap<TW, TH>;
   // values reduced per fragment: the 11 record slots, then G_SS, then G_TZ
   constexpr int NV = kNGrad + (SS ? 1 : 0) + (CONS ? 1 : 0);
   constexpr int RW = NV <= 12 ? 12 : 16;
+  constexpr int NT = M::NT;
   extern __shared__ float4 lds[];
   __shared__ int s_item;
-  constexpr int NT = TW * TH;
-  const int t = threadIdx.x, lane = t & 63, row = lane >> 4;
+  __shared__ uint32_t s_stop;
+  const int t = threadIdx.x, lane = t & 63, row = lane >> 4, wave = t >> 6;
+  const int quad = wave * M::QW + row / M::R;       // the tile's quadrant of this lane
   const float r2 = prm.r2, kappa = prm.kappa;
-  const int kmax = prm.k_max;
   for (int iter = 0;; ++iter) {
     const int item = next_item(queue, persistent, s_item, iter);
     if (item < 0 || item >= n_items) break;
@@ -565,11 +584,14 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
     const int lt = tile - v.tile_base;
     const int tx = lt % v.tiles_x, ty = lt / v.tiles_x;
     int lx, ly, sx0, sy0;
-    pixel_of_thread<TW, TH>(t, tx, ty, lx, ly, sx0, sy0);
+    // the forward's lane of this pixel: wave quad / 4, row quad % 4, same lane in the row
+    pixel_of_thread<TW, TH>((quad >> 2) * 64 + (quad & 3) * 16 + (lane & 15), tx, ty, lx, ly, sx0, sy0);
     const int px = tx * TW + lx, py = ty * TH + ly;
     const bool inside = px < v.W && py < v.H;
     const long long pix = v.pix_off + (long long)py * v.W + px;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    if (t == 0) s_stop = start;
+    __syncthreads();
 
     float G[3] = {0.f, 0.f, 0.f}, ga = 0.f;
     int nl = 0;
@@ -581,14 +603,17 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
     ConsCoef CC;
     CC.A = CC.B = CC.C = CC.z = CC.v = 0.f;
     float dc = 0.f, dd = 0.f, U = 0.f;
-    bool done = true;
+    int k = 0;
+    uint32_t adv = 0xffffffffu;   // list position where the next layer starts
+    uint32_t pend = 0u;           // list position where the pixel's walk ended
+    const uint32_t* const lp = lpos + pix * kPosStride;
     if (inside) {
       G[0] = d_image[3 * pix]; G[1] = d_image[3 * pix + 1]; G[2] = d_image[3 * pix + 2];
       ga = d_alpha ? d_alpha[pix] : 0.f;
       nl = nl_int[pix];
       float T = 1.f;
-      for (int k = 0; k < nl; ++k) {
-        const float4 st = stats[pix * kMaxLayers + k];
+      for (int kk = 0; kk < nl; ++kk) {
+        const float4 st = stats[pix * kMaxLayers + kk];
         const float a = -expm1f(-kappa * st.x), e = __expf(-kappa * st.x);
         const float s = T * a * layer_norm(prm.shade, st.x, st.y, st.z, st.w);
         Cf[0] += s * st.y; Cf[1] += s * st.z; Cf[2] += s * st.w;
@@ -612,22 +637,39 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
           U = 2.f * dc * cs + dd * dp;
           cons_coef(stats + pix * kMaxLayers, stats2 + pix * kMaxLayers, nl, 0, kappa, dc, dd, U, CC);
         }
-        done = false;
+        adv = nl > 1 ? lp[1] : 0xffffffffu;
+        pend = lp[nl];
+        // the block's batches end where the last of its pixels' walks ended
+        atomicMax(&s_stop, pend < end ? pend + 1u : end);
       }
     }
-    int k = 0;
-    float Wg = 0.f, zmax = 0.f;
-    for (uint32_t b0 = start; b0 < end; b0 += (uint32_t)B) {
-      if (__syncthreads_and(done)) break;
+    __syncthreads();
+    const uint32_t stop = s_stop;
+    const long long slot0 = mask_base + (start >> 5) + (tile - tile_begin);
+    uint64_t* const smask = reinterpret_cast<uint64_t*>(lds + 4 * B);  // [chunk of the batch][quadrant]
+    for (uint32_t b0 = start; b0 < stop; b0 += (uint32_t)B) {
       const int cnt = (int)min((uint32_t)B, end - b0);
       load_batch<NT>(lds, vals, recs, b0, cnt);
+      // the walk masks of the batch's chunks, every quadrant of the tile
+      const int nch = (cnt + 63) >> 6;
+      for (int i = t; i < nch * M::NQ; i += NT) {
+        const int ch = i / M::NQ, q = i - ch * M::NQ;
+        smask[i] = qmask[(slot0 + ((b0 + (uint32_t)(ch << 6) - start) >> 5)) * M::NQ + q];
+      }
       __syncthreads();
       for (int c0 = 0; c0 < cnt; c0 += 64) {
-        if (__ballot(!done) == 0ull) break;
-        uint64_t m[4];
-        chunk_masks<!PPX>(lds, c0, cnt, lane, sx0, sy0, r2, m);
-        while ((m[0] | m[1] | m[2] | m[3]) != 0ull) {
-          const int jl = next_records(m, row);
+        const uint64_t* qm = smask + (c0 >> 6) * M::NQ + wave * M::QW;
+        uint64_t mq0 = uniform64(qm[0]), mq1 = M::QW > 1 ? uniform64(qm[1]) : 0ull;
+        while ((mq0 | mq1) != 0ull) {
+          // row r takes copy r % R of quadrant r / R: the next R records of its mask
+          int jr[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            uint64_t& m = (M::QW > 1 && r >= 2) ? mq1 : mq0;
+            jr[r] = m ? (int)__builtin_ctzll(m) : -1;
+            m = uniform64(m & (m - 1));
+          }
+          const int jl = row == 0 ? jr[0] : (row == 1 ? jr[1] : (row == 2 ? jr[2] : jr[3]));
           // idle rows read a valid record and contribute nothing
           float rec[kRecFloats];
           load_record(lds + 4 * (c0 + (jl < 0 ? 0 : jl)), rec);
@@ -638,38 +680,28 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
             frag_eval(rec, px, py, r2, f);
           bool contrib = false;
           float gw = 0.f, gcs = 0.f, gz = 0.f, zf = 0.f;
-          if (jl >= 0 && f.cov && !done) {
-            bool live = true;
-            if (Wg > 0.f && rec[R_ZS] > zmax) {
-              // next layer: the forward flushed layer k here
+          const uint32_t p = b0 + (uint32_t)(c0 + jl);
+          if (jl >= 0 && f.cov && p < pend) {
+            while (p >= adv) {
+              // the fragment lies in a later layer: advance (as the forward composited)
               pre[0] += Tk * L.a * L.Ch0; pre[1] += Tk * L.a * L.Ch1; pre[2] += Tk * L.a * L.Ch2;
               Tk *= L.e;
               ++k;
-              if (k >= kmax || k >= nl) {
-                done = true;
-                live = false;
-              } else {
-                layer_coef(stats[pix * kMaxLayers + k], Tk, kappa, G, ga, Tfin, Cf, pre, prm.shade, L);
-                if constexpr (CONS)
-                  cons_coef(stats + pix * kMaxLayers, stats2 + pix * kMaxLayers, nl, k, kappa, dc, dd, U, CC);
-                Wg = 0.f;
-                zmax = 0.f;
-              }
+              layer_coef(stats[pix * kMaxLayers + k], Tk, kappa, G, ga, Tfin, Cf, pre, prm.shade, L);
+              if constexpr (CONS)
+                cons_coef(stats + pix * kMaxLayers, stats2 + pix * kMaxLayers, nl, k, kappa, dc, dd, U, CC);
+              adv = k + 1 < nl ? lp[k + 1] : 0xffffffffu;
             }
-            if (live) {
-              zmax = fmaxf(zmax, rec[R_ZE]);
-              Wg += f.w;
-              const float Gc = L.G0 * rec[R_CR] + L.G1 * rec[R_CG] + L.G2 * rec[R_CB];
-              gw = L.dW + L.coef * (Gc - L.GC);
-              gcs = f.w * L.coef;
-              if constexpr (CONS) {
-                zf = frag_depth(rec, f);
-                const float dz = zf - CC.z;
-                gw += CC.A + CC.B * dz + CC.C * (dz * dz - CC.v);
-                gz = f.w * (CC.B + 2.f * CC.C * dz);
-              }
-              contrib = true;
+            const float Gc = L.G0 * rec[R_CR] + L.G1 * rec[R_CG] + L.G2 * rec[R_CB];
+            gw = L.dW + L.coef * (Gc - L.GC);
+            gcs = f.w * L.coef;
+            if constexpr (CONS) {
+              zf = frag_depth(rec, f);
+              const float dz = zf - CC.z;
+              gw += CC.A + CC.B * dz + CC.C * (dz * dz - CC.v);
+              gz = f.w * (CC.B + 2.f * CC.C * dz);
             }
+            contrib = true;
           }
           if (__ballot(contrib) == 0ull) continue;
           // d(rho^2)/d(record) for q = d^T Q d / s^2, s = 1 + a3 dx + b3 dy.  Lanes that
@@ -822,11 +854,11 @@ static hipError_t fwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vi
                         const Params& prm, int B, float* image, float* alpha, uint8_t* nlo,
                         uint8_t* nli, float4* stats, float2* stats2, float* cons, float* depth,
                         int* queue, const int* order, int pers, const int* status,
-                        unsigned long long* counters) {
+                        unsigned long long* counters, const WalkBufs& wb) {
 #define SS_FWD_V(CV, PV)                                                                                 \
   hipLaunchKernelGGL((raster_forward_kernel<TW, TH, CV, PV>), grid, dim3(TW * TH), lds, st, views, nv, tb, ni, \
                      ranges, vals, recs, prm, B, image, alpha, nlo, nli, stats, stats2, cons, depth, queue,    \
-                     order, pers, status, counters)
+                     order, pers, status, counters, wb.pos, wb.masks, wb.mask_base)
   if (prm.mip == 1) {
     if (prm.cons) SS_FWD_V(true, true);
     else SS_FWD_V(false, true);
@@ -843,15 +875,16 @@ static void bwd_launch(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vie
                        const uint32_t* ranges, const uint32_t* vals, const float* recs, const Params& prm,
                        int B, const float* di, const float* da, const uint8_t* nli, const float4* stats,
                        const float2* stats2, const float* dcons, const float* ddepth, float* grad, long long R,
-                       int* queue, const int* order, int pers) {
+                       int* queue, const int* order, int pers, const WalkBufs& wb) {
+  const dim3 block(BwdMap<TW, TH>::NT);
   if (prm.mip == 1)
-    hipLaunchKernelGGL((raster_backward_kernel<TW, TH, SS, CONS, true>), grid, dim3(TW * TH), lds, st, views, nv,
+    hipLaunchKernelGGL((raster_backward_kernel<TW, TH, SS, CONS, true>), grid, block, lds, st, views, nv,
                        tb, ni, ranges, vals, recs, prm, B, di, da, nli, stats, stats2, dcons, ddepth, grad, R,
-                       queue, order, pers);
+                       queue, order, pers, wb.pos, wb.masks, wb.mask_base);
   else
-    hipLaunchKernelGGL((raster_backward_kernel<TW, TH, SS, CONS, false>), grid, dim3(TW * TH), lds, st, views, nv,
+    hipLaunchKernelGGL((raster_backward_kernel<TW, TH, SS, CONS, false>), grid, block, lds, st, views, nv,
                        tb, ni, ranges, vals, recs, prm, B, di, da, nli, stats, stats2, dcons, ddepth, grad, R,
-                       queue, order, pers);
+                       queue, order, pers, wb.pos, wb.masks, wb.mask_base);
 }
 
 template <int TW, int TH>
@@ -860,10 +893,10 @@ static hipError_t bwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vi
                         const Params& prm, int B, const float* di, const float* da,
                         const uint8_t* nli, const float4* stats, const float2* stats2, const float* dcons,
                         const float* ddepth, float* grad, long long R, int* queue, const int* order,
-                        int pers) {
+                        int pers, const WalkBufs& wb) {
 #define SS_BWD_V(SSV, CV) bwd_launch<TW, TH, SSV, CV>(grid, lds, st, views, nv, tb, ni, ranges, vals, recs, \
                                                        prm, B, di, da, nli, stats, stats2, dcons, ddepth,    \
-                                                       grad, R, queue, order, pers)
+                                                       grad, R, queue, order, pers, wb)
   if (prm.ss_grad && prm.cons) SS_BWD_V(true, true);
   else if (prm.ss_grad) SS_BWD_V(true, false);
   else if (prm.cons) SS_BWD_V(false, true);
@@ -886,18 +919,18 @@ hipError_t launch_raster_forward(const ViewDev* views, int n_views, int tile_beg
                                  uint8_t* n_layers, float4* layer_stats, float2* layer_stats2,
                                  float* cons, float* depth, int* queue, const int* order,
                                  int persistent, const int* status, unsigned long long* counters,
-                                 hipStream_t st) {
+                                 const WalkBufs& wb, hipStream_t st) {
   const int n_items = tile_end - tile_begin;
   if (n_items <= 0) return hipSuccess;
   if (prm.cons && (!layer_stats2 || (!cons && !depth))) return hipErrorInvalidValue;
-  if (!status || (prm.counters && !counters)) return hipErrorInvalidValue;
+  if (!status || (prm.counters && !counters) || !wb.pos || !wb.masks) return hipErrorInvalidValue;
   const int threads = prm.tile_w * prm.tile_h;
   dim3 grid(persistent ? persistent_grid(n_items, threads) : (unsigned)n_items);
   const size_t lds = (size_t)lds_batch * kRecFloats * sizeof(float);
 #define SS_FWD(TW, TH) fwd_t<TW, TH>(grid, lds, st, views, n_views, tile_begin, n_items, ranges, \
                                      sorted_vals, recs, prm, lds_batch, image, alpha,            \
                                      n_layers_out, n_layers, layer_stats, layer_stats2, cons,    \
-                                     depth, queue, order, persistent, status, counters)
+                                     depth, queue, order, persistent, status, counters, wb)
   switch (prm.tile_w * 100 + prm.tile_h) {
     case 808: return SS_FWD(8, 8);
     case 1608: return SS_FWD(16, 8);
@@ -916,17 +949,21 @@ hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_be
                                   const uint8_t* n_layers, const float4* layer_stats,
                                   const float2* layer_stats2, const float* d_cons,
                                   const float* d_depth, float* grad, long long R, int* queue,
-                                  const int* order, int persistent, hipStream_t st) {
+                                  const int* order, int persistent, const WalkBufs& wb, hipStream_t st) {
   const int n_items = tile_end - tile_begin;
   if (n_items <= 0) return hipSuccess;
   if (prm.cons && (!layer_stats2 || (!d_cons && !d_depth))) return hipErrorInvalidValue;
-  const int threads = prm.tile_w * prm.tile_h;
+  if (!wb.pos || !wb.masks) return hipErrorInvalidValue;
+  // four lanes per pixel (wave i owns 4 x 4 quadrant i), at most 1024 threads
+  const int threads = prm.tile_w * prm.tile_h * 4 > 1024 ? 1024 : prm.tile_w * prm.tile_h * 4;
   dim3 grid(persistent ? persistent_grid(n_items, threads) : (unsigned)n_items);
-  const size_t lds = (size_t)lds_batch * kRecFloats * sizeof(float);
+  // staged records, then the walk masks of the batch's chunks (per quadrant)
+  const size_t lds = (size_t)lds_batch * kRecFloats * sizeof(float) +
+                     (size_t)((lds_batch + 63) / 64) * (prm.tile_w * prm.tile_h / 16) * sizeof(uint64_t);
 #define SS_BWD(TW, TH) bwd_t<TW, TH>(grid, lds, st, views, n_views, tile_begin, n_items, ranges, \
                                      sorted_vals, recs, prm, lds_batch, d_image, d_alpha,        \
                                      n_layers, layer_stats, layer_stats2, d_cons, d_depth, grad, \
-                                     R, queue, order, persistent)
+                                     R, queue, order, persistent, wb)
   switch (prm.tile_w * 100 + prm.tile_h) {
     case 808: return SS_BWD(8, 8);
     case 1608: return SS_BWD(16, 8);
