@@ -647,9 +647,13 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
     const uint32_t stop = s_stop;
     const long long slot0 = mask_base + (start >> 5) + (tile - tile_begin);
     uint64_t* const smask = reinterpret_cast<uint64_t*>(lds + 4 * B);  // [chunk of the batch][quadrant]
+    // per wave, the batch's records' gradient sums [wave][record][value]
+    float* const acc = reinterpret_cast<float*>(smask + ((B + 63) >> 6) * M::NQ);
+    float* const wacc = acc + (long long)wave * B * NV;
     for (uint32_t b0 = start; b0 < stop; b0 += (uint32_t)B) {
       const int cnt = (int)min((uint32_t)B, end - b0);
       load_batch<NT>(lds, vals, recs, b0, cnt);
+      for (int i = t; i < M::NW * B * NV; i += NT) acc[i] = 0.f;
       // the walk masks of the batch's chunks, every quadrant of the tile
       const int nch = (cnt + 63) >> 6;
       for (int i = t; i < nch * M::NQ; i += NT) {
@@ -768,12 +772,33 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
             tot = row_reduce12(g, lane, &vidx);
           else
             tot = row_reduce16(g, lane, &vidx);
-          if (vidx >= 0 && vidx < NV && tot != 0.f) {
-            // reduced index -> gradient slot (the extras are packed after the 11)
-            const int slot = vidx < kNGrad ? vidx : (vidx == NV - 1 && CONS ? (int)G_TZ : (int)G_SS);
-            const uint32_t id = __float_as_uint(rec[R_ID]);
-            atomicAdd(grad + (long long)id * kGradStride + slot, tot);
+          // into the wave's sums: with one quadrant per wave the rows hold
+          // different records (distinct words); with two, the second quadrant's
+          // rows add after the first's (a wave's LDS operations complete in order)
+          const bool put = jl >= 0 && vidx >= 0 && vidx < NV && tot != 0.f;
+          float* const a = wacc + (c0 + (jl < 0 ? 0 : jl)) * NV + (vidx < 0 ? 0 : vidx);
+          if constexpr (M::QW == 1) {
+            if (put) *a += tot;
+          } else {
+            // volatile: the two exclusive per-lane updates must stay two, in order
+            volatile float* const va = a;
+            if (put && row < 2) *va = *va + tot;
+            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the first rows' adds are done
+            if (put && row >= 2) *va = *va + tot;
           }
+        }
+      }
+      __syncthreads();
+      // one atomic per (record, value) of the tile: the waves' sums in a fixed order
+      for (int i = t; i < cnt * NV; i += NT) {
+        const int j = i / NV, vi = i - j * NV;
+        float sum = 0.f;
+#pragma unroll
+        for (int w = 0; w < M::NW; ++w) sum += acc[((long long)w * B + j) * NV + vi];
+        if (sum != 0.f) {
+          const int slot = vi < kNGrad ? vi : (vi == NV - 1 && CONS ? (int)G_TZ : (int)G_SS);
+          const uint32_t id = __float_as_uint(lds[4 * j + 3].w);
+          atomicAdd(grad + (long long)id * kGradStride + slot, sum);
         }
       }
       __syncthreads();
@@ -957,9 +982,16 @@ hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_be
   // four lanes per pixel (wave i owns 4 x 4 quadrant i), at most 1024 threads
   const int threads = prm.tile_w * prm.tile_h * 4 > 1024 ? 1024 : prm.tile_w * prm.tile_h * 4;
   dim3 grid(persistent ? persistent_grid(n_items, threads) : (unsigned)n_items);
-  // staged records, then the walk masks of the batch's chunks (per quadrant)
-  const size_t lds = (size_t)lds_batch * kRecFloats * sizeof(float) +
-                     (size_t)((lds_batch + 63) / 64) * (prm.tile_w * prm.tile_h / 16) * sizeof(uint64_t);
+  // staged records, the walk masks of the batch's chunks (per quadrant) and
+  // the waves' gradient sums; the batch shrinks until they fit in 120 KiB
+  const int nq = prm.tile_w * prm.tile_h / 16, nw = nq > 16 ? 16 : nq;
+  const int nv = kNGrad + (prm.ss_grad ? 1 : 0) + (prm.cons ? 1 : 0);
+  auto lds_for = [&](int b) {
+    return (size_t)b * kRecFloats * sizeof(float) + (size_t)((b + 63) / 64) * nq * sizeof(uint64_t) +
+           (size_t)nw * b * nv * sizeof(float);
+  };
+  while (lds_batch > 32 && lds_for(lds_batch) > 120 * 1024) lds_batch /= 2;
+  const size_t lds = lds_for(lds_batch);
 #define SS_BWD(TW, TH) bwd_t<TW, TH>(grid, lds, st, views, n_views, tile_begin, n_items, ranges, \
                                      sorted_vals, recs, prm, lds_batch, d_image, d_alpha,        \
                                      n_layers, layer_stats, layer_stats2, d_cons, d_depth, grad, \
