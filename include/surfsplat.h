@@ -111,12 +111,16 @@ typedef struct ss_options {
                           as after the K_max-th layer (App. A.1); the image keeps
                           T_{K+1} bg.  0 (default): off, the exact semantics        */
   int32_t deterministic; /* 1: ss_render_backward returns bitwise identical gradients
-                          for identical inputs: the raster backward sums each
-                          record's per-fragment gradients per (record, tile) in a
-                          fixed order and the tiles of a record in a fixed order
-                          (instead of float atomics in arrival order), and the
-                          environment gradients are accumulated in 64-bit fixed
-                          point.  Slower, and it reserves 48 bytes per pair more */
+                          for identical inputs and options: the raster backward sums
+                          each record's per-fragment gradients per (record, tile)
+                          in a fixed order, stores that partial at the pair's
+                          emission slot and adds a record's slots in emission order
+                          (instead of float atomics in arrival order); the shading
+                          adjoint adds environment texel gradients as 64-bit
+                          integers (a per-scene power-of-two scale bounded from the
+                          records, every level in global memory) and the
+                          environment adjoint sums fixed chunks in a fixed order.
+                          Slower; reserves 64 bytes per pair and 4 per record more */
   int32_t validate;    /* 1: every ss_render counts the non-finite surfel parameters
                           and environment texels, every ss_render_backward the
                           non-finite entries of d_image / d_alpha; the count of the

@@ -58,6 +58,7 @@ struct Group {
 struct SceneEnv {
   int He = 0, We = 0;
   DevBuf dirs, lv, Z /* output-texel table (R, 1/Z) of levels 1..6 */, dlv, part /* prefilter partials */;
+  DevBuf dlv_fx, adj_part;  // deterministic backward: fixed-point level gradients, adjoint partials
   int lh[7], lw[7];
   long long off[7];   // float offsets of levels 1..6 in lv
   long long doff[7];  // float offsets of levels 0..6 in dlv
@@ -85,7 +86,9 @@ struct ss_context {
   std::vector<Group> groups;
   std::vector<SceneEnv> env;
   DevBuf views_d, recs, counts, offsets, scan_tmp, keys, vals, keys2, vals2, hist, ranges, nl, stats,
-      grad, misc, partial, sg, order, stats2, zkey, zkey2, zidx, zidx2, prect, zrect, lpos, qmask;
+      grad, misc, partial, sg, order, stats2, zkey, zkey2, zidx, zidx2, prect, zrect, lpos, qmask,
+      pgrad /* deterministic: per-pair gradient partials */, inv /* record -> depth position */,
+      detw /* deterministic: per scene fixed-point bound and exponent */;
   std::vector<long long> soff;
   long long scan_tmp_n = 0, pair_total = 0, hist_n = 0;
   DevBuf lut;
@@ -147,7 +150,6 @@ ss_status check_options(const ss_options* o) {
   if (o->env_lds < -1) return SS_ERR_INVALID_ARG;
   if (!(o->t_min >= 0.f) || !(o->t_min < 1.f)) return SS_ERR_INVALID_ARG;
   if ((o->deterministic | o->validate | o->counters | o->tonemap) & ~1) return SS_ERR_INVALID_ARG;
-  if (o->deterministic) return SS_ERR_UNSUPPORTED;
   return SS_OK;
 }
 
@@ -257,6 +259,7 @@ void build_views(ss_context* c, const ss_batch* b, std::vector<ViewDev>& out) {
       SceneEnv& e = c->env[k.scene];
       d.lvl[0] = b->envmap[k.scene];
       d.dlvl[0] = P<float>(e.dlv) + e.doff[0];
+      for (int l = 0; l < 7; ++l) d.dlvl_fx[l] = e.dlv_fx.p ? P<long long>(e.dlv_fx) + e.doff[l] : nullptr;
       for (int l = 1; l < 7; ++l) {
         d.lvl[l] = P<float>(e.lv) + e.off[l];
         d.dlvl[l] = P<float>(e.dlv) + e.doff[l];
@@ -301,7 +304,8 @@ void env_layout(const ss_context* c, const ss_batch* b, int s, SceneEnv& e, long
   e.loc_total = 0;
   for (int l : {6, 5, 4, 3, 2, 1, 0}) {
     const int n = 3 * e.lh[l] * e.lw[l];
-    const int budget = c->opt.env_lds < 0 ? kLocalMapFloats : std::min(c->opt.env_lds, kLocalMapFloats);
+    const int budget = c->opt.deterministic ? 0
+                       : (c->opt.env_lds < 0 ? kLocalMapFloats : std::min(c->opt.env_lds, kLocalMapFloats));
     if (e.loc_total + n > budget) break;
     e.loc_off[l] = e.loc_total;
     e.loc_total += n;
@@ -324,6 +328,10 @@ ss_status prepare_env(ss_context* c, const ss_batch* b, hipStream_t st) {
     SS_HIP(ensure(e.dlv, d * sizeof(float)));
     SS_HIP(ensure(e.Z, (size_t)(lv_n / 3 + 1) * 4 * sizeof(float)));
     SS_HIP(ensure(e.part, (size_t)envmap_prefilter_chunks(He, We) * (size_t)lv_n * sizeof(float)));
+    if (c->opt.deterministic) {
+      SS_HIP(ensure(e.dlv_fx, d * sizeof(long long)));
+      SS_HIP(ensure(e.adj_part, (size_t)envmap_adjoint_chunks((int)(lv_n / 3)) * He * We * 3 * sizeof(float)));
+    }
     if (e.He != He || e.We != We || !e.dirs.p) {
       SS_HIP(ensure(e.dirs, (size_t)He * We * 4 * sizeof(float)));
       SS_HIP(launch_envmap_dirs(P<float>(e.dirs), He, We, st));
@@ -483,6 +491,11 @@ WalkBufs walk_bufs(ss_context* c, const Group& g) {
   w.pos = P<uint32_t>(c->lpos);
   w.masks = P<uint64_t>(c->qmask);
   w.mask_base = g.mask_base;
+  const bool det = c->opt.deterministic && c->pgrad.p;
+  w.pgrad = det ? P<float>(c->pgrad) : nullptr;
+  w.inv = det ? P<uint32_t>(c->inv) : nullptr;
+  w.offs = P<uint32_t>(c->offsets) + g.rec_begin;
+  w.pair_base = g.pair_base;
   return w;
 }
 
@@ -544,6 +557,11 @@ ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
     c->lds_batch = mean >= 256 ? 256 : (mean >= 128 ? 128 : (mean >= 64 ? 64 : 32));
   }
   SS_HIP(ensure(c->qmask, (size_t)layout_masks(c) * sizeof(uint64_t)));
+  if (c->opt.deterministic) {
+    SS_HIP(ensure(c->pgrad, (size_t)base * kGradStride * sizeof(float)));
+    SS_HIP(ensure(c->inv, (size_t)R * sizeof(uint32_t)));
+    SS_HIP(ensure(c->detw, (size_t)2 * (c->n_scenes > 0 ? c->n_scenes : 1) * sizeof(uint32_t)));
+  }
   SS_HIP(ensure(c->keys, (size_t)base * sizeof(uint32_t)));
   SS_HIP(ensure(c->keys2, (size_t)base * sizeof(uint32_t)));
   SS_HIP(ensure(c->vals, (size_t)base * sizeof(uint32_t)));
@@ -598,8 +616,9 @@ size_t workspace_bytes(const ss_context* c) {
   size_t s = c->views_d.n + c->recs.n + c->counts.n + c->offsets.n + c->scan_tmp.n + c->keys.n +
              c->vals.n + c->keys2.n + c->vals2.n + c->hist.n + c->ranges.n + c->nl.n + c->stats.n +
              c->grad.n + c->misc.n + c->lut.n + c->partial.n + c->sg.n + c->order.n + c->stats2.n + c->zkey.n +
-             c->zkey2.n + c->zidx.n + c->zidx2.n + c->prect.n + c->zrect.n + c->lpos.n + c->qmask.n;
-  for (const SceneEnv& e : c->env) s += e.dirs.n + e.lv.n + e.Z.n + e.dlv.n + e.part.n;
+             c->zkey2.n + c->zidx.n + c->zidx2.n + c->prect.n + c->zrect.n + c->lpos.n + c->qmask.n +
+             c->pgrad.n + c->inv.n + c->detw.n;
+  for (const SceneEnv& e : c->env) s += e.dirs.n + e.lv.n + e.Z.n + e.dlv.n + e.part.n + e.dlv_fx.n + e.adj_part.n;
   return s;
 }
 
@@ -805,9 +824,13 @@ ss_status ss_destroy(ss_context* c) {
   DevBuf* bufs[] = {&c->views_d, &c->recs, &c->counts, &c->offsets, &c->scan_tmp, &c->keys,
                     &c->vals, &c->keys2, &c->vals2, &c->hist, &c->ranges, &c->nl, &c->stats,
                     &c->grad, &c->misc, &c->lut, &c->partial, &c->sg, &c->order, &c->stats2,
-                    &c->zkey, &c->zkey2, &c->zidx, &c->zidx2, &c->prect, &c->zrect, &c->lpos, &c->qmask};
+                    &c->zkey, &c->zkey2, &c->zidx, &c->zidx2, &c->prect, &c->zrect, &c->lpos, &c->qmask,
+                    &c->pgrad, &c->inv, &c->detw};
   for (DevBuf* b : bufs) release(*b);
-  for (SceneEnv& e : c->env) { release(e.dirs); release(e.lv); release(e.Z); release(e.dlv); release(e.part); }
+  for (SceneEnv& e : c->env) {
+    release(e.dirs); release(e.lv); release(e.Z); release(e.dlv); release(e.part);
+    release(e.dlv_fx); release(e.adj_part);
+  }
   for (auto& pe : c->prof_ev) { c->ev_pool.push_back(pe.second.first); c->ev_pool.push_back(pe.second.second); }
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->side) {
@@ -890,7 +913,8 @@ static ss_status envmap_backward(ss_context* c, const ss_grads* gr, const int* s
     const float* dl[7];
     for (int l = 0; l < 7; ++l) dl[l] = P<float>(e.dlv) + e.doff[l];
     SS_HIP(launch_envmap_adjoint(dl, e.lh, e.lw, P<float>(e.Z), e.He, e.We, P<float>(e.dirs),
-                                 gr->d_envmap[s], status, st));
+                                 gr->d_envmap[s], status, c->opt.deterministic ? P<float>(e.adj_part) : nullptr,
+                                 st));
   }
   return SS_OK;
 }
@@ -917,11 +941,16 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
     SS_HIP(launch_count_nonfinite(gin->d_image, 3 * c->n_pix, cnt, st));
     if (gin->d_alpha) SS_HIP(launch_count_nonfinite(gin->d_alpha, c->n_pix, cnt, st));
   }
+  const bool det = c->opt.deterministic != 0;
   SS_HIP(launch_fill_f32(P<float>(c->grad), 0.f, (long long)c->R * kGradStride, st));
   if (c->opt.shade == SS_SHADE_SPLITSUM)
     for (SceneEnv& e : c->env) SS_HIP(launch_fill_f32(P<float>(e.dlv), 0.f, (long long)(e.dlv.n / 4), st));
+  if (det) SS_HIP(launch_fill_f32(P<float>(c->pgrad), 0.f, c->pair_total * kGradStride, st));
   for (size_t gi = 0; gi < c->groups.size(); ++gi) {
     const Group& g = c->groups[gi];
+    if (det)
+      SS_HIP(launch_invert_order(P<uint32_t>(c->zidx) + g.rec_begin, g.rec_end - g.rec_begin, P<uint32_t>(c->inv),
+                                 st));
     SS_HIP(launch_fill_u32(misc + kMiscQueue, 0u, 1, st));
     hipEvent_t t0 = prof_begin(c, st);
     SS_HIP(launch_raster_backward(P<ViewDev>(c->views_d), c->n_views, g.tile_base,
@@ -933,6 +962,11 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
                                   reinterpret_cast<int*>(misc + kMiscQueue),
                                   c->opt.persistent ? P<int>(c->order) + g.tile_base : nullptr,
                                   c->opt.persistent, walk_bufs(c, g), st));
+    if (det)  // each record's gradient: its (record, tile) partials in emission order
+      SS_HIP(launch_ordered_record_sums(P<uint32_t>(c->zidx) + g.rec_begin, P<uint2>(c->zrect) + g.rec_begin,
+                                        P<uint32_t>(c->offsets) + g.rec_begin, g.rec_end - g.rec_begin,
+                                        c->opt.tile_w, c->opt.tile_h, P<float>(c->pgrad), g.pair_base,
+                                        g.pair_cap, P<float>(c->grad), st));
     prof_end(c, t0, ST_RBWD, st);
   }
   const float* pp[7];
@@ -948,9 +982,22 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
       std::vector<int> sv;
       for (int v = 0; v < c->n_views; ++v)
         if (c->views_h[v].scene == s) sv.push_back(v);
+      int* fx_exp = nullptr;
+      if (det) {  // fixed-point texel gradients with a scale bounded from this scene's records
+        unsigned* bound = P<unsigned>(c->detw) + 2 * s;
+        fx_exp = reinterpret_cast<int*>(bound + 1);
+        SS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(P<long long>(e.dlv_fx)), 0u,
+                               (long long)(e.dlv_fx.n / 4), st));
+        SS_HIP(launch_fixed_point_scale(P<float>(c->grad), b->albedo, c->N, P<ViewDev>(c->views_d), sv.data(),
+                                        (int)sv.size(), c->soff[s + 1] - c->soff[s], bound, fx_exp, st));
+      }
       SS_HIP(launch_shade_backward(pp, c->N, P<ViewDev>(c->views_d), sv.data(), (int)sv.size(), c->soff[s],
                                    (int)(c->soff[s + 1] - c->soff[s]), e.loc_off, e.loc_total,
-                                   P<float>(c->partial), lg, prm, P<float>(c->grad), P<float>(c->sg), st));
+                                   P<float>(c->partial), lg, prm, P<float>(c->grad), P<float>(c->sg), fx_exp,
+                                   st));
+      if (det)  // exactly the texels of levels 0..6 (the buffers may be larger)
+        SS_HIP(launch_fixed_to_float(P<long long>(e.dlv_fx), e.doff[6] + 3LL * e.lh[6] * e.lw[6], fx_exp,
+                                     P<float>(e.dlv), st));
     }
   }
   // The environment adjoint reads only the level gradients that the shading

@@ -74,6 +74,56 @@ hipError_t launch_count_nonfinite(const float* p, long long n, unsigned long lon
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- deterministic record sums
+__global__ void invert_order_kernel(const uint32_t* __restrict__ zidx, long long n, uint32_t* __restrict__ inv) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) inv[zidx[i]] = (uint32_t)i;
+}
+hipError_t launch_invert_order(const uint32_t* zidx, long long n, uint32_t* inv, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(invert_order_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, zidx, n, inv);
+  return hipGetLastError();
+}
+// One thread per depth-sorted record: its gradient row is the sum, in emission
+// order, of the partials at its pairs' emission slots (slots past the pair
+// capacity, after an overflow, are left out).
+__global__ void ordered_record_sums_kernel(const uint32_t* __restrict__ zidx, const uint2* __restrict__ zrect,
+                                           const uint32_t* __restrict__ offs, long long n, int tile_w, int tile_h,
+                                           const float* __restrict__ pgrad, long long pair_base,
+                                           long long pair_cap, float* __restrict__ grad) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint2 q = zrect[i];
+  const int il = (int)(q.x & 0xffffu), ih = (int)(q.x >> 16), jl = (int)(q.y & 0xffffu), jh = (int)(q.y >> 16);
+  float4 s0 = make_float4(0.f, 0.f, 0.f, 0.f), s1 = s0, s2 = s0, s3 = s0;
+  if (il <= ih && jl <= jh) {
+    const long long cnt = (long long)(ih / tile_w - il / tile_w + 1) * (jh / tile_h - jl / tile_h + 1);
+    const long long o = offs[i];
+    const long long k1 = o + cnt < pair_cap ? o + cnt : pair_cap;
+    for (long long k = o; k < k1; ++k) {
+      const float4* p = reinterpret_cast<const float4*>(pgrad + (pair_base + k) * kGradStride);
+      const float4 a = p[0], b = p[1], c = p[2], d = p[3];
+      s0.x += a.x; s0.y += a.y; s0.z += a.z; s0.w += a.w;
+      s1.x += b.x; s1.y += b.y; s1.z += b.z; s1.w += b.w;
+      s2.x += c.x; s2.y += c.y; s2.z += c.z; s2.w += c.w;
+      s3.x += d.x; s3.y += d.y; s3.z += d.z; s3.w += d.w;
+    }
+  }
+  float4* g = reinterpret_cast<float4*>(grad + (long long)zidx[i] * kGradStride);
+  g[0] = s0;
+  g[1] = s1;
+  g[2] = s2;
+  g[3] = s3;
+}
+hipError_t launch_ordered_record_sums(const uint32_t* zidx, const uint2* zrect, const uint32_t* offs, long long n,
+                                      int tile_w, int tile_h, const float* pgrad, long long pair_base,
+                                      long long pair_cap, float* grad, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ordered_record_sums_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, zidx, zrect,
+                     offs, n, tile_w, tile_h, pgrad, pair_base, pair_cap, grad);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- scan
 // Exclusive scan of u32 in three kernels: block sums, scan of the block sums
 // (one block), per-block scan plus carry.  Blocks of 256 threads hold

@@ -47,6 +47,14 @@ struct WalkBufs {
   uint32_t* pos;
   uint64_t* masks;
   long long mask_base;  // first slot of the group
+  // deterministic backward: each (record, tile) partial goes to the pair's
+  // emission slot, pgrad[(pair_base + offs[inv[record]] + k) * kGradStride + slot]
+  // with k the tile's row-major index in the record's tile rectangle (the
+  // order in which the pairs were emitted); null pgrad: float atomics
+  float* pgrad;
+  const uint32_t* inv;   // global record index -> depth-sorted position in its group
+  const uint32_t* offs;  // depth-sorted position -> first emission slot (group-relative)
+  long long pair_base;
 };
 inline long long mask_slots(long long pair_cap, int n_tiles) { return pair_cap / 32 + n_tiles + 2; }
 
@@ -68,6 +76,7 @@ struct ViewDev {
   // environment levels: 0 = E, 1..5 specular, 6 = irradiance (split-sum only)
   const float* lvl[7];
   float* dlvl[7];          // their gradients (backward)
+  long long* dlvl_fx[7];   // deterministic backward: the same gradients in 64-bit fixed point
   int lh[7], lw[7];
 };
 
@@ -350,10 +359,13 @@ int envmap_prefilter_chunks(int He, int We);
 hipError_t launch_envmap_prefilter(const float* E, int He, int We, const float* in_dirs,
                                    const float* out_dirs, float* const lvl_out[7], const int lh[7],
                                    const int lw[7], float* part, hipStream_t st);
-// status (device): a latched SS_ERR_CAPACITY makes dE NaN.
+// status (device): a latched SS_ERR_CAPACITY makes dE NaN.  part (or null):
+// deterministic mode, scratch of 3 He We envmap_adjoint_chunks(texels of levels
+// 1..6) floats for per-chunk partial sums added in a fixed order.
+int envmap_adjoint_chunks(int out_texels);
 hipError_t launch_envmap_adjoint(const float* const dlvl[7], const int lh[7], const int lw[7],
                                  const float* out_dirs, int He, int We, const float* in_dirs,
-                                 float* dE, const int* status, hipStream_t st);
+                                 float* dE, const int* status, float* part, hipStream_t st);
 hipError_t launch_brdf_lut(float* lut, int n_nv, int n_r, int samples, hipStream_t st);
 
 hipError_t launch_preprocess(const float* const P[7], long long N, const ViewDev* views, int v0,
@@ -368,11 +380,24 @@ constexpr int kBackwardThreads = 512;      // threads per block of the shading a
 constexpr int kLocalMapFloats = 39936;
 constexpr int kReduceSplit = 32;           // first-stage chunks of the partial reduction
 int backward_blocks(long long n_items);
+// fx_exp (device int, or null): deterministic mode; the texel gradients are
+// added as integers x 2^(*fx_exp) into the views' dlvl_fx levels (no LDS
+// copies: local_total must be 0).
 hipError_t launch_shade_backward(const float* const P[7], long long N, const ViewDev* views,
                                  const int* scene_views, int n_scene_views, long long surf_off,
                                  int n_surf, const int local_off[7], int local_total, float* partial,
                                  float* const level_grad[7], const Params& prm, const float* grad,
-                                 float* sg, hipStream_t st);
+                                 float* sg, const int* fx_exp, hipStream_t st);
+// Deterministic mode: the fixed-point exponent s of a scene, written to *fx_exp
+// (after clearing *bound): every texel-gradient contribution of the shading
+// adjoint is bounded by 2 max_c |dL/dc_c| max(1, max_c |albedo_c|) of its
+// record, and a record adds at most 36 of them, so with s = 61 - ceil(log2(36 n
+// bound)) no sum can leave the int64 range.
+hipError_t launch_fixed_point_scale(const float* grad, const float* albedo, long long N, const ViewDev* views,
+                                    const int* scene_views, int n_scene_views, long long n_surf,
+                                    unsigned* bound, int* fx_exp, hipStream_t st);
+// dst[i] = src[i] 2^-(*fx_exp) rounded to float, i < n.
+hipError_t launch_fixed_to_float(const long long* src, long long n, const int* fx_exp, float* dst, hipStream_t st);
 // status (device): a latched SS_ERR_CAPACITY makes every output gradient NaN.
 hipError_t launch_geometry_backward(const float* const P[7], long long N, const ViewDev* views,
                                     int n_views, const Params& prm, const float* grad,
@@ -381,6 +406,14 @@ hipError_t launch_geometry_backward(const float* const P[7], long long N, const 
 
 hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint32_t* total, uint32_t* tmp,
                            long long tmp_n, hipStream_t st);
+// Deterministic backward of one group: inv[zidx[i]] = i for the depth order
+// zidx of its n records, and, once the raster backward has written the
+// per-(record, tile) partials at their emission slots, each record's
+// gradient = the sum of its slots in emission order (grad rows overwritten).
+hipError_t launch_invert_order(const uint32_t* zidx, long long n, uint32_t* inv, hipStream_t st);
+hipError_t launch_ordered_record_sums(const uint32_t* zidx, const uint2* zrect, const uint32_t* offs, long long n,
+                                      int tile_w, int tile_h, const float* pgrad, long long pair_base,
+                                      long long pair_cap, float* grad, hipStream_t st);
 // Exclusive scan of the tile counts of record pixel rectangles (il | ih << 16, jl | jh << 16).
 hipError_t launch_scan_rect_tiles(const uint2* rect, int tile_w, int tile_h, uint32_t* out, long long n,
                                   uint32_t* total, uint32_t* tmp, long long tmp_n, hipStream_t st);

@@ -247,7 +247,8 @@ struct DLevelSet {
 __global__ void __launch_bounds__(256) envmap_adjoint_kernel(DLevelSet L, int nt,
                                                              const float4* __restrict__ dirs,
                                                              const float4* __restrict__ out_dirs,
-                                                             float* __restrict__ dE, int chunk) {
+                                                             float* __restrict__ dE, int chunk,
+                                                             float* __restrict__ part) {
   __shared__ float4 sR[256], sG[256];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = t < nt;
@@ -319,14 +320,31 @@ __global__ void __launch_bounds__(256) envmap_adjoint_kernel(DLevelSet L, int nt
     acc1 += L.g[0][3 * t + 1];
     acc2 += L.g[0][3 * t + 2];
   }
+  if (part) {  // deterministic: the chunk's partial sums, added in chunk order afterwards
+    float* p = part + ((long long)blockIdx.y * nt + t) * 3;
+    p[0] = acc0;
+    p[1] = acc1;
+    p[2] = acc2;
+    return;
+  }
   atomicAdd(dE + 3 * t, acc0);
   atomicAdd(dE + 3 * t + 1, acc1);
   atomicAdd(dE + 3 * t + 2, acc2);
 }
 
+__global__ void envmap_adjoint_reduce_kernel(const float* __restrict__ part, int n, int nchunk, float* __restrict__ dE) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc = 0.f;
+  for (int c = 0; c < nchunk; ++c) acc += part[(long long)c * n + i];
+  dE[i] = acc;
+}
+
+int envmap_adjoint_chunks(int lh_total) { return (lh_total + 255) / 256; }
+
 hipError_t launch_envmap_adjoint(const float* const dlvl[7], const int lh[7], const int lw[7],
                                  const float* out_dirs, int He, int We, const float* in_dirs,
-                                 float* dE, const int* status, hipStream_t st) {
+                                 float* dE, const int* status, float* part, hipStream_t st) {
   DLevelSet L;
   L.first[1] = 0;
   for (int l = 0; l < 7; ++l) L.g[l] = dlvl[l];
@@ -340,7 +358,11 @@ hipError_t launch_envmap_adjoint(const float* const dlvl[7], const int lh[7], co
   const int nchunk = (L.first[7] + chunk - 1) / chunk;
   hipLaunchKernelGGL(envmap_adjoint_kernel, dim3((nt + 255) / 256, nchunk), dim3(256), 0, st, L, nt,
                      reinterpret_cast<const float4*>(in_dirs),
-                     reinterpret_cast<const float4*>(out_dirs), dE, chunk);
+                     reinterpret_cast<const float4*>(out_dirs), dE, chunk, part);
+  e = hipGetLastError();
+  if (e == hipSuccess && part)
+    hipLaunchKernelGGL(envmap_adjoint_reduce_kernel, dim3((3 * nt + 255) / 256), dim3(256), 0, st, part, 3 * nt,
+                       nchunk, dE);
   e = hipGetLastError();
   if (e != hipSuccess || !status) return e;
   return launch_poison_if_capacity(dE, (long long)nt * 3, status, st);

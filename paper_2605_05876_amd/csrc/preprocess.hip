@@ -269,6 +269,42 @@ __device__ inline void tap_scatter_global_wave(bool mine, float* dm, const Tap& 
   }
 }
 
+// Deterministic variant of tap_scatter_global_wave: the same cooperative walk
+// over the wave's lookups, each value added as the 64-bit integer
+// round(x 2^s) (integer sums do not depend on their order).
+__device__ inline void tap_scatter_global_wave_fx(bool mine, long long* dm, const Tap& T, const float g[3],
+                                                  double scale) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int tap = lane / 3, c = lane - 3 * tap;
+  const uint64_t bal = __ballot(mine);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)bal);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(bal >> 32));
+  uint64_t m = ((uint64_t)hi << 32) | lo;
+  const uint64_t pd = (uint64_t)(uintptr_t)dm;
+  while (m) {
+    const int src = (int)__builtin_ctzll(m);
+    m &= m - 1;
+    const uint64_t base = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(pd >> 32), src) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)pd, src);
+    const int o0 = __builtin_amdgcn_readlane(T.o00, src), o1 = __builtin_amdgcn_readlane(T.o01, src);
+    const int o2 = __builtin_amdgcn_readlane(T.o10, src), o3 = __builtin_amdgcn_readlane(T.o11, src);
+    const float fa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(T.fa), src));
+    const float fb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(T.fb), src));
+    const float g0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g[0]), src));
+    const float g1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g[1]), src));
+    const float g2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g[2]), src));
+    if (lane < 12) {
+      const int o = tap == 0 ? o0 : (tap == 1 ? o1 : (tap == 2 ? o2 : o3));
+      const float wa = tap < 2 ? 1.f - fa : fa, wb = (tap & 1) ? fb : 1.f - fb;
+      const float x = (c == 0 ? g0 : (c == 1 ? g1 : g2)) * (wa * wb);
+      if (x != 0.f) {
+        const long long q = __double2ll_rn((double)x * scale);
+        atomicAdd(reinterpret_cast<unsigned long long*>((long long*)(uintptr_t)base + o + c), (unsigned long long)q);
+      }
+    }
+  }
+}
+
 // The environment levels of one view as the shading adjoint sees them:
 // texels, gradient maps, sizes and the float offset of the level's LDS copy
 // (-1: not privatised).  Filled from wave-uniform values once per view; a lane
@@ -276,6 +312,7 @@ __device__ inline void tap_scatter_global_wave(bool mine, float* dm, const Tap& 
 struct LevelSet {
   const float* lvl[7];
   float* dlvl[7];
+  long long* dfx[7];
   int lh[7], lw[7], off[7];
 };
 template <class T>
@@ -475,17 +512,25 @@ __device__ inline void shade_adjoint(const Params& P, const ShadeSt& S, ShadeOut
 
 // Called by every lane of the wave (the global maps are written cooperatively);
 // lanes without a record to scatter have O.r < 0.
-__device__ inline void shade_scatter(const LevelSet& LS, const ShadeOut& O, float* sm, float* __restrict__ sg) {
+template <bool DET>
+__device__ inline void shade_scatter(const LevelSet& LS, const ShadeOut& O, float* sm, float* __restrict__ sg,
+                                     double fx_scale) {
   const bool act = O.r >= 0;
   const int l1 = O.l0 + 1;
-  const int offs[3] = {LS.off[6], pick_level(LS.off, O.l0), pick_level(LS.off, l1)};
-  float* const gls[3] = {LS.dlvl[6], pick_level(LS.dlvl, O.l0), pick_level(LS.dlvl, l1)};
   const Tap* taps[3] = {&O.Td, &O.Ta, &O.Tb};
   const float* gs[3] = {O.gLd, O.gXa, O.gXb};
+  if constexpr (DET) {
+    long long* const gfx[3] = {LS.dfx[6], pick_level(LS.dfx, O.l0), pick_level(LS.dfx, l1)};
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    if (act && offs[i] >= 0) tap_scatter_lds((lds_f32*)sm + offs[i], *taps[i], gs[i]);
-    tap_scatter_global_wave(act && offs[i] < 0, gls[i], *taps[i], gs[i]);
+    for (int i = 0; i < 3; ++i) tap_scatter_global_wave_fx(act, gfx[i], *taps[i], gs[i], fx_scale);
+  } else {
+    const int offs[3] = {LS.off[6], pick_level(LS.off, O.l0), pick_level(LS.off, l1)};
+    float* const gls[3] = {LS.dlvl[6], pick_level(LS.dlvl, O.l0), pick_level(LS.dlvl, l1)};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (act && offs[i] >= 0) tap_scatter_lds((lds_f32*)sm + offs[i], *taps[i], gs[i]);
+      tap_scatter_global_wave(act && offs[i] < 0, gls[i], *taps[i], gs[i]);
+    }
   }
   if (act) {
     float4* out = reinterpret_cast<float4*>(sg + O.r * 12);
@@ -683,10 +728,13 @@ __device__ inline bool record_has_grad(const float* grad, long long r, float gr[
   return any;
 }
 
+template <bool DET>
 __global__ void __launch_bounds__(kBackwardThreads, 1) shade_backward_kernel(
     PPtrs PP, long long N, const ViewDev* __restrict__ views, SceneViews sv, Params prm,
-    const float* __restrict__ grad, float* __restrict__ sg, LocalMaps lm, float* __restrict__ partial) {
+    const float* __restrict__ grad, float* __restrict__ sg, LocalMaps lm, float* __restrict__ partial,
+    const int* __restrict__ fx_exp) {
   extern __shared__ float sm[];
+  const double fx_scale = DET ? ldexp(1.0, *fx_exp) : 0.0;
   for (int i = threadIdx.x; i < lm.total; i += blockDim.x) sm[i] = 0.f;
   __syncthreads();
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -703,6 +751,7 @@ __global__ void __launch_bounds__(kBackwardThreads, 1) shade_backward_kernel(
     for (int l = 0; l < 7; ++l) {
       LS.lvl[l] = v.lvl[l];
       LS.dlvl[l] = v.dlvl[l];
+      LS.dfx[l] = v.dlvl_fx[l];
       LS.lh[l] = v.lh[l];
       LS.lw[l] = v.lw[l];
       LS.off[l] = lm.off[l];
@@ -717,7 +766,7 @@ __global__ void __launch_bounds__(kBackwardThreads, 1) shade_backward_kernel(
       shade_load(PP, N, grad, rec(local), sv.surf_off + local, in);
       shade_fetch(LS, cam_o, prm, in, S);
       shade_adjoint(prm, S, O);
-      shade_scatter(LS, O, sm, sg);
+      shade_scatter<DET>(LS, O, sm, sg, fx_scale);
     }
   }
   if (lm.total > 0) {
@@ -909,8 +958,9 @@ hipError_t launch_shade_backward(const float* const P[7], long long N, const Vie
                                  const int* scene_views, int n_scene_views, long long surf_off,
                                  int n_surf, const int local_off[7], int local_total, float* partial,
                                  float* const level_grad[7], const Params& prm, const float* grad,
-                                 float* sg, hipStream_t st) {
+                                 float* sg, const int* fx_exp, hipStream_t st) {
   if (n_surf <= 0 || n_scene_views <= 0) return hipSuccess;
+  if (fx_exp && local_total != 0) return hipErrorInvalidValue;
   PPtrs PP;
   for (int k = 0; k < 7; ++k) PP.p[k] = P[k];
   SceneViews sv;
@@ -922,17 +972,22 @@ hipError_t launch_shade_backward(const float* const P[7], long long N, const Vie
   lm.total = local_total;
   for (int l = 0; l < 7; ++l) lm.off[l] = local_total > 0 ? local_off[l] : -1;
   const int nb = backward_blocks((long long)n_surf * n_scene_views);
+  if (fx_exp) {
+    hipLaunchKernelGGL(shade_backward_kernel<true>, dim3(nb), dim3(kBackwardThreads), 0, st, PP, N, views, sv,
+                       prm, grad, sg, lm, partial, fx_exp);
+    return hipGetLastError();
+  }
   static bool lds_attr = false;  // allow the privatised levels beyond the default dynamic-LDS limit
   if (!lds_attr) {
-    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&shade_backward_kernel),
+    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&shade_backward_kernel<false>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize,
                                         kLocalMapFloats * (int)sizeof(float));
     if (ea != hipSuccess) return ea;
     lds_attr = true;
   }
-  hipLaunchKernelGGL(shade_backward_kernel, dim3(nb), dim3(kBackwardThreads),
+  hipLaunchKernelGGL(shade_backward_kernel<false>, dim3(nb), dim3(kBackwardThreads),
                      (size_t)local_total * sizeof(float), st, PP, N, views, sv, prm, grad, sg, lm,
-                     partial);
+                     partial, nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || local_total == 0) return e;
   LevelPtrs lp;
@@ -955,6 +1010,72 @@ hipError_t launch_geometry_backward(const float* const P[7], long long N, const 
   for (int k = 0; k < 7; ++k) { PP.p[k] = P[k]; GG.p[k] = G[k]; }
   hipLaunchKernelGGL(geometry_backward_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, PP, N,
                      views, n_views, prm, grad, sg, GG, recs, ss_out, vis_out, status);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- deterministic mode
+// Per record the bound 2 max_c |dL/dc_c| max(1, max_c |albedo_c|) of its texel
+// gradients, maxed into *bound as float bits (non-negative floats order like
+// their bit patterns).
+__global__ void fixed_point_bound_kernel(const float* __restrict__ grad, const float* __restrict__ albedo,
+                                         long long N, const ViewDev* __restrict__ views, SceneViews sv,
+                                         unsigned* __restrict__ bound) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  float b = 0.f;
+  if (i < sv.n_surf * sv.n) {
+    const int k = (int)(i / sv.n_surf);
+    const long long local = i - (long long)k * sv.n_surf;
+    const ViewDev& v = views[sv.idx[k]];
+    const long long r = v.rec_off + local, s = v.surf_off + local;
+    const float4 g = reinterpret_cast<const float4*>(grad + r * kGradStride)[2];  // slots 8..11: CR, CG, CB, SS
+    const float gc = fmaxf(fabsf(g.x), fmaxf(fabsf(g.y), fabsf(g.z)));
+    const float ra = fmaxf(1.f, fmaxf(fabsf(albedo[s]), fmaxf(fabsf(albedo[N + s]), fabsf(albedo[2 * N + s]))));
+    b = 2.f * gc * ra;
+  }
+  // a wave maximum, one atomic per wave
+  for (int off = 32; off > 0; off >>= 1) b = fmaxf(b, __shfl_xor(b, off));
+  if ((threadIdx.x & 63) == 0 && b > 0.f) atomicMax(bound, __float_as_uint(b));
+}
+__global__ void fixed_point_exponent_kernel(const unsigned* __restrict__ bound, long long n_rec, int* fx_exp) {
+  const float b = __uint_as_float(*bound);
+  int e = 0;
+  // 36 n b < 2^61: s = 61 - ceil(log2(36 n b)); no contribution at all: any s
+  const double t = 36.0 * (double)(n_rec > 0 ? n_rec : 1) * (double)b;
+  if (t > 0.0 && t < 1e300) {
+    (void)frexp(t, &e);  // t < 2^e
+    *fx_exp = 61 - e;
+  } else {
+    *fx_exp = 0;
+  }
+}
+hipError_t launch_fixed_point_scale(const float* grad, const float* albedo, long long N, const ViewDev* views,
+                                    const int* scene_views, int n_scene_views, long long n_surf,
+                                    unsigned* bound, int* fx_exp, hipStream_t st) {
+  SceneViews sv;
+  for (int k = 0; k < n_scene_views; ++k) sv.idx[k] = scene_views[k];
+  sv.n = n_scene_views;
+  sv.n_surf = (int)n_surf;
+  sv.surf_off = 0;  // unused: each record's surfel comes from its view
+  hipError_t e = launch_fill_u32(bound, 0u, 1, st);
+  if (e != hipSuccess) return e;
+  const long long n = n_surf * n_scene_views;
+  if (n > 0)
+    hipLaunchKernelGGL(fixed_point_bound_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, grad,
+                       albedo, N, views, sv, bound);
+  hipLaunchKernelGGL(fixed_point_exponent_kernel, dim3(1), dim3(1), 0, st, bound, n, fx_exp);
+  return hipGetLastError();
+}
+__global__ void fixed_to_float_kernel(const long long* __restrict__ src, long long n, const int* __restrict__ fx_exp,
+                                      float* __restrict__ dst) {
+  const double inv = ldexp(1.0, -*fx_exp);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = (float)((double)src[i] * inv);
+}
+hipError_t launch_fixed_to_float(const long long* src, long long n, const int* fx_exp, float* dst, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const long long b = (n + 255) / 256;
+  hipLaunchKernelGGL(fixed_to_float_kernel, dim3((unsigned)(b < 4096 ? b : 4096)), dim3(256), 0, st, src, n,
+                     fx_exp, dst);
   return hipGetLastError();
 }
 

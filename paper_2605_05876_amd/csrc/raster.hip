@@ -563,9 +563,11 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
     const float* __restrict__ d_alpha, const uint8_t* __restrict__ nl_int,
     const float4* __restrict__ stats, const float2* __restrict__ stats2, const float* __restrict__ d_cons,
     const float* __restrict__ d_depth, float* __restrict__ grad, long long R, int* queue,
-    const int* __restrict__ order, int persistent, const uint32_t* __restrict__ lpos,
-    const uint64_t* __restrict__ qmask, long long mask_base) {
+    const int* __restrict__ order, int persistent, WalkBufs wb) {
   using M = BwdMap<TW, TH>;
+  const uint32_t* __restrict__ lpos = wb.pos;
+  const uint64_t* __restrict__ qmask = wb.masks;
+  const long long mask_base = wb.mask_base;
   // values reduced per fragment: the 11 record slots, then G_SS, then G_TZ
   constexpr int NV = kNGrad + (SS ? 1 : 0) + (CONS ? 1 : 0);
   constexpr int RW = NV <= 12 ? 12 : 16;
@@ -789,7 +791,8 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
         }
       }
       __syncthreads();
-      // one atomic per (record, value) of the tile: the waves' sums in a fixed order
+      // per (record, value) of the tile, the waves' sums in a fixed order: one
+      // atomic, or (deterministic) a store at the pair's emission slot
       for (int i = t; i < cnt * NV; i += NT) {
         const int j = i / NV, vi = i - j * NV;
         float sum = 0.f;
@@ -797,8 +800,16 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
         for (int w = 0; w < M::NW; ++w) sum += acc[((long long)w * B + j) * NV + vi];
         if (sum != 0.f) {
           const int slot = vi < kNGrad ? vi : (vi == NV - 1 && CONS ? (int)G_TZ : (int)G_SS);
-          const uint32_t id = __float_as_uint(lds[4 * j + 3].w);
-          atomicAdd(grad + (long long)id * kGradStride + slot, sum);
+          const float4 q3 = lds[4 * j + 3];
+          const uint32_t id = __float_as_uint(q3.w);
+          if (wb.pgrad) {
+            const int rx = __float_as_int(q3.x), ry = __float_as_int(q3.y);
+            const int tx0 = (rx & 0xffff) / TW, ty0 = (ry & 0xffff) / TH, nx = (rx >> 16) / TW - tx0 + 1;
+            const long long e = wb.pair_base + wb.offs[wb.inv[id]] + (ty - ty0) * nx + (tx - tx0);
+            wb.pgrad[e * kGradStride + slot] = sum;
+          } else {
+            atomicAdd(grad + (long long)id * kGradStride + slot, sum);
+          }
         }
       }
       __syncthreads();
@@ -905,11 +916,11 @@ static void bwd_launch(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vie
   if (prm.mip == 1)
     hipLaunchKernelGGL((raster_backward_kernel<TW, TH, SS, CONS, true>), grid, block, lds, st, views, nv,
                        tb, ni, ranges, vals, recs, prm, B, di, da, nli, stats, stats2, dcons, ddepth, grad, R,
-                       queue, order, pers, wb.pos, wb.masks, wb.mask_base);
+                       queue, order, pers, wb);
   else
     hipLaunchKernelGGL((raster_backward_kernel<TW, TH, SS, CONS, false>), grid, block, lds, st, views, nv,
                        tb, ni, ranges, vals, recs, prm, B, di, da, nli, stats, stats2, dcons, ddepth, grad, R,
-                       queue, order, pers, wb.pos, wb.masks, wb.mask_base);
+                       queue, order, pers, wb);
 }
 
 template <int TW, int TH>

@@ -164,3 +164,46 @@ def test_library_picked_lds_batch(ss):
     ga, gb = ra.backward(b, G), rb.backward(b, G)
     for k in ("position", "normal", "scale", "albedo"):
         assert rel_l2(ga[k].cpu().numpy(), gb[k].cpu().numpy()) <= 1e-5, k
+
+
+def _det_case(case):
+    import math
+    if case == "C1":
+        w = g.make_config("C1")
+        return w.scenes, w.cameras, "albedo", {}
+    if case == "multiview":
+        sc = g.superquadric_scene(33, 30_000, scale_mu=math.log(0.012), scale_sigma=0.5)
+        sc.envmap = g.lognormal_envmap(33, 16, 32)
+        cams = [g.look_at_camera(3.0 * d, 72, 56) for d in g.fibonacci_directions(3)]
+        return [sc], cams, "splitsum", {}
+    scenes, cams = small_c2()
+    return scenes, cams, "splitsum", dict(launch="per_view")
+
+
+@pytest.mark.parametrize("case", ["C1", "multiview", "per_view"])
+def test_deterministic_backward_is_bitwise_reproducible(O, ss, case):
+    """options.deterministic: two backward passes (and a second renderer) give
+    bit-identical gradients of every parameter group, the environment maps and the
+    densification statistic; and they pass the oracle bar."""
+    scenes, cams, shade, kw = _det_case(case)
+    opts = ss.Options(shade=shade, deterministic=True, **kw)
+    b = ss.batch_from_scenes(scenes, cams)
+    gen = torch.Generator("cuda").manual_seed(11)
+    G = torch.randn((b.n_pixels, 3), device="cuda", generator=gen)
+    Ga = torch.randn((b.n_pixels,), device="cuda", generator=gen)
+    runs = []
+    for r in (ss.Renderer(opts), ss.Renderer(opts)):
+        for _ in range(2):
+            r.forward(b)
+            gr = r.backward(b, G, Ga, want_screen_grad=True)
+            torch.cuda.synchronize()
+            runs.append({k: ([e.clone() for e in v] if isinstance(v, list) else v.clone()) for k, v in gr.items()})
+    for other in runs[1:]:
+        for k, v in runs[0].items():
+            if isinstance(v, list):
+                for a, c in zip(v, other[k]):
+                    assert torch.equal(a, c), k
+            else:
+                assert torch.equal(v, other[k]), k
+    errs = _backward_case(O, ss, scenes, cams, shade, lambda c, v: all_pix(c), deterministic=True, **kw)
+    assert max(errs.values()) <= GRAD_REL_L2, errs
