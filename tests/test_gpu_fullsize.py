@@ -11,7 +11,7 @@ import pytest
 
 import scenegen as g
 from parity_util import (GRAD_REL_L2, assert_image_parity, compare_images, decision_ok,
-                         oracle_forward, oracle_maps, oracle_options, pixel_index, rel_l2)
+                         oracle_forward, oracle_maps, oracle_options, per_surfel_report, pixel_index, rel_l2)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -40,19 +40,63 @@ def bench_options(ss, name, shade):
                       lds_batch=t.get("lds_batch", 128))
 
 
-def sample(cam, k, seed):
+def tile_list_lengths(O, scene, cam, opts):
+    """Records per tile, from the oracle's FP32 tile rectangles (2-D prefix sums)."""
+    keep, _, rect = O.bin_f32(scene, cam, oracle_options(O, opts))
+    tx, ty = -(-cam.width // opts.tile_w), -(-cam.height // opts.tile_h)
+    r = rect[keep.astype(bool)].astype(np.int64)
+    d = np.zeros((ty + 1, tx + 1), np.int64)
+    np.add.at(d, (r[:, 1], r[:, 0]), 1)
+    np.add.at(d, (r[:, 1], r[:, 2] + 1), -1)
+    np.add.at(d, (r[:, 3] + 1, r[:, 0]), -1)
+    np.add.at(d, (r[:, 3] + 1, r[:, 2] + 1), 1)
+    return d.cumsum(0).cumsum(1)[:ty, :tx]
+
+
+def sample(O, scene, cam, opts, k, seed):
+    """k pixels, seeded: a quarter in the tiles with the longest lists (the
+    density clusters, deepest layer walks), a quarter on the image border rows
+    and columns (clipped rectangles, ragged tiles), half uniform over the image."""
     rng = np.random.default_rng(seed)
-    xs = rng.integers(int(cam.width * 0.2), int(cam.width * 0.8), k)
-    ys = rng.integers(int(cam.height * 0.2), int(cam.height * 0.8), k)
-    return np.unique(np.stack([xs, ys], 1), axis=0).astype(np.int32)
+    W, H = cam.width, cam.height
+    kc, kb = k // 4, k // 4
+    ku = k - kc - kb
+    cnt = tile_list_lengths(O, scene, cam, opts)
+    top = np.argsort(cnt.ravel())[::-1][:max(4, kc // 4)]
+    t = top[rng.integers(0, len(top), kc)]
+    tyi, txi = t // cnt.shape[1], t % cnt.shape[1]
+    cx = np.minimum(txi * opts.tile_w + rng.integers(0, opts.tile_w, kc), W - 1)
+    cy = np.minimum(tyi * opts.tile_h + rng.integers(0, opts.tile_h, kc), H - 1)
+    side = rng.integers(0, 4, kb)
+    along = rng.random(kb)
+    bx = np.where(side == 0, 0, np.where(side == 1, W - 1, (along * W).astype(np.int64)))
+    by = np.where(side == 2, 0, np.where(side == 3, H - 1, (along * H).astype(np.int64)))
+    ux, uy = rng.integers(0, W, ku), rng.integers(0, H, ku)
+    xy = np.stack([np.concatenate([cx, bx, ux]), np.concatenate([cy, by, uy])], 1)
+    return np.unique(xy, axis=0).astype(np.int32)
 
 
-@pytest.mark.parametrize("name,k", [("C3", 96), ("C5", 64)])
+def stratified(cam, cell, seed):
+    """One seeded pixel in every cell x cell block of the image (ragged edges kept)."""
+    rng = np.random.default_rng(seed)
+    ys, xs = np.mgrid[0:cam.height:cell, 0:cam.width:cell]
+    x = np.minimum(xs.ravel() + rng.integers(0, cell, xs.size), cam.width - 1)
+    y = np.minimum(ys.ravel() + rng.integers(0, cell, ys.size), cam.height - 1)
+    return np.stack([x, y], 1).astype(np.int32)
+
+
+@pytest.mark.parametrize("name,k", [("C2", 0), ("C3", 96), ("C4", 160), ("C5", 64)])
 def test_fullsize_sampled_parity(O, ss, name, k):
+    """C2 on a stratified grid (one pixel per 4 x 4 block: 16384 of its 262144
+    pixels; the whole image would take the oracle minutes), the others on
+    cluster + border + uniform samples of every view."""
     w = g.make_config(name)
     opts = bench_options(ss, name, w.shade)
     cams = w.cameras
-    pix = [sample(c, k, 100 + v) for v, c in enumerate(cams)]
+    if k == 0:
+        pix = [stratified(c, 4, 100 + v) for v, c in enumerate(cams)]
+    else:
+        pix = [sample(O, w.scenes[c.scene], c, opts, k, 100 + v) for v, c in enumerate(cams)]
     maps, lut = oracle_maps(O, w.scenes, w.shade)
     ref = oracle_forward(O, w.scenes, cams, opts, pix, maps, lut)
     r = ss.Renderer(opts)
@@ -91,7 +135,11 @@ def test_fullsize_sampled_parity(O, ss, name, k):
         ref_maps[c.scene] += gr["maps"]
     errs = {}
     for n in names:
-        errs[n] = rel_l2(grads[n].cpu().numpy(), np.concatenate([rg[n] for rg in ref_g], axis=-1))
+        got, want = grads[n].cpu().numpy(), np.concatenate([rg[n] for rg in ref_g], axis=-1)
+        errs[n] = rel_l2(got, want)
+        ps = per_surfel_report(got, want)
+        print(name, n, "per surfel", ps)
+        assert ps["n_over"] == 0, (n, ps)
     for i, sc in enumerate(w.scenes):
         dE = O.envmap_adjoint(ref_maps[i], *sc.envmap.shape[:2])
         errs[f"envmap{i}"] = rel_l2(grads["envmap"][i].cpu().numpy(), dE)
@@ -99,7 +147,7 @@ def test_fullsize_sampled_parity(O, ss, name, k):
     assert max(errs.values()) <= GRAD_REL_L2, errs
 
 
-@pytest.mark.parametrize("name", ["C3"])
+@pytest.mark.parametrize("name", ["C3", "C4"])
 def test_fullsize_binning_properties(O, ss, name):
     """Tile lists at full size, where the oracle's per-record pair listing is too
     slow: z_start bits and tile rectangles against the oracle's FP32 binning
