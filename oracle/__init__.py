@@ -37,7 +37,8 @@ PARAM_ROWS = [3, 3, 3, 2, 3, 1, 1]
 def lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "liboracle.so")
+        # ORACLE_LIBRARY: another build of oracle.cpp (the sanitizer test's)
+        path = os.environ.get("ORACLE_LIBRARY") or os.path.join(_HERE, "liboracle.so")
         if not os.path.exists(path):
             from . import build as _b
             _b.build()
@@ -213,7 +214,13 @@ def sorted_pairs(keep, zbits, rect, tiles_x, tile_base=0, rec_base=0):
     return keys[order], recs[order]
 
 
-def _maps_lut(maps, lut, He, We):
+def _maps_lut(maps, lut, He, We, opt):
+    if opt.shade == "splitsum":
+        # the C side indexes the map set by (He, We) and the table by its shape
+        if maps is None or lut is None or He <= 0 or We <= 0:
+            raise ValueError("split-sum shading needs maps, lut and env_hw")
+        if np.size(maps) != lib().orc_envmap_size(int(He), int(We)):
+            raise ValueError("maps do not match env_hw")
     if maps is None:
         maps = np.zeros(1, np.float64)
         He, We = 0, 0
@@ -235,7 +242,7 @@ def render(scene, cam, opt: Options, pix, maps=None, lut=None, env_hw=(0, 0)):
     P = _Params(scene)
     pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 2)
     k = pix.shape[0]
-    maps, lut, He, We = _maps_lut(maps, lut, *env_hw)
+    maps, lut, He, We = _maps_lut(maps, lut, *env_hw, opt)
     img = np.zeros((k, 3), np.float64)
     alpha = np.zeros(k, np.float64)
     nl = np.zeros(k, np.int32)
@@ -280,7 +287,7 @@ def render_jvp(scene, cam, opt: Options, pix, direction: dict, maps=None, dmaps=
     P = _Params(scene)
     pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 2)
     k = pix.shape[0]
-    maps, lut, He, We = _maps_lut(maps, lut, *env_hw)
+    maps, lut, He, We = _maps_lut(maps, lut, *env_hw, opt)
     keep = []
     vp = (ctypes.c_void_p * 7)()
     for j, name in enumerate(PARAM_NAMES):
@@ -315,7 +322,7 @@ def render_grad(scene, cam, opt: Options, pix, dimage, dalpha=None, maps=None, l
     n = P.n
     pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 2)
     k = pix.shape[0]
-    maps, lut, He, We = _maps_lut(maps, lut, *env_hw)
+    maps, lut, He, We = _maps_lut(maps, lut, *env_hw, opt)
     dimage = np.ascontiguousarray(dimage, np.float64).reshape(k, 3)
     da = None if dalpha is None else np.ascontiguousarray(dalpha, np.float64).reshape(k)
     grads = [np.zeros((r, n) if r > 1 else (n,), np.float64) for r in PARAM_ROWS]
@@ -344,7 +351,7 @@ def screen_grad(scene, cam, opt: Options, pix, dimage, dalpha=None, maps=None, l
     n = P.n
     pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 2)
     k = pix.shape[0]
-    maps, lut, He, We = _maps_lut(maps, lut, *env_hw)
+    maps, lut, He, We = _maps_lut(maps, lut, *env_hw, opt)
     dimage = np.ascontiguousarray(dimage, np.float64).reshape(k, 3)
     da = None if dalpha is None else np.ascontiguousarray(dalpha, np.float64).reshape(k)
     a = np.zeros(n, np.float64)
@@ -364,7 +371,7 @@ def pixel_fragments(scene, cam, opt: Options, px: int, py: int, maps=None, lut=N
     """Covering fragments of one pixel in visiting order: record index, z_start,
     z_end, weight, layer (-1 = discarded by the layer cap)."""
     P = _Params(scene)
-    maps, lut, He, We = _maps_lut(maps, lut, *env_hw)
+    maps, lut, He, We = _maps_lut(maps, lut, *env_hw, opt)
     idx = np.zeros(cap, np.int32)
     zs, ze, w = (np.zeros(cap, np.float64) for _ in range(3))
     lay = np.zeros(cap, np.int32)

@@ -379,6 +379,61 @@ def test_delta_envmap_irradiance(oracle_lib):
                                        rtol=1e-12, atol=1e-16)
 
 
+def _ggx_mean_cosine(alpha):
+    """<R.l> under the split-sum prefilter lobe K(R, l) = D(R.h) (R.l) with
+    n = v = R (eq:ibl), as a 1-D integral over the half-vector angle: l is R
+    reflected about h, so R.l = cos 2 theta_h and d omega_l = 4 cos theta_h
+    d omega_h; the lobe is cut where R.l <= 0 (theta_h = pi/4)."""
+    from scipy.integrate import quad
+
+    def D(mu):
+        a2 = alpha * alpha
+        t = mu * mu * (a2 - 1.0) + 1.0
+        return a2 / (math.pi * t * t)
+
+    def integrand(th, p):
+        return D(math.cos(th)) * math.cos(2 * th) ** p * 4 * math.cos(th) * math.sin(th)
+    kw = dict(limit=200, points=[alpha] if alpha < 0.7 else None)
+    return quad(integrand, 0, math.pi / 4, args=(2,), **kw)[0] / quad(integrand, 0, math.pi / 4, args=(1,), **kw)[0]
+
+
+def test_linear_envmap_prefilter_lobe(oracle_lib):
+    """An environment whose RGB is its own direction, E(l) = l: the lobe is
+    symmetric about R, so level l of the prefilter is c_l R at every output texel
+    direction R of that level's grid, with c_l = <R.l> of the GGX lobe at
+    alpha_l = (l/5)^2 (from a quadrature in half-vector space, not the texel sum);
+    the irradiance is (1/pi) int l max(0, d.l) d omega = (2/3) d.  A lobe of
+    alpha = l/5, D taken at R.l instead of R.h, a missing (R.l) factor or a
+    level on the wrong grid moves c_l R by 1e-2 or more; the lat-long texel sum
+    is within ~1e-4 of the integral away from the poles."""
+    O = oracle_lib
+    He, We = 64, 128
+
+    def dirs(h, w):
+        a, b = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+        th, ph = math.pi * (a + 0.5) / h, 2 * math.pi * (b + 0.5) / w
+        return np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], -1), th
+    E, _ = dirs(He, We)
+    m = O.envmap(E)
+    lay = O.map_layout(He, We)
+    for l in range(1, 6):
+        h, w, off = lay[l]
+        assert (h, w) == (max(He >> l, 4), max(We >> l, 8))
+        S = m[off:off + h * w * 3].reshape(h, w, 3)
+        R, th = dirs(h, w)
+        c = _ggx_mean_cosine((l / 5) ** 2)
+        band = (th > 0.25 * math.pi) & (th < 0.75 * math.pi)
+        assert np.abs(S - c * R)[band].max() < 2e-4, l
+        assert np.abs(S - c * R).max() < 2e-3, l
+        if l < 5:   # alpha = l/5 would give a lobe this far off
+            assert abs(_ggx_mean_cosine(l / 5) - c) > 2e-2
+    h, w, off = lay[6]
+    irr = m[off:off + h * w * 3].reshape(h, w, 3)
+    d, th = dirs(h, w)
+    band = (th > 0.25 * math.pi) & (th < 0.75 * math.pi)
+    assert np.abs(irr - 2.0 / 3.0 * d)[band].max() < 2e-3
+
+
 def test_brdf_lut_properties(oracle_lib):
     """Split-sum table: at r = 0 the lobe is a mirror, so beta1 = 1 - (1-n.v)^5 and
     beta2 = (1-n.v)^5 (Schlick); beta1 + beta2 <= 1 (energy) and beta2 >= 0."""
