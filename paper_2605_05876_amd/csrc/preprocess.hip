@@ -315,11 +315,16 @@ struct LevelSet {
   long long* dfx[7];
   int lh[7], lw[7], off[7];
 };
+// (the empty asm keeps the compiler from folding the select chain back into
+// an indexed load, which would put the level table in scratch memory)
 template <class T>
 __device__ __forceinline__ T pick_level(const T a[7], int l) {
   T r = a[0];
 #pragma unroll
-  for (int i = 1; i < 6; ++i) r = l == i ? a[i] : r;
+  for (int i = 1; i < 6; ++i) {
+    r = l == i ? a[i] : r;
+    asm volatile("" : "+v"(r));
+  }
   return r;
 }
 
