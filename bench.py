@@ -45,7 +45,7 @@ def log(*a):
 
 
 def algorithmic_bytes(stage, n_pairs, n_rec_vis, n_pix, mean_layers, n_surf):
-    """Algorithmic HBM bytes of one launch of a raster kernel (see DESIGN.md):
+    """Algorithmic HBM bytes of one launch of a raster kernel:
     per pair a 4-byte sorted id and the 64-byte record; per pixel the image,
     alpha and layer count (forward writes, backward reads dL/dimage, dL/dalpha),
     16 bytes per composited layer; backward adds a read-modify-write of the 11
@@ -203,9 +203,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU design (split the "
-                                   "views, one all-reduce of the surfel gradients) is described in "
-                                   "DESIGN.md and not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "runs on one GPU only; the multi-GPU path (split the views, one "
+                                   "all-reduce of the surfel gradients) is not implemented",
+                                   "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np

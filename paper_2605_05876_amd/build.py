@@ -20,7 +20,8 @@ def _hipcc():
 
 
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
-         # packed FP32 instructions stay off ("Build flags")
+         # packed FP32 instructions stay off: some of their forms have given wrong
+         # results on these machines
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", SRC]
 
