@@ -106,6 +106,8 @@ def test_fullsize_sampled_parity(O, ss, name, k):
     rep, masks = compare_images(cams, pix, ref, img.cpu().numpy(), a.cpu().numpy())
     print(name, "forward", {k_: v for k_, v in rep.items() if k_ != "worst"})
     assert_image_parity(rep)
+    # the samples exercise the layer separation (Alg. 1): some pixels composite several layers
+    assert max(int(r["n_layers"].max()) for r in ref) >= 2
     # backward with the gradient concentrated on the compared pixels
     rng = np.random.default_rng(7)
     n_pix = b.n_pixels
