@@ -53,6 +53,8 @@ struct Group {
   long long pair_base, pair_cap;
   int pair_passes;  // radix passes of the pair sort: 8-bit digits of the local tile index
   long long mask_base, mask_n;  // the group's chunk slots of walk masks (WalkBufs)
+  // raster work items when long lists are split: all items, those of split tiles
+  long long item_base, item_cap, mitem_base, mitem_cap;
 };
 
 struct SceneEnv {
@@ -88,7 +90,9 @@ struct ss_context {
   DevBuf views_d, recs, counts, offsets, scan_tmp, keys, vals, keys2, vals2, hist, ranges, nl, stats,
       grad, misc, partial, sg, order, stats2, zkey, zkey2, zidx, zidx2, prect, zrect, lpos, qmask,
       pgrad /* deterministic: per-pair gradient partials */, inv /* record -> depth position */,
-      detw /* deterministic: per scene fixed-point bound and exponent */;
+      detw /* deterministic: per scene fixed-point bound and exponent */,
+      items, mitems, segbase /* split lists: work items and their scan scratch */,
+      segL, segS, segF, segM, segZ, segZI /* split lists: the segments' local layers and z_max */;
   std::vector<long long> soff;
   long long scan_tmp_n = 0, pair_total = 0, hist_n = 0;
   DevBuf lut;
@@ -97,6 +101,8 @@ struct ss_context {
   bool fwd_cons = false;  // the last forward wrote the per-layer depth statistics
   long long generation = 0;  // number of the last ss_render (its forward state)
   int lds_batch = 128;       // the LDS batch in use (options.lds_batch, or picked by the reserve)
+  int seg_len = 0;           // list entries per segment of a split tile list (0: lists are not split)
+  bool fwd_split = false;    // the last forward split long lists (the backward walks the same items)
   std::vector<long long> fwd_sig;
   hipStream_t last_stream = nullptr;  // may be the null stream
   bool used = false;                  // a stream call has been made
@@ -120,7 +126,8 @@ constexpr int kMiscStatus = 0, kMiscQueue = 1, kMiscPairs = 8;
 constexpr int kMiscOrder = kMiscPairs + kMaxViews;  // 66 u32: tile-order bucket counts and cursors
 constexpr int kMiscNonfinite = kMiscOrder + 66;     // u64 [2]: forward, backward
 constexpr int kMiscCounters = kMiscNonfinite + 4;   // u64 [3] + f64: E, F, layers, sum W
-constexpr int kMiscWords = kMiscCounters + 8;
+constexpr int kMiscSeg = kMiscCounters + 8;         // per group: raster items, items of split tiles
+constexpr int kMiscWords = kMiscSeg + 2 * kMaxViews;
 
 #define SS_HIP(x)                                                            \
   do {                                                                       \
@@ -150,6 +157,8 @@ ss_status check_options(const ss_options* o) {
   if (o->env_lds < -1) return SS_ERR_INVALID_ARG;
   if (!(o->t_min >= 0.f) || !(o->t_min < 1.f)) return SS_ERR_INVALID_ARG;
   if ((o->deterministic | o->validate | o->counters | o->tonemap) & ~1) return SS_ERR_INVALID_ARG;
+  if (o->seg_len != 0 && o->seg_len != -1 && (o->seg_len < 256 || o->seg_len > 32768 || o->seg_len % 256 != 0))
+    return SS_ERR_INVALID_ARG;
   return SS_OK;
 }
 
@@ -469,6 +478,7 @@ void plan_batch(ss_context* c, const ss_batch* b, std::vector<ViewDev>& vh) {
     g.pair_cap = 0;
     g.mask_base = 0;
     g.mask_n = 0;
+    g.item_base = g.item_cap = g.mitem_base = g.mitem_cap = 0;
     c->groups.push_back(g);
   }
   c->lds_batch = c->opt.lds_batch > 0 ? c->opt.lds_batch : 128;
@@ -484,6 +494,26 @@ long long layout_masks(ss_context* c) {
     base += g.mask_n;
   }
   return base * (long long)(c->opt.tile_w * c->opt.tile_h / 16);
+}
+
+// The split-list buffers of a group (items null: lists are not split).
+SegBufs seg_bufs(ss_context* c, const Group& g, int gi, bool split) {
+  SegBufs sb{};
+  if (!split) return sb;
+  const size_t np = (size_t)c->opt.tile_w * c->opt.tile_h, m0 = (size_t)g.mitem_base * np;
+  uint32_t* misc = P<uint32_t>(c->misc);
+  sb.items = P<int4>(c->items) + g.item_base;
+  sb.n_items = misc + kMiscSeg + 2 * gi;
+  sb.mitems = P<int4>(c->mitems) + g.mitem_base;
+  sb.n_mitems = misc + kMiscSeg + 2 * gi + 1;
+  sb.seg_len = c->seg_len;
+  sb.L = P<float4>(c->segL) + m0 * kSegLayers;
+  sb.S = P<uint16_t>(c->segS) + m0 * (kSegLayers + 1);
+  sb.F = P<uint16_t>(c->segF) + m0 * kSegLayers;
+  sb.M = P<uint32_t>(c->segM) + m0;
+  sb.Z = P<float>(c->segZ) + m0;
+  sb.ZI = P<float>(c->segZI) + m0;
+  return sb;
 }
 
 WalkBufs walk_bufs(ss_context* c, const Group& g) {
@@ -519,7 +549,7 @@ ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
   SS_HIP(ensure(c->prect, (size_t)R * sizeof(uint2)));
   SS_HIP(ensure(c->zrect, (size_t)R * sizeof(uint2)));
   SS_HIP(ensure(c->misc, kMiscWords * sizeof(uint32_t)));
-  c->scan_tmp_n = scan_tmp_size(R) + 16;
+  c->scan_tmp_n = scan_tmp_size(R > c->n_tiles ? R : c->n_tiles) + 16;
   SS_HIP(ensure(c->scan_tmp, (size_t)c->scan_tmp_n * sizeof(uint32_t)));
   SS_HIP(ensure(c->ranges, (size_t)2 * (c->n_tiles > 0 ? c->n_tiles : 1) * sizeof(uint32_t)));
   SS_HIP(ensure(c->nl, (size_t)(c->n_pix > 0 ? c->n_pix : 1)));
@@ -557,6 +587,31 @@ ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
     c->lds_batch = mean >= 256 ? 256 : (mean >= 128 ? 128 : (mean >= 64 ? 64 : 32));
   }
   SS_HIP(ensure(c->qmask, (size_t)layout_masks(c) * sizeof(uint64_t)));
+  // split lists (persistent launches): a group's items are its tiles plus one
+  // per further segment; a split tile's segments number at most 2 len / seg_len
+  c->seg_len = (!c->opt.persistent || c->opt.seg_len < 0) ? 0 : (c->opt.seg_len > 0 ? c->opt.seg_len : 2048);
+  if (c->seg_len > 0) {
+    long long ib = 0, mb = 0, maxt = 1;
+    for (Group& g : c->groups) {
+      g.item_base = ib;
+      g.item_cap = g.n_tiles + g.pair_cap / c->seg_len + 1;
+      g.mitem_base = mb;
+      g.mitem_cap = 2 * g.pair_cap / c->seg_len + 2;
+      ib += g.item_cap;
+      mb += g.mitem_cap;
+      maxt = g.n_tiles > maxt ? g.n_tiles : maxt;
+    }
+    const size_t np = (size_t)mb * c->opt.tile_w * c->opt.tile_h;
+    SS_HIP(ensure(c->items, (size_t)ib * sizeof(int4)));
+    SS_HIP(ensure(c->mitems, (size_t)mb * sizeof(int4)));
+    SS_HIP(ensure(c->segbase, (size_t)2 * maxt * sizeof(uint32_t)));
+    SS_HIP(ensure(c->segL, np * kSegLayers * sizeof(float4)));
+    SS_HIP(ensure(c->segS, np * (kSegLayers + 1) * sizeof(uint16_t)));
+    SS_HIP(ensure(c->segF, np * kSegLayers * sizeof(uint16_t)));
+    SS_HIP(ensure(c->segM, np * sizeof(uint32_t)));
+    SS_HIP(ensure(c->segZ, np * sizeof(float)));
+    SS_HIP(ensure(c->segZI, np * sizeof(float)));
+  }
   if (c->opt.deterministic) {
     SS_HIP(ensure(c->pgrad, (size_t)base * kGradStride * sizeof(float)));
     SS_HIP(ensure(c->inv, (size_t)R * sizeof(uint32_t)));
@@ -617,7 +672,8 @@ size_t workspace_bytes(const ss_context* c) {
              c->vals.n + c->keys2.n + c->vals2.n + c->hist.n + c->ranges.n + c->nl.n + c->stats.n +
              c->grad.n + c->misc.n + c->lut.n + c->partial.n + c->sg.n + c->order.n + c->stats2.n + c->zkey.n +
              c->zkey2.n + c->zidx.n + c->zidx2.n + c->prect.n + c->zrect.n + c->lpos.n + c->qmask.n +
-             c->pgrad.n + c->inv.n + c->detw.n;
+             c->pgrad.n + c->inv.n + c->detw.n + c->items.n + c->mitems.n + c->segbase.n + c->segL.n + c->segS.n +
+             c->segF.n + c->segM.n + c->segZ.n + c->segZI.n;
   for (const SceneEnv& e : c->env) s += e.dirs.n + e.lv.n + e.Z.n + e.dlv.n + e.part.n + e.dlv_fx.n + e.adj_part.n;
   return s;
 }
@@ -654,6 +710,8 @@ ss_status forward_body(ss_context* c, const ss_batch* b, const ss_outputs* out, 
   Params prm = make_params(c);
   prm.cons = (out->cons || out->depth) ? 1 : 0;
   int* status = reinterpret_cast<int*>(misc + kMiscStatus);
+  // long lists split into segments (persistent launches without depth statistics)
+  const bool split = c->seg_len > 0 && c->opt.persistent && !prm.cons;
   for (size_t gi = 0; gi < c->groups.size(); ++gi) {
     const Group& g = c->groups[gi];
     t0 = prof_begin(c, st);
@@ -668,6 +726,12 @@ ss_status forward_body(ss_context* c, const ss_batch* b, const ss_outputs* out, 
       SS_HIP(launch_tile_order(P<uint32_t>(c->ranges), g.tile_base, g.n_tiles, order,
                                misc + kMiscOrder, st));
     }
+    const SegBufs sb = seg_bufs(c, g, (int)gi, split);
+    if (split)
+      SS_HIP(launch_seg_items(P<uint32_t>(c->ranges), order, g.n_tiles, c->seg_len, P<uint32_t>(c->segbase),
+                              misc + kMiscSeg + 2 * gi, P<int4>(c->items) + g.item_base,
+                              P<int4>(c->mitems) + g.mitem_base, g.item_cap, g.mitem_cap,
+                              P<uint32_t>(c->scan_tmp), c->scan_tmp_n, st));
     prof_end(c, t0, ST_BIN, st);
     SS_HIP(launch_fill_u32(misc + kMiscQueue, 0u, 1, st));
     const WalkBufs wb = walk_bufs(c, g);
@@ -682,9 +746,11 @@ ss_status forward_body(ss_context* c, const ss_batch* b, const ss_outputs* out, 
                                  P<float2>(c->stats2), out->cons, out->depth,
                                  reinterpret_cast<int*>(misc + kMiscQueue), order,
                                  c->opt.persistent, status,
-                                 reinterpret_cast<unsigned long long*>(misc + kMiscCounters), wb, st));
+                                 reinterpret_cast<unsigned long long*>(misc + kMiscCounters), wb, sb, g.item_cap,
+                                 g.mitem_cap, st));
     prof_end(c, t0, ST_RFWD, st);
   }
+  c->fwd_split = split;
   return SS_OK;
 }
 
@@ -804,6 +870,7 @@ ss_status ss_default_options(ss_options* o) {
   o->validate = 0;
   o->counters = 0;
   o->tonemap = 0;
+  o->seg_len = 0;
   return SS_OK;
 }
 
@@ -825,7 +892,8 @@ ss_status ss_destroy(ss_context* c) {
                     &c->vals, &c->keys2, &c->vals2, &c->hist, &c->ranges, &c->nl, &c->stats,
                     &c->grad, &c->misc, &c->lut, &c->partial, &c->sg, &c->order, &c->stats2,
                     &c->zkey, &c->zkey2, &c->zidx, &c->zidx2, &c->prect, &c->zrect, &c->lpos, &c->qmask,
-                    &c->pgrad, &c->inv, &c->detw};
+                    &c->pgrad, &c->inv, &c->detw, &c->items, &c->mitems, &c->segbase, &c->segL, &c->segS,
+                    &c->segF, &c->segM, &c->segZ, &c->segZI};
   for (DevBuf* b : bufs) release(*b);
   for (SceneEnv& e : c->env) {
     release(e.dirs); release(e.lv); release(e.Z); release(e.dlv); release(e.part);
@@ -961,7 +1029,8 @@ ss_status ss_render_backward(ss_context* c, const ss_batch* b, const ss_grad_in*
                                   P<float>(c->grad), c->R,
                                   reinterpret_cast<int*>(misc + kMiscQueue),
                                   c->opt.persistent ? P<int>(c->order) + g.tile_base : nullptr,
-                                  c->opt.persistent, walk_bufs(c, g), st));
+                                  c->opt.persistent, walk_bufs(c, g), seg_bufs(c, g, (int)gi, c->fwd_split),
+                                  g.item_cap, st));
     if (det)  // each record's gradient: its (record, tile) partials in emission order
       SS_HIP(launch_ordered_record_sums(P<uint32_t>(c->zidx) + g.rec_begin, P<uint2>(c->zrect) + g.rec_begin,
                                         P<uint32_t>(c->offsets) + g.rec_begin, g.rec_end - g.rec_begin,

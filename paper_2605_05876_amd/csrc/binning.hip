@@ -259,6 +259,53 @@ hipError_t launch_scan_rect_tiles(const uint2* rect, int tile_w, int tile_h, uin
   return scan_with(ScanRectTiles{rect, tile_w, tile_h}, out, n, total, tmp, tmp_n, st);
 }
 
+// ---------------------------------------------------------------- raster work items
+// Segments of the tile at position k of the order: one, or ceil(len / seg_len)
+// for a list longer than seg_len; SPLIT counts only the tiles that are split.
+template <bool SPLIT>
+struct ScanSegs {
+  const uint32_t* ranges;
+  const int* order;
+  uint32_t seg_len;
+  __device__ uint32_t operator()(long long k) const {
+    const int tile = order[k];
+    const uint32_t len = ranges[2 * tile + 1] - ranges[2 * tile];
+    const uint32_t n = len > seg_len ? (len + seg_len - 1) / seg_len : 1u;
+    return SPLIT ? (n > 1u ? n : 0u) : n;
+  }
+};
+
+__global__ void seg_items_kernel(const uint32_t* __restrict__ ranges, const int* __restrict__ order, int n_tiles,
+                                 uint32_t seg_len, const uint32_t* __restrict__ base,
+                                 const uint32_t* __restrict__ mbase, int4* __restrict__ items,
+                                 int4* __restrict__ mitems, long long cap, long long mcap) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_tiles) return;
+  const int tile = order[k];
+  const uint32_t len = ranges[2 * tile + 1] - ranges[2 * tile];
+  const int n = len > seg_len ? (int)((len + seg_len - 1) / seg_len) : 1;
+  for (int s = 0; s < n; ++s) {
+    const long long i = (long long)base[k] + s, m = n > 1 ? (long long)mbase[k] + s : -1;
+    const int4 it = make_int4(tile, s, n, (int)m);
+    if (i < cap) items[i] = it;
+    if (m >= 0 && m < mcap) mitems[m] = it;
+  }
+}
+
+hipError_t launch_seg_items(const uint32_t* ranges, const int* order, int n_tiles, int seg_len, uint32_t* base,
+                            uint32_t* counts, int4* items, int4* mitems, long long items_cap,
+                            long long mitems_cap, uint32_t* tmp, long long tmp_n, hipStream_t st) {
+  if (n_tiles <= 0 || seg_len <= 0) return hipErrorInvalidValue;
+  hipError_t e = scan_with(ScanSegs<false>{ranges, order, (uint32_t)seg_len}, base, n_tiles, counts, tmp, tmp_n, st);
+  if (e != hipSuccess) return e;
+  e = scan_with(ScanSegs<true>{ranges, order, (uint32_t)seg_len}, base + n_tiles, n_tiles, counts + 1, tmp, tmp_n,
+                st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(seg_items_kernel, dim3((n_tiles + 255) / 256), dim3(256), 0, st, ranges, order, n_tiles,
+                     (uint32_t)seg_len, base, base + n_tiles, items, mitems, items_cap, mitems_cap);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- emission
 // Position i of the depth-sorted record list (record order[i], pixel rectangle
 // rect[i]) emits its pairs into slots offsets[i] on, in row-major order of its

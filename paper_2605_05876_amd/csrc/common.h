@@ -58,6 +58,30 @@ struct WalkBufs {
 };
 inline long long mask_slots(long long pair_cap, int n_tiles) { return pair_cap / 32 + n_tiles + 2; }
 
+// Long tile lists are split into segments so that no single tile's walk bounds
+// a raster launch.  Work item of the persistent raster kernels: (tile, segment,
+// segments of the tile, index among the items of split tiles or -1).  A split
+// tile's forward runs in three steps: per segment the largest z_end of its
+// covering fragments at each pixel, their running maximum over the segments
+// (the z_max with which Alg. 1 enters the segment), then the segment walks,
+// each recording its own layers -- at most kSegLayers (W, C) totals with their
+// fragment counts, and where each began, one more start after them -- which a
+// last kernel merges per pixel in list order into the composited result.
+constexpr int kSegLayers = 16;
+struct SegBufs {
+  const int4* items;        // null: one item per tile (order, or tile_begin + item)
+  const uint32_t* n_items;  // device count of items
+  const int4* mitems;       // the items of split tiles, by their index
+  const uint32_t* n_mitems; // device count of those
+  int seg_len;              // list entries per segment, a multiple of every LDS batch
+  float4* L;                // [mitem][kSegLayers][pixel] local layer (W, C)
+  uint16_t* S;              // [mitem][kSegLayers + 1][pixel] local layer start - segment start
+  uint16_t* F;              // [mitem][kSegLayers][pixel] fragments of each local layer
+  uint32_t* M;              // [mitem][pixel] layers | continues-the-open-layer << 8 | truncated << 9
+  float* Z;                 // [mitem][pixel] largest z_end of the segment's covering fragments
+  float* ZI;                // [mitem][pixel] largest z_end before the segment (0: none)
+};
+
 // ---------------------------------------------------------------- views
 struct ViewDev {
   float fx, fy, cx, cy;
@@ -440,6 +464,15 @@ hipError_t launch_tile_ranges(const uint32_t* keys, const uint32_t* n_pairs, lon
 // scratch: 66 u32 of device memory (cleared by the call).
 hipError_t launch_tile_order(const uint32_t* ranges, int tile_begin, int n_tiles, int* order, uint32_t* scratch,
                              hipStream_t st);
+// Work items of a group's raster kernels (persistent launches): every tile in
+// `order`, lists longer than seg_len split into segments.  base: 2 n_tiles u32
+// of scratch; counts: 2 u32 (items, items of split tiles); tmp: scan scratch.
+hipError_t launch_seg_items(const uint32_t* ranges, const int* order, int n_tiles, int seg_len, uint32_t* base,
+                            uint32_t* counts, int4* items, int4* mitems, long long items_cap,
+                            long long mitems_cap, uint32_t* tmp, long long tmp_n, hipStream_t st);
+// n_items: the host's upper bound (grid size); with sb.items the kernels read
+// the device count.  With split tiles the forward also runs the z_max steps
+// before and the merge after the segment walks.
 hipError_t launch_raster_forward(const ViewDev* views, int n_views, int tile_begin, int tile_end,
                                  const uint32_t* ranges, const uint32_t* sorted_vals,
                                  const float* recs, const Params& prm, int lds_batch,
@@ -447,7 +480,8 @@ hipError_t launch_raster_forward(const ViewDev* views, int n_views, int tile_beg
                                  uint8_t* n_layers, float4* layer_stats, float2* layer_stats2,
                                  float* cons, float* depth, int* queue, const int* order,
                                  int persistent, const int* status, unsigned long long* counters,
-                                 const WalkBufs& wb, hipStream_t st);
+                                 const WalkBufs& wb, const SegBufs& sb, long long n_items, long long n_mitems,
+                                 hipStream_t st);
 hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_begin, int tile_end,
                                   const uint32_t* ranges, const uint32_t* sorted_vals,
                                   const float* recs, const Params& prm, int lds_batch,
@@ -455,6 +489,7 @@ hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_be
                                   const uint8_t* n_layers, const float4* layer_stats,
                                   const float2* layer_stats2, const float* d_cons,
                                   const float* d_depth, float* grad, long long R, int* queue,
-                                  const int* order, int persistent, const WalkBufs& wb, hipStream_t st);
+                                  const int* order, int persistent, const WalkBufs& wb, const SegBufs& sb,
+                                  long long n_items, hipStream_t st);
 
 }  // namespace ss

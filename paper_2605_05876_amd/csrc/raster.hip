@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     float4* __restrict__ stats, float2* __restrict__ stats2, float* __restrict__ cons_out,
     float* __restrict__ depth_out, int* queue, const int* __restrict__ order, int persistent,
     const int* __restrict__ status, unsigned long long* __restrict__ counters, uint32_t* __restrict__ lpos,
-    uint64_t* __restrict__ qmask, long long mask_base) {
+    uint64_t* __restrict__ qmask, long long mask_base, SegBufs sb) {
   extern __shared__ float4 lds[];
   __shared__ int s_item;
   constexpr int NT = TW * TH;
@@ -218,10 +218,14 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
   const float r2 = prm.r2, kappa = prm.kappa, t_min = prm.t_min;
   const int kmax = prm.k_max;
   const bool poisoned = *status == 3;  // SS_ERR_CAPACITY
+  const int nit = sb.items ? min((int)*sb.n_items, n_items) : n_items;
   for (int iter = 0;; ++iter) {
     const int item = next_item(queue, persistent, s_item, iter);
-    if (item < 0 || item >= n_items) break;
-    const int tile = order ? order[item] : tile_begin + item;
+    if (item < 0 || item >= nit) break;
+    const int4 it = sb.items ? sb.items[item] : make_int4(order ? order[item] : tile_begin + item, 0, 1, -1);
+    const int tile = it.x;
+    // a segment of a split list: its walk records its own layers for the merge
+    const bool split = !CONS && it.z > 1;
     const ViewDev& v = views[view_of_tile(views, n_views, tile)];
     const int lt = tile - v.tile_base;
     const int tx = lt % v.tiles_x, ty = lt / v.tiles_x;
@@ -231,8 +235,19 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     const bool inside = px < v.W && py < v.H;
     const long long pix = v.pix_off + (long long)py * v.W + px;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    const uint32_t seg_lo = start + (uint32_t)it.y * (uint32_t)sb.seg_len;
+    const uint32_t seg_hi = split ? min(end, seg_lo + (uint32_t)sb.seg_len) : end;
+    // split: this pixel's rows of the segment buffers; the largest z_end before
+    // the segment is the running z_max of the layer a previous segment left open
+    const long long mrow = split ? (long long)it.w * NT + t : 0;
+    const long long mlay = split ? (long long)it.w * kSegLayers * NT + t : 0;
+    const long long mlayS = split ? (long long)it.w * (kSegLayers + 1) * NT + t : 0;
+    const float zin = split ? sb.ZI[mrow] : 0.f;
+    bool open_prev = zin > 0.f;
+    int Kl = 0, nFl = 0;        // split: local layers closed, fragments of the open one
+    bool cont = false, capped = false;
 
-    float C0 = 0.f, C1 = 0.f, C2 = 0.f, Wg = 0.f, zmax = 0.f;
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, Wg = 0.f, zmax = zin;
     float O0 = 0.f, O1 = 0.f, O2 = 0.f, T = 1.f;
     float zr = 0.f, S1 = 0.f, S2 = 0.f;  // CONS: reference depth, sum w dz, sum w dz^2
     int K = 0;
@@ -245,9 +260,9 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     float sumW = 0.f;        // counters: sum of its layers' weights
     // this row's walk mask of chunk slot 0 of the tile (one writer lane per row)
     uint64_t* const qrow = qmask + (mask_base + (start >> 5) + (tile - tile_begin)) * NQ + wave * 4 + (lane >> 4);
-    for (uint32_t b0 = start; b0 < end; b0 += (uint32_t)B) {
+    for (uint32_t b0 = seg_lo; b0 < seg_hi; b0 += (uint32_t)B) {
       if (__syncthreads_and(done)) break;
-      const int cnt = (int)min((uint32_t)B, end - b0);
+      const int cnt = (int)min((uint32_t)B, seg_hi - b0);
       load_batch<NT>(lds, vals, recs, b0, cnt);
       __syncthreads();
       for (int c0 = 0; c0 < cnt; c0 += 64) {
@@ -272,7 +287,28 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
           // compiler then keeps the step's reconvergence simple, which measured
           // faster)
           if (f.cov && !done) {
-            if (Wg > 0.f && rec[R_ZS] > zmax) {
+            if ((Wg > 0.f || open_prev) && rec[R_ZS] > zmax && split) {
+              // gap in a segment: close the local layer (if the segment has one open;
+              // otherwise this fragment starts a layer after the one a previous
+              // segment left open)
+              if (Wg > 0.f) {
+                sb.L[mlay + (long long)Kl * NT] = make_float4(Wg, C0, C1, C2);
+                sb.F[mlay + (long long)Kl * NT] = (uint16_t)nFl;
+                ++Kl;
+              }
+              C0 = C1 = C2 = 0.f;
+              Wg = 0.f;
+              zmax = 0.f;
+              lstart = 0xffffffffu;
+              nFl = 0;
+              open_prev = false;
+              // kSegLayers closed: the layer starting here is beyond K_max globally
+              if (Kl >= kSegLayers) {
+                done = true;
+                capped = true;
+                sb.S[mlayS + (long long)kSegLayers * NT] = (uint16_t)(b0 + (uint32_t)j - seg_lo);
+              }
+            } else if (Wg > 0.f && rec[R_ZS] > zmax) {
               // gap: finalise the layer (Shepard-normalised colour, coverage opacity)
               const float a = -expm1f(-kappa * Wg), e = __expf(-kappa * Wg);
               const float s = T * a * layer_norm(prm.shade, Wg, C0, C1, C2);
@@ -299,6 +335,12 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
               }
             }
             if (!done) {
+              if (split) {
+                cont = cont || open_prev;  // continues the layer a previous segment left open
+                open_prev = false;
+                if (lstart == 0xffffffffu) sb.S[mlayS + (long long)Kl * NT] = (uint16_t)(b0 + (uint32_t)j - seg_lo);
+                ++nFl;
+              }
               lstart = lstart == 0xffffffffu ? b0 + (uint32_t)j : lstart;
               lm0 |= (uint32_t)bit;
               lm1 |= (uint32_t)(bit >> 32);
@@ -324,7 +366,17 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
       }
       __syncthreads();
     }
-    if (inside) {
+    if (split && inside) {
+      if (!done && Wg > 0.f) {
+        sb.L[mlay + (long long)Kl * NT] = make_float4(Wg, C0, C1, C2);
+        sb.F[mlay + (long long)Kl * NT] = (uint16_t)nFl;
+        ++Kl;
+      }
+      sb.M[mrow] = (uint32_t)Kl | (cont ? 1u << 8 : 0u) | (capped ? 1u << 9 : 0u);
+    } else if (split) {
+      sb.M[mrow] = 0u;
+    }
+    if (!split && inside) {
       if (!done && Wg > 0.f) {
         const float a = -expm1f(-kappa * Wg), e = __expf(-kappa * Wg);
         const float s = T * a * layer_norm(prm.shade, Wg, C0, C1, C2);
@@ -362,9 +414,10 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
       if (nl_out) nl_out[pix] = (uint8_t)K;
     }
     if (prm.counters) {
-      // wave sums, one set of atomics per wave and tile
-      unsigned long long f = (unsigned)nF, k = inside ? (unsigned)K : 0u, e = nE;
-      float w = inside ? sumW : 0.f;
+      // wave sums, one set of atomics per wave and tile (a split tile's
+      // fragments, layers and weights are counted by the merge)
+      unsigned long long f = split ? 0u : (unsigned)nF, k = (inside && !split) ? (unsigned)K : 0u, e = nE;
+      float w = (inside && !split) ? sumW : 0.f;
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
         f += __shfl_xor(f, off);
@@ -378,6 +431,206 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
         if (k) atomicAdd(counters + 2, k);
         if (w != 0.f) atomicAdd(reinterpret_cast<double*>(counters + 3), (double)w);
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- split lists
+// Step 1 of a split tile: per segment except the last, the largest z_end of
+// the covering fragments at each pixel (the same walk and tests as the
+// forward, nothing accumulated).  One block per split item.
+template <int TW, int TH, bool PPX>
+__global__ void __launch_bounds__(TW* TH) seg_zmax_kernel(const ViewDev* __restrict__ views, int n_views,
+                                                           const uint32_t* __restrict__ ranges,
+                                                           const uint32_t* __restrict__ vals,
+                                                           const float* __restrict__ recs, Params prm, int B,
+                                                           SegBufs sb) {
+  extern __shared__ float4 lds[];
+  constexpr int NT = TW * TH;
+  const int m = blockIdx.x;
+  if (m >= (int)*sb.n_mitems) return;
+  const int4 it = sb.mitems[m];
+  if (it.y == it.z - 1) return;  // nothing follows the last segment
+  const int t = threadIdx.x, lane = t & 63;
+  const ViewDev& v = views[view_of_tile(views, n_views, it.x)];
+  const int lt = it.x - v.tile_base;
+  const int tx = lt % v.tiles_x, ty = lt / v.tiles_x;
+  int lx, ly, sx0, sy0;
+  pixel_of_thread<TW, TH>(t, tx, ty, lx, ly, sx0, sy0);
+  const int px = tx * TW + lx, py = ty * TH + ly;
+  const uint32_t start = ranges[2 * it.x], end = ranges[2 * it.x + 1];
+  const uint32_t seg_lo = start + (uint32_t)it.y * (uint32_t)sb.seg_len;
+  const uint32_t seg_hi = min(end, seg_lo + (uint32_t)sb.seg_len);
+  float zm = 0.f;
+  for (uint32_t b0 = seg_lo; b0 < seg_hi; b0 += (uint32_t)B) {
+    const int cnt = (int)min((uint32_t)B, seg_hi - b0);
+    load_batch<NT>(lds, vals, recs, b0, cnt);
+    __syncthreads();
+    for (int c0 = 0; c0 < cnt; c0 += 64) {
+      uint64_t mk = chunk_mask<!PPX>(lds, c0, cnt, lane, sx0, sy0, prm.r2);
+      while (mk) {
+        const int j = c0 + __builtin_ctzll(mk);
+        mk &= mk - 1;
+        float rec[kRecFloats];
+        load_record<true>(lds + 4 * j, rec);
+        FragEval f;
+        if constexpr (PPX)
+          frag_eval_pp(rec, px, py, prm.r2, prm.sigma_f, f);
+        else
+          frag_eval(rec, px, py, prm.r2, f);
+        if (f.cov) zm = fmaxf(zm, rec[R_ZE]);
+      }
+    }
+    __syncthreads();
+  }
+  sb.Z[(long long)m * NT + t] = zm;
+}
+
+// Step 2: per split tile and pixel, the running maximum over its segments.
+// One block per split item; the first segment's block does the tile.
+template <int NT>
+__global__ void __launch_bounds__(NT) seg_zin_kernel(SegBufs sb) {
+  const int m = blockIdx.x;
+  if (m >= (int)*sb.n_mitems) return;
+  const int4 it = sb.mitems[m];
+  if (it.y != 0) return;
+  const int t = threadIdx.x;
+  float z = 0.f;
+  for (int k = 0; k < it.z; ++k) {
+    sb.ZI[(long long)(m + k) * NT + t] = z;
+    if (k + 1 < it.z) z = fmaxf(z, sb.Z[(long long)(m + k) * NT + t]);
+  }
+}
+
+// Step 4: per split tile and pixel, the segments' local layers merged in list
+// order: a segment's first layer joins the layer left open before it when it
+// continues that layer; every other local layer is a layer of Alg. 1 (the
+// segment entered with the true z_max).  Then the compositing, the K_max cap
+// and the early-out, the outputs and the backward's walk record exactly as
+// the unsplit forward writes them.
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW* TH) seg_merge_kernel(
+    const ViewDev* __restrict__ views, int n_views, const uint32_t* __restrict__ ranges, Params prm,
+    float* __restrict__ image, float* __restrict__ alpha, uint8_t* __restrict__ nl_out,
+    uint8_t* __restrict__ nl_int, float4* __restrict__ stats, const int* __restrict__ status,
+    unsigned long long* __restrict__ counters, uint32_t* __restrict__ lpos, SegBufs sb) {
+  constexpr int NT = TW * TH;
+  const int m0 = blockIdx.x;
+  if (m0 >= (int)*sb.n_mitems) return;
+  const int4 it = sb.mitems[m0];
+  if (it.y != 0) return;
+  const int t = threadIdx.x, lane = t & 63;
+  const ViewDev& v = views[view_of_tile(views, n_views, it.x)];
+  const int lt = it.x - v.tile_base;
+  const int tx = lt % v.tiles_x, ty = lt / v.tiles_x;
+  int lx, ly, sx0, sy0;
+  pixel_of_thread<TW, TH>(t, tx, ty, lx, ly, sx0, sy0);
+  const int px = tx * TW + lx, py = ty * TH + ly;
+  const bool inside = px < v.W && py < v.H;
+  const long long pix = v.pix_off + (long long)py * v.W + px;
+  const uint32_t start = ranges[2 * it.x];
+  const float kappa = prm.kappa, t_min = prm.t_min;
+  const int kmax = prm.k_max;
+  const bool poisoned = *status == 3;  // SS_ERR_CAPACITY
+  uint32_t* const lp = lpos + pix * kPosStride;
+  float O0 = 0.f, O1 = 0.f, O2 = 0.f, T = 1.f, sumW = 0.f;
+  int K = 0, nF = 0;
+  bool done = !inside || poisoned;
+  // the open layer: totals, first list position, fragments
+  float W = 0.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  uint32_t ls = 0u;
+  int lf = 0;
+  // finalise the open layer; a layer starting at `next` follows it
+  auto close = [&](uint32_t next) {
+    const float a = -expm1f(-kappa * W), e = __expf(-kappa * W);
+    const float s = T * a * layer_norm(prm.shade, W, C0, C1, C2);
+    O0 += s * C0; O1 += s * C1; O2 += s * C2;
+    stats[pix * kMaxLayers + K] = make_float4(W, C0, C1, C2);
+    lp[K] = ls;
+    T *= e;
+    ++K;
+    sumW += W;
+    nF += lf;
+    W = 0.f;
+    if (K >= kmax || T < t_min) {
+      done = true;
+      lp[K] = next;
+    }
+  };
+  for (int k = 0; k < it.z && !done; ++k) {
+    const long long m = m0 + k;
+    const uint32_t meta = sb.M[m * NT + t];
+    const int kl = (int)(meta & 255u);
+    const bool cont = (meta >> 8) & 1u, capped = (meta >> 9) & 1u;
+    const uint32_t seg_lo = start + (uint32_t)k * (uint32_t)sb.seg_len;
+    const long long lay = m * kSegLayers * NT + t, layS = m * (kSegLayers + 1) * NT + t;
+    for (int j = 0; j < kl && !done; ++j) {
+      const float4 L = sb.L[lay + (long long)j * NT];
+      const int fj = sb.F[lay + (long long)j * NT];
+      if (j == 0 && cont && W > 0.f) {
+        W += L.x; C0 += L.y; C1 += L.z; C2 += L.w;
+        lf += fj;
+        continue;
+      }
+      const uint32_t sj = seg_lo + sb.S[layS + (long long)j * NT];
+      if (W > 0.f) close(sj);
+      if (done) break;
+      W = L.x; C0 = L.y; C1 = L.z; C2 = L.w;
+      ls = sj;
+      lf = fj;
+    }
+    // the segment's walk stopped where its (kSegLayers + 1)-th layer starts,
+    // which is past K_max globally
+    if (capped && !done) {
+      const uint32_t sj = seg_lo + sb.S[layS + (long long)kSegLayers * NT];
+      if (W > 0.f) close(sj);
+      if (!done) {
+        done = true;
+        lp[K] = sj;
+      }
+    }
+  }
+  if (inside) {
+    if (!done && W > 0.f) {
+      const float a = -expm1f(-kappa * W), e = __expf(-kappa * W);
+      const float s = T * a * layer_norm(prm.shade, W, C0, C1, C2);
+      O0 += s * C0; O1 += s * C1; O2 += s * C2;
+      stats[pix * kMaxLayers + K] = make_float4(W, C0, C1, C2);
+      lp[K] = ls;
+      T *= e;
+      ++K;
+      sumW += W;
+      nF += lf;
+    }
+    if (!done) lp[K] = 0xffffffffu;  // the walk ran to the end of the list
+    float o0 = O0 + T * v.bg[0], o1 = O1 + T * v.bg[1], o2 = O2 + T * v.bg[2];
+    if (prm.tonemap) {
+      o0 = tonemap_srgb_log(o0);
+      o1 = tonemap_srgb_log(o1);
+      o2 = tonemap_srgb_log(o2);
+    }
+    float a = 1.f - T;
+    if (poisoned) o0 = o1 = o2 = a = __builtin_nanf("");
+    image[3 * pix + 0] = o0;
+    image[3 * pix + 1] = o1;
+    image[3 * pix + 2] = o2;
+    alpha[pix] = a;
+    nl_int[pix] = (uint8_t)K;
+    if (nl_out) nl_out[pix] = (uint8_t)K;
+  }
+  if (prm.counters) {
+    unsigned long long f = inside ? (unsigned)nF : 0u, kk = inside ? (unsigned)K : 0u;
+    float w = inside ? sumW : 0.f;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      f += __shfl_xor(f, off);
+      kk += __shfl_xor(kk, off);
+      w += __shfl_xor(w, off);
+    }
+    if (lane == 0) {
+      if (f) atomicAdd(counters + 1, f);
+      if (kk) atomicAdd(counters + 2, kk);
+      if (w != 0.f) atomicAdd(reinterpret_cast<double*>(counters + 3), (double)w);
     }
   }
 }
@@ -563,7 +816,7 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
     const float* __restrict__ d_alpha, const uint8_t* __restrict__ nl_int,
     const float4* __restrict__ stats, const float2* __restrict__ stats2, const float* __restrict__ d_cons,
     const float* __restrict__ d_depth, float* __restrict__ grad, long long R, int* queue,
-    const int* __restrict__ order, int persistent, WalkBufs wb) {
+    const int* __restrict__ order, int persistent, WalkBufs wb, SegBufs sb) {
   using M = BwdMap<TW, TH>;
   const uint32_t* __restrict__ lpos = wb.pos;
   const uint64_t* __restrict__ qmask = wb.masks;
@@ -578,10 +831,14 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
   const int t = threadIdx.x, lane = t & 63, row = lane >> 4, wave = t >> 6;
   const int quad = wave * M::QW + row / M::R;       // the tile's quadrant of this lane
   const float r2 = prm.r2, kappa = prm.kappa;
+  const int nit = sb.items ? min((int)*sb.n_items, n_items) : n_items;
   for (int iter = 0;; ++iter) {
     const int item = next_item(queue, persistent, s_item, iter);
-    if (item < 0 || item >= n_items) break;
-    const int tile = order ? order[item] : tile_begin + item;
+    if (item < 0 || item >= nit) break;
+    // a segment of a split list walks its own stretch of the list; a lane's
+    // layer state catches up at its first fragment (the layers' starts are known)
+    const int4 it = sb.items ? sb.items[item] : make_int4(order ? order[item] : tile_begin + item, 0, 1, -1);
+    const int tile = it.x;
     const ViewDev& v = views[view_of_tile(views, n_views, tile)];
     const int lt = tile - v.tile_base;
     const int tx = lt % v.tiles_x, ty = lt / v.tiles_x;
@@ -592,7 +849,9 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
     const bool inside = px < v.W && py < v.H;
     const long long pix = v.pix_off + (long long)py * v.W + px;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
-    if (t == 0) s_stop = start;
+    const uint32_t seg_lo = start + (uint32_t)it.y * (uint32_t)sb.seg_len;
+    const uint32_t seg_hi = it.z > 1 ? min(end, seg_lo + (uint32_t)sb.seg_len) : end;
+    if (t == 0) s_stop = seg_lo;
     __syncthreads();
 
     float G[3] = {0.f, 0.f, 0.f}, ga = 0.f;
@@ -646,14 +905,14 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
       }
     }
     __syncthreads();
-    const uint32_t stop = s_stop;
+    const uint32_t stop = min(s_stop, seg_hi);
     const long long slot0 = mask_base + (start >> 5) + (tile - tile_begin);
     uint64_t* const smask = reinterpret_cast<uint64_t*>(lds + 4 * B);  // [chunk of the batch][quadrant]
     // per wave, the batch's records' gradient sums [wave][record][value]
     float* const acc = reinterpret_cast<float*>(smask + ((B + 63) >> 6) * M::NQ);
     float* const wacc = acc + (long long)wave * B * NV;
-    for (uint32_t b0 = start; b0 < stop; b0 += (uint32_t)B) {
-      const int cnt = (int)min((uint32_t)B, end - b0);
+    for (uint32_t b0 = seg_lo; b0 < stop; b0 += (uint32_t)B) {
+      const int cnt = (int)min((uint32_t)B, seg_hi - b0);
       load_batch<NT>(lds, vals, recs, b0, cnt);
       for (int i = t; i < M::NW * B * NV; i += NT) acc[i] = 0.f;
       // the walk masks of the batch's chunks, every quadrant of the tile
@@ -890,11 +1149,21 @@ static hipError_t fwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vi
                         const Params& prm, int B, float* image, float* alpha, uint8_t* nlo,
                         uint8_t* nli, float4* stats, float2* stats2, float* cons, float* depth,
                         int* queue, const int* order, int pers, const int* status,
-                        unsigned long long* counters, const WalkBufs& wb) {
+                        unsigned long long* counters, const WalkBufs& wb, const SegBufs& sb, long long nmi) {
+  // split lists: the z_max carried into each segment first
+  if (sb.items && nmi > 0) {
+    if (prm.mip == 1)
+      hipLaunchKernelGGL((seg_zmax_kernel<TW, TH, true>), dim3((unsigned)nmi), dim3(TW * TH), lds, st, views, nv,
+                         ranges, vals, recs, prm, B, sb);
+    else
+      hipLaunchKernelGGL((seg_zmax_kernel<TW, TH, false>), dim3((unsigned)nmi), dim3(TW * TH), lds, st, views, nv,
+                         ranges, vals, recs, prm, B, sb);
+    hipLaunchKernelGGL((seg_zin_kernel<TW * TH>), dim3((unsigned)nmi), dim3(TW * TH), 0, st, sb);
+  }
 #define SS_FWD_V(CV, PV)                                                                                 \
   hipLaunchKernelGGL((raster_forward_kernel<TW, TH, CV, PV>), grid, dim3(TW * TH), lds, st, views, nv, tb, ni, \
                      ranges, vals, recs, prm, B, image, alpha, nlo, nli, stats, stats2, cons, depth, queue,    \
-                     order, pers, status, counters, wb.pos, wb.masks, wb.mask_base)
+                     order, pers, status, counters, wb.pos, wb.masks, wb.mask_base, sb)
   if (prm.mip == 1) {
     if (prm.cons) SS_FWD_V(true, true);
     else SS_FWD_V(false, true);
@@ -903,6 +1172,9 @@ static hipError_t fwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vi
     else SS_FWD_V(false, false);
   }
 #undef SS_FWD_V
+  if (sb.items && nmi > 0)
+    hipLaunchKernelGGL((seg_merge_kernel<TW, TH>), dim3((unsigned)nmi), dim3(TW * TH), 0, st, views, nv, ranges,
+                       prm, image, alpha, nlo, nli, stats, status, counters, wb.pos, sb);
   return hipGetLastError();
 }
 
@@ -911,16 +1183,16 @@ static void bwd_launch(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vie
                        const uint32_t* ranges, const uint32_t* vals, const float* recs, const Params& prm,
                        int B, const float* di, const float* da, const uint8_t* nli, const float4* stats,
                        const float2* stats2, const float* dcons, const float* ddepth, float* grad, long long R,
-                       int* queue, const int* order, int pers, const WalkBufs& wb) {
+                       int* queue, const int* order, int pers, const WalkBufs& wb, const SegBufs& sb) {
   const dim3 block(BwdMap<TW, TH>::NT);
   if (prm.mip == 1)
     hipLaunchKernelGGL((raster_backward_kernel<TW, TH, SS, CONS, true>), grid, block, lds, st, views, nv,
                        tb, ni, ranges, vals, recs, prm, B, di, da, nli, stats, stats2, dcons, ddepth, grad, R,
-                       queue, order, pers, wb);
+                       queue, order, pers, wb, sb);
   else
     hipLaunchKernelGGL((raster_backward_kernel<TW, TH, SS, CONS, false>), grid, block, lds, st, views, nv,
                        tb, ni, ranges, vals, recs, prm, B, di, da, nli, stats, stats2, dcons, ddepth, grad, R,
-                       queue, order, pers, wb);
+                       queue, order, pers, wb, sb);
 }
 
 template <int TW, int TH>
@@ -929,10 +1201,10 @@ static hipError_t bwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vi
                         const Params& prm, int B, const float* di, const float* da,
                         const uint8_t* nli, const float4* stats, const float2* stats2, const float* dcons,
                         const float* ddepth, float* grad, long long R, int* queue, const int* order,
-                        int pers, const WalkBufs& wb) {
+                        int pers, const WalkBufs& wb, const SegBufs& sb) {
 #define SS_BWD_V(SSV, CV) bwd_launch<TW, TH, SSV, CV>(grid, lds, st, views, nv, tb, ni, ranges, vals, recs, \
                                                        prm, B, di, da, nli, stats, stats2, dcons, ddepth,    \
-                                                       grad, R, queue, order, pers, wb)
+                                                       grad, R, queue, order, pers, wb, sb)
   if (prm.ss_grad && prm.cons) SS_BWD_V(true, true);
   else if (prm.ss_grad) SS_BWD_V(true, false);
   else if (prm.cons) SS_BWD_V(false, true);
@@ -955,18 +1227,25 @@ hipError_t launch_raster_forward(const ViewDev* views, int n_views, int tile_beg
                                  uint8_t* n_layers, float4* layer_stats, float2* layer_stats2,
                                  float* cons, float* depth, int* queue, const int* order,
                                  int persistent, const int* status, unsigned long long* counters,
-                                 const WalkBufs& wb, hipStream_t st) {
-  const int n_items = tile_end - tile_begin;
-  if (n_items <= 0) return hipSuccess;
+                                 const WalkBufs& wb, const SegBufs& sb, long long n_items_max, long long n_mitems,
+                                 hipStream_t st) {
+  const int n_tiles = tile_end - tile_begin;
+  if (n_tiles <= 0) return hipSuccess;
   if (prm.cons && (!layer_stats2 || (!cons && !depth))) return hipErrorInvalidValue;
   if (!status || (prm.counters && !counters) || !wb.pos || !wb.masks) return hipErrorInvalidValue;
+  // split lists need the persistent queue (the item count is on the device) and no depth statistics
+  if (sb.items && (!persistent || prm.cons || !sb.n_items || !sb.mitems || !sb.n_mitems || sb.seg_len <= 0 ||
+                   sb.seg_len % lds_batch != 0 || !sb.L || !sb.S || !sb.F || !sb.M || !sb.Z || !sb.ZI))
+    return hipErrorInvalidValue;
+  const int n_items = sb.items ? (int)n_items_max : n_tiles;
   const int threads = prm.tile_w * prm.tile_h;
   dim3 grid(persistent ? persistent_grid(n_items, threads) : (unsigned)n_items);
   const size_t lds = (size_t)lds_batch * kRecFloats * sizeof(float);
 #define SS_FWD(TW, TH) fwd_t<TW, TH>(grid, lds, st, views, n_views, tile_begin, n_items, ranges, \
                                      sorted_vals, recs, prm, lds_batch, image, alpha,            \
                                      n_layers_out, n_layers, layer_stats, layer_stats2, cons,    \
-                                     depth, queue, order, persistent, status, counters, wb)
+                                     depth, queue, order, persistent, status, counters, wb, sb,  \
+                                     n_mitems)
   switch (prm.tile_w * 100 + prm.tile_h) {
     case 808: return SS_FWD(8, 8);
     case 1608: return SS_FWD(16, 8);
@@ -985,11 +1264,15 @@ hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_be
                                   const uint8_t* n_layers, const float4* layer_stats,
                                   const float2* layer_stats2, const float* d_cons,
                                   const float* d_depth, float* grad, long long R, int* queue,
-                                  const int* order, int persistent, const WalkBufs& wb, hipStream_t st) {
-  const int n_items = tile_end - tile_begin;
-  if (n_items <= 0) return hipSuccess;
+                                  const int* order, int persistent, const WalkBufs& wb, const SegBufs& sb,
+                                  long long n_items_max, hipStream_t st) {
+  const int n_tiles = tile_end - tile_begin;
+  if (n_tiles <= 0) return hipSuccess;
   if (prm.cons && (!layer_stats2 || (!d_cons && !d_depth))) return hipErrorInvalidValue;
   if (!wb.pos || !wb.masks) return hipErrorInvalidValue;
+  if (sb.items && (!persistent || !sb.n_items || sb.seg_len <= 0 || sb.seg_len % 64 != 0))
+    return hipErrorInvalidValue;
+  const int n_items = sb.items ? (int)n_items_max : n_tiles;
   // four lanes per pixel (wave i owns 4 x 4 quadrant i), at most 1024 threads
   const int threads = prm.tile_w * prm.tile_h * 4 > 1024 ? 1024 : prm.tile_w * prm.tile_h * 4;
   dim3 grid(persistent ? persistent_grid(n_items, threads) : (unsigned)n_items);
@@ -1006,7 +1289,7 @@ hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_be
 #define SS_BWD(TW, TH) bwd_t<TW, TH>(grid, lds, st, views, n_views, tile_begin, n_items, ranges, \
                                      sorted_vals, recs, prm, lds_batch, d_image, d_alpha,        \
                                      n_layers, layer_stats, layer_stats2, d_cons, d_depth, grad, \
-                                     R, queue, order, persistent, wb)
+                                     R, queue, order, persistent, wb, sb)
   switch (prm.tile_w * 100 + prm.tile_h) {
     case 808: return SS_BWD(8, 8);
     case 1608: return SS_BWD(16, 8);
