@@ -300,7 +300,9 @@ ss_status ss_poll(ss_context* ctx, ss_diag* out);
  * the context's workspace: it calls no allocating routine and does not
  * synchronise.  The context supplies only its options and BRDF table, and its
  * own forward state is left as it was (a backward still refers to the last
- * ss_render).  Limits: batched launch mode (else SS_ERR_UNSUPPORTED); records,
+ * ss_render).  Tile lists are never split (options.seg_len is ignored), so the
+ * result equals ss_render's with seg_len = -1 bit for bit.  Limits: batched
+ * launch mode (else SS_ERR_UNSUPPORTED); records,
  * pixels, tiles and environment levels must fit the array with room for at
  * least 4096 pairs, else SS_ERR_STATIC_LIMIT before any device work.  The
  * pair capacity is what the array has left; an overflow latches

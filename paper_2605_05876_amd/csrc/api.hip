@@ -728,8 +728,9 @@ ss_status forward_body(ss_context* c, const ss_batch* b, const ss_outputs* out, 
     }
     const SegBufs sb = seg_bufs(c, g, (int)gi, split);
     if (split)
-      SS_HIP(launch_seg_items(P<uint32_t>(c->ranges), order, g.n_tiles, c->seg_len, P<uint32_t>(c->segbase),
-                              misc + kMiscSeg + 2 * gi, P<int4>(c->items) + g.item_base,
+      SS_HIP(launch_seg_items(P<uint32_t>(c->ranges), order, g.n_tiles, c->seg_len,
+                              c->opt.tile_w * c->opt.tile_h, misc + kMiscPairs + gi,
+                              P<uint32_t>(c->segbase), misc + kMiscSeg + 2 * gi, P<int4>(c->items) + g.item_base,
                               P<int4>(c->mitems) + g.mitem_base, g.item_cap, g.mitem_cap,
                               P<uint32_t>(c->scan_tmp), c->scan_tmp_n, st));
     prof_end(c, t0, ST_BIN, st);

@@ -261,29 +261,35 @@ hipError_t launch_scan_rect_tiles(const uint2* rect, int tile_w, int tile_h, uin
 
 // ---------------------------------------------------------------- raster work items
 // Segments of the tile at position k of the order: one, or ceil(len / seg_len)
-// for a list longer than seg_len; SPLIT counts only the tiles that are split.
+// for a list longer than the split threshold.  SPLIT: count only split tiles.
+__device__ inline uint32_t seg_count(const uint32_t* ranges, int tile, uint32_t seg_len, uint32_t thr) {
+  const uint32_t len = ranges[2 * tile + 1] - ranges[2 * tile];
+  return len > thr ? (len + seg_len - 1) / seg_len : 1u;
+}
+__device__ inline uint32_t split_threshold(const uint32_t* n_pairs, uint32_t seg_len, uint32_t waves_per_tile) {
+  const uint32_t t = (uint32_t)(2ull * *n_pairs * waves_per_tile / kResidentWaves);
+  return t > seg_len ? t : seg_len;
+}
 template <bool SPLIT>
 struct ScanSegs {
   const uint32_t* ranges;
   const int* order;
-  uint32_t seg_len;
+  uint32_t seg_len, wpt;
+  const uint32_t* n_pairs;
   __device__ uint32_t operator()(long long k) const {
-    const int tile = order[k];
-    const uint32_t len = ranges[2 * tile + 1] - ranges[2 * tile];
-    const uint32_t n = len > seg_len ? (len + seg_len - 1) / seg_len : 1u;
+    const uint32_t n = seg_count(ranges, order[k], seg_len, split_threshold(n_pairs, seg_len, wpt));
     return SPLIT ? (n > 1u ? n : 0u) : n;
   }
 };
 
 __global__ void seg_items_kernel(const uint32_t* __restrict__ ranges, const int* __restrict__ order, int n_tiles,
-                                 uint32_t seg_len, const uint32_t* __restrict__ base,
-                                 const uint32_t* __restrict__ mbase, int4* __restrict__ items,
-                                 int4* __restrict__ mitems, long long cap, long long mcap) {
+                                 uint32_t seg_len, uint32_t wpt, const uint32_t* __restrict__ n_pairs,
+                                 const uint32_t* __restrict__ base, const uint32_t* __restrict__ mbase,
+                                 int4* __restrict__ items, int4* __restrict__ mitems, long long cap, long long mcap) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_tiles) return;
   const int tile = order[k];
-  const uint32_t len = ranges[2 * tile + 1] - ranges[2 * tile];
-  const int n = len > seg_len ? (int)((len + seg_len - 1) / seg_len) : 1;
+  const int n = (int)seg_count(ranges, tile, seg_len, split_threshold(n_pairs, seg_len, wpt));
   for (int s = 0; s < n; ++s) {
     const long long i = (long long)base[k] + s, m = n > 1 ? (long long)mbase[k] + s : -1;
     const int4 it = make_int4(tile, s, n, (int)m);
@@ -292,17 +298,19 @@ __global__ void seg_items_kernel(const uint32_t* __restrict__ ranges, const int*
   }
 }
 
-hipError_t launch_seg_items(const uint32_t* ranges, const int* order, int n_tiles, int seg_len, uint32_t* base,
-                            uint32_t* counts, int4* items, int4* mitems, long long items_cap,
-                            long long mitems_cap, uint32_t* tmp, long long tmp_n, hipStream_t st) {
-  if (n_tiles <= 0 || seg_len <= 0) return hipErrorInvalidValue;
-  hipError_t e = scan_with(ScanSegs<false>{ranges, order, (uint32_t)seg_len}, base, n_tiles, counts, tmp, tmp_n, st);
+hipError_t launch_seg_items(const uint32_t* ranges, const int* order, int n_tiles, int seg_len, int tile_pixels,
+                            const uint32_t* n_pairs, uint32_t* base, uint32_t* counts, int4* items, int4* mitems,
+                            long long items_cap, long long mitems_cap, uint32_t* tmp, long long tmp_n,
+                            hipStream_t st) {
+  if (n_tiles <= 0 || seg_len <= 0 || tile_pixels < 64) return hipErrorInvalidValue;
+  const uint32_t sl = (uint32_t)seg_len, wpt = (uint32_t)(tile_pixels / 64);
+  hipError_t e = scan_with(ScanSegs<false>{ranges, order, sl, wpt, n_pairs}, base, n_tiles, counts, tmp, tmp_n, st);
   if (e != hipSuccess) return e;
-  e = scan_with(ScanSegs<true>{ranges, order, (uint32_t)seg_len}, base + n_tiles, n_tiles, counts + 1, tmp, tmp_n,
+  e = scan_with(ScanSegs<true>{ranges, order, sl, wpt, n_pairs}, base + n_tiles, n_tiles, counts + 1, tmp, tmp_n,
                 st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(seg_items_kernel, dim3((n_tiles + 255) / 256), dim3(256), 0, st, ranges, order, n_tiles,
-                     (uint32_t)seg_len, base, base + n_tiles, items, mitems, items_cap, mitems_cap);
+  hipLaunchKernelGGL(seg_items_kernel, dim3((n_tiles + 255) / 256), dim3(256), 0, st, ranges, order, n_tiles, sl,
+                     wpt, n_pairs, base, base + n_tiles, items, mitems, items_cap, mitems_cap);
   return hipGetLastError();
 }
 

@@ -465,11 +465,18 @@ hipError_t launch_tile_ranges(const uint32_t* keys, const uint32_t* n_pairs, lon
 hipError_t launch_tile_order(const uint32_t* ranges, int tile_begin, int n_tiles, int* order, uint32_t* scratch,
                              hipStream_t st);
 // Work items of a group's raster kernels (persistent launches): every tile in
-// `order`, lists longer than seg_len split into segments.  base: 2 n_tiles u32
-// of scratch; counts: 2 u32 (items, items of split tiles); tmp: scan scratch.
-hipError_t launch_seg_items(const uint32_t* ranges, const int* order, int n_tiles, int seg_len, uint32_t* base,
-                            uint32_t* counts, int4* items, int4* mitems, long long items_cap,
-                            long long mitems_cap, uint32_t* tmp, long long tmp_n, hipStream_t st);
+// `order`; a list longer than max(seg_len, 2 n_pairs / resident tiles) is split
+// into segments of seg_len entries (a shorter list's walk ends within about
+// the launch's balanced share of the work, so it sets no tail worth the split's
+// extra z_max walk and merge).  Resident tiles:
+// kResidentWaves forward waves on the chip, one per 8 x 8 sub-tile.  base:
+// 2 n_tiles u32 of scratch; counts: 2 u32 (items, items of split tiles); tmp:
+// scan scratch.
+constexpr uint32_t kResidentWaves = 6144;  // 256 CUs x 4 SIMDs x 6 waves
+hipError_t launch_seg_items(const uint32_t* ranges, const int* order, int n_tiles, int seg_len, int tile_pixels,
+                            const uint32_t* n_pairs, uint32_t* base, uint32_t* counts, int4* items, int4* mitems,
+                            long long items_cap, long long mitems_cap, uint32_t* tmp, long long tmp_n,
+                            hipStream_t st);
 // n_items: the host's upper bound (grid size); with sb.items the kernels read
 // the device count.  With split tiles the forward also runs the z_max steps
 // before and the merge after the segment walks.

@@ -200,8 +200,244 @@ __device__ __forceinline__ uint32_t row_or(uint32_t x) {
 // every pixel NaN.  With prm.counters the kernel adds its work to counters[]:
 // (pixel, record) evaluations, accumulated fragments, composited layers (u64)
 // and the sum of their weights (f64 in counters[3]).
+//
+// One work item of the forward: a whole tile (SPLIT false) or one segment of a
+// split list (SPLIT true), whose walk records its local layers for the merge
+// instead of compositing.  Two instances, so that the plain walk carries none
+// of the segment's state.
+template <int TW, int TH, bool CONS, bool PPX, bool SPLIT>
+__device__ __forceinline__ void forward_item(
+    const ViewDev* __restrict__ views, int n_views, int tile_begin, const uint32_t* __restrict__ ranges,
+    const uint32_t* __restrict__ vals, const float* __restrict__ recs, const Params& prm, int B,
+    float* __restrict__ image, float* __restrict__ alpha, uint8_t* __restrict__ nl_out,
+    uint8_t* __restrict__ nl_int, float4* __restrict__ stats, float2* __restrict__ stats2,
+    float* __restrict__ cons_out, float* __restrict__ depth_out, bool poisoned,
+    unsigned long long* __restrict__ counters, uint32_t* __restrict__ lpos, uint64_t* __restrict__ qmask,
+    long long mask_base, const SegBufs& sb, const int4 it) {
+  extern __shared__ float4 lds[];
+  constexpr int NT = TW * TH;
+  constexpr int NQ = TW * TH / 16;  // 4 x 4 quadrants of the tile
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const float r2 = prm.r2, kappa = prm.kappa, t_min = prm.t_min;
+  const int kmax = prm.k_max;
+  const int tile = it.x;
+  constexpr bool split = SPLIT && !CONS;
+  const ViewDev& v = views[view_of_tile(views, n_views, tile)];
+  const int lt = tile - v.tile_base;
+  const int tx = lt % v.tiles_x, ty = lt / v.tiles_x;
+  int lx, ly, sx0, sy0;
+  pixel_of_thread<TW, TH>(t, tx, ty, lx, ly, sx0, sy0);
+  const int px = tx * TW + lx, py = ty * TH + ly;
+  const bool inside = px < v.W && py < v.H;
+  const long long pix = v.pix_off + (long long)py * v.W + px;
+  const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+  const uint32_t seg_lo = start + (uint32_t)it.y * (uint32_t)sb.seg_len;
+  const uint32_t seg_hi = split ? min(end, seg_lo + (uint32_t)sb.seg_len) : end;
+  // split: this pixel's rows of the segment buffers; the largest z_end before
+  // the segment is the running z_max of the layer a previous segment left open
+  const long long mrow = split ? (long long)it.w * NT + t : 0;
+  const long long mlay = split ? (long long)it.w * kSegLayers * NT + t : 0;
+  const long long mlayS = split ? (long long)it.w * (kSegLayers + 1) * NT + t : 0;
+  const float zin = split ? sb.ZI[mrow] : 0.f;
+  bool open_prev = zin > 0.f;
+  int Kl = 0, nFl = 0;        // split: local layers closed, fragments of the open one
+  bool cont = false, capped = false;
+
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f, Wg = 0.f, zmax = zin;
+  float O0 = 0.f, O1 = 0.f, O2 = 0.f, T = 1.f;
+  float zr = 0.f, S1 = 0.f, S2 = 0.f;  // CONS: reference depth, sum w dz, sum w dz^2
+  int K = 0;
+  bool done = !inside || poisoned;
+  // list position of the current layer's first fragment (0xffffffff: none yet)
+  uint32_t lstart = 0xffffffffu;
+  uint32_t* const lp = lpos + pix * kPosStride;
+  int nF = 0;              // counters: fragments accumulated by this pixel
+  unsigned nE = 0;         // counters: records evaluated at this pixel
+  float sumW = 0.f;        // counters: sum of its layers' weights
+  // this row's walk mask of chunk slot 0 of the tile (one writer lane per row)
+  uint64_t* const qrow = qmask + (mask_base + (start >> 5) + (tile - tile_begin)) * NQ + wave * 4 + (lane >> 4);
+  for (uint32_t b0 = seg_lo; b0 < seg_hi; b0 += (uint32_t)B) {
+    if (__syncthreads_and(done)) break;
+    const int cnt = (int)min((uint32_t)B, seg_hi - b0);
+    load_batch<NT>(lds, vals, recs, b0, cnt);
+    __syncthreads();
+    for (int c0 = 0; c0 < cnt; c0 += 64) {
+      if (__ballot(!done) == 0ull) break;
+      uint64_t m = chunk_mask<!PPX>(lds, c0, cnt, lane, sx0, sy0, r2);
+      nE += inside ? (unsigned)__popcll(m) : 0u;
+      // the records of the chunk this pixel accumulated; OR-ed over each row of
+      // 16 lanes (a 4 x 4 quadrant) they are the backward's walk lists
+      uint32_t lm0 = 0u, lm1 = 0u;
+      while (m) {
+        const int j = c0 + __builtin_ctzll(m);
+        const uint64_t bit = m & (0ull - m);  // the record's bit in the chunk
+        m &= m - 1;
+        float rec[kRecFloats];
+        load_record<true>(lds + 4 * j, rec);
+        FragEval f;
+        if constexpr (PPX)
+          frag_eval_pp(rec, px, py, r2, prm.sigma_f, f);
+        else
+          frag_eval(rec, px, py, r2, f);
+        // (structured as nested branches rather than early continues: the
+        // compiler then keeps the step's reconvergence simple, which measured
+        // faster)
+        if (f.cov && !done) {
+          if (split && (Wg > 0.f || open_prev) && rec[R_ZS] > zmax) {
+            // gap in a segment: close the local layer (if the segment has one open;
+            // otherwise this fragment starts a layer after the one a previous
+            // segment left open)
+            if (Wg > 0.f) {
+              sb.L[mlay + (long long)Kl * NT] = make_float4(Wg, C0, C1, C2);
+              sb.F[mlay + (long long)Kl * NT] = (uint16_t)nFl;
+              ++Kl;
+            }
+            C0 = C1 = C2 = 0.f;
+            Wg = 0.f;
+            zmax = 0.f;
+            lstart = 0xffffffffu;
+            nFl = 0;
+            open_prev = false;
+            // kSegLayers closed: the layer starting here is beyond K_max globally
+            if (Kl >= kSegLayers) {
+              done = true;
+              capped = true;
+              sb.S[mlayS + (long long)kSegLayers * NT] = (uint16_t)(b0 + (uint32_t)j - seg_lo);
+            }
+          } else if (Wg > 0.f && rec[R_ZS] > zmax) {
+            // gap: finalise the layer (Shepard-normalised colour, coverage opacity)
+            const float a = -expm1f(-kappa * Wg), e = __expf(-kappa * Wg);
+            const float s = T * a * layer_norm(prm.shade, Wg, C0, C1, C2);
+            O0 += s * C0; O1 += s * C1; O2 += s * C2;
+            stats[pix * kMaxLayers + K] = make_float4(Wg, C0, C1, C2);
+            lp[K] = lstart;
+            if constexpr (CONS) {
+              const float m = S1 / Wg;
+              stats2[pix * kMaxLayers + K] = make_float2(zr + m, S2 / Wg - m * m);
+              S1 = S2 = 0.f;
+            }
+            T *= e;
+            ++K;
+            sumW += Wg;
+            C0 = C1 = C2 = 0.f;
+            Wg = 0.f;
+            zmax = 0.f;
+            lstart = 0xffffffffu;
+            // K_max cap, or the early-out once the transmittance is below t_min;
+            // the discarded fragment's list position ends the pixel's walk
+            if (K >= kmax || T < t_min) {
+              done = true;
+              lp[K] = b0 + (uint32_t)j;
+            }
+          }
+          if (!done) {
+            if constexpr (split) {
+              cont = cont || open_prev;  // continues the layer a previous segment left open
+              open_prev = false;
+              if (lstart == 0xffffffffu) sb.S[mlayS + (long long)Kl * NT] = (uint16_t)(b0 + (uint32_t)j - seg_lo);
+              ++nFl;
+            }
+            lstart = lstart == 0xffffffffu ? b0 + (uint32_t)j : lstart;
+            lm0 |= (uint32_t)bit;
+            lm1 |= (uint32_t)(bit >> 32);
+            if constexpr (CONS) {
+              const float z = frag_depth(rec, f);
+              if (Wg == 0.f) zr = z;
+              const float dz = z - zr;
+              S1 += f.w * dz;
+              S2 += f.w * dz * dz;
+            }
+            zmax = fmaxf(zmax, rec[R_ZE]);
+            C0 += f.w * rec[R_CR];
+            C1 += f.w * rec[R_CG];
+            C2 += f.w * rec[R_CB];
+            Wg += f.w;
+            ++nF;
+          }
+        }
+      }
+      lm0 = row_or(lm0);
+      lm1 = row_or(lm1);
+      if ((lane & 15) == 0) qrow[(long long)((b0 + (uint32_t)c0 - start) >> 5) * NQ] = ((uint64_t)lm1 << 32) | lm0;
+    }
+    __syncthreads();
+  }
+  if (split && inside) {
+    if (!done && Wg > 0.f) {
+      sb.L[mlay + (long long)Kl * NT] = make_float4(Wg, C0, C1, C2);
+      sb.F[mlay + (long long)Kl * NT] = (uint16_t)nFl;
+      ++Kl;
+    }
+    sb.M[mrow] = (uint32_t)Kl | (cont ? 1u << 8 : 0u) | (capped ? 1u << 9 : 0u);
+  } else if (split) {
+    sb.M[mrow] = 0u;
+  }
+  if (!split && inside) {
+    if (!done && Wg > 0.f) {
+      const float a = -expm1f(-kappa * Wg), e = __expf(-kappa * Wg);
+      const float s = T * a * layer_norm(prm.shade, Wg, C0, C1, C2);
+      O0 += s * C0; O1 += s * C1; O2 += s * C2;
+      stats[pix * kMaxLayers + K] = make_float4(Wg, C0, C1, C2);
+      lp[K] = lstart;
+      if constexpr (CONS) {
+        const float m = S1 / Wg;
+        stats2[pix * kMaxLayers + K] = make_float2(zr + m, S2 / Wg - m * m);
+      }
+      T *= e;
+      ++K;
+      sumW += Wg;
+    }
+    if (!done) lp[K] = 0xffffffffu;  // the walk ran to the end of the list
+    if constexpr (CONS) {
+      float cs, dp;
+      depth_stats_of_pixel(stats + pix * kMaxLayers, stats2 + pix * kMaxLayers, K, kappa, cs, dp);
+      if (cons_out) cons_out[pix] = poisoned ? __builtin_nanf("") : cs;
+      if (depth_out) depth_out[pix] = poisoned ? __builtin_nanf("") : dp;
+    }
+    float o0 = O0 + T * v.bg[0], o1 = O1 + T * v.bg[1], o2 = O2 + T * v.bg[2];
+    if (prm.tonemap) {
+      o0 = tonemap_srgb_log(o0);
+      o1 = tonemap_srgb_log(o1);
+      o2 = tonemap_srgb_log(o2);
+    }
+    float a = 1.f - T;
+    if (poisoned) o0 = o1 = o2 = a = __builtin_nanf("");
+    image[3 * pix + 0] = o0;
+    image[3 * pix + 1] = o1;
+    image[3 * pix + 2] = o2;
+    alpha[pix] = a;
+    nl_int[pix] = (uint8_t)K;
+    if (nl_out) nl_out[pix] = (uint8_t)K;
+  }
+  if (prm.counters) {
+    // wave sums, one set of atomics per wave and tile (a split tile's
+    // fragments, layers and weights are counted by the merge)
+    unsigned long long f = split ? 0u : (unsigned)nF, k = (inside && !split) ? (unsigned)K : 0u, e = nE;
+    float w = (inside && !split) ? sumW : 0.f;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      f += __shfl_xor(f, off);
+      k += __shfl_xor(k, off);
+      e += __shfl_xor(e, off);
+      w += __shfl_xor(w, off);
+    }
+    if (lane == 0) {
+      if (e) atomicAdd(counters + 0, e);
+      if (f) atomicAdd(counters + 1, f);
+      if (k) atomicAdd(counters + 2, k);
+      if (w != 0.f) atomicAdd(reinterpret_cast<double*>(counters + 3), (double)w);
+    }
+  }
+}
+
+// Occupancy target of the plain variant: 7 waves per SIMD (at most 72 VGPRs,
+// as the plain walk alone) for 8 x 8 tiles, 6 for the larger ones (which spill
+// at 72); the compiler's choice for the variants with statistics or the
+// per-pixel filter.
 template <int TW, int TH, bool CONS, bool PPX>
-__global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
+__global__ void __launch_bounds__(TW* TH)
+__attribute__((amdgpu_waves_per_eu((CONS || PPX) ? 1 : (TW * TH > 64 ? 6 : 7))))
+raster_forward_kernel(
     const ViewDev* __restrict__ views, int n_views, int tile_begin, int n_items,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float* __restrict__ recs, Params prm, int B, float* __restrict__ image,
@@ -210,228 +446,22 @@ __global__ void __launch_bounds__(TW* TH) raster_forward_kernel(
     float* __restrict__ depth_out, int* queue, const int* __restrict__ order, int persistent,
     const int* __restrict__ status, unsigned long long* __restrict__ counters, uint32_t* __restrict__ lpos,
     uint64_t* __restrict__ qmask, long long mask_base, SegBufs sb) {
-  extern __shared__ float4 lds[];
   __shared__ int s_item;
-  constexpr int NT = TW * TH;
-  constexpr int NQ = TW * TH / 16;  // 4 x 4 quadrants of the tile
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const float r2 = prm.r2, kappa = prm.kappa, t_min = prm.t_min;
-  const int kmax = prm.k_max;
   const bool poisoned = *status == 3;  // SS_ERR_CAPACITY
+  // the items: every tile (in order), or with split lists the tiles and segments
   const int nit = sb.items ? min((int)*sb.n_items, n_items) : n_items;
   for (int iter = 0;; ++iter) {
     const int item = next_item(queue, persistent, s_item, iter);
     if (item < 0 || item >= nit) break;
     const int4 it = sb.items ? sb.items[item] : make_int4(order ? order[item] : tile_begin + item, 0, 1, -1);
-    const int tile = it.x;
-    // a segment of a split list: its walk records its own layers for the merge
-    const bool split = !CONS && it.z > 1;
-    const ViewDev& v = views[view_of_tile(views, n_views, tile)];
-    const int lt = tile - v.tile_base;
-    const int tx = lt % v.tiles_x, ty = lt / v.tiles_x;
-    int lx, ly, sx0, sy0;
-    pixel_of_thread<TW, TH>(t, tx, ty, lx, ly, sx0, sy0);
-    const int px = tx * TW + lx, py = ty * TH + ly;
-    const bool inside = px < v.W && py < v.H;
-    const long long pix = v.pix_off + (long long)py * v.W + px;
-    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
-    const uint32_t seg_lo = start + (uint32_t)it.y * (uint32_t)sb.seg_len;
-    const uint32_t seg_hi = split ? min(end, seg_lo + (uint32_t)sb.seg_len) : end;
-    // split: this pixel's rows of the segment buffers; the largest z_end before
-    // the segment is the running z_max of the layer a previous segment left open
-    const long long mrow = split ? (long long)it.w * NT + t : 0;
-    const long long mlay = split ? (long long)it.w * kSegLayers * NT + t : 0;
-    const long long mlayS = split ? (long long)it.w * (kSegLayers + 1) * NT + t : 0;
-    const float zin = split ? sb.ZI[mrow] : 0.f;
-    bool open_prev = zin > 0.f;
-    int Kl = 0, nFl = 0;        // split: local layers closed, fragments of the open one
-    bool cont = false, capped = false;
-
-    float C0 = 0.f, C1 = 0.f, C2 = 0.f, Wg = 0.f, zmax = zin;
-    float O0 = 0.f, O1 = 0.f, O2 = 0.f, T = 1.f;
-    float zr = 0.f, S1 = 0.f, S2 = 0.f;  // CONS: reference depth, sum w dz, sum w dz^2
-    int K = 0;
-    bool done = !inside || poisoned;
-    // list position of the current layer's first fragment (0xffffffff: none yet)
-    uint32_t lstart = 0xffffffffu;
-    uint32_t* const lp = lpos + pix * kPosStride;
-    int nF = 0;              // counters: fragments accumulated by this pixel
-    unsigned nE = 0;         // counters: records evaluated at this pixel
-    float sumW = 0.f;        // counters: sum of its layers' weights
-    // this row's walk mask of chunk slot 0 of the tile (one writer lane per row)
-    uint64_t* const qrow = qmask + (mask_base + (start >> 5) + (tile - tile_begin)) * NQ + wave * 4 + (lane >> 4);
-    for (uint32_t b0 = seg_lo; b0 < seg_hi; b0 += (uint32_t)B) {
-      if (__syncthreads_and(done)) break;
-      const int cnt = (int)min((uint32_t)B, seg_hi - b0);
-      load_batch<NT>(lds, vals, recs, b0, cnt);
-      __syncthreads();
-      for (int c0 = 0; c0 < cnt; c0 += 64) {
-        if (__ballot(!done) == 0ull) break;
-        uint64_t m = chunk_mask<!PPX>(lds, c0, cnt, lane, sx0, sy0, r2);
-        nE += inside ? (unsigned)__popcll(m) : 0u;
-        // the records of the chunk this pixel accumulated; OR-ed over each row of
-        // 16 lanes (a 4 x 4 quadrant) they are the backward's walk lists
-        uint32_t lm0 = 0u, lm1 = 0u;
-        while (m) {
-          const int j = c0 + __builtin_ctzll(m);
-          const uint64_t bit = m & (0ull - m);  // the record's bit in the chunk
-          m &= m - 1;
-          float rec[kRecFloats];
-          load_record<true>(lds + 4 * j, rec);
-          FragEval f;
-          if constexpr (PPX)
-            frag_eval_pp(rec, px, py, r2, prm.sigma_f, f);
-          else
-            frag_eval(rec, px, py, r2, f);
-          // (structured as nested branches rather than early continues: the
-          // compiler then keeps the step's reconvergence simple, which measured
-          // faster)
-          if (f.cov && !done) {
-            if ((Wg > 0.f || open_prev) && rec[R_ZS] > zmax && split) {
-              // gap in a segment: close the local layer (if the segment has one open;
-              // otherwise this fragment starts a layer after the one a previous
-              // segment left open)
-              if (Wg > 0.f) {
-                sb.L[mlay + (long long)Kl * NT] = make_float4(Wg, C0, C1, C2);
-                sb.F[mlay + (long long)Kl * NT] = (uint16_t)nFl;
-                ++Kl;
-              }
-              C0 = C1 = C2 = 0.f;
-              Wg = 0.f;
-              zmax = 0.f;
-              lstart = 0xffffffffu;
-              nFl = 0;
-              open_prev = false;
-              // kSegLayers closed: the layer starting here is beyond K_max globally
-              if (Kl >= kSegLayers) {
-                done = true;
-                capped = true;
-                sb.S[mlayS + (long long)kSegLayers * NT] = (uint16_t)(b0 + (uint32_t)j - seg_lo);
-              }
-            } else if (Wg > 0.f && rec[R_ZS] > zmax) {
-              // gap: finalise the layer (Shepard-normalised colour, coverage opacity)
-              const float a = -expm1f(-kappa * Wg), e = __expf(-kappa * Wg);
-              const float s = T * a * layer_norm(prm.shade, Wg, C0, C1, C2);
-              O0 += s * C0; O1 += s * C1; O2 += s * C2;
-              stats[pix * kMaxLayers + K] = make_float4(Wg, C0, C1, C2);
-              lp[K] = lstart;
-              if constexpr (CONS) {
-                const float m = S1 / Wg;
-                stats2[pix * kMaxLayers + K] = make_float2(zr + m, S2 / Wg - m * m);
-                S1 = S2 = 0.f;
-              }
-              T *= e;
-              ++K;
-              sumW += Wg;
-              C0 = C1 = C2 = 0.f;
-              Wg = 0.f;
-              zmax = 0.f;
-              lstart = 0xffffffffu;
-              // K_max cap, or the early-out once the transmittance is below t_min;
-              // the discarded fragment's list position ends the pixel's walk
-              if (K >= kmax || T < t_min) {
-                done = true;
-                lp[K] = b0 + (uint32_t)j;
-              }
-            }
-            if (!done) {
-              if (split) {
-                cont = cont || open_prev;  // continues the layer a previous segment left open
-                open_prev = false;
-                if (lstart == 0xffffffffu) sb.S[mlayS + (long long)Kl * NT] = (uint16_t)(b0 + (uint32_t)j - seg_lo);
-                ++nFl;
-              }
-              lstart = lstart == 0xffffffffu ? b0 + (uint32_t)j : lstart;
-              lm0 |= (uint32_t)bit;
-              lm1 |= (uint32_t)(bit >> 32);
-              if constexpr (CONS) {
-                const float z = frag_depth(rec, f);
-                if (Wg == 0.f) zr = z;
-                const float dz = z - zr;
-                S1 += f.w * dz;
-                S2 += f.w * dz * dz;
-              }
-              zmax = fmaxf(zmax, rec[R_ZE]);
-              C0 += f.w * rec[R_CR];
-              C1 += f.w * rec[R_CG];
-              C2 += f.w * rec[R_CB];
-              Wg += f.w;
-              ++nF;
-            }
-          }
-        }
-        lm0 = row_or(lm0);
-        lm1 = row_or(lm1);
-        if ((lane & 15) == 0) qrow[(long long)((b0 + (uint32_t)c0 - start) >> 5) * NQ] = ((uint64_t)lm1 << 32) | lm0;
-      }
-      __syncthreads();
-    }
-    if (split && inside) {
-      if (!done && Wg > 0.f) {
-        sb.L[mlay + (long long)Kl * NT] = make_float4(Wg, C0, C1, C2);
-        sb.F[mlay + (long long)Kl * NT] = (uint16_t)nFl;
-        ++Kl;
-      }
-      sb.M[mrow] = (uint32_t)Kl | (cont ? 1u << 8 : 0u) | (capped ? 1u << 9 : 0u);
-    } else if (split) {
-      sb.M[mrow] = 0u;
-    }
-    if (!split && inside) {
-      if (!done && Wg > 0.f) {
-        const float a = -expm1f(-kappa * Wg), e = __expf(-kappa * Wg);
-        const float s = T * a * layer_norm(prm.shade, Wg, C0, C1, C2);
-        O0 += s * C0; O1 += s * C1; O2 += s * C2;
-        stats[pix * kMaxLayers + K] = make_float4(Wg, C0, C1, C2);
-        lp[K] = lstart;
-        if constexpr (CONS) {
-          const float m = S1 / Wg;
-          stats2[pix * kMaxLayers + K] = make_float2(zr + m, S2 / Wg - m * m);
-        }
-        T *= e;
-        ++K;
-        sumW += Wg;
-      }
-      if (!done) lp[K] = 0xffffffffu;  // the walk ran to the end of the list
-      if constexpr (CONS) {
-        float cs, dp;
-        depth_stats_of_pixel(stats + pix * kMaxLayers, stats2 + pix * kMaxLayers, K, kappa, cs, dp);
-        if (cons_out) cons_out[pix] = poisoned ? __builtin_nanf("") : cs;
-        if (depth_out) depth_out[pix] = poisoned ? __builtin_nanf("") : dp;
-      }
-      float o0 = O0 + T * v.bg[0], o1 = O1 + T * v.bg[1], o2 = O2 + T * v.bg[2];
-      if (prm.tonemap) {
-        o0 = tonemap_srgb_log(o0);
-        o1 = tonemap_srgb_log(o1);
-        o2 = tonemap_srgb_log(o2);
-      }
-      float a = 1.f - T;
-      if (poisoned) o0 = o1 = o2 = a = __builtin_nanf("");
-      image[3 * pix + 0] = o0;
-      image[3 * pix + 1] = o1;
-      image[3 * pix + 2] = o2;
-      alpha[pix] = a;
-      nl_int[pix] = (uint8_t)K;
-      if (nl_out) nl_out[pix] = (uint8_t)K;
-    }
-    if (prm.counters) {
-      // wave sums, one set of atomics per wave and tile (a split tile's
-      // fragments, layers and weights are counted by the merge)
-      unsigned long long f = split ? 0u : (unsigned)nF, k = (inside && !split) ? (unsigned)K : 0u, e = nE;
-      float w = (inside && !split) ? sumW : 0.f;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        f += __shfl_xor(f, off);
-        k += __shfl_xor(k, off);
-        e += __shfl_xor(e, off);
-        w += __shfl_xor(w, off);
-      }
-      if (lane == 0) {
-        if (e) atomicAdd(counters + 0, e);
-        if (f) atomicAdd(counters + 1, f);
-        if (k) atomicAdd(counters + 2, k);
-        if (w != 0.f) atomicAdd(reinterpret_cast<double*>(counters + 3), (double)w);
-      }
-    }
+    if (!CONS && it.z > 1)
+      forward_item<TW, TH, CONS, PPX, true>(views, n_views, tile_begin, ranges, vals, recs, prm, B, image, alpha,
+                                            nl_out, nl_int, stats, stats2, cons_out, depth_out, poisoned,
+                                            counters, lpos, qmask, mask_base, sb, it);
+    else
+      forward_item<TW, TH, CONS, PPX, false>(views, n_views, tile_begin, ranges, vals, recs, prm, B, image, alpha,
+                                             nl_out, nl_int, stats, stats2, cons_out, depth_out, poisoned,
+                                             counters, lpos, qmask, mask_base, sb, it);
   }
 }
 
@@ -1143,6 +1173,13 @@ hipError_t launch_tile_order(const uint32_t* ranges, int tile_begin, int n_tiles
 }
 
 // ---------------------------------------------------------------- launchers
+static unsigned persistent_grid(int n_items, int threads) {
+  // 256 CUs; enough resident blocks to cover the chip several times over
+  int per_cu = threads <= 64 ? 16 : (threads <= 128 ? 12 : (threads <= 256 ? 8 : 4));
+  long long g = 256LL * per_cu;
+  return (unsigned)(g < n_items ? g : (n_items > 0 ? n_items : 1));
+}
+
 template <int TW, int TH>
 static hipError_t fwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* views, int nv, int tb,
                         int ni, const uint32_t* ranges, const uint32_t* vals, const float* recs,
@@ -1161,8 +1198,8 @@ static hipError_t fwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vi
     hipLaunchKernelGGL((seg_zin_kernel<TW * TH>), dim3((unsigned)nmi), dim3(TW * TH), 0, st, sb);
   }
 #define SS_FWD_V(CV, PV)                                                                                 \
-  hipLaunchKernelGGL((raster_forward_kernel<TW, TH, CV, PV>), grid, dim3(TW * TH), lds, st, views, nv, tb, ni, \
-                     ranges, vals, recs, prm, B, image, alpha, nlo, nli, stats, stats2, cons, depth, queue,    \
+  hipLaunchKernelGGL((raster_forward_kernel<TW, TH, CV, PV>), grid, dim3(TW * TH), lds, st, views, nv, tb,        \
+                     ni, ranges, vals, recs, prm, B, image, alpha, nlo, nli, stats, stats2, cons, depth, queue, \
                      order, pers, status, counters, wb.pos, wb.masks, wb.mask_base, sb)
   if (prm.mip == 1) {
     if (prm.cons) SS_FWD_V(true, true);
@@ -1211,13 +1248,6 @@ static hipError_t bwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vi
   else SS_BWD_V(false, false);
 #undef SS_BWD_V
   return hipGetLastError();
-}
-
-static unsigned persistent_grid(int n_items, int threads) {
-  // 256 CUs; enough resident blocks to cover the chip several times over
-  int per_cu = threads <= 64 ? 16 : (threads <= 128 ? 12 : (threads <= 256 ? 8 : 4));
-  long long g = 256LL * per_cu;
-  return (unsigned)(g < n_items ? g : (n_items > 0 ? n_items : 1));
 }
 
 hipError_t launch_raster_forward(const ViewDev* views, int n_views, int tile_begin, int tile_end,

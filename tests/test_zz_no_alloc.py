@@ -2,7 +2,8 @@
 allocate device memory) against ss_render, through the C ABI.
 
 Forward images are deterministic (every pixel sums its fragments in list
-order), so the two entry points must agree bit for bit.  Two calls in a row,
+order) and the allocation-free path never splits long tile lists, so against
+ss_render with unsplit lists the two entry points must agree bit for bit.  Two calls in a row,
 the second with a smaller batch (and another shading mode), check that the
 shared fixed workspace is cleared and re-laid out per call."""
 import ctypes
@@ -42,7 +43,7 @@ def _albedo_case():
 
 
 def _compare(ss, scenes, cams, shade):
-    opts = ss.Options(shade=shade, tile_w=16, tile_h=8)
+    opts = ss.Options(shade=shade, tile_w=16, tile_h=8, seg_len=-1)
     b = ss.batch_from_scenes(scenes, cams)
     ref = ss.Renderer(opts)
     img0, a0, nl0 = ref.forward(b, want_layers=True)
