@@ -134,13 +134,18 @@ typedef struct ss_options {
                           srgb(v) = 12.92 v for v <= 0.0031308, else
                           1.055 v^(1/2.4) - 0.055.  d_image is then dL/dy and the
                           backward applies dy/dx itself.  alpha is not mapped     */
-  int32_t seg_len;     /* tile lists longer than this many entries are split into
-                          segments walked in parallel (persistent launches without
-                          depth statistics; the forward merges the segments' layers
-                          per pixel in list order, so only the float summation order
-                          of a layer that spans a segment boundary changes).
-                          0 (default): 2048; -1: never split; otherwise a multiple
-                          of 256 from 256 to 32768                                */
+  int32_t seg_len;     /* segment length of split tile lists.  A tile's list is
+                          split into segments of this many entries, walked in
+                          parallel, when it is longer than both seg_len and
+                          2 P w / 6144 (P the pairs of the batch, w the wave64s
+                          of a tile: twice an even share of the pairs over the
+                          waves the chip keeps resident).  Persistent launches
+                          without depth statistics only; the forward merges the
+                          segments' layers per pixel in list order, so the
+                          decisions are those of one walk and only the float
+                          summation order of a layer that spans a segment
+                          boundary changes.  0 (default): 2048; -1: never split;
+                          otherwise a multiple of 256 from 256 to 32768           */
 } ss_options;
 
 typedef struct ss_camera {
