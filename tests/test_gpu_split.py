@@ -38,9 +38,32 @@ def stacked_planes():
     return [make_scene(*[np.concatenate(x) for x in (pos, nrm, tan, scl, alb)])], [cam], "albedo"
 
 
+def deep_stack():
+    """90 planes of 3 x 3 wide surfels 0.03 apart in depth, each shifted
+    sideways by up to 5 px about the corner the four 16 x 16 tiles share: a
+    256-entry segment holds about 30 of them, so many pixels reach the 16-layer
+    cap inside their first segment, others in a later one or never."""
+    cam = axis_camera(32, 32, 100.0)
+    pos, nrm, tan, scl, alb = [], [], [], [], []
+    rng = np.random.default_rng(1)
+    for k in range(90):
+        th = np.radians(rng.uniform(-3.0, 3.0))
+        ox, oy = rng.uniform(-0.1, 0.1, 2)
+        gx, gy = np.meshgrid(np.arange(-1, 2) * 0.06 + ox, np.arange(-1, 2) * 0.06 + oy)
+        n = gx.size
+        pos.append(np.stack([gx.ravel(), gy.ravel() * np.cos(th), 2.0 + 0.03 * k + gy.ravel() * np.sin(th)], 1))
+        nrm.append(np.tile([0, -np.sin(th), np.cos(th)], (n, 1)))
+        tan.append(np.tile([1.0, 0, 0], (n, 1)))
+        scl.append(np.full((n, 2), 0.05))
+        alb.append(rng.uniform(0, 1, (n, 3)))
+    return [make_scene(*[np.concatenate(x) for x in (pos, nrm, tan, scl, alb)])], [cam], "albedo"
+
+
 def _case(name):
     if name == "stacked":
         return stacked_planes()
+    if name == "deep":
+        return deep_stack()
     if name == "tie_planes":
         w = g.tie_planes_workload()
         c = w.cameras[0]
@@ -60,7 +83,7 @@ def _lengths(ss, scenes, cams, opts):
     return rg[:, 1] - rg[:, 0]
 
 
-@pytest.mark.parametrize("name", ["stacked", "tie_planes", "multiview", "two_spheres"])
+@pytest.mark.parametrize("name", ["stacked", "deep", "tie_planes", "multiview", "two_spheres"])
 def test_split_parity(O, ss, name):
     scenes, cams, shade = _case(name)
     kw = dict(tile_w=16, tile_h=16, seg_len=256)
@@ -75,9 +98,10 @@ def test_split_parity(O, ss, name):
     assert max(errs.values()) <= GRAD_REL_L2, errs
 
 
-@pytest.mark.parametrize("name,t_min", [("stacked", 0.0), ("stacked", 0.02), ("tie_planes", 0.0),
-                                        ("multiview", 0.0), ("two_spheres", 0.0)])
-def test_split_matches_unsplit(ss, name, t_min):
+@pytest.mark.parametrize("name,t_min,k_max", [("stacked", 0.0, 16), ("stacked", 0.02, 16), ("deep", 0.0, 16),
+                                              ("deep", 0.0, 5), ("deep", 1e-3, 16), ("tie_planes", 0.0, 16),
+                                              ("multiview", 0.0, 16), ("two_spheres", 0.0, 16)])
+def test_split_matches_unsplit(ss, name, t_min, k_max):
     """The same per-pixel decisions as the unsplit walk: identical layer counts
     and work counters (fragments, layers); images and gradients equal up to the
     FP32 summation order of layers that span a segment boundary."""
@@ -88,7 +112,7 @@ def test_split_matches_unsplit(ss, name, t_min):
     Ga = rng.normal(size=n_pix)
     out = []
     for seg in (256, -1):
-        opts = ss.Options(shade=shade, tile_w=16, tile_h=16, seg_len=seg, counters=True, t_min=t_min)
+        opts = ss.Options(shade=shade, tile_w=16, tile_h=16, seg_len=seg, counters=True, t_min=t_min, k_max=k_max)
         r, b, img, a, nl, gr = gpu_run(ss, scenes, cams, opts, G, Ga)
         out.append((img, a, nl, gr, r.poll()))
     (i0, a0, n0, g0, d0), (i1, a1, n1, g1, d1) = out
