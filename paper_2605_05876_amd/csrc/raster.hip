@@ -1,29 +1,34 @@
 // Tile rasterizer, forward and backward (Alg. 1, eq:shepard, eq:alpha,
 // eq:compositing, App. A.1).
 //
-// A block owns one tile of TW x TH pixels; each wave64 owns an 8 x 8 sub-tile
-// and each of its four 16-lane rows a 4 x 4 quadrant of it, one pixel per
-// lane.  The tile's sorted records are staged through LDS in batches (one
-// 64-byte record per surfel, coalesced gathers by the whole block).  For each
-// chunk of 64 staged records every lane tests one record against the wave's
-// sub-tile (pixel rectangle, then the acceptance ellipse).  The forward walks
-// the resulting wave-wide mask: every lane evaluates each surviving record.
-// The backward, whose per-record step is heavier (gradients and a reduction),
-// splits the mask per quadrant: each row walks its own records, so a wave step
-// evaluates up to four different records, each on the 16 pixels it may cover,
-// and reduces them row by row.  Either way each lane visits every covering
-// record in list order, as Alg. 1 requires.
+// Forward: a block owns one tile of TW x TH pixels and each wave64 an 8 x 8
+// sub-tile of it, one pixel per lane.  The tile's sorted records are staged
+// through LDS in batches (one 64-byte record per surfel, coalesced gathers by
+// the whole block).  For each chunk of 64 staged records every lane tests one
+// record against the wave's sub-tile (pixel rectangle, then the acceptance
+// ellipse), and the wave walks the resulting mask in list order: every lane
+// evaluates each surviving record, as Alg. 1 requires.  Per pixel it writes
+// the image, alpha, the layer count and each layer's (W_k, C_k)
+// (unnormalised), at most K_max of them, the list position where each layer
+// starts and where the walk ended, and per (chunk, 4 x 4 quadrant) the mask
+// of records that had a fragment accumulated there.
 //
-// Forward: per pixel it writes the image, alpha, the layer count and each
-// layer's (W_k, C_k) (unnormalised), at most K_max of them.
-// Backward: instead of a replay pass it reads those per-layer totals back
-// (per pixel, never per fragment), rebuilds T_k, alpha_k, C_hat_k and the
-// suffix sums, and re-walks the tile front to back with the identical
-// per-fragment evaluation and grouping decisions.  Per fragment it forms
-// dL/dw and dL/dc, maps them to the record's 11 parameters, reduces them over
-// each row with cross-lane DPP moves and issues one atomic add per value per
-// row.
+// Backward: instead of a replay pass it reads those back (per pixel, never per
+// fragment) and rebuilds T_k, alpha_k, C_hat_k and the suffix sums; it takes
+// no gap decisions.  One wave per 4 x 4 quadrant steps only the records of the
+// quadrant's masks, four at a time (one per 16-lane row), and a lane moves to
+// its pixel's next layer when a record's list position reaches that layer's
+// recorded start.  Per fragment it forms dL/dw and dL/dc, maps them to the
+// record's 11 parameters, reduces them over each row with cross-lane DPP
+// moves into the wave's per-record sums in LDS, and after each batch adds
+// the waves' sums with one atomic per (record, value) of the tile.
+//
+// Long tile lists may be split into segments walked in parallel; the
+// segment kernels below carry Alg. 1's state across the boundaries.
 #include "common.h"
+
+#include <mutex>
+#include <vector>
 
 namespace ss {
 
@@ -247,7 +252,11 @@ __device__ __forceinline__ void forward_item(
   float O0 = 0.f, O1 = 0.f, O2 = 0.f, T = 1.f;
   float zr = 0.f, S1 = 0.f, S2 = 0.f;  // CONS: reference depth, sum w dz, sum w dz^2
   int K = 0;
-  bool done = !inside || poisoned;
+  // r2l: this pixel's cutoff, -inf once its walk has ended (K_max, t_min, a
+  // segment's layer cap; outside the view) so that no later fragment covers
+  // it.  (A float rather than a flag: the compiler keeps per-lane flags as
+  // scalar lane masks and merges them in every branch of the step.)
+  float r2l = (!inside || poisoned) ? -__builtin_inff() : r2;
   // list position of the current layer's first fragment (0xffffffff: none yet)
   uint32_t lstart = 0xffffffffu;
   uint32_t* const lp = lpos + pix * kPosStride;
@@ -257,32 +266,33 @@ __device__ __forceinline__ void forward_item(
   // this row's walk mask of chunk slot 0 of the tile (one writer lane per row)
   uint64_t* const qrow = qmask + (mask_base + (start >> 5) + (tile - tile_begin)) * NQ + wave * 4 + (lane >> 4);
   for (uint32_t b0 = seg_lo; b0 < seg_hi; b0 += (uint32_t)B) {
-    if (__syncthreads_and(done)) break;
+    if (__syncthreads_and(r2l < 0.f)) break;
     const int cnt = (int)min((uint32_t)B, seg_hi - b0);
     load_batch<NT>(lds, vals, recs, b0, cnt);
     __syncthreads();
     for (int c0 = 0; c0 < cnt; c0 += 64) {
-      if (__ballot(!done) == 0ull) break;
+      if (__ballot(r2l >= 0.f) == 0ull) break;
       uint64_t m = chunk_mask<!PPX>(lds, c0, cnt, lane, sx0, sy0, r2);
       nE += inside ? (unsigned)__popcll(m) : 0u;
       // the records of the chunk this pixel accumulated; OR-ed over each row of
       // 16 lanes (a 4 x 4 quadrant) they are the backward's walk lists
       uint32_t lm0 = 0u, lm1 = 0u;
       while (m) {
-        const int j = c0 + __builtin_ctzll(m);
-        const uint64_t bit = m & (0ull - m);  // the record's bit in the chunk
-        m &= m - 1;
+        const int b = __builtin_ctzll(m);
+        const uint64_t bit = 1ull << b;  // the record's bit in the chunk
+        m ^= bit;
+        const int j = c0 + b;
         float rec[kRecFloats];
         load_record<true>(lds + 4 * j, rec);
         FragEval f;
         if constexpr (PPX)
-          frag_eval_pp(rec, px, py, r2, prm.sigma_f, f);
+          frag_eval_pp(rec, px, py, r2l, prm.sigma_f, f);
         else
-          frag_eval(rec, px, py, r2, f);
+          frag_eval(rec, px, py, r2l, f);
         // (structured as nested branches rather than early continues: the
         // compiler then keeps the step's reconvergence simple, which measured
         // faster)
-        if (f.cov && !done) {
+        if (f.cov) {
           if (split && (Wg > 0.f || open_prev) && rec[R_ZS] > zmax) {
             // gap in a segment: close the local layer (if the segment has one open;
             // otherwise this fragment starts a layer after the one a previous
@@ -300,7 +310,7 @@ __device__ __forceinline__ void forward_item(
             open_prev = false;
             // kSegLayers closed: the layer starting here is beyond K_max globally
             if (Kl >= kSegLayers) {
-              done = true;
+              r2l = -__builtin_inff();
               capped = true;
               sb.S[mlayS + (long long)kSegLayers * NT] = (uint16_t)(b0 + (uint32_t)j - seg_lo);
             }
@@ -326,11 +336,11 @@ __device__ __forceinline__ void forward_item(
             // K_max cap, or the early-out once the transmittance is below t_min;
             // the discarded fragment's list position ends the pixel's walk
             if (K >= kmax || T < t_min) {
-              done = true;
+              r2l = -__builtin_inff();
               lp[K] = b0 + (uint32_t)j;
             }
           }
-          if (!done) {
+          if (r2l >= 0.f) {
             if constexpr (split) {
               cont = cont || open_prev;  // continues the layer a previous segment left open
               open_prev = false;
@@ -347,7 +357,7 @@ __device__ __forceinline__ void forward_item(
               S1 += f.w * dz;
               S2 += f.w * dz * dz;
             }
-            zmax = fmaxf(zmax, rec[R_ZE]);
+            zmax = rec[R_ZE] > zmax ? rec[R_ZE] : zmax;  // (fmaxf would canonicalise both)
             C0 += f.w * rec[R_CR];
             C1 += f.w * rec[R_CG];
             C2 += f.w * rec[R_CB];
@@ -363,7 +373,7 @@ __device__ __forceinline__ void forward_item(
     __syncthreads();
   }
   if (split && inside) {
-    if (!done && Wg > 0.f) {
+    if (r2l >= 0.f && Wg > 0.f) {
       sb.L[mlay + (long long)Kl * NT] = make_float4(Wg, C0, C1, C2);
       sb.F[mlay + (long long)Kl * NT] = (uint16_t)nFl;
       ++Kl;
@@ -373,7 +383,7 @@ __device__ __forceinline__ void forward_item(
     sb.M[mrow] = 0u;
   }
   if (!split && inside) {
-    if (!done && Wg > 0.f) {
+    if (r2l >= 0.f && Wg > 0.f) {
       const float a = -expm1f(-kappa * Wg), e = __expf(-kappa * Wg);
       const float s = T * a * layer_norm(prm.shade, Wg, C0, C1, C2);
       O0 += s * C0; O1 += s * C1; O2 += s * C2;
@@ -387,7 +397,7 @@ __device__ __forceinline__ void forward_item(
       ++K;
       sumW += Wg;
     }
-    if (!done) lp[K] = 0xffffffffu;  // the walk ran to the end of the list
+    if (r2l >= 0.f) lp[K] = 0xffffffffu;  // the walk ran to the end of the list
     if constexpr (CONS) {
       float cs, dp;
       depth_stats_of_pixel(stats + pix * kMaxLayers, stats2 + pix * kMaxLayers, K, kappa, cs, dp);
@@ -1173,11 +1183,41 @@ hipError_t launch_tile_order(const uint32_t* ranges, int tile_begin, int n_tiles
 }
 
 // ---------------------------------------------------------------- launchers
-static unsigned persistent_grid(int n_items, int threads) {
-  // 256 CUs; enough resident blocks to cover the chip several times over
-  int per_cu = threads <= 64 ? 16 : (threads <= 128 ? 12 : (threads <= 256 ? 8 : 4));
-  long long g = 256LL * per_cu;
-  return (unsigned)(g < n_items ? g : (n_items > 0 ? n_items : 1));
+// Blocks of a persistent launch: as many as the chip keeps resident at once
+// (the kernel's registers and occupancy target, its LDS), at most one per item.
+// The occupancy query is cached per (kernel, block, LDS) and not made while the
+// stream is being captured; a fixed estimate stands in until it is known.
+static unsigned persistent_grid(const void* fn, int n_items, int threads, size_t lds, hipStream_t st) {
+  struct Entry {
+    const void* fn;
+    int threads;
+    size_t lds;
+    int dev, blocks;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> cache;
+  int dev = 0, blocks = 0;
+  (void)hipGetDevice(&dev);
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Entry& e : cache)
+      if (e.fn == fn && e.threads == threads && e.lds == lds && e.dev == dev) blocks = e.blocks;
+  }
+  if (blocks == 0) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    int cus = 0, per_cu = 0;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) == hipSuccess && cus > 0 &&
+        per_cu > 0) {
+      blocks = cus * per_cu;
+      std::lock_guard<std::mutex> lock(mu);
+      cache.push_back(Entry{fn, threads, lds, dev, blocks});
+    } else {
+      blocks = 256 * (threads <= 64 ? 16 : (threads <= 128 ? 12 : (threads <= 256 ? 8 : 4)));
+    }
+  }
+  return (unsigned)(blocks < n_items ? blocks : (n_items > 0 ? n_items : 1));
 }
 
 template <int TW, int TH>
@@ -1197,10 +1237,15 @@ static hipError_t fwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vi
                          ranges, vals, recs, prm, B, sb);
     hipLaunchKernelGGL((seg_zin_kernel<TW * TH>), dim3((unsigned)nmi), dim3(TW * TH), 0, st, sb);
   }
-#define SS_FWD_V(CV, PV)                                                                                 \
-  hipLaunchKernelGGL((raster_forward_kernel<TW, TH, CV, PV>), grid, dim3(TW * TH), lds, st, views, nv, tb,        \
-                     ni, ranges, vals, recs, prm, B, image, alpha, nlo, nli, stats, stats2, cons, depth, queue, \
-                     order, pers, status, counters, wb.pos, wb.masks, wb.mask_base, sb)
+#define SS_FWD_V(CV, PV)                                                                                   \
+  do {                                                                                                      \
+    if (pers)                                                                                               \
+      grid = dim3(persistent_grid(reinterpret_cast<const void*>(&raster_forward_kernel<TW, TH, CV, PV>), ni, \
+                                  TW * TH, lds, st));                                                       \
+    hipLaunchKernelGGL((raster_forward_kernel<TW, TH, CV, PV>), grid, dim3(TW * TH), lds, st, views, nv, tb,  \
+                       ni, ranges, vals, recs, prm, B, image, alpha, nlo, nli, stats, stats2, cons, depth,    \
+                       queue, order, pers, status, counters, wb.pos, wb.masks, wb.mask_base, sb);             \
+  } while (0)
   if (prm.mip == 1) {
     if (prm.cons) SS_FWD_V(true, true);
     else SS_FWD_V(false, true);
@@ -1222,6 +1267,11 @@ static void bwd_launch(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vie
                        const float2* stats2, const float* dcons, const float* ddepth, float* grad, long long R,
                        int* queue, const int* order, int pers, const WalkBufs& wb, const SegBufs& sb) {
   const dim3 block(BwdMap<TW, TH>::NT);
+  if (pers)
+    grid = dim3(persistent_grid(prm.mip == 1
+                                    ? reinterpret_cast<const void*>(&raster_backward_kernel<TW, TH, SS, CONS, true>)
+                                    : reinterpret_cast<const void*>(&raster_backward_kernel<TW, TH, SS, CONS, false>),
+                                ni, BwdMap<TW, TH>::NT, lds, st));
   if (prm.mip == 1)
     hipLaunchKernelGGL((raster_backward_kernel<TW, TH, SS, CONS, true>), grid, block, lds, st, views, nv,
                        tb, ni, ranges, vals, recs, prm, B, di, da, nli, stats, stats2, dcons, ddepth, grad, R,
@@ -1268,8 +1318,8 @@ hipError_t launch_raster_forward(const ViewDev* views, int n_views, int tile_beg
                    sb.seg_len % lds_batch != 0 || !sb.L || !sb.S || !sb.F || !sb.M || !sb.Z || !sb.ZI))
     return hipErrorInvalidValue;
   const int n_items = sb.items ? (int)n_items_max : n_tiles;
-  const int threads = prm.tile_w * prm.tile_h;
-  dim3 grid(persistent ? persistent_grid(n_items, threads) : (unsigned)n_items);
+  // persistent launches size their grid per kernel variant
+  dim3 grid((unsigned)n_items);
   const size_t lds = (size_t)lds_batch * kRecFloats * sizeof(float);
 #define SS_FWD(TW, TH) fwd_t<TW, TH>(grid, lds, st, views, n_views, tile_begin, n_items, ranges, \
                                      sorted_vals, recs, prm, lds_batch, image, alpha,            \
@@ -1303,9 +1353,9 @@ hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_be
   if (sb.items && (!persistent || !sb.n_items || sb.seg_len <= 0 || sb.seg_len % 64 != 0))
     return hipErrorInvalidValue;
   const int n_items = sb.items ? (int)n_items_max : n_tiles;
-  // four lanes per pixel (wave i owns 4 x 4 quadrant i), at most 1024 threads
-  const int threads = prm.tile_w * prm.tile_h * 4 > 1024 ? 1024 : prm.tile_w * prm.tile_h * 4;
-  dim3 grid(persistent ? persistent_grid(n_items, threads) : (unsigned)n_items);
+  // four lanes per pixel (wave i owns 4 x 4 quadrant i), at most 1024 threads;
+  // persistent launches size their grid per kernel variant
+  dim3 grid((unsigned)n_items);
   // staged records, the walk masks of the batch's chunks (per quadrant) and
   // the waves' gradient sums; the batch shrinks until they fit in 120 KiB
   const int nq = prm.tile_w * prm.tile_h / 16, nw = nq > 16 ? 16 : nq;

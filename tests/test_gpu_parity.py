@@ -157,6 +157,7 @@ def _forward_case(O, ss, scenes, cams, shade, pix_fn, exact_ties=False, **kw):
     ref = oracle_forward(O, scenes, cams, opts, pix, maps, lut, conditioning=not exact_ties)
     _, _, img, a, nl, _ = gpu_run(ss, scenes, cams, opts)
     rep, masks = compare_images(cams, pix, ref, img, a, exact_ties)
+    print("forward", {k: v for k, v in rep.items() if k != "worst"})
     for v, c in enumerate(cams):
         idx = pixel_index(cams, v, pix[v])
         assert (nl[idx][masks[v]] == ref[v]["n_layers"][masks[v]]).all()
@@ -247,6 +248,7 @@ def _backward_case(O, ss, scenes, cams, shade, pix_fn, seed=0, with_alpha=True, 
             He, We = np.asarray(sc.envmap).shape[:2]
             dE = O.envmap_adjoint(ref_maps[i], He, We)
             errs[f"envmap{i}"] = rel_l2(gg["envmap"][i], dE)
+    print("gradients (relative L2)", errs)
     return errs
 
 

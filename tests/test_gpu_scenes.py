@@ -50,10 +50,8 @@ def test_scene_parity(O, ss, name):
     w = _scene(name)
     kw = dict(tile_w=16, tile_h=8, exact_ties=(name == "tie_planes"))
     rep = _forward_case(O, ss, w.scenes, w.cameras, w.shade, lambda c, v: all_pix(c), **kw)
-    print(name, {k: v for k, v in rep.items() if k != "worst"})
     assert_image_parity(rep)
     errs = _backward_case(O, ss, w.scenes, w.cameras, w.shade, lambda c, v: all_pix(c), **kw)
-    print(name, "gradients", errs)
     assert max(errs.values()) <= GRAD_REL_L2, errs
 
 
