@@ -189,6 +189,8 @@ def main():
     ap.add_argument("--config", default="C3", choices=list(WORKLOAD_DESC))
     ap.add_argument("--tile", default=None, help="WxH, e.g. 16x16 (default: autotune cache or 16x16)")
     ap.add_argument("--lds-batch", type=int, default=None)
+    ap.add_argument("--bwd-walk", default=None, choices=["auto", "rows", "records"],
+                    help="walk of the raster backward (default: autotune cache or auto)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -227,13 +229,17 @@ def main():
     tune = autotune.lookup(args.config)
     tw, th = (16, 16)
     lb = 128
+    walk = "auto"
     if tune:
         tw, th, lb = tune["tile_w"], tune["tile_h"], tune["lds_batch"]
+        walk = tune.get("bwd_walk", "auto")
     if args.tile:
         tw, th = (int(x) for x in args.tile.lower().split("x"))
     if args.lds_batch:
         lb = args.lds_batch
-    opts = ss.Options(shade=w.shade, tile_w=tw, tile_h=th, lds_batch=lb)
+    if args.bwd_walk:
+        walk = args.bwd_walk
+    opts = ss.Options(shade=w.shade, tile_w=tw, tile_h=th, lds_batch=lb, bwd_walk=walk)
     batch = ss.batch_from_scenes(w.scenes, w.cameras)
     n_pix = batch.n_pixels
     rng = np.random.default_rng(0)
@@ -372,8 +378,9 @@ def main():
            "data": "synthetic",
            "config": {"workload": f"{args.config}: {WORKLOAD_DESC[args.config]}",
                       "launch": "batched" + ("+hipgraph" if use_graph else ""),
-                      "tile": f"{tw}x{th}", "lds_batch": lb, "pixel_views": n_pix,
-                      "surfels": w.n_surfels},
+                      "tile": f"{tw}x{th}", "lds_batch": lb,
+                      "bwd_walk": walk if walk != "auto" else ("records" if tw * th > 64 else "rows"),
+                      "pixel_views": n_pix, "surfels": w.n_surfels},
            "roofline": roof,
            "step_roofline": step_roof,
            "work": work,
@@ -433,10 +440,10 @@ def run_autotune(args):
     Ga = torch.from_numpy(rng.normal(size=n).astype(np.float32)).cuda()
     keep = []
 
-    def make_step(tw, th, lb):
+    def make_step(tw, th, lb, walk):
         keep.clear()
         torch.cuda.empty_cache()
-        r = ss.Renderer(ss.Options(shade=w.shade, tile_w=tw, tile_h=th, lds_batch=lb))
+        r = ss.Renderer(ss.Options(shade=w.shade, tile_w=tw, tile_h=th, lds_batch=lb, bwd_walk=walk))
         r.reserve(batch)
         out = (torch.empty((n, 3), device="cuda"), torch.empty(n, device="cuda"), None)
         grads = {k: torch.empty_like(batch.params[k]) for k in ss.PARAMS}

@@ -146,6 +146,15 @@ typedef struct ss_options {
                           summation order of a layer that spans a segment
                           boundary changes.  0 (default): 2048; -1: never split;
                           otherwise a multiple of 256 from 256 to 32768           */
+  int32_t bwd_walk;    /* how the raster backward (App. A.1 "Backward Pass
+                          Implementation") walks a tile; both give the same
+                          gradients to float summation order.  1: rows -- per
+                          4 x 4 quadrant, four of its recorded records per wave
+                          step, one per 16-lane row, reduced across the row;
+                          2: record-major -- per 8 x 8 sub-tile, the records of
+                          a quadrant one per lane, each summing its gradient
+                          over the quadrant's pixels.  0 (default): record-major
+                          for tiles larger than 8 x 8, rows for 8 x 8          */
 } ss_options;
 
 typedef struct ss_camera {

@@ -85,8 +85,8 @@ hipError_t launch_invert_order(const uint32_t* zidx, long long n, uint32_t* inv,
   return hipGetLastError();
 }
 // One thread per depth-sorted record: its gradient row is the sum, in emission
-// order, of the partials at its pairs' emission slots (slots past the pair
-// capacity, after an overflow, are left out).
+// order and sub-tile order, of the partials at its pairs' emission slots (slots
+// past the pair capacity, after an overflow, are left out).
 __global__ void ordered_record_sums_kernel(const uint32_t* __restrict__ zidx, const uint2* __restrict__ zrect,
                                            const uint32_t* __restrict__ offs, long long n, int tile_w, int tile_h,
                                            const float* __restrict__ pgrad, long long pair_base,
@@ -98,10 +98,10 @@ __global__ void ordered_record_sums_kernel(const uint32_t* __restrict__ zidx, co
   float4 s0 = make_float4(0.f, 0.f, 0.f, 0.f), s1 = s0, s2 = s0, s3 = s0;
   if (il <= ih && jl <= jh) {
     const long long cnt = (long long)(ih / tile_w - il / tile_w + 1) * (jh / tile_h - jl / tile_h + 1);
-    const long long o = offs[i];
-    const long long k1 = o + cnt < pair_cap ? o + cnt : pair_cap;
-    for (long long k = o; k < k1; ++k) {
-      const float4* p = reinterpret_cast<const float4*>(pgrad + (pair_base + k) * kGradStride);
+    const long long o = offs[i], nsub = sub_tiles(tile_w, tile_h);
+    const long long k1 = (o + cnt < pair_cap ? o + cnt : pair_cap) * nsub;
+    for (long long k = o * nsub; k < k1; ++k) {
+      const float4* p = reinterpret_cast<const float4*>(pgrad + (pair_base * nsub + k) * kGradStride);
       const float4 a = p[0], b = p[1], c = p[2], d = p[3];
       s0.x += a.x; s0.y += a.y; s0.z += a.z; s0.w += a.w;
       s1.x += b.x; s1.y += b.y; s1.z += b.z; s1.w += b.w;

@@ -47,8 +47,9 @@ struct WalkBufs {
   uint32_t* pos;
   uint64_t* masks;
   long long mask_base;  // first slot of the group
-  // deterministic backward: each (record, tile) partial goes to the pair's
-  // emission slot, pgrad[(pair_base + offs[inv[record]] + k) * kGradStride + slot]
+  // deterministic backward: each (record, tile, 8 x 8 sub-tile s) partial goes
+  // to sub-slot s of the pair's emission slot,
+  // pgrad[((pair_base + offs[inv[record]] + k) * sub_tiles + s) * kGradStride + slot]
   // with k the tile's row-major index in the record's tile rectangle (the
   // order in which the pairs were emitted); null pgrad: float atomics
   float* pgrad;
@@ -57,6 +58,8 @@ struct WalkBufs {
   long long pair_base;
 };
 inline long long mask_slots(long long pair_cap, int n_tiles) { return pair_cap / 32 + n_tiles + 2; }
+// 8 x 8 sub-tiles of a tile (the backward's unit of work)
+__host__ __device__ inline int sub_tiles(int tile_w, int tile_h) { return (tile_w / 8) * (tile_h / 8); }
 
 // Long tile lists are split into segments so that no single tile's walk bounds
 // a raster launch.  Work item of the persistent raster kernels: (tile, segment,
@@ -115,6 +118,7 @@ struct Params {
   float t_min;  // transmittance early-out (0: off)
   int tonemap;  // 1: log-space + sRGB transfer of the image (and its derivative in the backward)
   int counters; // forward: count evaluated pairs, fragments, layers and their weight
+  int bwd_walk; // backward walk: 1 rows (four records of a quadrant per wave step), 2 record-major
 };
 
 // Log-space + sRGB transfer of one linear channel value (the HDR transfer
@@ -432,8 +436,9 @@ hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint3
                            long long tmp_n, hipStream_t st);
 // Deterministic backward of one group: inv[zidx[i]] = i for the depth order
 // zidx of its n records, and, once the raster backward has written the
-// per-(record, tile) partials at their emission slots, each record's
-// gradient = the sum of its slots in emission order (grad rows overwritten).
+// per-(record, tile, sub-tile) partials at their emission slots, each record's
+// gradient = the sum of its slots in emission order, sub-tiles in order (grad
+// rows overwritten).
 hipError_t launch_invert_order(const uint32_t* zidx, long long n, uint32_t* inv, hipStream_t st);
 hipError_t launch_ordered_record_sums(const uint32_t* zidx, const uint2* zrect, const uint32_t* offs, long long n,
                                       int tile_w, int tile_h, const float* pgrad, long long pair_base,
@@ -495,7 +500,7 @@ hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_be
                                   const float* d_image, const float* d_alpha,
                                   const uint8_t* n_layers, const float4* layer_stats,
                                   const float2* layer_stats2, const float* d_cons,
-                                  const float* d_depth, float* grad, long long R, int* queue,
+                                  const float* d_depth, float* grad, int* queue,
                                   const int* order, int persistent, const WalkBufs& wb, const SegBufs& sb,
                                   long long n_items, hipStream_t st);
 

@@ -818,6 +818,380 @@ __device__ inline void cons_coef(const float4* __restrict__ st, const float2* __
   c.v = zk.y;
 }
 
+// The backward works on 8 x 8 sub-tiles of the forward's tiles: one block of
+// four waves per (work item, sub-tile), wave q owning the sub-tile's 4 x 4
+// quadrant q (walk-mask quadrant 4 s + q of the tile, s the sub-tile in the
+// forward's wave order).  It is record-major: the 64 lanes of a wave take the
+// records of its quadrant's walk masks, packed across the batch's chunks, and
+// loop over the quadrant's 16 pixels together (the pixel uniform across the
+// wave), each lane summing its own record's gradient values over the pixels in
+// registers; no cross-lane reduction is needed.  A lane finds the layer of its
+// fragment by comparing its list position with the pixel's recorded layer
+// starts, and reads that layer's coefficients from a per-pixel table the wave
+// builds once per work item.
+constexpr int kBwdWaves = 4;
+constexpr int kBwdThreads = 64 * kBwdWaves;
+
+// The per-pixel table, in float4s: a header {walk end, G (the pixel's dL/dC)}
+// and per layer an entry of 1 + normal + 2 cons float4s: {start (layer 0: the
+// pixel's layer count), dW, coef, GC}; for the normal image {G' of the layer};
+// with the depth statistics {A, B, C, z}, {v}.
+__host__ __device__ constexpr int bwd_entry_floats(bool normal, bool cons) {
+  return 4 + (normal ? 4 : 0) + (cons ? 8 : 0);
+}
+// LDS of a backward block in floats: staged records, the batch's walk masks
+// (four quadrants, two floats each), the per-record sums (one set per wave;
+// LDS float atomics would cost several cycles per lane), the waves' packed
+// record lists (one byte per entry) and the per-pixel tables.  Every part
+// starts on a 16-byte boundary.
+__host__ __device__ inline size_t bwd_lds_floats(int B, int nv, int lw) {
+  return (size_t)B * kRecFloats + (size_t)((B + 63) / 64) * kBwdWaves * 2 + (size_t)kBwdWaves * B * nv +
+         (size_t)kBwdWaves * B / 4 + (size_t)kBwdWaves * 16 * (4 + kMaxLayers * lw);
+}
+
+// Set bits of m below this lane.
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// SS: also accumulate the densification statistic in slot G_SS.
+// CONS: add the adjoint of the depth statistics (loss weights d_cons on the
+// consolidation term, d_depth on the composited depth; either may be null).
+// PPX: the per-pixel-Jacobian MIP filter (frag_eval_pp and its adjoint).
+// Deterministic mode (wb.pgrad): each (record, sub-tile) sum is stored at the
+// pair's emission slot, sub-tile s at sub-slot s; otherwise float atomics.
+template <int TW, int TH, bool SS, bool CONS, bool PPX>
+__global__ void __launch_bounds__(kBwdThreads)
+__attribute__((amdgpu_waves_per_eu(PPX ? 3 : 4))) raster_backward_records_kernel(
+    const ViewDev* __restrict__ views, int n_views, int tile_begin, int n_items,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const float* __restrict__ recs, Params prm, int B, const float* __restrict__ d_image,
+    const float* __restrict__ d_alpha, const uint8_t* __restrict__ nl_int,
+    const float4* __restrict__ stats, const float2* __restrict__ stats2, const float* __restrict__ d_cons,
+    const float* __restrict__ d_depth, float* __restrict__ grad, int* queue,
+    const int* __restrict__ order, int persistent, WalkBufs wb, SegBufs sb) {
+  constexpr int NSUB = (TW / 8) * (TH / 8);  // 8 x 8 sub-tiles of a tile
+  constexpr int NQ = TW * TH / 16;           // walk-mask quadrants of a tile
+  constexpr int WX = TW / 8;
+  // values summed per record: the 11 record slots, then G_SS, then G_TZ
+  constexpr int NV = kNGrad + (SS ? 1 : 0) + (CONS ? 1 : 0);
+  constexpr int NT = kBwdThreads;
+  // Without the per-fragment statistic or the per-pixel filter, the x0 and y0
+  // gradients are linear in per-fragment terms whose record-constant factors
+  // come out of the sum: a lane sums the terms and forms them once.
+  constexpr bool DEF = !SS && !PPX;
+  const uint32_t* __restrict__ lpos = wb.pos;
+  const uint64_t* __restrict__ qmask = wb.masks;
+  extern __shared__ float4 lds[];
+  __shared__ int s_item;
+  __shared__ uint32_t s_stop;
+  const int t = threadIdx.x, lane = t & 63, q = t >> 6;
+  const float r2 = prm.r2, kappa = prm.kappa;
+  const bool det = wb.pgrad != nullptr;
+  const bool normal = prm.shade == 2;
+  const int LW4 = bwd_entry_floats(normal, CONS) / 4;  // float4s per layer entry
+  const int pstride = 1 + kMaxLayers * LW4;            // float4s per pixel
+  float* const lf = reinterpret_cast<float*>(lds);
+  uint64_t* const smask = reinterpret_cast<uint64_t*>(lf + (size_t)B * kRecFloats);  // [chunk][quadrant]
+  float* const acc = reinterpret_cast<float*>(smask + ((B + 63) >> 6) * kBwdWaves);
+  uint8_t* const lists = reinterpret_cast<uint8_t*>(acc + (size_t)kBwdWaves * B * NV);
+  float4* const wtab = reinterpret_cast<float4*>(lists + kBwdWaves * B) + (size_t)q * 16 * pstride;
+  uint8_t* const wlist = lists + q * B;
+  const int nbase = sb.items ? min((int)*sb.n_items, n_items) : n_items;
+  const int nit = nbase * NSUB;
+  for (int iter = 0;; ++iter) {
+    const int item = next_item(queue, persistent, s_item, iter);
+    if (item < 0 || item >= nit) break;
+    const int bi = item / NSUB, sub = item - bi * NSUB;
+    // a segment of a split list walks its own stretch of the list
+    const int4 it = sb.items ? sb.items[bi] : make_int4(order ? order[bi] : tile_begin + bi, 0, 1, -1);
+    const int tile = it.x;
+    const ViewDev& v = views[view_of_tile(views, n_views, tile)];
+    const int lt = tile - v.tile_base;
+    const int tx = lt % v.tiles_x, ty = lt / v.tiles_x;
+    // this wave's quadrant (as the forward's wave `sub`, row q, laid its pixels out)
+    const int qx0 = tx * TW + (sub % WX) * 8 + (q & 1) * 4, qy0 = ty * TH + (sub / WX) * 8 + (q >> 1) * 4;
+    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    const uint32_t seg_lo = start + (uint32_t)it.y * (uint32_t)sb.seg_len;
+    const uint32_t seg_hi = it.z > 1 ? min(end, seg_lo + (uint32_t)sb.seg_len) : end;
+    if (t == 0) s_stop = seg_lo;
+    __syncthreads();
+
+    // The per-pixel table: lane u < 16 takes pixel u = 4 y + x of the quadrant.
+    // Entry k: as the forward composited -- transmittance T_k, prefix colour and
+    // the suffix through layer_coef, in the order of the layers.
+    if (lane < 16) {
+      const int px = qx0 + (lane & 3), py = qy0 + (lane >> 2);
+      float4* const ph = wtab + lane * pstride;
+      uint32_t pend = 0u;
+      int nl = 0;
+      float G[3] = {0.f, 0.f, 0.f};
+      if (px < v.W && py < v.H) {
+        const long long pix = v.pix_off + (long long)py * v.W + px;
+        G[0] = d_image[3 * pix]; G[1] = d_image[3 * pix + 1]; G[2] = d_image[3 * pix + 2];
+        const float ga = d_alpha ? d_alpha[pix] : 0.f;
+        nl = nl_int[pix];
+        float Cf[3] = {0.f, 0.f, 0.f}, T = 1.f;
+        for (int k = 0; k < nl; ++k) {
+          const float4 st = stats[pix * kMaxLayers + k];
+          const float a = -expm1f(-kappa * st.x), e = __expf(-kappa * st.x);
+          const float s = T * a * layer_norm(prm.shade, st.x, st.y, st.z, st.w);
+          Cf[0] += s * st.y; Cf[1] += s * st.z; Cf[2] += s * st.w;
+          T *= e;
+        }
+        const float Tfin = T;
+        Cf[0] += T * v.bg[0]; Cf[1] += T * v.bg[1]; Cf[2] += T * v.bg[2];
+        if (prm.tonemap) {
+          // d_image is dL/dy for the tone-mapped y; the walk needs dL/dx
+          G[0] *= tonemap_srgb_log_deriv(Cf[0]);
+          G[1] *= tonemap_srgb_log_deriv(Cf[1]);
+          G[2] *= tonemap_srgb_log_deriv(Cf[2]);
+        }
+        if (nl > 0) {
+          const uint32_t* const lp = lpos + pix * kPosStride;
+          pend = lp[nl];
+          float dc = 0.f, dd = 0.f, U = 0.f;
+          if constexpr (CONS) {
+            dc = d_cons ? d_cons[pix] : 0.f;
+            dd = d_depth ? d_depth[pix] : 0.f;
+            float cs, dp;
+            depth_stats_of_pixel(stats + pix * kMaxLayers, stats2 + pix * kMaxLayers, nl, kappa, cs, dp);
+            U = 2.f * dc * cs + dd * dp;
+          }
+          float pre[3] = {0.f, 0.f, 0.f}, Tk = 1.f;
+          for (int k = 0; k < nl; ++k) {
+            LayerCoef L;
+            layer_coef(stats[pix * kMaxLayers + k], Tk, kappa, G, ga, Tfin, Cf, pre, prm.shade, L);
+            float4* const e = ph + 1 + k * LW4;
+            e[0] = make_float4(k == 0 ? __int_as_float(nl) : __uint_as_float(lp[k]), L.dW, L.coef, L.GC);
+            if (normal) e[1] = make_float4(L.G0, L.G1, L.G2, 0.f);
+            if constexpr (CONS) {
+              ConsCoef CC;
+              cons_coef(stats + pix * kMaxLayers, stats2 + pix * kMaxLayers, nl, k, kappa, dc, dd, U, CC);
+              e[LW4 - 2] = make_float4(CC.A, CC.B, CC.C, CC.z);
+              e[LW4 - 1] = make_float4(CC.v, 0.f, 0.f, 0.f);
+            }
+            pre[0] += Tk * L.a * L.Ch0; pre[1] += Tk * L.a * L.Ch1; pre[2] += Tk * L.a * L.Ch2;
+            Tk *= L.e;
+          }
+          // the block's batches end where the last of its pixels' walks ended
+          atomicMax(&s_stop, pend < end ? pend + 1u : end);
+        }
+      }
+      ph[0] = make_float4(__uint_as_float(pend), G[0], G[1], G[2]);
+      if (nl == 0) ph[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __syncthreads();
+    const uint32_t stop = min(s_stop, seg_hi);
+    const long long slot0 = wb.mask_base + (start >> 5) + (tile - tile_begin);
+    for (uint32_t b0 = seg_lo; b0 < stop; b0 += (uint32_t)B) {
+      const int cnt = (int)min((uint32_t)B, seg_hi - b0);
+      const int nch = (cnt + 63) >> 6;
+      load_batch<NT>(lds, vals, recs, b0, cnt);
+      for (int i = t; i < kBwdWaves * cnt * NV; i += NT) acc[i] = 0.f;
+      // the walk masks of the batch's chunks, the sub-tile's four quadrants
+      for (int i = t; i < nch * kBwdWaves; i += NT) {
+        const int ch = i >> 2, qq = i & 3;
+        smask[i] = qmask[(slot0 + ((b0 + (uint32_t)(ch << 6) - start) >> 5)) * NQ + 4 * sub + qq];
+      }
+      __syncthreads();
+      // this wave's records: the set bits of its quadrant's masks, in list order
+      // (a wave's LDS operations complete in order, so its lanes read the list
+      // back without a barrier).  Bits past the batch are dropped: a chunk the
+      // forward did not reach still holds an earlier render's mask.
+      int n = 0;
+      for (int ch = 0; ch < nch; ++ch) {
+        const int left = cnt - (ch << 6);
+        const uint64_t m = uniform64(smask[ch * kBwdWaves + q]) & (left >= 64 ? ~0ull : (1ull << left) - 1ull);
+        if ((m >> lane) & 1ull) wlist[n + lanes_below(m)] = (uint8_t)(ch * 64 + lane);
+        n += __popcll(m);
+      }
+      for (int e0 = 0; e0 < n; e0 += 64) {
+        const bool act = e0 + lane < n;
+        const int j = act ? (int)wlist[e0 + lane] : 0;
+        float rec[kRecFloats];
+        load_record(lds + 4 * j, rec);
+        const uint32_t p = b0 + (uint32_t)j;
+        const float a3 = rec[R_A3], b3 = rec[R_B3], qxx = rec[R_QXX], qxy2 = rec[R_QXY2], qyy = rec[R_QYY];
+        // the pixel offsets from the centre, formed as frag_eval forms them
+        const int il = __float_as_int(rec[R_RX]) & 0xffff, jl = __float_as_int(rec[R_RY]) & 0xffff;
+        float sum[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sum[i] = 0.f;
+        float svq = 0.f, sgs = 0.f;  // DEF: sums of v and (CONS) of the depth term's s-derivative
+        // each pixel's header and first layer (the same address in every lane)
+        // are read one pixel ahead, so the LDS latency overlaps the arithmetic
+        float4 hd = wtab[0], l0 = wtab[1];
+        for (int r = 0; r < 4; ++r) {
+          const float dyr = ((float)(qy0 + r - jl) + 0.5f) - rec[R_Y0];
+          const float sb = __builtin_fmaf(b3, dyr, 1.0f), tq = qxy2 * dyr, nq = (qyy * dyr) * dyr;
+          for (int c = 0; c < 4; ++c) {
+            const float4* const ph = wtab + (4 * r + c) * pstride;
+            const float4 hdc = hd, l0c = l0;
+            if (4 * r + c < 15) {
+              hd = ph[pstride];
+              l0 = ph[pstride + 1];
+            }
+            FragEval f;
+            if constexpr (PPX) {
+              frag_eval_pp(rec, qx0 + c, qy0 + r, r2, prm.sigma_f, f);
+            } else {
+              // frag_eval's arithmetic, with the row's terms shared
+              f.dx = ((float)(qx0 + c - il) + 0.5f) - rec[R_X0];
+              f.dy = dyr;
+              f.s = __builtin_fmaf(a3, f.dx, sb);
+              f.N = __builtin_fmaf(__builtin_fmaf(qxx, f.dx, tq), f.dx, nq);
+              const float s2 = f.s * f.s;
+              f.cov = f.N < r2 * s2;
+              f.q = f.N * __builtin_amdgcn_rcpf(s2);
+              f.e = __expf(-0.5f * f.q);
+              f.w = rec[R_NF] * f.e;
+            }
+            if (__ballot(act && f.cov) == 0ull) continue;
+            if (act && f.cov && p < __float_as_uint(hdc.x)) {
+              // the fragment's layer: the number of the pixel's layer starts at or before p
+              const int nl = __float_as_int(l0c.x);
+              int k = 0;
+              float4 ev = l0c;
+              if (nl > 1) {
+                for (int kk = 1; kk < nl; ++kk) k += p >= __float_as_uint(ph[1 + kk * LW4].x) ? 1 : 0;
+                ev = ph[1 + k * LW4];
+              }
+              float G0 = hdc.y, G1 = hdc.z, G2 = hdc.w;
+              if (normal) {
+                const float4 gv = ph[2 + k * LW4];
+                G0 = gv.x; G1 = gv.y; G2 = gv.z;
+              }
+              const float Gc = G0 * rec[R_CR] + G1 * rec[R_CG] + G2 * rec[R_CB];
+              float gw = ev.y + ev.z * (Gc - ev.w);
+              const float gcs = f.w * ev.z;
+              float gz = 0.f, zf = 0.f;
+              if constexpr (CONS) {
+                const float4 ca = ph[1 + k * LW4 + LW4 - 2], cb = ph[1 + k * LW4 + LW4 - 1];
+                zf = frag_depth(rec, f);
+                const float dz = zf - ca.w;
+                gw += ca.x + ca.y * dz + ca.z * (dz * dz - cb.x);
+                gz = f.w * (ca.y + 2.f * ca.z * dz);
+              }
+              // d(rho^2)/d(record) for q = d^T Q d / s^2, s = 1 + a3 dx + b3 dy:
+              // u = gq / s^2 and v = -2 gq q / s factor every slot of the kernel shape
+              const float is = __builtin_amdgcn_rcpf(f.s);
+              const float gq = -0.5f * f.w * gw;
+              if constexpr (DEF) {
+                const float uu = gq * is * is, vq = -2.f * gq * f.q * is;
+                const float ux = uu * f.dx, uy = uu * f.dy;
+                sum[G_X0] += ux;  // sums of u dx and u dy; x0, y0 after the loop
+                sum[G_Y0] += uy;
+                svq += vq;
+                sum[G_QXX] += ux * f.dx;
+                sum[G_QXY2] += ux * f.dy;
+                sum[G_QYY] += uy * f.dy;
+                sum[G_A3] += vq * f.dx;
+                sum[G_B3] += vq * f.dy;
+                sum[G_NF] += gw * f.e;  // w / n_f
+                sum[G_CR] += gcs * G0;
+                sum[G_CG] += gcs * G1;
+                sum[G_CB] += gcs * G2;
+                if constexpr (CONS) {
+                  // z_f = T4z / s: dz/dT4z = 1/s, dz/ds = -z_f/s, ds/d(a3, b3) = (dx, dy),
+                  // ds/d(x0, y0) = -(a3, b3)
+                  const float gs = -gz * zf * is;
+                  sgs += gs;
+                  sum[G_A3] += gs * f.dx;
+                  sum[G_B3] += gs * f.dy;
+                  sum[NV - 1] += gz * is;
+                }
+              } else {
+                float g[NV];
+                if constexpr (PPX) {
+                  frag_grad_pp(rec, qx0 + c, qy0 + r, prm.sigma_f, f.w * gw, true, g);
+                } else {
+                  const float uu = gq * is * is, vq = -2.f * gq * f.q * is;
+                  const float ux = uu * f.dx, uy = uu * f.dy;
+                  g[G_X0] = -(2.f * qxx * ux + qxy2 * uy + a3 * vq);
+                  g[G_Y0] = -(qxy2 * ux + 2.f * qyy * uy + b3 * vq);
+                  g[G_QXX] = ux * f.dx;
+                  g[G_QXY2] = ux * f.dy;
+                  g[G_QYY] = uy * f.dy;
+                  g[G_A3] = vq * f.dx;
+                  g[G_B3] = vq * f.dy;
+                  g[G_NF] = gw * f.e;
+                }
+                g[G_CR] = gcs * G0;
+                g[G_CG] = gcs * G1;
+                g[G_CB] = gcs * G2;
+                if constexpr (CONS) {
+                  const float gs = -gz * zf * is;
+                  g[G_X0] -= gs * a3;
+                  g[G_Y0] -= gs * b3;
+                  g[G_A3] += gs * f.dx;
+                  g[G_B3] += gs * f.dy;
+                  g[NV - 1] = gz * is;
+                }
+                if constexpr (SS) {
+                  // (dL_p/dT1z, dL_p/dT2z) T4z from the record gradients: a change of
+                  // T1z (T2z) is the screen map x += delta s / T4z (y += ...), which
+                  // moves the centre by delta/T4z and M by E M with E = e1 (a3, b3) / T4z
+                  // (e2 ...); the record fields follow in closed form, with
+                  // P = I - sigma_f Q and (p1, p2) = (a3, b3) P.
+                  const float qxy = 0.5f * qxy2, sg = prm.sigma_f;
+                  const float p1 = a3 * (1.f - sg * qxx) - b3 * sg * qxy;
+                  const float p2 = b3 * (1.f - sg * qyy) - a3 * sg * qxy;
+                  const float gab = a3 * g[G_A3] + b3 * g[G_B3];
+                  const float gnf = sg * gw * f.w;  // n_f dL/dn_f sigma_f
+                  const float gx = g[G_X0] - 2.f * (qxx * p1 * g[G_QXX] + (qxx * p2 + qxy * p1) * g[G_QXY2] +
+                                                    qxy * p2 * g[G_QYY]) -
+                                   a3 * gab + gnf * (a3 * qxx + b3 * qxy);
+                  const float gy = g[G_Y0] - 2.f * (qxy * p1 * g[G_QXX] + (qxy * p2 + qyy * p1) * g[G_QXY2] +
+                                                    qyy * p2 * g[G_QYY]) -
+                                   b3 * gab + gnf * (a3 * qxy + b3 * qyy);
+                  g[kNGrad] = sqrtf(gx * gx + gy * gy);
+                }
+#pragma unroll
+                for (int i = 0; i < NV; ++i) sum[i] += g[i];
+              }
+            }
+          }
+        }
+        if constexpr (DEF) {
+          const float sux = sum[G_X0], suy = sum[G_Y0];
+          sum[G_X0] = -(2.f * qxx * sux + qxy2 * suy + a3 * svq) - a3 * sgs;
+          sum[G_Y0] = -(qxy2 * sux + 2.f * qyy * suy + b3 * svq) - b3 * sgs;
+        }
+        // into the wave's sums for the batch (lanes hold distinct records)
+        if (act) {
+          float* const a = acc + ((long long)q * cnt + j) * NV;
+#pragma unroll
+          for (int i = 0; i < NV; ++i) a[i] = sum[i];
+        }
+      }
+      __syncthreads();
+      // per (record, value) the waves' sums in a fixed order: one atomic, or
+      // (deterministic) a store at the pair's emission slot
+      for (int i = t; i < cnt * NV; i += NT) {
+        const int j = i / NV, vi = i - j * NV;
+        float total = 0.f;
+#pragma unroll
+        for (int w = 0; w < kBwdWaves; ++w) total += acc[((long long)w * cnt + j) * NV + vi];
+        if (total != 0.f) {
+          const int slot = vi < kNGrad ? vi : (vi == NV - 1 && CONS ? (int)G_TZ : (int)G_SS);
+          const float4 q3 = lds[4 * j + 3];
+          const uint32_t id = __float_as_uint(q3.w);
+          if (det) {
+            const int rx = __float_as_int(q3.x), ry = __float_as_int(q3.y);
+            const int tx0 = (rx & 0xffff) / TW, ty0 = (ry & 0xffff) / TH, nx = (rx >> 16) / TW - tx0 + 1;
+            const long long e = wb.pair_base + wb.offs[wb.inv[id]] + (ty - ty0) * nx + (tx - tx0);
+            wb.pgrad[(e * NSUB + sub) * kGradStride + slot] = total;
+          } else {
+            atomicAdd(grad + (long long)id * kGradStride + slot, total);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Lane -> pixel of the backward.  A block owns a tile; wave i owns the tile's
 // 4 x 4 quadrant(s) numbered as in the forward (quadrant 4 w + r is row r of
 // forward wave w).  With up to 16 quadrants a wave owns one and all four rows
@@ -833,10 +1207,8 @@ struct BwdMap {
   static constexpr int NT = NW * 64;                // threads per block
 };
 
-// SS: also accumulate the densification statistic in slot G_SS.
-// CONS: add the adjoint of the depth statistics (loss weights d_cons on the
-// consolidation term, d_depth on the composited depth; either may be null).
-// PPX: the per-pixel-Jacobian MIP filter (frag_eval_pp and its adjoint).
+// The row walk.  SS, CONS, PPX as for the record-major walk; deterministic
+// mode stores each (record, tile) sum at sub-slot 0 of the pair's emission slot.
 //
 // The walk needs no gap tests: the forward recorded where each of a pixel's
 // layers starts in the tile list and where its walk ended, and per chunk and
@@ -849,13 +1221,13 @@ struct BwdMap {
 // extra statistics or the per-pixel filter.
 template <int TW, int TH, bool SS, bool CONS, bool PPX>
 __global__ void __launch_bounds__((BwdMap<TW, TH>::NT))
-__attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backward_kernel(
+__attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backward_rows_kernel(
     const ViewDev* __restrict__ views, int n_views, int tile_begin, int n_items,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float* __restrict__ recs, Params prm, int B, const float* __restrict__ d_image,
     const float* __restrict__ d_alpha, const uint8_t* __restrict__ nl_int,
     const float4* __restrict__ stats, const float2* __restrict__ stats2, const float* __restrict__ d_cons,
-    const float* __restrict__ d_depth, float* __restrict__ grad, long long R, int* queue,
+    const float* __restrict__ d_depth, float* __restrict__ grad, int* queue,
     const int* __restrict__ order, int persistent, WalkBufs wb, SegBufs sb) {
   using M = BwdMap<TW, TH>;
   const uint32_t* __restrict__ lpos = wb.pos;
@@ -1105,7 +1477,7 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
             const int rx = __float_as_int(q3.x), ry = __float_as_int(q3.y);
             const int tx0 = (rx & 0xffff) / TW, ty0 = (ry & 0xffff) / TH, nx = (rx >> 16) / TW - tx0 + 1;
             const long long e = wb.pair_base + wb.offs[wb.inv[id]] + (ty - ty0) * nx + (tx - tx0);
-            wb.pgrad[e * kGradStride + slot] = sum;
+            wb.pgrad[e * ((TW / 8) * (TH / 8)) * kGradStride + slot] = sum;  // sub-slot 0
           } else {
             atomicAdd(grad + (long long)id * kGradStride + slot, sum);
           }
@@ -1261,37 +1633,44 @@ static hipError_t fwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vi
 }
 
 template <int TW, int TH, bool SS, bool CONS>
-static void bwd_launch(dim3 grid, size_t lds, hipStream_t st, const ViewDev* views, int nv, int tb, int ni,
+static void bwd_launch(size_t lds, hipStream_t st, const ViewDev* views, int nv, int tb, int ni,
                        const uint32_t* ranges, const uint32_t* vals, const float* recs, const Params& prm,
                        int B, const float* di, const float* da, const uint8_t* nli, const float4* stats,
-                       const float2* stats2, const float* dcons, const float* ddepth, float* grad, long long R,
+                       const float2* stats2, const float* dcons, const float* ddepth, float* grad,
                        int* queue, const int* order, int pers, const WalkBufs& wb, const SegBufs& sb) {
-  const dim3 block(BwdMap<TW, TH>::NT);
-  if (pers)
-    grid = dim3(persistent_grid(prm.mip == 1
-                                    ? reinterpret_cast<const void*>(&raster_backward_kernel<TW, TH, SS, CONS, true>)
-                                    : reinterpret_cast<const void*>(&raster_backward_kernel<TW, TH, SS, CONS, false>),
-                                ni, BwdMap<TW, TH>::NT, lds, st));
-  if (prm.mip == 1)
-    hipLaunchKernelGGL((raster_backward_kernel<TW, TH, SS, CONS, true>), grid, block, lds, st, views, nv,
-                       tb, ni, ranges, vals, recs, prm, B, di, da, nli, stats, stats2, dcons, ddepth, grad, R,
-                       queue, order, pers, wb, sb);
-  else
-    hipLaunchKernelGGL((raster_backward_kernel<TW, TH, SS, CONS, false>), grid, block, lds, st, views, nv,
-                       tb, ni, ranges, vals, recs, prm, B, di, da, nli, stats, stats2, dcons, ddepth, grad, R,
-                       queue, order, pers, wb, sb);
+  const bool rows = prm.bwd_walk == 1;
+  // record-major: one block per (work item, 8 x 8 sub-tile); rows: one per work item
+  const int n = rows ? ni : ni * ((TW / 8) * (TH / 8));
+  const int threads = rows ? BwdMap<TW, TH>::NT : kBwdThreads;
+  const void* fn =
+      rows ? (prm.mip == 1 ? reinterpret_cast<const void*>(&raster_backward_rows_kernel<TW, TH, SS, CONS, true>)
+                           : reinterpret_cast<const void*>(&raster_backward_rows_kernel<TW, TH, SS, CONS, false>))
+           : (prm.mip == 1 ? reinterpret_cast<const void*>(&raster_backward_records_kernel<TW, TH, SS, CONS, true>)
+                           : reinterpret_cast<const void*>(&raster_backward_records_kernel<TW, TH, SS, CONS, false>));
+  const dim3 grid(pers ? persistent_grid(fn, n, threads, lds, st) : (unsigned)n), block(threads);
+#define SS_BWD_K(K, PV)                                                                                     \
+  hipLaunchKernelGGL((K<TW, TH, SS, CONS, PV>), grid, block, lds, st, views, nv, tb, ni, ranges, vals, recs, \
+                     prm, B, di, da, nli, stats, stats2, dcons, ddepth, grad, queue, order, pers, wb, sb)
+  if (rows) {
+    if (prm.mip == 1) SS_BWD_K(raster_backward_rows_kernel, true);
+    else SS_BWD_K(raster_backward_rows_kernel, false);
+  } else {
+    if (prm.mip == 1) SS_BWD_K(raster_backward_records_kernel, true);
+    else SS_BWD_K(raster_backward_records_kernel, false);
+  }
+#undef SS_BWD_K
 }
 
 template <int TW, int TH>
-static hipError_t bwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* views, int nv, int tb,
+static hipError_t bwd_t(size_t lds, hipStream_t st, const ViewDev* views, int nv, int tb,
                         int ni, const uint32_t* ranges, const uint32_t* vals, const float* recs,
                         const Params& prm, int B, const float* di, const float* da,
                         const uint8_t* nli, const float4* stats, const float2* stats2, const float* dcons,
-                        const float* ddepth, float* grad, long long R, int* queue, const int* order,
+                        const float* ddepth, float* grad, int* queue, const int* order,
                         int pers, const WalkBufs& wb, const SegBufs& sb) {
-#define SS_BWD_V(SSV, CV) bwd_launch<TW, TH, SSV, CV>(grid, lds, st, views, nv, tb, ni, ranges, vals, recs, \
-                                                       prm, B, di, da, nli, stats, stats2, dcons, ddepth,    \
-                                                       grad, R, queue, order, pers, wb, sb)
+#define SS_BWD_V(SSV, CV) bwd_launch<TW, TH, SSV, CV>(lds, st, views, nv, tb, ni, ranges, vals, recs, \
+                                                       prm, B, di, da, nli, stats, stats2, dcons, ddepth, \
+                                                       grad, queue, order, pers, wb, sb)
   if (prm.ss_grad && prm.cons) SS_BWD_V(true, true);
   else if (prm.ss_grad) SS_BWD_V(true, false);
   else if (prm.cons) SS_BWD_V(false, true);
@@ -1343,33 +1722,38 @@ hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_be
                                   const float* d_image, const float* d_alpha,
                                   const uint8_t* n_layers, const float4* layer_stats,
                                   const float2* layer_stats2, const float* d_cons,
-                                  const float* d_depth, float* grad, long long R, int* queue,
+                                  const float* d_depth, float* grad, int* queue,
                                   const int* order, int persistent, const WalkBufs& wb, const SegBufs& sb,
                                   long long n_items_max, hipStream_t st) {
   const int n_tiles = tile_end - tile_begin;
   if (n_tiles <= 0) return hipSuccess;
   if (prm.cons && (!layer_stats2 || (!d_cons && !d_depth))) return hipErrorInvalidValue;
   if (!wb.pos || !wb.masks) return hipErrorInvalidValue;
+  if (wb.pgrad && (!wb.inv || !wb.offs)) return hipErrorInvalidValue;
   if (sb.items && (!persistent || !sb.n_items || sb.seg_len <= 0 || sb.seg_len % 64 != 0))
     return hipErrorInvalidValue;
   const int n_items = sb.items ? (int)n_items_max : n_tiles;
-  // four lanes per pixel (wave i owns 4 x 4 quadrant i), at most 1024 threads;
-  // persistent launches size their grid per kernel variant
-  dim3 grid((unsigned)n_items);
-  // staged records, the walk masks of the batch's chunks (per quadrant) and
-  // the waves' gradient sums; the batch shrinks until they fit in 120 KiB
-  const int nq = prm.tile_w * prm.tile_h / 16, nw = nq > 16 ? 16 : nq;
+  if (prm.bwd_walk != 1 && prm.bwd_walk != 2) return hipErrorInvalidValue;
+  // The batch shrinks until the block's LDS fits (64 KiB record-major, 120 KiB
+  // rows), but not below one 64-record chunk: the forward's walk masks are per
+  // chunk of 64 list entries (per 32 when its batch was 32).
+  // Record-major: staged records, masks, per-wave sums, record lists, per-pixel
+  // tables.  Rows: staged records, the masks of every quadrant, per-wave sums.
   const int nv = kNGrad + (prm.ss_grad ? 1 : 0) + (prm.cons ? 1 : 0);
-  auto lds_for = [&](int b) {
+  const int lw = bwd_entry_floats(prm.shade == 2, prm.cons != 0);
+  const int nq = prm.tile_w * prm.tile_h / 16, nw = nq > 16 ? 16 : nq;
+  auto lds_for = [&](int b) -> size_t {
+    if (prm.bwd_walk == 2) return bwd_lds_floats(b, nv, lw) * sizeof(float);
     return (size_t)b * kRecFloats * sizeof(float) + (size_t)((b + 63) / 64) * nq * sizeof(uint64_t) +
            (size_t)nw * b * nv * sizeof(float);
   };
-  while (lds_batch > 32 && lds_for(lds_batch) > 120 * 1024) lds_batch /= 2;
+  const size_t budget = (prm.bwd_walk == 2 ? 64 : 120) * 1024;
+  while (lds_batch > 64 && lds_for(lds_batch) > budget) lds_batch /= 2;
   const size_t lds = lds_for(lds_batch);
-#define SS_BWD(TW, TH) bwd_t<TW, TH>(grid, lds, st, views, n_views, tile_begin, n_items, ranges, \
-                                     sorted_vals, recs, prm, lds_batch, d_image, d_alpha,        \
-                                     n_layers, layer_stats, layer_stats2, d_cons, d_depth, grad, \
-                                     R, queue, order, persistent, wb, sb)
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+#define SS_BWD(TW, TH) bwd_t<TW, TH>(lds, st, views, n_views, tile_begin, n_items, ranges, sorted_vals, recs, \
+                                     prm, lds_batch, d_image, d_alpha, n_layers, layer_stats, layer_stats2, \
+                                     d_cons, d_depth, grad, queue, order, persistent, wb, sb)
   switch (prm.tile_w * 100 + prm.tile_h) {
     case 808: return SS_BWD(8, 8);
     case 1608: return SS_BWD(16, 8);

@@ -43,7 +43,7 @@ class ss_options(ctypes.Structure):
                 ("persistent", ctypes.c_int32), ("depth_stats", ctypes.c_int32), ("mip", ctypes.c_int32),
                 ("env_lds", ctypes.c_int32), ("t_min", ctypes.c_float), ("deterministic", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("counters", ctypes.c_int32), ("tonemap", ctypes.c_int32),
-                ("seg_len", ctypes.c_int32)]
+                ("seg_len", ctypes.c_int32), ("bwd_walk", ctypes.c_int32)]
 
 
 class ss_camera(ctypes.Structure):
@@ -164,6 +164,7 @@ class Options:
     counters: bool = False      # count the raster forward's work (ss_poll)
     tonemap: str = "linear"     # "linear" | "srgb_log" (log-space + sRGB transfer, eq:photo_loss)
     seg_len: int = 0            # split tile lists longer than this (0: 2048, -1: never)
+    bwd_walk: str = "auto"      # raster backward walk: "auto" | "rows" | "records"
 
     def to_c(self) -> ss_options:
         return ss_options(self.r_cut, self.k_max, self.gamma, self.sigma_f, SHADE[self.shade],
@@ -172,7 +173,7 @@ class Options:
                           {"centre": 0, "pixel": 1}[self.mip], int(self.env_lds), float(self.t_min),
                           1 if self.deterministic else 0, 1 if self.validate else 0,
                           1 if self.counters else 0, {"linear": 0, "srgb_log": 1}[self.tonemap],
-                          int(self.seg_len))
+                          int(self.seg_len), {"auto": 0, "rows": 1, "records": 2}[self.bwd_walk])
 
 
 def camera_to_c(cam) -> ss_camera:

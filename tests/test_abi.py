@@ -69,7 +69,7 @@ def test_host_argument_checks(lib):
     o = s.ss_options()
     assert lib.ss_default_options(ctypes.byref(o)) == 0
     assert (o.r_cut, o.k_max, o.tile_w, o.tile_h, o.env_lds) == (3.0, 16, 16, 16, -1)
-    assert (o.t_min, o.deterministic, o.validate, o.counters, o.tonemap, o.seg_len) == (0.0, 0, 0, 0, 0, 0)
+    assert (o.t_min, o.deterministic, o.validate, o.counters, o.tonemap, o.seg_len, o.bwd_walk) == (0.0,) + (0,) * 6
     ctx = ctypes.c_void_p()
     bad = s.ss_options.from_buffer_copy(o)
     bad.tile_w = 12
@@ -86,12 +86,13 @@ def test_host_argument_checks(lib):
     for field, value, want in (("t_min", -0.1, s.SS_ERR_INVALID_ARG), ("t_min", 1.0, s.SS_ERR_INVALID_ARG),
                                ("validate", 2, s.SS_ERR_INVALID_ARG), ("tonemap", 3, s.SS_ERR_INVALID_ARG),
                                ("counters", -1, s.SS_ERR_INVALID_ARG), ("seg_len", 100, s.SS_ERR_INVALID_ARG),
-                               ("seg_len", 65536, s.SS_ERR_INVALID_ARG), ("seg_len", -2, s.SS_ERR_INVALID_ARG)):
+                               ("seg_len", 65536, s.SS_ERR_INVALID_ARG), ("seg_len", -2, s.SS_ERR_INVALID_ARG),
+                               ("bwd_walk", 3, s.SS_ERR_INVALID_ARG), ("bwd_walk", -1, s.SS_ERR_INVALID_ARG)):
         bad = s.ss_options.from_buffer_copy(o)
         setattr(bad, field, value)
         assert lib.ss_create(ctypes.byref(bad), ctypes.byref(ctx)) == want, field
     ok = s.ss_options.from_buffer_copy(o)
-    ok.lds_batch, ok.t_min, ok.validate, ok.counters, ok.tonemap, ok.seg_len = 0, 0.01, 1, 1, 1, 512
+    ok.lds_batch, ok.t_min, ok.validate, ok.counters, ok.tonemap, ok.seg_len, ok.bwd_walk = 0, 0.01, 1, 1, 1, 512, 2
     assert lib.ss_create(ctypes.byref(ok), ctypes.byref(ctx)) == 0
     assert lib.ss_destroy(ctx) == 0
     assert lib.ss_create(None, ctypes.byref(ctx)) == s.SS_ERR_INVALID_ARG

@@ -180,12 +180,14 @@ def _det_case(case):
     return scenes, cams, "splitsum", dict(launch="per_view")
 
 
+@pytest.mark.parametrize("walk", ["rows", "records"])
 @pytest.mark.parametrize("case", ["C1", "multiview", "per_view"])
-def test_deterministic_backward_is_bitwise_reproducible(O, ss, case):
+def test_deterministic_backward_is_bitwise_reproducible(O, ss, case, walk):
     """options.deterministic: two backward passes (and a second renderer) give
     bit-identical gradients of every parameter group, the environment maps and the
     densification statistic; and they pass the oracle bar."""
     scenes, cams, shade, kw = _det_case(case)
+    kw["bwd_walk"] = walk
     opts = ss.Options(shade=shade, deterministic=True, **kw)
     b = ss.batch_from_scenes(scenes, cams)
     gen = torch.Generator("cuda").manual_seed(11)

@@ -252,16 +252,49 @@ def _backward_case(O, ss, scenes, cams, shade, pix_fn, seed=0, with_alpha=True, 
     return errs
 
 
-def test_backward_parity_albedo_full_image(O, ss):
+# the two walks of the raster backward (options.bwd_walk)
+WALKS = ["rows", "records"]
+
+
+@pytest.mark.parametrize("walk", WALKS)
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_backward_parity_albedo_full_image(O, ss, walk, tile):
     w = g.make_config("C1")
-    errs = _backward_case(O, ss, w.scenes, w.cameras, "albedo", lambda c, v: all_pix(c))
+    errs = _backward_case(O, ss, w.scenes, w.cameras, "albedo", lambda c, v: all_pix(c), bwd_walk=walk,
+                          tile_w=tile[0], tile_h=tile[1])
     assert max(errs.values()) <= GRAD_REL_L2, errs
 
 
-def test_backward_parity_splitsum_full_image(O, ss):
+@pytest.mark.parametrize("walk", WALKS)
+def test_backward_parity_splitsum_full_image(O, ss, walk):
     scenes, cams = small_c2()
-    errs = _backward_case(O, ss, scenes, cams, "splitsum", lambda c, v: all_pix(c))
+    errs = _backward_case(O, ss, scenes, cams, "splitsum", lambda c, v: all_pix(c), bwd_walk=walk)
     assert max(errs.values()) <= GRAD_REL_L2, errs
+
+
+@pytest.mark.parametrize("case", ["C1", "multiview"])
+@pytest.mark.parametrize("tile", [(8, 8), (16, 8), (32, 16)])
+def test_backward_walks_agree(ss, case, tile):
+    """Both walks of the backward sum the same fragment contributions: gradients
+    equal to float summation order (relative L2 <= 1e-5 per group)."""
+    if case == "C1":
+        w = g.make_config("C1")
+        scenes, cams, shade = w.scenes, w.cameras, "albedo"
+    else:
+        scenes, cams = small_multiview()
+        shade = "splitsum"
+    n_pix = sum(c.width * c.height for c in cams)
+    rng = np.random.default_rng(29)
+    G, Ga = rng.normal(size=(n_pix, 3)), rng.normal(size=n_pix)
+    out = [gpu_run(ss, scenes, cams, ss.Options(shade=shade, bwd_walk=walk, tile_w=tile[0], tile_h=tile[1]),
+                   G, Ga)[5] for walk in WALKS]
+    pos = np.linalg.norm(out[0]["position"])
+    for k in ("position", "normal", "scale", "albedo", "roughness", "metallic"):
+        if np.linalg.norm(out[0][k]) <= 1e-6 * pos:
+            continue
+        assert rel_l2(out[1][k], out[0][k]) <= 1e-5, (k, rel_l2(out[1][k], out[0][k]))
+    if shade == "splitsum":
+        assert rel_l2(out[1]["envmap"][0], out[0]["envmap"][0]) <= 1e-5
 
 
 @pytest.mark.parametrize("env_lds", [0, 6144])
@@ -274,9 +307,10 @@ def test_backward_parity_splitsum_global_levels(O, ss, env_lds):
     assert max(errs.values()) <= GRAD_REL_L2, errs
 
 
-def test_backward_parity_multiview(O, ss):
+@pytest.mark.parametrize("walk", WALKS)
+def test_backward_parity_multiview(O, ss, walk):
     scenes, cams = small_multiview()
-    errs = _backward_case(O, ss, scenes, cams, "splitsum", lambda c, v: all_pix(c), seed=3)
+    errs = _backward_case(O, ss, scenes, cams, "splitsum", lambda c, v: all_pix(c), seed=3, bwd_walk=walk)
     assert max(errs.values()) <= GRAD_REL_L2, errs
 
 
@@ -291,8 +325,9 @@ def _two_scene_views():
     return [a, b], cams
 
 
+@pytest.mark.parametrize("walk", WALKS)
 @pytest.mark.parametrize("case", ["C1_sigma0.5", "multiview", "two_scenes"])
-def test_screen_grad_parity(O, ss, case):
+def test_screen_grad_parity(O, ss, case, walk):
     """Sec. 3.6.1 statistic (sum over views and pixels of |(dL_p/dT1z, dL_p/dT2z)| T4z)
     and the visible-view count against the oracle; the other gradients are unchanged
     by requesting it."""
@@ -305,7 +340,7 @@ def test_screen_grad_parity(O, ss, case):
     else:
         scenes, cams = _two_scene_views()
         shade, kw = "splitsum", {}
-    opts = ss.Options(shade=shade, **kw)
+    opts = ss.Options(shade=shade, bwd_walk=walk, **kw)
     maps, lut = oracle_maps(O, scenes, shade)
     oo = oracle_options(O, opts)
     pix = [all_pix(c) for c in cams]
@@ -348,8 +383,9 @@ def test_screen_grad_parity(O, ss, case):
 
 
 # ---------------------------------------------------------------- depth consolidation
+@pytest.mark.parametrize("walk", WALKS)
 @pytest.mark.parametrize("case", ["C1", "multiview"])
-def test_cons_parity(O, ss, case):
+def test_cons_parity(O, ss, case, walk):
     """eq:cons_loss per pixel against the oracle (relative L2 <= 1e-3: the FP32 depth of
     a fragment carries ~2 ulp(z) from T4z = (z_start + z_end)/2, against layer depth
     spreads of ~1e-2), the composited depth (image protocol), the image unchanged by
@@ -363,7 +399,7 @@ def test_cons_parity(O, ss, case):
         shade = "splitsum"
     # unsplit lists: the forward with depth statistics never splits them, so the
     # image without the statistics is then bit-identical
-    opts = ss.Options(shade=shade, depth_stats=True, seg_len=-1)
+    opts = ss.Options(shade=shade, depth_stats=True, seg_len=-1, bwd_walk=walk)
     maps, lut = oracle_maps(O, scenes, shade)
     oo = oracle_options(O, opts)
     pix = [all_pix(c) for c in cams]
@@ -434,14 +470,15 @@ def test_cons_parity(O, ss, case):
         r.backward(b, gt, None, d_cons=dct)
 
 
-def test_normal_image_parity(O, ss):
+@pytest.mark.parametrize("walk", WALKS)
+def test_normal_image_parity(O, ss, walk):
     """Normal image (Sec. 4.2.3): per layer the Shepard mean of the unit normals,
     renormalised, composited like colour; forward with the image protocol and the
     geometric gradients (relative L2 <= 1e-3 per group)."""
     scenes, cams = small_multiview()
     rep = _forward_case(O, ss, scenes, cams, "normal", lambda c, v: all_pix(c))
     assert_image_parity(rep)
-    errs = _backward_case(O, ss, scenes, cams, "normal", lambda c, v: all_pix(c), seed=5)
+    errs = _backward_case(O, ss, scenes, cams, "normal", lambda c, v: all_pix(c), seed=5, bwd_walk=walk)
     errs = {k: e for k, e in errs.items() if k not in ("albedo", "roughness", "metallic")}
     assert max(errs.values()) <= GRAD_REL_L2, errs
 
@@ -468,13 +505,14 @@ def test_per_pixel_mip_forward_parity(O, ss, case):
     assert_image_parity(rep)
 
 
+@pytest.mark.parametrize("walk", WALKS)
 @pytest.mark.parametrize("case", ["checkerboard", "C1_sigma0.5", "multiview"])
-def test_per_pixel_mip_backward_parity(O, ss, case):
+def test_per_pixel_mip_backward_parity(O, ss, case, walk):
     """Adjoint of the per-pixel-Jacobian filter (Sec. 3.3.1): dL/d(record) through the
     pixel's own Sigma_mip and det, against the oracle's tape adjoint (relative L2 per
     group, split-sum and the environment maps included for the multi-view case)."""
     scenes, cams, shade, kw = _per_pixel_case(case)
-    errs = _backward_case(O, ss, scenes, cams, shade, lambda c, v: all_pix(c), mip="pixel", **kw)
+    errs = _backward_case(O, ss, scenes, cams, shade, lambda c, v: all_pix(c), mip="pixel", bwd_walk=walk, **kw)
     assert max(errs.values()) <= GRAD_REL_L2, errs
 
 

@@ -83,11 +83,12 @@ def _lengths(ss, scenes, cams, opts):
     return rg[:, 1] - rg[:, 0]
 
 
+@pytest.mark.parametrize("walk", ["rows", "records"])
 @pytest.mark.parametrize("name", ["stacked", "deep", "tie_planes", "multiview", "two_spheres"])
-def test_split_parity(O, ss, name):
+def test_split_parity(O, ss, name, walk):
     scenes, cams, shade = _case(name)
-    kw = dict(tile_w=16, tile_h=16, seg_len=256)
-    L = _lengths(ss, scenes, cams, ss.Options(shade=shade, **kw))
+    kw = dict(tile_w=16, tile_h=16, seg_len=256, bwd_walk=walk)
+    L = _lengths(ss, scenes, cams, ss.Options(shade=shade, tile_w=16, tile_h=16, seg_len=256))
     kw["exact_ties"] = name == "tie_planes"
     assert (L > 256).sum() >= 2, L.max()      # several tiles are split
     rep = _forward_case(O, ss, scenes, cams, shade, lambda c, v: all_pix(c), **kw)
@@ -127,9 +128,10 @@ def test_split_matches_unsplit(ss, name, t_min, k_max):
         assert rel_l2(g0[k], g1[k]) <= 1e-5, k
 
 
-def test_split_deterministic_bitwise(ss):
+@pytest.mark.parametrize("walk", ["rows", "records"])
+def test_split_deterministic_bitwise(ss, walk):
     scenes, cams, shade = _case("multiview")
-    opts = ss.Options(shade=shade, tile_w=16, tile_h=16, seg_len=256, deterministic=True)
+    opts = ss.Options(shade=shade, tile_w=16, tile_h=16, seg_len=256, deterministic=True, bwd_walk=walk)
     b = ss.batch_from_scenes(scenes, cams)
     gen = torch.Generator("cuda").manual_seed(5)
     G = torch.randn((b.n_pixels, 3), device="cuda", generator=gen)
