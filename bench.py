@@ -379,7 +379,7 @@ def main():
            "config": {"workload": f"{args.config}: {WORKLOAD_DESC[args.config]}",
                       "launch": "batched" + ("+hipgraph" if use_graph else ""),
                       "tile": f"{tw}x{th}", "lds_batch": lb,
-                      "bwd_walk": walk if walk != "auto" else ("records" if tw * th > 64 else "rows"),
+                      "bwd_walk": walk if walk != "auto" else ("records" if lb >= 256 else "rows"),
                       "pixel_views": n_pix, "surfels": w.n_surfels},
            "roofline": roof,
            "step_roofline": step_roof,

@@ -154,7 +154,7 @@ typedef struct ss_options {
                           2: record-major -- per 8 x 8 sub-tile, the records of
                           a quadrant one per lane, each summing its gradient
                           over the quadrant's pixels.  0 (default): record-major
-                          for tiles larger than 8 x 8, rows for 8 x 8          */
+                          when the LDS batch is 256 records, rows otherwise    */
 } ss_options;
 
 typedef struct ss_camera {

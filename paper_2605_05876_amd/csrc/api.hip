@@ -235,9 +235,10 @@ Params make_params(const ss_context* c) {
   p.t_min = c->opt.t_min;
   p.tonemap = c->opt.tonemap;
   p.counters = c->opt.counters;
-  // automatic choice of the backward walk: record-major for tiles larger than
-  // 8 x 8 (measured faster on the 16 x 8 workloads), rows for 8 x 8 tiles
-  p.bwd_walk = c->opt.bwd_walk != 0 ? c->opt.bwd_walk : (c->opt.tile_w * c->opt.tile_h > 64 ? 2 : 1);
+  // automatic choice of the backward walk: record-major with 256-record
+  // batches (where the row walk's per-wave sums halve its occupancy), rows
+  // otherwise -- the faster of the two on every measured workload
+  p.bwd_walk = c->opt.bwd_walk != 0 ? c->opt.bwd_walk : (c->lds_batch >= 256 ? 2 : 1);
   return p;
 }
 
