@@ -92,7 +92,8 @@ struct ss_context {
       pgrad /* deterministic: per-pair gradient partials */, inv /* record -> depth position */,
       detw /* deterministic: per scene fixed-point bound and exponent */,
       items, mitems, segbase /* split lists: work items and their scan scratch */,
-      segL, segS, segF, segM, segZ, segZI /* split lists: the segments' local layers and z_max */;
+      segL, segS, segF, segM, segZ, segZI /* split lists: the segments' local layers and z_max */,
+      ovf /* record-major backward: per-pixel table entries of the deeper layers */;
   std::vector<long long> soff;
   long long scan_tmp_n = 0, pair_total = 0, hist_n = 0;
   DevBuf lut;
@@ -216,6 +217,14 @@ std::vector<long long> signature(const ss_context* c, const ss_batch* b) {
   return s;
 }
 
+// The walk of the raster backward: 1 rows, 2 record-major.  Automatic choice:
+// record-major with 256-record batches (where the row walk's per-wave sums
+// halve its occupancy), rows otherwise -- the faster of the two on every
+// measured workload.
+int backward_walk(const ss_context* c) {
+  return c->opt.bwd_walk != 0 ? c->opt.bwd_walk : (c->lds_batch >= 256 ? 2 : 1);
+}
+
 Params make_params(const ss_context* c) {
   Params p;
   p.r_cut = c->opt.r_cut;
@@ -235,10 +244,7 @@ Params make_params(const ss_context* c) {
   p.t_min = c->opt.t_min;
   p.tonemap = c->opt.tonemap;
   p.counters = c->opt.counters;
-  // automatic choice of the backward walk: record-major with 256-record
-  // batches (where the row walk's per-wave sums halve its occupancy), rows
-  // otherwise -- the faster of the two on every measured workload
-  p.bwd_walk = c->opt.bwd_walk != 0 ? c->opt.bwd_walk : (c->lds_batch >= 256 ? 2 : 1);
+  p.bwd_walk = backward_walk(c);
   return p;
 }
 
@@ -531,6 +537,7 @@ WalkBufs walk_bufs(ss_context* c, const Group& g) {
   w.inv = det ? P<uint32_t>(c->inv) : nullptr;
   w.offs = P<uint32_t>(c->offsets) + g.rec_begin;
   w.pair_base = g.pair_base;
+  w.ovf = c->ovf.p ? P<float4>(c->ovf) : nullptr;
   return w;
 }
 
@@ -592,6 +599,11 @@ ss_status reserve_impl(ss_context* c, const ss_batch* b, hipStream_t st) {
     c->lds_batch = mean >= 256 ? 256 : (mean >= 128 ? 128 : (mean >= 64 ? 64 : 32));
   }
   SS_HIP(ensure(c->qmask, (size_t)layout_masks(c) * sizeof(uint64_t)));
+  if (backward_walk(c) == 2) {  // entry float4s per layer: 1, + 1 normal image, + 2 depth statistics
+    const int lw4 = 1 + (c->opt.shade == SS_SHADE_NORMAL ? 1 : 0) + (c->opt.depth_stats ? 2 : 0);
+    SS_HIP(ensure(c->ovf, (size_t)(c->n_pix > 0 ? c->n_pix : 1) * (kMaxLayers - kBwdTabLayers) * lw4 *
+                              sizeof(float4)));
+  }
   // split lists (persistent launches): a group's items are its tiles plus one
   // per further segment; a split tile's segments number at most 2 len / seg_len
   c->seg_len = (!c->opt.persistent || c->opt.seg_len < 0) ? 0 : (c->opt.seg_len > 0 ? c->opt.seg_len : 2048);
@@ -678,7 +690,7 @@ size_t workspace_bytes(const ss_context* c) {
              c->grad.n + c->misc.n + c->lut.n + c->partial.n + c->sg.n + c->order.n + c->stats2.n + c->zkey.n +
              c->zkey2.n + c->zidx.n + c->zidx2.n + c->prect.n + c->zrect.n + c->lpos.n + c->qmask.n +
              c->pgrad.n + c->inv.n + c->detw.n + c->items.n + c->mitems.n + c->segbase.n + c->segL.n + c->segS.n +
-             c->segF.n + c->segM.n + c->segZ.n + c->segZI.n;
+             c->segF.n + c->segM.n + c->segZ.n + c->segZI.n + c->ovf.n;
   for (const SceneEnv& e : c->env) s += e.dirs.n + e.lv.n + e.Z.n + e.dlv.n + e.part.n + e.dlv_fx.n + e.adj_part.n;
   return s;
 }
@@ -900,7 +912,7 @@ ss_status ss_destroy(ss_context* c) {
                     &c->grad, &c->misc, &c->lut, &c->partial, &c->sg, &c->order, &c->stats2,
                     &c->zkey, &c->zkey2, &c->zidx, &c->zidx2, &c->prect, &c->zrect, &c->lpos, &c->qmask,
                     &c->pgrad, &c->inv, &c->detw, &c->items, &c->mitems, &c->segbase, &c->segL, &c->segS,
-                    &c->segF, &c->segM, &c->segZ, &c->segZI};
+                    &c->segF, &c->segM, &c->segZ, &c->segZI, &c->ovf};
   for (DevBuf* b : bufs) release(*b);
   for (SceneEnv& e : c->env) {
     release(e.dirs); release(e.lv); release(e.Z); release(e.dlv); release(e.part);

@@ -56,7 +56,12 @@ struct WalkBufs {
   const uint32_t* inv;   // global record index -> depth-sorted position in its group
   const uint32_t* offs;  // depth-sorted position -> first emission slot (group-relative)
   long long pair_base;
+  // record-major backward: the per-pixel table entries of layers kBwdTabLayers ..
+  // kMaxLayers - 1, [pixel][layer - kBwdTabLayers][entry float4s] (the first
+  // kBwdTabLayers layers stay in LDS)
+  float4* ovf;
 };
+constexpr int kBwdTabLayers = 8;
 inline long long mask_slots(long long pair_cap, int n_tiles) { return pair_cap / 32 + n_tiles + 2; }
 // 8 x 8 sub-tiles of a tile (the backward's unit of work)
 __host__ __device__ inline int sub_tiles(int tile_w, int tile_h) { return (tile_w / 8) * (tile_h / 8); }

@@ -835,7 +835,9 @@ constexpr int kBwdThreads = 64 * kBwdWaves;
 // The per-pixel table, in float4s: a header {walk end, G (the pixel's dL/dC)}
 // and per layer an entry of 1 + normal + 2 cons float4s: {start (layer 0: the
 // pixel's layer count), dW, coef, GC}; for the normal image {G' of the layer};
-// with the depth statistics {A, B, C, z}, {v}.
+// with the depth statistics {A, B, C, z}, {v}.  The entries of the first
+// kBwdTabLayers layers are in LDS, those of deeper layers in global memory
+// (WalkBufs::ovf), so that the LDS leaves room for four blocks per CU.
 __host__ __device__ constexpr int bwd_entry_floats(bool normal, bool cons) {
   return 4 + (normal ? 4 : 0) + (cons ? 8 : 0);
 }
@@ -846,7 +848,27 @@ __host__ __device__ constexpr int bwd_entry_floats(bool normal, bool cons) {
 // starts on a 16-byte boundary.
 __host__ __device__ inline size_t bwd_lds_floats(int B, int nv, int lw) {
   return (size_t)B * kRecFloats + (size_t)((B + 63) / 64) * kBwdWaves * 2 + (size_t)kBwdWaves * B * nv +
-         (size_t)kBwdWaves * B / 4 + (size_t)kBwdWaves * 16 * (4 + kMaxLayers * lw);
+         (size_t)kBwdWaves * B / 4 + (size_t)kBwdWaves * 16 * (4 + kBwdTabLayers * lw);
+}
+
+// Scalar find-first-set of a wave-uniform mask (-1 when it is empty) and the
+// clearing of that bit, one scalar instruction each (a generic ctz adds a zero
+// test and a select, m & (m - 1) takes three 64-bit instructions); clearing
+// bit -1 of an empty mask (bit 63) leaves it empty.
+__device__ __forceinline__ int sfirst(uint64_t m) {
+  int r;
+  asm("s_ff1_i32_b64 %0, %1" : "=s"(r) : "s"(m));
+  return r;
+}
+__device__ __forceinline__ uint64_t sclear(uint64_t m, int b) {
+  asm("s_bitset0_b64 %0, %1" : "+s"(m) : "s"(b));
+  return m;
+}
+// Two wave-uniform values as the low and high 16-bit halves of one scalar.
+__device__ __forceinline__ uint32_t spack16(int lo, int hi) {
+  uint32_t r;
+  asm("s_pack_ll_b32_b16 %0, %1, %2" : "=s"(r) : "s"(lo), "s"(hi));
+  return r;
 }
 
 // Set bits of m below this lane.
@@ -862,7 +884,7 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
 // pair's emission slot, sub-tile s at sub-slot s; otherwise float atomics.
 template <int TW, int TH, bool SS, bool CONS, bool PPX>
 __global__ void __launch_bounds__(kBwdThreads)
-__attribute__((amdgpu_waves_per_eu(PPX ? 3 : 4))) raster_backward_records_kernel(
+__attribute__((amdgpu_waves_per_eu((PPX || SS) ? 3 : 4))) raster_backward_records_kernel(
     const ViewDev* __restrict__ views, int n_views, int tile_begin, int n_items,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float* __restrict__ recs, Params prm, int B, const float* __restrict__ d_image,
@@ -890,7 +912,7 @@ __attribute__((amdgpu_waves_per_eu(PPX ? 3 : 4))) raster_backward_records_kernel
   const bool det = wb.pgrad != nullptr;
   const bool normal = prm.shade == 2;
   const int LW4 = bwd_entry_floats(normal, CONS) / 4;  // float4s per layer entry
-  const int pstride = 1 + kMaxLayers * LW4;            // float4s per pixel
+  const int pstride = 1 + kBwdTabLayers * LW4;         // float4s per pixel in LDS
   float* const lf = reinterpret_cast<float*>(lds);
   uint64_t* const smask = reinterpret_cast<uint64_t*>(lf + (size_t)B * kRecFloats);  // [chunk][quadrant]
   float* const acc = reinterpret_cast<float*>(smask + ((B + 63) >> 6) * kBwdWaves);
@@ -962,7 +984,8 @@ __attribute__((amdgpu_waves_per_eu(PPX ? 3 : 4))) raster_backward_records_kernel
           for (int k = 0; k < nl; ++k) {
             LayerCoef L;
             layer_coef(stats[pix * kMaxLayers + k], Tk, kappa, G, ga, Tfin, Cf, pre, prm.shade, L);
-            float4* const e = ph + 1 + k * LW4;
+            float4* const e = k < kBwdTabLayers ? ph + 1 + k * LW4
+                                                 : wb.ovf + (pix * (kMaxLayers - kBwdTabLayers) + k - kBwdTabLayers) * LW4;
             e[0] = make_float4(k == 0 ? __int_as_float(nl) : __uint_as_float(lp[k]), L.dW, L.coef, L.GC);
             if (normal) e[1] = make_float4(L.G0, L.G1, L.G2, 0.f);
             if constexpr (CONS) {
@@ -1050,16 +1073,36 @@ __attribute__((amdgpu_waves_per_eu(PPX ? 3 : 4))) raster_backward_records_kernel
             if (__ballot(act && f.cov) == 0ull) continue;
             if (act && f.cov && p < __float_as_uint(hdc.x)) {
               // the fragment's layer: the number of the pixel's layer starts at or before p
+              // (each table read in its own address space: LDS, or global past kBwdTabLayers)
               const int nl = __float_as_int(l0c.x);
-              int k = 0;
-              float4 ev = l0c;
+              float4 ev = l0c, gv = l0c, ca = l0c, cb = l0c;
+              auto extras = [&](const float4* e) {
+                if (normal) gv = e[1];
+                if constexpr (CONS) {
+                  ca = e[LW4 - 2];
+                  cb = e[LW4 - 1];
+                }
+              };
               if (nl > 1) {
-                for (int kk = 1; kk < nl; ++kk) k += p >= __float_as_uint(ph[1 + kk * LW4].x) ? 1 : 0;
-                ev = ph[1 + k * LW4];
+                int k = 0;
+                const int nlt = min(nl, kBwdTabLayers);
+                for (int kk = 1; kk < nlt; ++kk) k += p >= __float_as_uint(ph[1 + kk * LW4].x) ? 1 : 0;
+                // entries of layers past the LDS table: [pixel][layer - kBwdTabLayers]
+                const long long db = (v.pix_off + (long long)(qy0 + r) * v.W + qx0 + c) *
+                                     (kMaxLayers - kBwdTabLayers) - kBwdTabLayers;
+                for (int kk = kBwdTabLayers; kk < nl; ++kk) k += p >= __float_as_uint(wb.ovf[(db + kk) * LW4].x) ? 1 : 0;
+                if (k < kBwdTabLayers) {
+                  ev = ph[1 + k * LW4];
+                  extras(ph + 1 + k * LW4);
+                } else {
+                  ev = wb.ovf[(db + k) * LW4];
+                  extras(wb.ovf + (db + k) * LW4);
+                }
+              } else {
+                extras(ph + 1);
               }
               float G0 = hdc.y, G1 = hdc.z, G2 = hdc.w;
               if (normal) {
-                const float4 gv = ph[2 + k * LW4];
                 G0 = gv.x; G1 = gv.y; G2 = gv.z;
               }
               const float Gc = G0 * rec[R_CR] + G1 * rec[R_CG] + G2 * rec[R_CB];
@@ -1067,7 +1110,6 @@ __attribute__((amdgpu_waves_per_eu(PPX ? 3 : 4))) raster_backward_records_kernel
               const float gcs = f.w * ev.z;
               float gz = 0.f, zf = 0.f;
               if constexpr (CONS) {
-                const float4 ca = ph[1 + k * LW4 + LW4 - 2], cb = ph[1 + k * LW4 + LW4 - 1];
                 zf = frag_depth(rec, f);
                 const float dz = zf - ca.w;
                 gw += ca.x + ca.y * dz + ca.z * (dz * dz - cb.x);
@@ -1343,10 +1385,13 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             uint64_t& m = (M::QW > 1 && r >= 2) ? mq1 : mq0;
-            jr[r] = m ? (int)__builtin_ctzll(m) : -1;
-            m = uniform64(m & (m - 1));
+            jr[r] = sfirst(m);
+            m = sclear(m, jr[r]);
           }
-          const int jl = row == 0 ? jr[0] : (row == 1 ? jr[1] : (row == 2 ? jr[2] : jr[3]));
+          // the four record indices as 16-bit halves of two scalars; each lane takes its row's
+          const uint32_t p01 = spack16(jr[0], jr[1]), p23 = spack16(jr[2], jr[3]);
+          const uint32_t pw = (row & 2) ? p23 : p01;
+          const int jl = (int)(short)(pw >> ((row & 1) << 4));
           // idle rows read a valid record and contribute nothing
           float rec[kRecFloats];
           load_record(lds + 4 * (c0 + (jl < 0 ? 0 : jl)), rec);
@@ -1734,6 +1779,7 @@ hipError_t launch_raster_backward(const ViewDev* views, int n_views, int tile_be
     return hipErrorInvalidValue;
   const int n_items = sb.items ? (int)n_items_max : n_tiles;
   if (prm.bwd_walk != 1 && prm.bwd_walk != 2) return hipErrorInvalidValue;
+  if (prm.bwd_walk == 2 && !wb.ovf) return hipErrorInvalidValue;
   // The batch shrinks until the block's LDS fits (64 KiB record-major, 120 KiB
   // rows), but not below one 64-record chunk: the forward's walk masks are per
   // chunk of 64 list entries (per 32 when its batch was 32).
