@@ -480,15 +480,12 @@ raster_forward_kernel(
 // the covering fragments at each pixel (the same walk and tests as the
 // forward, nothing accumulated).  One block per split item.
 template <int TW, int TH, bool PPX>
-__global__ void __launch_bounds__(TW* TH) seg_zmax_kernel(const ViewDev* __restrict__ views, int n_views,
-                                                           const uint32_t* __restrict__ ranges,
-                                                           const uint32_t* __restrict__ vals,
-                                                           const float* __restrict__ recs, Params prm, int B,
-                                                           SegBufs sb) {
+__device__ __forceinline__ void seg_zmax_item(const ViewDev* __restrict__ views, int n_views,
+                                              const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
+                                              const float* __restrict__ recs, const Params& prm, int B,
+                                              const SegBufs& sb, int m) {
   extern __shared__ float4 lds[];
   constexpr int NT = TW * TH;
-  const int m = blockIdx.x;
-  if (m >= (int)*sb.n_mitems) return;
   const int4 it = sb.mitems[m];
   if (it.y == it.z - 1) return;  // nothing follows the last segment
   const int t = threadIdx.x, lane = t & 63;
@@ -526,19 +523,33 @@ __global__ void __launch_bounds__(TW* TH) seg_zmax_kernel(const ViewDev* __restr
   sb.Z[(long long)m * NT + t] = zm;
 }
 
+template <int TW, int TH, bool PPX>
+__global__ void __launch_bounds__(TW* TH) seg_zmax_kernel(const ViewDev* __restrict__ views, int n_views,
+                                                           const uint32_t* __restrict__ ranges,
+                                                           const uint32_t* __restrict__ vals,
+                                                           const float* __restrict__ recs, Params prm, int B,
+                                                           SegBufs sb, int cap) {
+  const int n = min((int)*sb.n_mitems, cap);
+  for (int m = blockIdx.x; m < n; m += gridDim.x) {
+    seg_zmax_item<TW, TH, PPX>(views, n_views, ranges, vals, recs, prm, B, sb, m);
+    __syncthreads();  // the item's LDS batches are reused by the next
+  }
+}
+
 // Step 2: per split tile and pixel, the running maximum over its segments.
 // One block per split item; the first segment's block does the tile.
 template <int NT>
-__global__ void __launch_bounds__(NT) seg_zin_kernel(SegBufs sb) {
-  const int m = blockIdx.x;
-  if (m >= (int)*sb.n_mitems) return;
-  const int4 it = sb.mitems[m];
-  if (it.y != 0) return;
-  const int t = threadIdx.x;
-  float z = 0.f;
-  for (int k = 0; k < it.z; ++k) {
-    sb.ZI[(long long)(m + k) * NT + t] = z;
-    if (k + 1 < it.z) z = fmaxf(z, sb.Z[(long long)(m + k) * NT + t]);
+__global__ void __launch_bounds__(NT) seg_zin_kernel(SegBufs sb, int cap) {
+  const int n = min((int)*sb.n_mitems, cap);
+  for (int m = blockIdx.x; m < n; m += gridDim.x) {
+    const int4 it = sb.mitems[m];
+    if (it.y != 0) continue;
+    const int t = threadIdx.x;
+    float z = 0.f;
+    for (int k = 0; k < it.z; ++k) {
+      sb.ZI[(long long)(m + k) * NT + t] = z;
+      if (k + 1 < it.z) z = fmaxf(z, sb.Z[(long long)(m + k) * NT + t]);
+    }
   }
 }
 
@@ -549,14 +560,12 @@ __global__ void __launch_bounds__(NT) seg_zin_kernel(SegBufs sb) {
 // and the early-out, the outputs and the backward's walk record exactly as
 // the unsplit forward writes them.
 template <int TW, int TH>
-__global__ void __launch_bounds__(TW* TH) seg_merge_kernel(
-    const ViewDev* __restrict__ views, int n_views, const uint32_t* __restrict__ ranges, Params prm,
+__device__ __forceinline__ void seg_merge_item(
+    const ViewDev* __restrict__ views, int n_views, const uint32_t* __restrict__ ranges, const Params& prm,
     float* __restrict__ image, float* __restrict__ alpha, uint8_t* __restrict__ nl_out,
     uint8_t* __restrict__ nl_int, float4* __restrict__ stats, const int* __restrict__ status,
-    unsigned long long* __restrict__ counters, uint32_t* __restrict__ lpos, SegBufs sb) {
+    unsigned long long* __restrict__ counters, uint32_t* __restrict__ lpos, const SegBufs& sb, int m0) {
   constexpr int NT = TW * TH;
-  const int m0 = blockIdx.x;
-  if (m0 >= (int)*sb.n_mitems) return;
   const int4 it = sb.mitems[m0];
   if (it.y != 0) return;
   const int t = threadIdx.x, lane = t & 63;
@@ -673,6 +682,18 @@ __global__ void __launch_bounds__(TW* TH) seg_merge_kernel(
       if (w != 0.f) atomicAdd(reinterpret_cast<double*>(counters + 3), (double)w);
     }
   }
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW* TH) seg_merge_kernel(
+    const ViewDev* __restrict__ views, int n_views, const uint32_t* __restrict__ ranges, Params prm,
+    float* __restrict__ image, float* __restrict__ alpha, uint8_t* __restrict__ nl_out,
+    uint8_t* __restrict__ nl_int, float4* __restrict__ stats, const int* __restrict__ status,
+    unsigned long long* __restrict__ counters, uint32_t* __restrict__ lpos, SegBufs sb, int cap) {
+  const int n = min((int)*sb.n_mitems, cap);
+  for (int m = blockIdx.x; m < n; m += gridDim.x)
+    seg_merge_item<TW, TH>(views, n_views, ranges, prm, image, alpha, nl_out, nl_int, stats, status, counters,
+                           lpos, sb, m);
 }
 
 // ---------------------------------------------------------------- backward
@@ -851,18 +872,14 @@ __host__ __device__ inline size_t bwd_lds_floats(int B, int nv, int lw) {
          (size_t)kBwdWaves * B / 4 + (size_t)kBwdWaves * 16 * (4 + kBwdTabLayers * lw);
 }
 
-// Scalar find-first-set of a wave-uniform mask (-1 when it is empty) and the
-// clearing of that bit, one scalar instruction each (a generic ctz adds a zero
-// test and a select, m & (m - 1) takes three 64-bit instructions); clearing
-// bit -1 of an empty mask (bit 63) leaves it empty.
-__device__ __forceinline__ int sfirst(uint64_t m) {
+// The first set bit of a wave-uniform mask (-1 when it is empty), cleared
+// from the mask: one scalar find-first-set and one bit clear (a generic ctz
+// adds a zero test and a select, m & (m - 1) takes three 64-bit instructions);
+// clearing bit -1 of an empty mask (bit 63) leaves it empty.
+__device__ __forceinline__ int stake(uint64_t& m) {
   int r;
-  asm("s_ff1_i32_b64 %0, %1" : "=s"(r) : "s"(m));
+  asm("s_ff1_i32_b64 %0, %1\n\ts_bitset0_b64 %1, %0" : "=&s"(r), "+s"(m));
   return r;
-}
-__device__ __forceinline__ uint64_t sclear(uint64_t m, int b) {
-  asm("s_bitset0_b64 %0, %1" : "+s"(m) : "s"(b));
-  return m;
 }
 // Two wave-uniform values as the low and high 16-bit halves of one scalar.
 __device__ __forceinline__ uint32_t spack16(int lo, int hi) {
@@ -1383,11 +1400,7 @@ __attribute__((amdgpu_waves_per_eu((SS || CONS || PPX) ? 4 : 5))) raster_backwar
           // row r takes copy r % R of quadrant r / R: the next R records of its mask
           int jr[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            uint64_t& m = (M::QW > 1 && r >= 2) ? mq1 : mq0;
-            jr[r] = sfirst(m);
-            m = sclear(m, jr[r]);
-          }
+          for (int r = 0; r < 4; ++r) jr[r] = stake((M::QW > 1 && r >= 2) ? mq1 : mq0);
           // the four record indices as 16-bit halves of two scalars; each lane takes its row's
           const uint32_t p01 = spack16(jr[0], jr[1]), p23 = spack16(jr[2], jr[3]);
           const uint32_t pw = (row & 2) ? p23 : p01;
@@ -1647,12 +1660,21 @@ static hipError_t fwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vi
   // split lists: the z_max carried into each segment first
   if (sb.items && nmi > 0) {
     if (prm.mip == 1)
-      hipLaunchKernelGGL((seg_zmax_kernel<TW, TH, true>), dim3((unsigned)nmi), dim3(TW * TH), lds, st, views, nv,
-                         ranges, vals, recs, prm, B, sb);
+      hipLaunchKernelGGL((seg_zmax_kernel<TW, TH, true>),
+                         dim3(persistent_grid(reinterpret_cast<const void*>(&seg_zmax_kernel<TW, TH, true>),
+                                              (int)nmi, TW * TH, lds, st)),
+                         dim3(TW * TH), lds, st, views, nv,
+                         ranges, vals, recs, prm, B, sb, (int)nmi);
     else
-      hipLaunchKernelGGL((seg_zmax_kernel<TW, TH, false>), dim3((unsigned)nmi), dim3(TW * TH), lds, st, views, nv,
-                         ranges, vals, recs, prm, B, sb);
-    hipLaunchKernelGGL((seg_zin_kernel<TW * TH>), dim3((unsigned)nmi), dim3(TW * TH), 0, st, sb);
+      hipLaunchKernelGGL((seg_zmax_kernel<TW, TH, false>),
+                         dim3(persistent_grid(reinterpret_cast<const void*>(&seg_zmax_kernel<TW, TH, false>),
+                                              (int)nmi, TW * TH, lds, st)),
+                         dim3(TW * TH), lds, st, views, nv,
+                         ranges, vals, recs, prm, B, sb, (int)nmi);
+    hipLaunchKernelGGL((seg_zin_kernel<TW * TH>),
+                       dim3(persistent_grid(reinterpret_cast<const void*>(&seg_zin_kernel<TW * TH>), (int)nmi,
+                                            TW * TH, 0, st)),
+                       dim3(TW * TH), 0, st, sb, (int)nmi);
   }
 #define SS_FWD_V(CV, PV)                                                                                   \
   do {                                                                                                      \
@@ -1672,8 +1694,11 @@ static hipError_t fwd_t(dim3 grid, size_t lds, hipStream_t st, const ViewDev* vi
   }
 #undef SS_FWD_V
   if (sb.items && nmi > 0)
-    hipLaunchKernelGGL((seg_merge_kernel<TW, TH>), dim3((unsigned)nmi), dim3(TW * TH), 0, st, views, nv, ranges,
-                       prm, image, alpha, nlo, nli, stats, status, counters, wb.pos, sb);
+    hipLaunchKernelGGL((seg_merge_kernel<TW, TH>),
+                       dim3(persistent_grid(reinterpret_cast<const void*>(&seg_merge_kernel<TW, TH>), (int)nmi,
+                                            TW * TH, 0, st)),
+                       dim3(TW * TH), 0, st, views, nv, ranges,
+                       prm, image, alpha, nlo, nli, stats, status, counters, wb.pos, sb, (int)nmi);
   return hipGetLastError();
 }
 
