@@ -16,7 +16,7 @@ constexpr int kMaxLayers = 16;
 // projected centre, s = 1 + a3 dx + b3 dy and Q = (M M^T + sigma_f I)^{-1}
 // (M = d(x,y)/d(u,v) at the centre), rho^2_mip = d^T Q d / s^2.
 enum RecField {
-  R_X0 = 0 /* x0 - i_lo */, R_Y0 /* y0 - j_lo */, R_QXX, R_QXY2 /* 2 Q_xy */, R_QYY, R_A3, R_B3, R_NF,
+  R_X0 = 0 /* x0 - (i_lo + 1/2) */, R_Y0 /* y0 - (j_lo + 1/2) */, R_QXX, R_QXY2 /* 2 Q_xy */, R_QYY, R_A3, R_B3, R_NF,
   R_ZE, R_CR, R_CG, R_CB, R_RX /* i_lo | i_hi << 16 */, R_RY /* j_lo | j_hi << 16 */,
   R_ZS, R_ID /* record index, as bits */
 };
@@ -245,22 +245,29 @@ __device__ inline void bin_geometry(const float p[3], const float n[3], const fl
 // Evaluation of one record at one pixel, shared by the forward and backward
 // raster kernels so that both take identical cutoff decisions: explicit fmaf
 // and a fixed order, independent of the surrounding code.
+// exp(-q/2) as __expf forms it (the hardware exp2 of its argument times the
+// float log2 e), with the two constant factors folded into one: -q/2 and the
+// halved constant are exact, so the rounded product, and the result, are the same.
+__device__ __forceinline__ float exp_neg_half(float q) {
+  return __builtin_amdgcn_exp2f(q * -0.721347510814666748046875f);
+}
+
 struct FragEval {
   float dx, dy, s, N, q, w, e;  // e = exp(-q/2), so w = n_f e
   bool cov;
 };
 __device__ __forceinline__ void frag_eval(const float* rec, int px, int py, float r2, FragEval& f) {
-  // R_X0/R_Y0 hold the centre relative to the rectangle's integer corner
+  // R_X0/R_Y0 hold the centre relative to the rectangle's first pixel centre
   const int il = __float_as_int(rec[R_RX]) & 0xffff, jl = __float_as_int(rec[R_RY]) & 0xffff;
-  f.dx = ((float)(px - il) + 0.5f) - rec[R_X0];
-  f.dy = ((float)(py - jl) + 0.5f) - rec[R_Y0];
+  f.dx = (float)(px - il) - rec[R_X0];
+  f.dy = (float)(py - jl) - rec[R_Y0];
   f.s = __builtin_fmaf(rec[R_A3], f.dx, __builtin_fmaf(rec[R_B3], f.dy, 1.0f));
   float t = __builtin_fmaf(rec[R_QXX], f.dx, rec[R_QXY2] * f.dy);
   f.N = __builtin_fmaf(t, f.dx, (rec[R_QYY] * f.dy) * f.dy);
   float s2 = f.s * f.s;
   f.cov = f.N < r2 * s2;
   f.q = f.N * __builtin_amdgcn_rcpf(s2);
-  f.e = __expf(-0.5f * f.q);
+  f.e = exp_neg_half(f.q);
   f.w = rec[R_NF] * f.e;
 }
 
@@ -276,8 +283,8 @@ __device__ __forceinline__ void frag_eval_pp(const float* rec, int px, int py, f
                                              FragEval& f) {
   const int rx = __float_as_int(rec[R_RX]), ry = __float_as_int(rec[R_RY]);
   const int il = rx & 0xffff, ih = rx >> 16, jl = ry & 0xffff, jh = ry >> 16;
-  f.dx = ((float)(px - il) + 0.5f) - rec[R_X0];
-  f.dy = ((float)(py - jl) + 0.5f) - rec[R_Y0];
+  f.dx = (float)(px - il) - rec[R_X0];
+  f.dy = (float)(py - jl) - rec[R_Y0];
   const float a3 = rec[R_A3], b3 = rec[R_B3];
   f.s = __builtin_fmaf(a3, f.dx, __builtin_fmaf(b3, f.dy, 1.0f));
   const float qxx = rec[R_QXX], qxy = 0.5f * rec[R_QXY2], qyy = rec[R_QYY];
@@ -297,7 +304,7 @@ __device__ __forceinline__ void frag_eval_pp(const float* rec, int px, int py, f
   const float idetS = 1.f / detS;  // one division for both uses
   f.q = f.N * idetS;
   const float nfc = rec[R_NF];
-  f.e = __expf(-0.5f * f.q);
+  f.e = exp_neg_half(f.q);
   f.w = sqrtf(s2 * s2 * s2 * nfc * nfc * iq * idetS) * f.e;
 }
 
@@ -313,8 +320,8 @@ __device__ __forceinline__ void frag_eval_pp(const float* rec, int px, int py, f
 __device__ inline void frag_grad_pp(const float* rec, int px, int py, float sigma, float G, bool live,
                                     float* g) {
   const int il = __float_as_int(rec[R_RX]) & 0xffff, jl = __float_as_int(rec[R_RY]) & 0xffff;
-  const float dx = live ? ((float)(px - il) + 0.5f) - rec[R_X0] : 0.f;
-  const float dy = live ? ((float)(py - jl) + 0.5f) - rec[R_Y0] : 0.f;
+  const float dx = live ? (float)(px - il) - rec[R_X0] : 0.f;
+  const float dy = live ? (float)(py - jl) - rec[R_Y0] : 0.f;
   const float a3 = rec[R_A3], b3 = rec[R_B3];
   const float s = __builtin_fmaf(a3, dx, __builtin_fmaf(b3, dy, 1.0f));
   const float qxx = rec[R_QXX], qxy = 0.5f * rec[R_QXY2], qyy = rec[R_QYY];

@@ -613,8 +613,9 @@ __device__ inline void raster_geometry_f64(const float pf[3], const float nf_[3]
   const double detA = dm * dm;
   const double K11 = M11 * M11 + M12 * M12, K12 = M11 * M21 + M12 * M22, K22 = M21 * M21 + M22 * M22;
   const double detB = detA + sigma * (K11 + K22) + sigma * sigma;
-  out.x0r = (float)(x0 - (double)il);
-  out.y0r = (float)(y0 - (double)jl);
+  // the centre relative to the first pixel centre of the rectangle, rounded once
+  out.x0r = (float)(x0 - ((double)il + 0.5));
+  out.y0r = (float)(y0 - ((double)jl + 0.5));
   const double ib = 1.0 / detB, idm = 1.0 / dm;
   out.Qxx = (float)((K22 + sigma) * ib);
   out.Qxy2 = (float)(-2.0 * K12 * ib);

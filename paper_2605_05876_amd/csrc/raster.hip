@@ -95,8 +95,8 @@ template <int S>
 __device__ __forceinline__ bool ellipse_meets(const float4 q0, const float4 q1, const float4 q3,
                                               int bx, int by, float r2) {
   const int il = __float_as_int(q3.x) & 0xffff, jl = __float_as_int(q3.y) & 0xffff;
-  const float x0 = (float)(bx - il) + 0.5f - q0.x, x1 = x0 + (float)(S - 1);
-  const float y0 = (float)(by - jl) + 0.5f - q0.y, y1 = y0 + (float)(S - 1);
+  const float x0 = (float)(bx - il) - q0.x, x1 = x0 + (float)(S - 1);
+  const float y0 = (float)(by - jl) - q0.y, y1 = y0 + (float)(S - 1);
   const float qxx = q0.z, qxy = 0.5f * q0.w, qyy = q1.x, a3 = q1.y, b3 = q1.z;
   const float s00 = 1.f + a3 * x0 + b3 * y0, s01 = 1.f + a3 * x0 + b3 * y1;
   const float s10 = 1.f + a3 * x1 + b3 * y0, s11 = 1.f + a3 * x1 + b3 * y1;
@@ -1063,7 +1063,7 @@ __attribute__((amdgpu_waves_per_eu((PPX || SS) ? 3 : 4))) raster_backward_record
         // are read one pixel ahead, so the LDS latency overlaps the arithmetic
         float4 hd = wtab[0], l0 = wtab[1];
         for (int r = 0; r < 4; ++r) {
-          const float dyr = ((float)(qy0 + r - jl) + 0.5f) - rec[R_Y0];
+          const float dyr = (float)(qy0 + r - jl) - rec[R_Y0];
           const float sb = __builtin_fmaf(b3, dyr, 1.0f), tq = qxy2 * dyr, nq = (qyy * dyr) * dyr;
           for (int c = 0; c < 4; ++c) {
             const float4* const ph = wtab + (4 * r + c) * pstride;
@@ -1077,14 +1077,14 @@ __attribute__((amdgpu_waves_per_eu((PPX || SS) ? 3 : 4))) raster_backward_record
               frag_eval_pp(rec, qx0 + c, qy0 + r, r2, prm.sigma_f, f);
             } else {
               // frag_eval's arithmetic, with the row's terms shared
-              f.dx = ((float)(qx0 + c - il) + 0.5f) - rec[R_X0];
+              f.dx = (float)(qx0 + c - il) - rec[R_X0];
               f.dy = dyr;
               f.s = __builtin_fmaf(a3, f.dx, sb);
               f.N = __builtin_fmaf(__builtin_fmaf(qxx, f.dx, tq), f.dx, nq);
               const float s2 = f.s * f.s;
               f.cov = f.N < r2 * s2;
               f.q = f.N * __builtin_amdgcn_rcpf(s2);
-              f.e = __expf(-0.5f * f.q);
+              f.e = exp_neg_half(f.q);
               f.w = rec[R_NF] * f.e;
             }
             if (__ballot(act && f.cov) == 0ull) continue;
