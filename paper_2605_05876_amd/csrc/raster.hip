@@ -276,11 +276,16 @@ __device__ __forceinline__ void forward_item(
       nE += inside ? (unsigned)__popcll(m) : 0u;
       // the records of the chunk this pixel accumulated; OR-ed over each row of
       // 16 lanes (a 4 x 4 quadrant) they are the backward's walk lists
+      // (the two halves of 32 records in turn, so that a step sets its bit in
+      // one 32-bit mask)
       uint32_t lm0 = 0u, lm1 = 0u;
-      while (m) {
-        const int b = __builtin_ctzll(m);
-        const uint64_t bit = 1ull << b;  // the record's bit in the chunk
-        m ^= bit;
+#pragma unroll 1
+      for (int h = 0; h < 2; ++h) {
+      uint32_t mh = (uint32_t)(m >> (32 * h)), lm = 0u;
+      while (mh) {
+        const int b = 32 * h + __builtin_ctz(mh);
+        const uint32_t bit = 1u << (b & 31);  // the record's bit in its half
+        mh ^= bit;
         const int j = c0 + b;
         float rec[kRecFloats];
         load_record<true>(lds + 4 * j, rec);
@@ -347,9 +352,9 @@ __device__ __forceinline__ void forward_item(
               if (lstart == 0xffffffffu) sb.S[mlayS + (long long)Kl * NT] = (uint16_t)(b0 + (uint32_t)j - seg_lo);
               ++nFl;
             }
-            lstart = lstart == 0xffffffffu ? b0 + (uint32_t)j : lstart;
-            lm0 |= (uint32_t)bit;
-            lm1 |= (uint32_t)(bit >> 32);
+            // positions increase along the walk and lstart restarts at ~0u per layer
+            lstart = min(lstart, b0 + (uint32_t)j);
+            lm |= bit;
             if constexpr (CONS) {
               const float z = frag_depth(rec, f);
               if (Wg == 0.f) zr = z;
@@ -357,15 +362,20 @@ __device__ __forceinline__ void forward_item(
               S1 += f.w * dz;
               S2 += f.w * dz * dz;
             }
-            zmax = rec[R_ZE] > zmax ? rec[R_ZE] : zmax;  // (fmaxf would canonicalise both)
+            // depths are positive, so their bit patterns order like the values
+            // (one integer max; fmaxf would also canonicalise both operands)
+            zmax = __uint_as_float(max(__float_as_uint(rec[R_ZE]), __float_as_uint(zmax)));
             C0 += f.w * rec[R_CR];
             C1 += f.w * rec[R_CG];
             C2 += f.w * rec[R_CB];
             Wg += f.w;
-            ++nF;
           }
         }
       }
+      if (h == 0) lm0 = lm; else lm1 = lm;
+      }
+      // one bit per fragment this pixel accumulated
+      if (prm.counters) nF += __popc(lm0) + __popc(lm1);
       lm0 = row_or(lm0);
       lm1 = row_or(lm1);
       if ((lane & 15) == 0) qrow[(long long)((b0 + (uint32_t)c0 - start) >> 5) * NQ] = ((uint64_t)lm1 << 32) | lm0;
