@@ -279,16 +279,14 @@ __device__ __forceinline__ void forward_item(
       // (the two halves of 32 records in turn, so that a step sets its bit in
       // one 32-bit mask)
       uint32_t lm0 = 0u, lm1 = 0u;
-#pragma unroll 1
-      for (int h = 0; h < 2; ++h) {
-      uint32_t mh = (uint32_t)(m >> (32 * h)), lm = 0u;
-      while (mh) {
-        const int b = 32 * h + __builtin_ctz(mh);
+      // one record of the chunk at this pixel: its four 16-byte parts, its index
+      // b in the chunk, and the mask of its half that records the accumulation
+      auto step = [&](const float4 q0, const float4 q1, const float4 q2, const float4 q3, const int b,
+                      uint32_t& lm) {
         const uint32_t bit = 1u << (b & 31);  // the record's bit in its half
-        mh ^= bit;
         const int j = c0 + b;
-        float rec[kRecFloats];
-        load_record<true>(lds + 4 * j, rec);
+        const float rec[kRecFloats] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                                       q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
         FragEval f;
         if constexpr (PPX)
           frag_eval_pp(rec, px, py, r2l, prm.sigma_f, f);
@@ -371,8 +369,35 @@ __device__ __forceinline__ void forward_item(
             Wg += f.w;
           }
         }
-      }
-      if (h == 0) lm0 = lm; else lm1 = lm;
+      };
+#pragma unroll 1
+      for (int h = 0; h < 2; ++h) {
+        uint32_t mh = (uint32_t)(m >> (32 * h)), lm = 0u;
+        const float4* const lh = lds + 4 * (c0 + 32 * h);
+        // two record buffers: the next record's LDS reads are issued before the
+        // current one is evaluated, so their latency overlaps the step.  The reads
+        // are unconditional (the last step of a half reads its own record again),
+        // which keeps the wait for the current record from also waiting for them.
+        if (mh) {
+          int ba = __builtin_ctz(mh);
+          mh &= mh - 1u;
+          float4 a0 = lh[4 * ba], a1 = lh[4 * ba + 1], a2 = lh[4 * ba + 2], a3 = lh[4 * ba + 3];
+          for (;;) {
+            const bool more = mh != 0u;
+            const int bn = more ? __builtin_ctz(mh) : ba;
+            mh &= mh - 1u;
+            const float4 n0 = lh[4 * bn], n1 = lh[4 * bn + 1], n2 = lh[4 * bn + 2], n3 = lh[4 * bn + 3];
+            step(a0, a1, a2, a3, 32 * h + ba, lm);
+            if (!more) break;
+            const bool more2 = mh != 0u;
+            ba = more2 ? __builtin_ctz(mh) : bn;
+            mh &= mh - 1u;
+            a0 = lh[4 * ba]; a1 = lh[4 * ba + 1]; a2 = lh[4 * ba + 2]; a3 = lh[4 * ba + 3];
+            step(n0, n1, n2, n3, 32 * h + bn, lm);
+            if (!more2) break;
+          }
+        }
+        if (h == 0) lm0 = lm; else lm1 = lm;
       }
       // one bit per fragment this pixel accumulated
       if (prm.counters) nF += __popc(lm0) + __popc(lm1);
@@ -450,13 +475,13 @@ __device__ __forceinline__ void forward_item(
   }
 }
 
-// Occupancy target of the plain variant: 7 waves per SIMD (at most 72 VGPRs,
-// as the plain walk alone) for 8 x 8 tiles, 6 for the larger ones (which spill
-// at 72); the compiler's choice for the variants with statistics or the
-// per-pixel filter.
+// Occupancy target of the plain variant: 5 waves per SIMD (at most 102 VGPRs:
+// the walk holds two staged records; the LDS batches limit a CU to about 5
+// waves per SIMD anyway); the compiler's choice for the variants with
+// statistics or the per-pixel filter.
 template <int TW, int TH, bool CONS, bool PPX>
 __global__ void __launch_bounds__(TW* TH)
-__attribute__((amdgpu_waves_per_eu((CONS || PPX) ? 1 : (TW * TH > 64 ? 6 : 7))))
+__attribute__((amdgpu_waves_per_eu((CONS || PPX) ? 1 : 5)))
 raster_forward_kernel(
     const ViewDev* __restrict__ views, int n_views, int tile_begin, int n_items,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
