@@ -572,9 +572,10 @@ __device__ inline void raster_geometry(const Geo& o, float sigma, RasterGeo& r) 
 }
 
 // The raster parameters above evaluated in FP64 from the FP32 inputs and
-// rounded once.  The projected centre is stored relative to the integer corner
-// of the pixel rectangle (a few pixels at most), so the pixel offset d that the
-// raster forms is accurate to ~1e-7 px instead of the ~1e-4 px an FP32 centre
+// rounded once.  The projected centre is stored relative to the centre of the
+// pixel rectangle's first pixel (its integer corner + 1/2, a few pixels at
+// most), so the pixel offset d that the raster forms (one integer difference and
+// one subtraction) is accurate to ~1e-7 px instead of the ~1e-4 px an FP32 centre
 // near x = 1000 px would carry; thin (edge-on) ellipses amplify that error.
 struct RasterGeoF {
   float x0r, y0r, Qxx, Qxy2, Qyy, a3, b3, nf;
