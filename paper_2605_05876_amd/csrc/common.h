@@ -393,7 +393,7 @@ hipError_t launch_count_nonfinite(const float* p, long long n, unsigned long lon
 hipError_t launch_envmap_dirs(float* dirs, int H, int W, hipStream_t st);
 hipError_t launch_envmap_out_dirs(int He, int We, const float* in_dirs, const int lh[7],
                                   const int lw[7], float* out_dirs, hipStream_t st);
-constexpr int kEnvChunksMax = 32;  // input chunks of the environment prefilter
+constexpr int kEnvChunksMax = 64;  // input chunks of the environment prefilter
 int envmap_prefilter_chunks(int He, int We);
 // part: scratch of envmap_prefilter_chunks(He, We) x (texels of levels 1..6) x 3 floats
 hipError_t launch_envmap_prefilter(const float* E, int He, int We, const float* in_dirs,

@@ -210,10 +210,10 @@ hipError_t launch_envmap_out_dirs(int He, int We, const float* in_dirs, const in
 }
 
 int envmap_prefilter_chunks(int He, int We) {
-  // input chunks of at least 1024 texels: a 128 x 256 map gives 32 chunks, so
-  // the launch has about 6 waves per SIMD to hide its staging barriers
+  // input chunks of at least 512 texels: a 128 x 256 map gives 64 chunks, so
+  // the launch has about 13 waves per SIMD to hide its staging barriers
   const int nt = He * We;
-  int c = (nt + 1023) / 1024;
+  int c = (nt + 511) / 512;
   return c < 1 ? 1 : (c > kEnvChunksMax ? kEnvChunksMax : c);
 }
 
