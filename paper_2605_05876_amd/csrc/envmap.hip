@@ -251,9 +251,12 @@ __global__ void __launch_bounds__(256) envmap_adjoint_kernel(DLevelSet L, int nt
                                                              float* __restrict__ dE, int chunk,
                                                              float* __restrict__ part) {
   __shared__ float4 sR[256], sG[256];
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = t < nt;
-  const float4 dt = live ? dirs[t] : make_float4(0.f, 0.f, 1.f, 0.f);
+  // two input texels per thread, 256 apart, so that each staged output texel
+  // read from LDS serves two evaluations
+  const int t0 = blockIdx.x * 512 + threadIdx.x, t1 = t0 + 256;
+  const bool live0 = t0 < nt, live1 = t1 < nt;
+  const float4 d0 = live0 ? dirs[t0] : make_float4(0.f, 0.f, 1.f, 0.f);
+  const float4 d1 = live1 ? dirs[t1] : make_float4(0.f, 0.f, 1.f, 0.f);
   const int o_begin = blockIdx.y * chunk, o_end = min(o_begin + chunk, L.first[7]);
   // Latitude bands of the block's input texels and of the chunk's output texels
   // (texel-centre angles; rows are monotone within a level).  When they are
@@ -262,7 +265,7 @@ __global__ void __launch_bounds__(256) envmap_adjoint_kernel(DLevelSet L, int nt
   bool skip;
   {
     const int He = L.h[0], We = L.w[0];
-    const int ta = blockIdx.x * blockDim.x, tb = min(ta + (int)blockDim.x, nt) - 1;
+    const int ta = blockIdx.x * 512, tb = min(ta + 512, nt) - 1;
     const float ia = kPi * ((float)(ta / We) + 0.5f) / (float)He, ib = kPi * ((float)(tb / We) + 0.5f) / (float)He;
     float oa = 4.f, ob = -1.f;
     for (int lv = level_of(L.first, o_begin); lv <= 6 && L.first[lv] < o_end; ++lv) {
@@ -273,9 +276,9 @@ __global__ void __launch_bounds__(256) envmap_adjoint_kernel(DLevelSet L, int nt
     skip = fmaxf(ia - ob, oa - ib) > 0.5f * kPi + 1e-3f;
   }
   // Stage the chunk's output texels through LDS (direction and 1/Z; gradient
-  // and the GGX constant); the loops below then reads them as
-  // broadcasts, four texels' reads issued together, instead of a chain of
-  // dependent scalar loads per output texel.
+  // and the GGX constant); the loops below then read them as broadcasts, four
+  // texels' reads issued together, instead of a chain of dependent scalar
+  // loads per output texel.
   if (!skip) {
     const int o = o_begin + (int)threadIdx.x;
     if (o < o_end) {
@@ -290,7 +293,7 @@ __global__ void __launch_bounds__(256) envmap_adjoint_kernel(DLevelSet L, int nt
     }
   }
   __syncthreads();
-  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+  float a00 = 0.f, a01 = 0.f, a02 = 0.f, a10 = 0.f, a11 = 0.f, a12 = 0.f;
   if (!skip) {
     // the specular levels come first in the flattened output order, the
     // irradiance level last; weights are exactly 0 for c <= 0 through max(c, 0)
@@ -299,38 +302,43 @@ __global__ void __launch_bounds__(256) envmap_adjoint_kernel(DLevelSet L, int nt
 #pragma unroll 4
     for (int i = 0; i < i6; ++i) {
       const float4 R = sR[i], G = sG[i];
-      const float c = fmaxf(R.x * dt.x + R.y * dt.y + R.z * dt.z, 0.f);
-      const float kk = ggx_scaled(c, G.w) * dt.w * R.w;
-      acc0 += G.x * kk;
-      acc1 += G.y * kk;
-      acc2 += G.z * kk;
+      const float c0 = fmaxf(R.x * d0.x + R.y * d0.y + R.z * d0.z, 0.f);
+      const float c1 = fmaxf(R.x * d1.x + R.y * d1.y + R.z * d1.z, 0.f);
+      const float k0 = ggx_scaled(c0, G.w) * d0.w * R.w, k1 = ggx_scaled(c1, G.w) * d1.w * R.w;
+      a00 += G.x * k0; a01 += G.y * k0; a02 += G.z * k0;
+      a10 += G.x * k1; a11 += G.y * k1; a12 += G.z * k1;
     }
 #pragma unroll 4
     for (int i = i6; i < n; ++i) {
       const float4 R = sR[i], G = sG[i];
-      const float c = fmaxf(R.x * dt.x + R.y * dt.y + R.z * dt.z, 0.f);
-      const float kk = c * dt.w * R.w;
-      acc0 += G.x * kk;
-      acc1 += G.y * kk;
-      acc2 += G.z * kk;
+      const float c0 = fmaxf(R.x * d0.x + R.y * d0.y + R.z * d0.z, 0.f);
+      const float c1 = fmaxf(R.x * d1.x + R.y * d1.y + R.z * d1.z, 0.f);
+      const float k0 = c0 * d0.w * R.w, k1 = c1 * d1.w * R.w;
+      a00 += G.x * k0; a01 += G.y * k0; a02 += G.z * k0;
+      a10 += G.x * k1; a11 += G.y * k1; a12 += G.z * k1;
     }
   }
-  if (!live) return;
-  if (blockIdx.y == 0) {
-    acc0 += L.g[0][3 * t];
-    acc1 += L.g[0][3 * t + 1];
-    acc2 += L.g[0][3 * t + 2];
-  }
-  if (part) {  // deterministic: the chunk's partial sums, added in chunk order afterwards
-    float* p = part + ((long long)blockIdx.y * nt + t) * 3;
-    p[0] = acc0;
-    p[1] = acc1;
-    p[2] = acc2;
-    return;
-  }
-  atomicAdd(dE + 3 * t, acc0);
-  atomicAdd(dE + 3 * t + 1, acc1);
-  atomicAdd(dE + 3 * t + 2, acc2);
+  // each texel's sums: the first chunk adds the direct level-0 term; then the
+  // chunk's partials (deterministic, added in chunk order afterwards) or atomics
+  auto put = [&](int t, float acc0, float acc1, float acc2) {
+    if (blockIdx.y == 0) {
+      acc0 += L.g[0][3 * t];
+      acc1 += L.g[0][3 * t + 1];
+      acc2 += L.g[0][3 * t + 2];
+    }
+    if (part) {
+      float* p = part + ((long long)blockIdx.y * nt + t) * 3;
+      p[0] = acc0;
+      p[1] = acc1;
+      p[2] = acc2;
+      return;
+    }
+    atomicAdd(dE + 3 * t, acc0);
+    atomicAdd(dE + 3 * t + 1, acc1);
+    atomicAdd(dE + 3 * t + 2, acc2);
+  };
+  if (live0) put(t0, a00, a01, a02);
+  if (live1) put(t1, a10, a11, a12);
 }
 
 __global__ void envmap_adjoint_reduce_kernel(const float* __restrict__ part, int n, int nchunk, float* __restrict__ dE) {
@@ -357,7 +365,7 @@ hipError_t launch_envmap_adjoint(const float* const dlvl[7], const int lh[7], co
   if (e != hipSuccess) return e;
   const int chunk = 256;
   const int nchunk = (L.first[7] + chunk - 1) / chunk;
-  hipLaunchKernelGGL(envmap_adjoint_kernel, dim3((nt + 255) / 256, nchunk), dim3(256), 0, st, L, nt,
+  hipLaunchKernelGGL(envmap_adjoint_kernel, dim3((nt + 511) / 512, nchunk), dim3(256), 0, st, L, nt,
                      reinterpret_cast<const float4*>(in_dirs),
                      reinterpret_cast<const float4*>(out_dirs), dE, chunk, part);
   e = hipGetLastError();
