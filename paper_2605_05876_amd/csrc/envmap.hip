@@ -98,10 +98,10 @@ __global__ void __launch_bounds__(256) envmap_out_dirs_kernel(int nt, const floa
   if (threadIdx.x == 0) out_dirs[o] = make_float4(R[0], R[1], R[2], l < 6 ? 1.f / red[0] : 1.f / kPi);
 }
 
-// Prefilter, stage 1.  Block (x, y): 256 consecutive output texels of levels
-// 1..6 (one per thread) against input chunk y.  The chunk's texels are staged
+// Prefilter, stage 1.  Block (x, y): 512 consecutive output texels of levels
+// 1..6 (two per thread) against input chunk y.  The chunk's texels are staged
 // through LDS 256 at a time (every thread then reads the same entry: a
-// broadcast), so each input texel is fetched once per 256 outputs instead of
+// broadcast), so each input texel is fetched once per 512 outputs instead of
 // once per output.  A staged batch whose latitude band lies beyond the
 // hemisphere of every output direction of the wave (angular distance above
 // pi/2 + 1e-3, so the cosine is clearly negative in FP32) adds nothing and is
@@ -114,22 +114,24 @@ __global__ void __launch_bounds__(256) envmap_prefilter_kernel(const float* __re
   __shared__ float4 sd[256];
   __shared__ float4 se[256];  // (E, -): one 16-byte broadcast read per input texel
   const int nt = He * We;
-  const int o = blockIdx.x * 256 + threadIdx.x;
-  const bool live = o < n_out;
-  const int oo = live ? o : n_out - 1;
-  const int l = level_of(L.first, oo);
-  const float4 R = out_dirs[oo];
-  const float alpha = (float)(l * l) / 25.f;
-  const float thR = acosf(fminf(fmaxf(R.z, -1.f), 1.f));
+  // two output texels per thread, 256 apart, so that each staged input texel
+  // read from LDS serves two of them
+  const int oA = blockIdx.x * 512 + threadIdx.x, oB = oA + 256;
+  const bool liveA = oA < n_out, liveB = oB < n_out;
+  const int ooA = liveA ? oA : n_out - 1, ooB = liveB ? oB : n_out - 1;
+  const int lA = level_of(L.first, ooA), lB = level_of(L.first, ooB);
+  const float4 RA = out_dirs[ooA], RB = out_dirs[ooB];
+  const float alA = (float)(lA * lA) / 25.f, alB = (float)(lB * lB) / 25.f;
+  const float thA = acosf(fminf(fmaxf(RA.z, -1.f), 1.f)), thB = acosf(fminf(fmaxf(RB.z, -1.f), 1.f));
   const int t0 = blockIdx.y * chunk, t1 = min(t0 + chunk, nt);
-  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, b0 = 0.f, b1 = 0.f, b2 = 0.f;
   for (int tb = t0; tb < t1; tb += 256) {
     const int n = min(256, t1 - tb);
     // latitude band of the batch (texel-centre angles of its first and last rows)
     const float tha = kPi * ((float)(tb / We) + 0.5f) / (float)He;
     const float thb = kPi * ((float)((tb + n - 1) / We) + 0.5f) / (float)He;
-    const float gap = fmaxf(fmaxf(tha - thR, thR - thb), 0.f);
-    const bool skip = __ballot(!(gap > 0.5f * kPi + 1e-3f)) == 0ull;
+    const float gapA = fmaxf(fmaxf(tha - thA, thA - thb), 0.f), gapB = fmaxf(fmaxf(tha - thB, thB - thb), 0.f);
+    const bool skip = __ballot(!(gapA > 0.5f * kPi + 1e-3f) || !(gapB > 0.5f * kPi + 1e-3f)) == 0ull;
     __syncthreads();
     if (threadIdx.x < n) {
       const int t = tb + threadIdx.x;
@@ -138,37 +140,55 @@ __global__ void __launch_bounds__(256) envmap_prefilter_kernel(const float* __re
     }
     __syncthreads();
     if (skip) continue;
-    // texels behind the output direction (c <= 0) get weight exactly 0 through
+    // texels behind an output direction (c <= 0) get weight exactly 0 through
     // max(c, 0) (both weights carry a factor c), with no select or branch:
     // lanes of a wave face different ways, and a branch let the compiler sink
     // part of the staged reads into it and wait for LDS once per texel
-    if (l == 6) {
+    if (lA == 6 && lB == 6) {
 #pragma unroll 4
       for (int i = 0; i < n; ++i) {
         const float4 d = sd[i], e = se[i];
-        const float c = fmaxf(R.x * d.x + R.y * d.y + R.z * d.z, 0.f);
-        const float kk = c * d.w;
-        acc0 += e.x * kk;
-        acc1 += e.y * kk;
-        acc2 += e.z * kk;
+        const float cA = fmaxf(RA.x * d.x + RA.y * d.y + RA.z * d.z, 0.f);
+        const float cB = fmaxf(RB.x * d.x + RB.y * d.y + RB.z * d.z, 0.f);
+        const float kA = cA * d.w, kB = cB * d.w;
+        a0 += e.x * kA; a1 += e.y * kA; a2 += e.z * kA;
+        b0 += e.x * kB; b1 += e.y * kB; b2 += e.z * kB;
+      }
+    } else if (lA < 6 && lB < 6) {
+#pragma unroll 4
+      for (int i = 0; i < n; ++i) {
+        const float4 d = sd[i], e = se[i];
+        const float cA = fmaxf(RA.x * d.x + RA.y * d.y + RA.z * d.z, 0.f);
+        const float cB = fmaxf(RB.x * d.x + RB.y * d.y + RB.z * d.z, 0.f);
+        const float kA = ggx_weight(cA, alA) * d.w, kB = ggx_weight(cB, alB) * d.w;
+        a0 += e.x * kA; a1 += e.y * kA; a2 += e.z * kA;
+        b0 += e.x * kB; b1 += e.y * kB; b2 += e.z * kB;
       }
     } else {
-#pragma unroll 4
+      // a thread whose two texels straddle the last specular level and the
+      // irradiance level
       for (int i = 0; i < n; ++i) {
         const float4 d = sd[i], e = se[i];
-        const float c = fmaxf(R.x * d.x + R.y * d.y + R.z * d.z, 0.f);
-        const float kk = ggx_weight(c, alpha) * d.w;
-        acc0 += e.x * kk;
-        acc1 += e.y * kk;
-        acc2 += e.z * kk;
+        const float cA = fmaxf(RA.x * d.x + RA.y * d.y + RA.z * d.z, 0.f);
+        const float cB = fmaxf(RB.x * d.x + RB.y * d.y + RB.z * d.z, 0.f);
+        const float kA = (lA == 6 ? cA : ggx_weight(cA, alA)) * d.w;
+        const float kB = (lB == 6 ? cB : ggx_weight(cB, alB)) * d.w;
+        a0 += e.x * kA; a1 += e.y * kA; a2 += e.z * kA;
+        b0 += e.x * kB; b1 += e.y * kB; b2 += e.z * kB;
       }
     }
   }
-  if (live) {
-    float* dst = part + ((long long)blockIdx.y * n_out + o) * 3;
-    dst[0] = acc0;
-    dst[1] = acc1;
-    dst[2] = acc2;
+  if (liveA) {
+    float* dst = part + ((long long)blockIdx.y * n_out + oA) * 3;
+    dst[0] = a0;
+    dst[1] = a1;
+    dst[2] = a2;
+  }
+  if (liveB) {
+    float* dst = part + ((long long)blockIdx.y * n_out + oB) * 3;
+    dst[0] = b0;
+    dst[1] = b1;
+    dst[2] = b2;
   }
 }
 
@@ -224,7 +244,7 @@ hipError_t launch_envmap_prefilter(const float* E, int He, int We, const float* 
   const int n_out = L.first[7], nt = He * We;
   const int nc = envmap_prefilter_chunks(He, We);
   const int chunk = ((nt + nc - 1) / nc + 255) / 256 * 256;
-  hipLaunchKernelGGL(envmap_prefilter_kernel, dim3((n_out + 255) / 256, nc), dim3(256), 0, st, E, He, We, chunk,
+  hipLaunchKernelGGL(envmap_prefilter_kernel, dim3((n_out + 511) / 512, nc), dim3(256), 0, st, E, He, We, chunk,
                      reinterpret_cast<const float4*>(in_dirs),
                      reinterpret_cast<const float4*>(out_dirs), n_out, L, part);
   hipError_t e = hipGetLastError();
