@@ -337,6 +337,16 @@ ss_status ss_debug_binning(ss_context* ctx, uint32_t* rec_zbits, int32_t* rec_re
                            uint64_t* pair_keys, uint32_t* pair_vals, uint32_t* tile_ranges,
                            int64_t* n_pairs, int64_t* n_tiles, ss_stream stream);
 
+/* Test access to the environment levels of the last ss_render (split-sum
+ * shading, eq:ibl, Sec. 3.4.2): the GGX-prefiltered levels 1..5 and the
+ * irradiance level of scene `scene`, copied into `levels` (host or device),
+ * each level [row][column][rgb] float32 in that order, n = 3 x the sum of the
+ * levels' texel counts (level l of an He x We map: max(He >> l, 4) x
+ * max(We >> l, 8); irradiance 32 x 64).  SS_ERR_STATE without a split-sum
+ * forward, SS_ERR_INVALID_ARG for a scene out of range, a null destination or
+ * another n.  Synchronises the stream. */
+ss_status ss_debug_env_levels(ss_context* ctx, int32_t scene, float* levels, int64_t n, ss_stream stream);
+
 /* Stage timing.  While enabled, every stage of ss_render / ss_render_backward
  * is bracketed by HIP events on the caller's stream (not usable under graph
  * capture).  ss_profile_read synchronises the last stream and writes, for each

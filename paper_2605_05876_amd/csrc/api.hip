@@ -1313,6 +1313,18 @@ __global__ void copy_ranges_kernel(const uint32_t* r, int n, uint32_t add, uint3
 }
 }  // namespace
 
+extern "C" ss_status ss_debug_env_levels(ss_context* c, int32_t scene, float* levels, int64_t n, ss_stream stream) {
+  if (!c || !c->fwd_valid || c->opt.shade != SS_SHADE_SPLITSUM) return SS_ERR_STATE;
+  if (scene < 0 || scene >= (int32_t)c->env.size() || !levels) return SS_ERR_INVALID_ARG;
+  const SceneEnv& e = c->env[scene];
+  const long long need = e.off[6] + 3LL * e.lh[6] * e.lw[6];
+  if (n != need || !e.lv.p) return SS_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  SS_HIP(hipMemcpyAsync(levels, e.lv.p, (size_t)need * sizeof(float), hipMemcpyDefault, st));
+  SS_HIP(hipStreamSynchronize(st));
+  return SS_OK;
+}
+
 extern "C" ss_status ss_debug_binning(ss_context* c, uint32_t* rec_zbits, int32_t* rec_rect,
                                       uint64_t* pair_keys, uint32_t* pair_vals, uint32_t* tile_ranges,
                                       int64_t* n_pairs, int64_t* n_tiles, ss_stream stream) {

@@ -24,7 +24,8 @@ LAUNCH = {"batched": 0, "per_view": 1}
 
 EXPORTED = ["ss_default_options", "ss_create", "ss_destroy", "ss_set_options", "ss_brdf_lut",
             "ss_set_brdf_lut", "ss_reserve", "ss_render", "ss_render_backward", "ss_poll",
-            "ss_render_static", "ss_debug_binning", "ss_profile_enable", "ss_profile_read", "ss_status_str"]
+            "ss_render_static", "ss_debug_binning", "ss_debug_env_levels", "ss_profile_enable", "ss_profile_read",
+            "ss_status_str"]
 STATIC_SCRATCH_BYTES = 32 << 20  # SS_STATIC_SCRATCH_BYTES
 STAGES = ["envmap", "preprocess", "binning", "raster_forward", "raster_backward",
           "preprocess_backward", "envmap_backward"]
@@ -120,6 +121,7 @@ def load_library(path: str = LIB_PATH):
     L.ss_render_static.argtypes = [vp, ctypes.POINTER(ss_batch), ctypes.POINTER(ss_outputs), vp]
     L.ss_debug_binning.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int64), vp]
+    L.ss_debug_env_levels.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64, vp]
     L.ss_profile_enable.argtypes = [vp, ctypes.c_int32]
     L.ss_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     L.ss_status_str.argtypes = [ctypes.c_int]
@@ -423,6 +425,15 @@ class Renderer:
                                        ctypes.byref(np_), ctypes.byref(nt), _stream_ptr()), "ss_debug_binning")
         n = np_.value
         return dict(rec_zbits=zb, rec_rect=rect, keys=keys[:n], vals=vals[:n], ranges=ranges[:nt.value])
+
+    def debug_env_levels(self, batch: Batch, scene: int = 0):
+        """Environment levels 1..6 of a scene as the last forward computed them
+        (test access), flattened level by level, each [row][column][rgb]."""
+        He, We = (int(x) for x in batch.envmaps[scene].shape[:2])
+        n = 3 * sum(max(He >> l, 4) * max(We >> l, 8) for l in range(1, 6)) + 3 * 32 * 64
+        out = torch.empty(n, dtype=torch.float32, device=batch.params["position"].device)
+        _check(self.L.ss_debug_env_levels(self.ctx, scene, _ptr(out), n, _stream_ptr()), "ss_debug_env_levels")
+        return out
 
 
 def make_brdf_lut(n_nv: int = 64, n_r: int = 64, samples: int = 1024, device="cuda") -> torch.Tensor:

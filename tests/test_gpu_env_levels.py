@@ -1,0 +1,71 @@
+"""GPU test of the environment prefilter (eq:ibl, Sec. 3.4.2): the levels that the
+split-sum forward computes, element by element against the oracle's FP64
+prefilter of the same float32 map.  The map sizes take every path of the kernel:
+one input chunk (16 x 32) and many (64 at 128 x 256); threads whose two output
+texels lie in two specular levels, in the irradiance level, or one in each.
+
+Bound: the kernel forms the texel directions in FP32, and near the peak of a
+lobe a relative direction error eps moves the GGX weight by about 2 eps / alpha^2
+(alpha^2 = (l/5)^4: a factor ~1250 at level 1, 78 at level 2, below 16 beyond);
+the rest are FP32 sums of positive values (relative error ~1e-6).  Level 1 is
+held to a relative L2 error of 1e-4 and every texel to 2e-4 of the level's
+largest value; the other levels to 1e-5 and 2e-5.  (Measured: level 1 up to
+7e-6 and 3e-5, the others up to 3e-7 and 1e-6.)"""
+import math
+
+import numpy as np
+import pytest
+
+import scenegen as g
+from test_gpu_parity import O, ss  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+LEVEL_REL_L2 = {1: 1e-4}      # other levels: 1e-5
+TEXEL_REL_MAX = {1: 2e-4}     # other levels: 2e-5
+
+
+@pytest.mark.parametrize("hw", [(16, 32), (64, 128), (128, 256)])
+def test_env_levels_match_oracle(O, ss, hw):
+    H, W = hw
+    sc = g.torus_scene(22, 2_000, scale_mu=math.log(0.02), scale_sigma=0.3)
+    sc.envmap = g.lognormal_envmap(5 + H, H, W)
+    cam = g.look_at_camera((0.0, -3.0, 1.0), 32, 32)
+    b = ss.batch_from_scenes([sc], [cam])
+    r = ss.Renderer(ss.Options(shade="splitsum"))
+    r.forward(b)
+    got = r.debug_env_levels(b, 0).cpu().numpy().astype(np.float64)
+    E = b.envmaps[0].cpu().numpy().astype(np.float64)   # the float32 map the kernel read
+    ref = O.envmap(E)[3 * H * W:]
+    assert got.shape == ref.shape
+    base = 3 * H * W
+    for lvl, (h, w, off) in enumerate(O.map_layout(H, W)[1:], start=1):
+        n = 3 * h * w
+        gl, rl = got[off - base:off - base + n], ref[off - base:off - base + n]
+        scale = np.abs(rl).max()
+        rel_l2 = float(np.linalg.norm(gl - rl) / max(np.linalg.norm(rl), 1e-30))
+        worst = float(np.abs(gl - rl).max() / max(scale, 1e-30))
+        print(f"[env levels] {H}x{W} level {lvl} ({h}x{w}): rel L2 {rel_l2:.2e}, worst texel {worst:.2e} of max")
+        assert np.isfinite(gl).all(), lvl
+        assert rel_l2 <= LEVEL_REL_L2.get(lvl, 1e-5), (lvl, rel_l2)
+        assert worst <= TEXEL_REL_MAX.get(lvl, 2e-5), (lvl, worst)
+
+
+def test_env_levels_errors(ss):
+    """The hook's errors: no split-sum forward (state), scene out of range."""
+    sc = g.torus_scene(22, 500, scale_mu=math.log(0.02), scale_sigma=0.3)
+    cam = g.look_at_camera((0.0, -3.0, 1.0), 16, 16)
+    b = ss.batch_from_scenes([sc], [cam])
+    r = ss.Renderer(ss.Options())
+    r.forward(b)
+    import ctypes
+    buf = torch.empty(16, device="cuda")
+    assert r.L.ss_debug_env_levels(r.ctx, 0, ctypes.c_void_p(buf.data_ptr()), 16, None) == ss.SS_ERR_STATE
+    sc.envmap = g.lognormal_envmap(7, 16, 32)
+    b2 = ss.batch_from_scenes([sc], [cam])
+    r2 = ss.Renderer(ss.Options(shade="splitsum"))
+    r2.forward(b2)
+    assert r2.L.ss_debug_env_levels(r2.ctx, 1, ctypes.c_void_p(buf.data_ptr()), 16, None) == ss.SS_ERR_INVALID_ARG
+    assert r2.L.ss_debug_env_levels(r2.ctx, 0, ctypes.c_void_p(buf.data_ptr()), 16, None) == ss.SS_ERR_INVALID_ARG
