@@ -17,7 +17,8 @@ import numpy as np
 import pytest
 
 import scenegen as g
-from test_gpu_parity import O, ss  # noqa: F401
+from parity_util import GRAD_REL_L2
+from test_gpu_parity import O, _backward_case, all_pix, small_c2, ss  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -69,3 +70,16 @@ def test_env_levels_errors(ss):
     r2.forward(b2)
     assert r2.L.ss_debug_env_levels(r2.ctx, 1, ctypes.c_void_p(buf.data_ptr()), 16, None) == ss.SS_ERR_INVALID_ARG
     assert r2.L.ss_debug_env_levels(r2.ctx, 0, ctypes.c_void_p(buf.data_ptr()), 16, None) == ss.SS_ERR_INVALID_ARG
+
+
+def test_envmap_adjoint_large_map(O, ss):
+    """Gradient parity (every group, the environment map's included: the oracle's
+    level gradients through its FP64 prefilter adjoint) on the reduced C2 scene
+    lit by a 128 x 256 map, whose adjoint launch spans many blocks of input
+    texels and chunks of output texels."""
+    scenes, cams = small_c2()
+    scenes[0].envmap = g.lognormal_envmap(61, 128, 256)
+    errs = _backward_case(O, ss, scenes, cams, "splitsum", lambda c, v: all_pix(c))
+    print("[env adjoint 128x256]", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert "envmap0" in errs
+    assert max(errs.values()) <= GRAD_REL_L2, errs
