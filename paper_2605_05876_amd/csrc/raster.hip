@@ -106,10 +106,13 @@ __device__ __forceinline__ bool ellipse_meets(const float4 q0, const float4 q1, 
   if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return true;
   float nmin = 3.4e38f;
   {
-    const float ya = fminf(fmaxf(-qxy * x0 / qyy, y0), y1), yb = fminf(fmaxf(-qxy * x1 / qyy, y0), y1);
+    // the edges' 1-D minimisers by hardware reciprocals: a minimiser off by a
+    // relative 1e-7 raises the value found by ~1e-14 of it, far inside the margin
+    const float iqyy = __builtin_amdgcn_rcpf(qyy), iqxx = __builtin_amdgcn_rcpf(qxx);
+    const float ya = fminf(fmaxf(-qxy * x0 * iqyy, y0), y1), yb = fminf(fmaxf(-qxy * x1 * iqyy, y0), y1);
     nmin = fminf(nmin, qxx * x0 * x0 + 2.f * qxy * x0 * ya + qyy * ya * ya);
     nmin = fminf(nmin, qxx * x1 * x1 + 2.f * qxy * x1 * yb + qyy * yb * yb);
-    const float xa = fminf(fmaxf(-qxy * y0 / qxx, x0), x1), xb = fminf(fmaxf(-qxy * y1 / qxx, x0), x1);
+    const float xa = fminf(fmaxf(-qxy * y0 * iqxx, x0), x1), xb = fminf(fmaxf(-qxy * y1 * iqxx, x0), x1);
     nmin = fminf(nmin, qxx * xa * xa + 2.f * qxy * xa * y0 + qyy * y0 * y0);
     nmin = fminf(nmin, qxx * xb * xb + 2.f * qxy * xb * y1 + qyy * y1 * y1);
   }
