@@ -51,7 +51,8 @@ struct Group {
   int tile_base, n_tiles;
   long long rec_begin, rec_end;
   long long pair_base, pair_cap;
-  int pair_passes;  // radix passes of the pair sort: 8-bit digits of the local tile index
+  int pair_passes;  // radix passes of the pair sort over the bits of the local tile index:
+  int pair_first;   // 8-bit digits, the first 9 bits wide when that saves a pass
   long long mask_base, mask_n;  // the group's chunk slots of walk masks (WalkBufs)
   // raster work items when long lists are split: all items, those of split tiles
   long long item_base, item_cap, mitem_base, mitem_cap;
@@ -425,7 +426,7 @@ ss_status run_binning(ss_context* c, const Group& g, int gi, hipStream_t st) {
   SS_HIP(launch_radix_sort(zk, zi, P<uint32_t>(c->zkey2) + g.rec_begin, P<uint32_t>(c->zidx2) + g.rec_begin,
                            true, (uint32_t)g.rec_begin, P<uint2>(c->prect), zr,
                            // culled records: depth key 0xffffffff, empty rectangle (1, 0)
-                           0xffffffffu, make_uint2(1u, 0u), nullptr, n, n, 4,
+                           0xffffffffu, make_uint2(1u, 0u), nullptr, n, n, 4, 8,
                            P<uint32_t>(c->hist), c->hist_n, P<uint32_t>(c->scan_tmp), c->scan_tmp_n, st));
   SS_HIP(launch_scan_rect_tiles(zr, c->opt.tile_w, c->opt.tile_h, P<uint32_t>(c->offsets) + g.rec_begin, n,
                                 misc + kMiscPairs + gi, P<uint32_t>(c->scan_tmp), c->scan_tmp_n, st));
@@ -439,7 +440,8 @@ ss_status run_binning(ss_context* c, const Group& g, int gi, hipStream_t st) {
                            c->opt.tile_w, c->opt.tile_h, odd ? keys2 : keys, odd ? vals2 : vals, g.pair_cap, status,
                            st));
   SS_HIP(launch_radix_sort(odd ? keys2 : keys, odd ? vals2 : vals, odd ? keys : keys2, odd ? vals : vals2, false, 0u,
-                           nullptr, nullptr, 0u, make_uint2(0u, 0u), np, -1, g.pair_cap, g.pair_passes, P<uint32_t>(c->hist), c->hist_n,
+                           nullptr, nullptr, 0u, make_uint2(0u, 0u), np, -1, g.pair_cap, g.pair_passes, g.pair_first,
+                           P<uint32_t>(c->hist), c->hist_n,
                            P<uint32_t>(c->scan_tmp), c->scan_tmp_n, st));
   SS_HIP(launch_tile_ranges(keys, np, g.pair_cap, P<uint32_t>(c->ranges), g.tile_base, g.n_tiles, st));
   return SS_OK;
@@ -484,7 +486,11 @@ void plan_batch(ss_context* c, const ss_batch* b, std::vector<ViewDev>& vh) {
     for (int v = g.v0; v < g.v1; ++v) g.n_tiles += vh[v].tiles_x * vh[v].tiles_y;
     g.rec_begin = vh[g.v0].rec_off;
     g.rec_end = vh[g.v1 - 1].rec_off + vh[g.v1 - 1].n_surf;
-    g.pair_passes = g.n_tiles > 1 ? (bits_for(g.n_tiles) + 7) / 8 : 0;
+    {
+      const int bits = g.n_tiles > 1 ? bits_for(g.n_tiles) : 0;
+      g.pair_first = bits > 1 && bits % 8 == 1 ? 9 : 8;  // e.g. 17 bits: 9 + 8
+      g.pair_passes = bits > 0 ? (bits - (g.pair_first - 8) + 7) / 8 : 0;
+    }
     g.pair_base = 0;
     g.pair_cap = 0;
     g.mask_base = 0;

@@ -17,6 +17,8 @@
 // Every kernel reads the data-dependent pair count from device memory and is
 // sized by the reserved capacity on the host, so the whole sequence can be
 // captured in a HIP graph.
+#include <type_traits>
+
 #include "common.h"
 
 namespace ss {
@@ -411,8 +413,8 @@ hipError_t launch_emit_pairs(const uint32_t* order, const uint2* rect, const uin
 }
 
 // ---------------------------------------------------------------- radix sort
-// Stable LSD radix sort of 32-bit keys carrying 32-bit values, 8-bit digits,
-// reduce-then-scan.  The input is cut into chunks of kRadixItems pairs; each
+// Stable LSD radix sort of 32-bit keys carrying 32-bit values, 8-bit digits
+// (the first may have 9, so that 17 key bits take two passes), reduce-then-scan.  The input is cut into chunks of kRadixItems pairs; each
 // workgroup owns a contiguous run of chunks, each of its waves a contiguous
 // 1/8 of a chunk, so workgroup, chunk and wave order are the input order.
 // Per pass: the histogram kernel writes each workgroup's digit counts
@@ -441,18 +443,19 @@ static RadixGrid radix_grid(long long cap) {
   if (g.groups < 1) g.groups = 1;
   return g;
 }
-long long radix_hist_size(long long cap) { return 256LL * radix_grid(cap).groups; }
+long long radix_hist_size(long long cap) { return 512LL * radix_grid(cap).groups; }  // up to 9-bit digits
 
 __device__ inline long long radix_count(const uint32_t* n_dev, long long n_fixed, long long cap) {
   const long long n = n_fixed >= 0 ? n_fixed : (long long)*n_dev;
   return n < cap ? n : cap;
 }
 
-// Lanes of the wave holding the same 8-bit digit as this one, among live lanes.
+// Lanes of the wave holding the same BITS-bit digit as this one, among live lanes.
+template <int BITS>
 __device__ inline uint64_t match_digit(uint32_t d, bool live) {
   uint64_t m = __ballot(live);
 #pragma unroll
-  for (int b = 0; b < 8; ++b) {
+  for (int b = 0; b < BITS; ++b) {
     const bool bit = (d >> b) & 1u;
     const uint64_t bb = __ballot(bit);
     m &= bit ? bb : ~bb;
@@ -465,13 +468,16 @@ __device__ inline uint64_t lanes_below() {
   return lane == 0 ? 0ull : (~0ull) >> (64 - lane);
 }
 
+template <int BITS>
 __global__ void __launch_bounds__(kRadixThreads) radix_hist_kernel(const uint32_t* __restrict__ keys,
                                                                    const uint32_t* n_dev, long long n_fixed,
                                                                    long long cap, int shift, int cpg,
                                                                    uint32_t* __restrict__ hist) {
-  // 4 sub-histograms per wave (by lane & 3) cut same-address conflicts of the
-  // LDS atomics on skewed digits; rows padded to 257 to put them in other banks
-  constexpr int kSub = 4, kRow = 257;
+  // sub-histograms per wave (by lane: 4 for 8-bit digits, 2 for 9-bit ones)
+  // cut same-address conflicts of the LDS atomics on skewed digits; rows padded
+  // by one entry to put them in other banks
+  constexpr int NB = 1 << BITS, kSub = BITS == 8 ? 4 : 2, kRow = NB + 1;
+  static_assert(NB <= kRadixThreads, "one thread per digit");
   __shared__ uint32_t wh[kRadixWaves * kSub * kRow];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   uint32_t* my = wh + (wave * kSub + (lane & (kSub - 1))) * kRow;
@@ -487,14 +493,14 @@ __global__ void __launch_bounds__(kRadixThreads) radix_hist_kernel(const uint32_
 #pragma unroll
     for (int k = 0; k < kRadixRounds; ++k) {
       const long long i = base + 64 * k;
-      d[k] = (keys[i < n ? i : n - 1] >> shift) & 255u;
+      d[k] = (keys[i < n ? i : n - 1] >> shift) & (NB - 1u);
     }
 #pragma unroll
     for (int k = 0; k < kRadixRounds; ++k)
       if (base + 64 * k < n) atomicAdd(&my[d[k]], 1u);
   }
   __syncthreads();
-  if (t < 256) {
+  if (t < NB) {
     uint32_t s = 0;
 #pragma unroll
     for (int w = 0; w < kRadixWaves * kSub; ++w) s += wh[w * kRow + t];
@@ -506,26 +512,31 @@ __global__ void __launch_bounds__(kRadixThreads) radix_hist_kernel(const uint32_
 // GATHER: also writes gout[dst] = gsrc[value] (the last pass of a sort whose
 // values index gsrc), or gskip_val without reading gsrc where the key is
 // gskip_key (entries whose gathered value is known: culled records).
-template <bool IOTA, bool GATHER>
+template <bool IOTA, bool GATHER, int BITS>
 __global__ void __launch_bounds__(kRadixThreads) radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t val0,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint2* __restrict__ gsrc,
     uint2* __restrict__ gout, uint32_t gskip_key, uint2 gskip_val, const uint32_t* n_dev, long long n_fixed,
     long long cap, int shift, int cpg, const uint32_t* __restrict__ hist) {
-  __shared__ uint32_t woff[kRadixWaves][256];  // per-wave digit counts, then chunk-local run starts
-  __shared__ uint32_t loc[256];                // chunk-local start of each digit
-  __shared__ uint32_t run[256];                // global start of each digit's run of this chunk
-  __shared__ uint32_t wsum[4];
+  constexpr int NB = 1 << BITS;
+  // per-wave digit counts, then chunk-local run starts (both below kRadixItems,
+  // so 16 bits hold them for 9-bit digits and two blocks still fit a CU's LDS)
+  using Cnt = typename std::conditional<BITS == 8, uint32_t, uint16_t>::type;
+  static_assert(NB <= kRadixThreads && kRadixItems <= 65536, "one thread per digit, 16-bit positions");
+  __shared__ Cnt woff[kRadixWaves][NB];
+  __shared__ uint32_t loc[NB];                 // chunk-local start of each digit
+  __shared__ uint32_t run[NB];                 // global start of each digit's run of this chunk
+  __shared__ uint32_t wsum[NB / 64];
   __shared__ uint32_t sk[kRadixItems];
   __shared__ uint32_t sv[kRadixItems];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const long long n = radix_count(n_dev, n_fixed, cap);
-  if (t < 256) run[t] = hist[(long long)t * gridDim.x + blockIdx.x];
+  if (t < NB) run[t] = hist[(long long)t * gridDim.x + blockIdx.x];
   const uint64_t lt = lanes_below();
   for (int c = 0; c < cpg; ++c) {
     const long long b0 = ((long long)blockIdx.x * cpg + c) * kRadixItems;
     if (b0 >= n) break;
-    for (int i = t; i < kRadixWaves * 256; i += kRadixThreads) (&woff[0][0])[i] = 0u;
+    for (int i = t; i < kRadixWaves * NB; i += kRadixThreads) (&woff[0][0])[i] = 0u;
     const long long base = b0 + (long long)wave * kRadixPerWave + lane;
     // loads clamped into range (n > b0 >= 0), not branched round, so all are in flight at once
     uint32_t key[kRadixRounds], val[kRadixRounds];
@@ -542,23 +553,23 @@ __global__ void __launch_bounds__(kRadixThreads) radix_scatter_kernel(
 #pragma unroll
     for (int k = 0; k < kRadixRounds; ++k) {
       const bool live = base + 64 * k < n;
-      const uint32_t d = (key[k] >> shift) & 255u;
-      const uint64_t m = match_digit(d, live);
+      const uint32_t d = (key[k] >> shift) & (NB - 1u);
+      const uint64_t m = match_digit<BITS>(d, live);
       const uint32_t r = (uint32_t)__popcll(m & lt);
       const uint32_t cw = woff[wave][d];
       pre[k] = cw + r;
       __builtin_amdgcn_wave_barrier();
-      if (live && r == 0) woff[wave][d] = cw + (uint32_t)__popcll(m);
+      if (live && r == 0) woff[wave][d] = (Cnt)(cw + (uint32_t)__popcll(m));
       __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
     // digit totals -> exclusive scan over digits -> per-wave run starts
     uint32_t tot = 0, incl = 0;
-    if (t < 256) {
+    if (t < NB) {
 #pragma unroll
       for (int w = 0; w < kRadixWaves; ++w) {
         const uint32_t x = woff[w][t];
-        woff[w][t] = tot;
+        woff[w][t] = (Cnt)tot;
         tot += x;
       }
       incl = tot;
@@ -570,18 +581,18 @@ __global__ void __launch_bounds__(kRadixThreads) radix_scatter_kernel(
       if (lane == 63) wsum[wave] = incl;
     }
     __syncthreads();
-    if (t < 256) {
+    if (t < NB) {
       uint32_t ex = incl - tot;
       for (int w = 0; w < wave; ++w) ex += wsum[w];
       loc[t] = ex;
 #pragma unroll
-      for (int w = 0; w < kRadixWaves; ++w) woff[w][t] += ex;
+      for (int w = 0; w < kRadixWaves; ++w) woff[w][t] = (Cnt)(woff[w][t] + ex);
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kRadixRounds; ++k) {
       if (base + 64 * k < n) {
-        const uint32_t p = woff[wave][(key[k] >> shift) & 255u] + pre[k];
+        const uint32_t p = woff[wave][(key[k] >> shift) & (NB - 1u)] + pre[k];
         sk[p] = key[k];
         sv[p] = val[k];
       }
@@ -591,7 +602,7 @@ __global__ void __launch_bounds__(kRadixThreads) radix_scatter_kernel(
 #pragma unroll 4
     for (int p = t; p < cnt; p += kRadixThreads) {
       const uint32_t k = sk[p];
-      const uint32_t d = (k >> shift) & 255u;
+      const uint32_t d = (k >> shift) & (NB - 1u);
       const uint32_t dst = run[d] + ((uint32_t)p - loc[d]);
       const uint32_t v = sv[p];
       kout[dst] = k;
@@ -599,34 +610,45 @@ __global__ void __launch_bounds__(kRadixThreads) radix_scatter_kernel(
       if (GATHER) gout[dst] = k == gskip_key ? gskip_val : gsrc[v];
     }
     __syncthreads();
-    if (t < 256) run[t] += tot;
+    if (t < NB) run[t] += tot;
   }
 }
 
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                              bool iota, uint32_t val0, const uint2* gsrc, uint2* gout, uint32_t gskip_key,
                              uint2 gskip_val, const uint32_t* n_dev, long long n_fixed, long long cap, int passes,
-                             uint32_t* hist, long long hist_n, uint32_t* scan_tmp, long long scan_tmp_n,
-                             hipStream_t st) {
+                             int first_bits, uint32_t* hist, long long hist_n, uint32_t* scan_tmp,
+                             long long scan_tmp_n, hipStream_t st) {
   if (passes <= 0 || cap <= 0) return hipSuccess;
+  if (first_bits != 8 && first_bits != 9) return hipErrorInvalidValue;
   const RadixGrid rg = radix_grid(cap);
-  if (256LL * rg.groups > hist_n) return hipErrorInvalidValue;
+  if ((1LL << first_bits) * rg.groups > hist_n) return hipErrorInvalidValue;
   uint32_t *ka = keys, *va = vals, *kb = keys_tmp, *vb = vals_tmp;
+  int shift = 0;
   for (int p = 0; p < passes; ++p) {
-    const int shift = 8 * p;
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(rg.groups), dim3(kRadixThreads), 0, st, ka, n_dev, n_fixed, cap,
-                       shift, rg.chunks_per_group, hist);
-    hipError_t e = launch_scan_u32(hist, hist, 256LL * rg.groups, nullptr, scan_tmp, scan_tmp_n, st);
+    const int bits = p == 0 ? first_bits : 8;
+    if (bits == 9)
+      hipLaunchKernelGGL(radix_hist_kernel<9>, dim3(rg.groups), dim3(kRadixThreads), 0, st, ka, n_dev, n_fixed,
+                         cap, shift, rg.chunks_per_group, hist);
+    else
+      hipLaunchKernelGGL(radix_hist_kernel<8>, dim3(rg.groups), dim3(kRadixThreads), 0, st, ka, n_dev, n_fixed,
+                         cap, shift, rg.chunks_per_group, hist);
+    hipError_t e = launch_scan_u32(hist, hist, (1LL << bits) * rg.groups, nullptr, scan_tmp, scan_tmp_n, st);
     if (e != hipSuccess) return e;
     const bool io = iota && p == 0, ga = gsrc && p == passes - 1;
-#define SS_SCATTER(I, G)                                                                                     \
-  hipLaunchKernelGGL((radix_scatter_kernel<I, G>), dim3(rg.groups), dim3(kRadixThreads), 0, st, ka, va, val0, \
+#define SS_SCATTER(I, G, B)                                                                                    \
+  hipLaunchKernelGGL((radix_scatter_kernel<I, G, B>), dim3(rg.groups), dim3(kRadixThreads), 0, st, ka, va, val0, \
                      kb, vb, gsrc, gout, gskip_key, gskip_val, n_dev, n_fixed, cap, shift, rg.chunks_per_group, hist)
-    if (io && ga) SS_SCATTER(true, true);
-    else if (io) SS_SCATTER(true, false);
-    else if (ga) SS_SCATTER(false, true);
-    else SS_SCATTER(false, false);
+    if (bits == 9) {
+      // (a 9-bit digit only ever leads a pair sort: no values by position, no gather)
+      if (io || ga) return hipErrorInvalidValue;
+      SS_SCATTER(false, false, 9);
+    } else if (io && ga) SS_SCATTER(true, true, 8);
+    else if (io) SS_SCATTER(true, false, 8);
+    else if (ga) SS_SCATTER(false, true, 8);
+    else SS_SCATTER(false, false, 8);
 #undef SS_SCATTER
+    shift += bits;
     uint32_t* tk = ka; ka = kb; kb = tk;
     uint32_t* tv = va; va = vb; vb = tv;
   }

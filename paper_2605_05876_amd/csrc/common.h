@@ -462,7 +462,8 @@ long long scan_tmp_size(long long n);
 hipError_t launch_emit_pairs(const uint32_t* order, const uint2* rect, const uint32_t* offsets,
                              const ViewDev* views, int v0, int v1, long long n_rec, int tile_w, int tile_h,
                              uint32_t* keys, uint32_t* vals, long long cap, int* status, hipStream_t st);
-// Stable radix sort of (key, value) pairs over the low 8 * passes key bits; the
+// Stable radix sort of (key, value) pairs over the low first_bits + 8 (passes - 1)
+// key bits (first_bits 8, or 9 for a sort without iota values or gather); the
 // result is in (keys, vals) for an even pass count, else in the tmp buffers.
 // Count: n_fixed when >= 0, else *n_dev (device), at most cap; cap sizes the
 // grid and the histogram (radix_hist_size(cap) entries).  iota: the first pass
@@ -473,8 +474,8 @@ long long radix_hist_size(long long cap);
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                              bool iota, uint32_t val0, const uint2* gsrc, uint2* gout, uint32_t gskip_key,
                              uint2 gskip_val, const uint32_t* n_dev, long long n_fixed, long long cap, int passes,
-                             uint32_t* hist, long long hist_n, uint32_t* scan_tmp, long long scan_tmp_n,
-                             hipStream_t st);
+                             int first_bits, uint32_t* hist, long long hist_n, uint32_t* scan_tmp,
+                             long long scan_tmp_n, hipStream_t st);
 hipError_t launch_tile_ranges(const uint32_t* keys, const uint32_t* n_pairs, long long cap,
                               uint32_t* ranges, int tile_begin, int n_tiles, hipStream_t st);
 

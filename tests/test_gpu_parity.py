@@ -82,12 +82,14 @@ def small_multiview():
 
 # ---------------------------------------------------------------- binning
 # Tile counts cover every pair-sort pass count: C1 16x16 and MV (one radix pass),
-# C1 8x8 (two), one 16x16 tile (none), BIG 8x8 with 69696 tiles (three); MV
-# per view sorts each view on its own.
+# C1 8x8 (two), one 16x16 tile (none), BIG 8x8 with 69696 tiles (17 bits: a 9-bit
+# and an 8-bit pass), HUGE 8x8 with 135424 tiles (18 bits: three passes); MV per
+# view sorts each view on its own.
 @pytest.mark.parametrize("case,tile,launch", [("C1", (16, 16), "batched"), ("C1", (8, 8), "batched"),
                                               ("C2s", (16, 16), "batched"), ("MV", (16, 8), "batched"),
                                               ("MV", (32, 16), "batched"), ("MV", (16, 8), "per_view"),
-                                              ("ONE_TILE", (16, 16), "batched"), ("BIG", (8, 8), "batched")])
+                                              ("ONE_TILE", (16, 16), "batched"), ("BIG", (8, 8), "batched"),
+                                              ("HUGE", (8, 8), "batched")])
 def test_binning_bit_exact(O, ss, case, tile, launch):
     if case == "C1":
         w = g.make_config("C1")
@@ -97,9 +99,10 @@ def test_binning_bit_exact(O, ss, case, tile, launch):
     elif case == "ONE_TILE":
         (scenes, _), shade = small_multiview(), "albedo"
         cams = [g.look_at_camera(np.array([0.3, -2.8, 0.9]), 16, 16)]
-    elif case == "BIG":
+    elif case in ("BIG", "HUGE"):
         (scenes, _), shade = small_multiview(), "albedo"
-        cams = [g.look_at_camera(np.array([0.3, -2.8, 0.9]), 2112, 2112)]
+        side = 2112 if case == "BIG" else 2944
+        cams = [g.look_at_camera(np.array([0.3, -2.8, 0.9]), side, side)]
     else:
         (scenes, cams), shade = small_multiview(), "splitsum"
     opts = ss.Options(shade=shade, tile_w=tile[0], tile_h=tile[1], launch=launch)
